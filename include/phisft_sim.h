@@ -1,0 +1,193 @@
+/*
+ * phisft_sim.h -- C ABI of the differentiable cloth simulator (MI355X / gfx950).
+ *
+ * What it computes (Kairanda et al., "phi-SfT", CVPR 2022, Sec. 3.1):
+ *   * the deformation model S_t = PS(S_{t-1}; phi_{t-1}) (Eq. 1) with
+ *     phi = {d, S, B, F_t} (Eq. 2; the wind term w is not modelled here):
+ *     areal density d, stretching stiffness k_s (a scalar reduction of S),
+ *     bending stiffness k_b (a scalar reduction of B) and per-step,
+ *     per-vertex corrective forces F_t;
+ *   * per step one linearised backward-Euler update (Eq. 4 with the force
+ *     linearisation of Eq. 5, df/dv = 0), solved for Delta v by a
+ *     block-Jacobi preconditioned conjugate gradient:
+ *         (M + h^2 K_sys(x_{t-1})) Delta v = h (f(x_{t-1}) + M g + F_t - h K_sys v_{t-1})
+ *         v_t = v_{t-1} + Delta v,   x_t = x_{t-1} + h v_t
+ *     with M the lumped mass (density times a third of the incident triangle
+ *     areas), f = -dE/dx for E = sum_tri area (k_s/2) |G|_F^2 (Green strain G)
+ *     + sum_hinge k_b c_e (theta - theta_rest)^2, and K_sys the positive
+ *     semi-definite system stiffness (membrane Hessian with its compressive
+ *     stress term removed, Gauss-Newton bending Hessian);
+ *   * the adjoint of that rollout (the paper's backward pass by implicit
+ *     differentiation of Eq. 4): gradients of a per-frame loss with respect to
+ *     (k_s, k_b, d), the forces F_t and the initial state (x_0, v_0).
+ * Collisions (Eq. 6) are not part of this library.
+ *
+ * Conventions
+ *   Layout     Per-vertex device arrays are structure-of-arrays [3][V]
+ *              (all x, then all y, then all z), V = total vertices of the handle.
+ *              A batch handle concatenates its instances' vertices in order.
+ *   dtype      Device state arrays (x0, v0, forces, x_out, dl_dx, dl_dforces,
+ *              dl_dx0, dl_dv0) are float for SIM_FP32 and double for SIM_FP64.
+ *              Material arrays are always double, [n_instances][3] =
+ *              (k_s [N/m], k_b [N m], d [kg/m^2]).
+ *   Units      SI. Gravity defaults to (0, 0, -9.81) m/s^2.
+ *   Ownership  sim_create copies mesh, rest positions and pins. The caller owns
+ *              every device pointer passed to sim_rollout / sim_adjoint. The
+ *              forces and material buffers given to sim_rollout are read again
+ *              by the matching sim_adjoint (checkpoint recompute) and must stay
+ *              valid and unchanged until it has been enqueued and has run.
+ *              The library owns its workspace (trajectory/checkpoints, system
+ *              matrix, solver vectors).
+ *   Streams    Calls enqueue work on the given hipStream_t (NULL = default
+ *              stream) and return without synchronising. One handle must not
+ *              be used from two host threads at once.
+ *   State      create -> (rollout -> adjoint?)* -> destroy. sim_adjoint refers to
+ *              the most recent rollout; otherwise it returns SIM_E_STATE.
+ *   Errors     Argument and mesh errors return immediately. Device-side
+ *              conditions (non-finite values, CG not converged, CG breakdown
+ *              p.Ap <= 0) are sticky: they are recorded on the device and
+ *              reported by sim_sync_status. A solve that reaches cg_max_iter
+ *              keeps its last iterate and the rollout continues. After an error
+ *              outputs are unspecified; the handle stays valid.
+ */
+#ifndef PHISFT_SIM_H
+#define PHISFT_SIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_s sim_t;
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_E_INVALID = -1,       /* bad argument */
+  SIM_E_MESH = -2,          /* degenerate / non-manifold / inconsistently oriented mesh */
+  SIM_E_NOMEM = -3,         /* device or host allocation failed */
+  SIM_E_HIP = -4,           /* HIP runtime error (text in sim_last_error) */
+  SIM_E_NOT_CONVERGED = -5, /* a CG solve stopped at cg_max_iter */
+  SIM_E_INDEFINITE = -6,    /* CG breakdown: p.Ap <= 0 or a singular diagonal block */
+  SIM_E_NONFINITE = -7,     /* NaN/Inf in inputs, system or state */
+  SIM_E_STATE = -8          /* call out of order (e.g. adjoint without a rollout) */
+} sim_status;
+
+typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
+
+/* Host triangle mesh: tris [n_tris][3] vertex ids, counter-clockwise. */
+typedef struct {
+  int32_t n_verts;
+  int32_t n_tris;
+  const int32_t* tris;
+} sim_mesh;
+
+/* Material of one sheet (Eq. 2: d, and scalar stand-ins for S and B). */
+typedef struct {
+  double stretch; /* k_s [N/m]   */
+  double bend;    /* k_b [N m]   */
+  double density; /* d   [kg/m^2] */
+} sim_material;
+
+typedef struct {
+  int32_t precision;        /* sim_precision; storage type of state, matrix, forces     */
+  double cg_tol;            /* stop at ||r||_2 <= cg_tol * ||b||_2 (relative residual)  */
+  int32_t cg_max_iter;      /* cap per solve                                            */
+  int32_t checkpoint_every; /* k > 0: keep every k-th state, recompute in the adjoint;
+                               0: keep every state                                      */
+  double gravity[3];        /* m/s^2                                                    */
+  int32_t max_steps;        /* capacity: longest rollout this handle will run           */
+  int32_t rows_per_block;   /* solver rows per workgroup (64..256); 0 = tuned choice     */
+} sim_options;
+
+/* Per-handle statistics of the most recent rollout/adjoint (filled by
+ * sim_get_stats after sim_sync_status). */
+typedef struct {
+  int32_t n_steps;
+  int32_t n_instances;
+  int64_t cg_iters_forward;   /* summed over steps and instances */
+  int64_t cg_iters_recompute; /* forward solves repeated by checkpoint recompute */
+  int64_t cg_iters_adjoint;
+  int32_t cg_iters_max;       /* largest single solve */
+  double max_rel_residual;    /* largest final ||r||/||b|| of any solve */
+  int32_t device_status;      /* sticky device status (sim_status value) */
+  int32_t rows_per_block;     /* solver launch shape in use */
+  int32_t blocks;             /* solver workgroups per launch */
+} sim_stats;
+
+/* Fills *opt with the defaults: FP32, cg_tol 1e-7, cg_max_iter 20000, store
+ * every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block. */
+void sim_default_options(sim_options* opt);
+
+/* Creates a handle for one sheet.
+ *   mesh      host triangle mesh (fixed topology, Sec. 3.1)
+ *   rest_pos  host double [n_verts][3] rest (template) positions S_1
+ *   pins      host vertex ids held fixed (v = 0, x = x_0); may be NULL if n_pins = 0
+ *   mat       default material (used when sim_rollout gets material = NULL)
+ *   dt        time step h [s]
+ *   opt       options (NULL = sim_default_options)
+ * Computes the rest geometry (per-triangle inverse rest frame and area, lumped
+ * vertex areas, hinges with c_e and rest angles), the block sparsity pattern
+ * and the element-to-block maps on the host, uploads them and allocates the
+ * workspace for opt->max_steps steps. Errors: SIM_E_INVALID (bad argument),
+ * SIM_E_MESH (degenerate triangle, vertex id out of range, an edge shared by
+ * more than two triangles or used twice in the same direction),
+ * SIM_E_NOMEM, SIM_E_HIP. *out is NULL on error. */
+sim_status sim_create(const sim_mesh* mesh, const double* rest_pos, const int32_t* pins,
+                      int32_t n_pins, const sim_material* mat, double dt, const sim_options* opt,
+                      sim_t** out);
+
+/* Creates a handle over n independent sheets run together (one solver launch
+ * per step for all of them). Arguments are arrays of length n with the meaning
+ * of sim_create's; device arrays of the handle concatenate the instances'
+ * vertices in order. Same errors as sim_create. */
+sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,
+                            const int32_t* const* pins, const int32_t* n_pins,
+                            const sim_material* mats, double dt, const sim_options* opt,
+                            sim_t** out);
+
+/* Rollout of n_steps steps (Eq. 1 applied n_steps times).
+ *   x0, v0       device [3][V] initial state; v0 may be NULL (zero). Pinned
+ *                vertices keep x0 and zero velocity.
+ *   forces       device [n_steps][3][V]: forces[s-1] acts in step s; NULL = none
+ *   material     device double [n_instances][3]; NULL = the create-time materials
+ *   loss_frames  host int32 [n_loss], strictly increasing, each in 1..n_steps
+ *   x_out        device [n_loss][3][V]: positions after each loss frame
+ *   stream       hipStream_t
+ * Errors: SIM_E_INVALID (n_steps outside 1..max_steps, bad frames, NULL
+ * pointers), SIM_E_HIP. Device-side conditions: see sim_sync_status. */
+sim_status sim_rollout(sim_t* sim, int32_t n_steps, const void* x0, const void* v0,
+                       const void* forces, const void* material, const int32_t* loss_frames,
+                       int32_t n_loss, void* x_out, void* stream);
+
+/* Adjoint of the most recent rollout for a loss with gradient dl_dx
+ * (device [n_loss][3][V], one slice per loss frame).
+ *   dl_dmaterial  device double [n_instances][3] (dL/dk_s, dL/dk_b, dL/dd) or NULL
+ *   dl_dforces    device [n_steps][3][V] or NULL
+ *   dl_dx0        device [3][V] or NULL
+ *   dl_dv0        device [3][V] or NULL (zero on pinned vertices)
+ * Errors: SIM_E_STATE (no rollout), SIM_E_INVALID, SIM_E_HIP. */
+sim_status sim_adjoint(sim_t* sim, const void* dl_dx, void* dl_dmaterial, void* dl_dforces,
+                       void* dl_dx0, void* dl_dv0, void* stream);
+
+/* Waits for the handle's last stream and returns the sticky device status
+ * (SIM_OK, SIM_E_NOT_CONVERGED, SIM_E_INDEFINITE or SIM_E_NONFINITE) or a HIP
+ * error; clears it for the next call. */
+sim_status sim_sync_status(sim_t* sim);
+
+/* Copies the statistics of the most recent calls (valid after sim_sync_status). */
+sim_status sim_get_stats(const sim_t* sim, sim_stats* out);
+
+/* Per-step CG iteration counts [n_steps][n_instances] of the most recent
+ * rollout (forward) and adjoint; either pointer may be NULL. Host memory. */
+sim_status sim_get_cg_iters(const sim_t* sim, int32_t* forward, int32_t* adjoint);
+
+const char* sim_status_string(sim_status s);
+const char* sim_last_error(const sim_t* sim);
+void sim_destroy(sim_t* sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHISFT_SIM_H */

@@ -1,0 +1,306 @@
+"""FP64 CPU oracle of the phi-SfT cloth step and its adjoint -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never loads it and shares
+no code with it.
+
+The arithmetic lives in ``phisft_oracle.cpp`` (plain single-threaded C++17,
+FP64); this module is argument marshalling through ctypes. Arrays are
+vertex-major ``[V, 3]`` float64 (the GPU library's boundary uses ``[3, V]``).
+Every function cites the part of the paper it follows (Sec. 3.1, Eq. 1-5, and
+the backward pass by implicit differentiation).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import build_oracle, library_path
+
+ORC_OK = 0
+ORC_E_INVALID = -1
+ORC_E_MESH = -2
+ORC_E_NOT_CONVERGED = -5
+ORC_E_INDEFINITE = -6
+ORC_E_NONFINITE = -7
+
+_lib = None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        build_oracle()
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    I = ctypes.POINTER(ctypes.c_int)
+    c_int, c_double = ctypes.c_int, ctypes.c_double
+    sig = {
+        "orc_create": (P, [c_int, c_int, I, D, I, c_int, I]),
+        "orc_destroy": (None, [P]),
+        "orc_set_params": (c_int, [P] + [c_double] * 8 + [c_int]),
+        "orc_set_membrane_system": (c_int, [P, c_int]),
+        "orc_num_hinges": (c_int, [P]),
+        "orc_num_blocks": (c_int, [P]),
+        "orc_get_geometry": (None, [P, D, D, D, I, D, D]),
+        "orc_energy": (c_double, [P, D, D, D]),
+        "orc_internal_force": (None, [P, D, D]),
+        "orc_ksys_apply": (None, [P, D, D, D]),
+        "orc_kexact_apply": (None, [P, D, D, D]),
+        "orc_ksys_assembled_apply": (None, [P, D, D, D]),
+        "orc_third": (None, [P, D, D, D, D]),
+        "orc_hinge_theta": (c_double, [D]),
+        "orc_hinge_theta_grad": (None, [D, D]),
+        "orc_system": (c_int, [P, D, D, D, D, D]),
+        "orc_solve_step": (c_int, [P, D, D, D, D, I]),
+        "orc_step": (c_int, [P, D, D, D, D, D, D, I]),
+        "orc_rollout": (c_int, [P, c_int, D, D, D, I, c_int, D, D, I]),
+        "orc_gradient": (c_int, [P, c_int, D, D, D, I, c_int, D, D, D, D, D, I, I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _d(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def hinge_theta(x4):
+    """Dihedral angle of one hinge (x0, x1 | x2, x3), bending model reading R8."""
+    x4 = _f64(x4, (4, 3))
+    return _load().orc_hinge_theta(_d(x4))
+
+
+def hinge_theta_grad(x4):
+    """Closed-form gradient of the dihedral angle, shape [4, 3]."""
+    x4 = _f64(x4, (4, 3))
+    g = np.zeros((4, 3))
+    _load().orc_hinge_theta_grad(_d(x4), _d(g))
+    return g
+
+
+class Oracle:
+    """One cloth sheet: topology, rest state, pins (Sec. 3.1 'Deformation Model').
+
+    Parameters mirror the GPU library's ``sim_create``: a triangle mesh with
+    fixed topology, rest positions [V, 3], pinned vertex ids, material
+    (k_s [N/m], k_b [N m], d [kg/m^2]), time step h [s], gravity and the CG
+    tolerance of the oracle's own solver.
+    """
+
+    def __init__(self, tris, rest, pins=(), ks=1e3, kb=1e-4, density=0.1, dt=0.01,
+                 gravity=(0.0, 0.0, -9.81), cg_tol=1e-12, cg_max_iter=100000):
+        lib = _load()
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+        self.rest = _f64(rest).reshape(-1, 3)
+        self.pins = np.ascontiguousarray(pins, dtype=np.int32).reshape(-1)
+        self.nv = self.rest.shape[0]
+        self.nt = self.tris.shape[0]
+        st = ctypes.c_int(0)
+        self._h = lib.orc_create(self.nv, self.nt, _i(self.tris), _d(self.rest),
+                                 _i(self.pins) if self.pins.size else None,
+                                 int(self.pins.size), ctypes.byref(st))
+        if not self._h:
+            raise OracleError(st.value, "create")
+        self.set_params(ks, kb, density, dt, gravity, cg_tol, cg_max_iter)
+        self.nh = lib.orc_num_hinges(self._h)
+        self.nnzb = lib.orc_num_blocks(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    def set_params(self, ks=None, kb=None, density=None, dt=None, gravity=None, cg_tol=None,
+                   cg_max_iter=None):
+        self.ks = self.__dict__.get("ks", 0.0) if ks is None else float(ks)
+        self.kb = self.__dict__.get("kb", 0.0) if kb is None else float(kb)
+        self.density = self.__dict__.get("density", 0.0) if density is None else float(density)
+        self.dt = self.__dict__.get("dt", 0.01) if dt is None else float(dt)
+        if gravity is not None:
+            self.gravity = tuple(float(g) for g in gravity)
+        if cg_tol is not None:
+            self.cg_tol = float(cg_tol)
+        if cg_max_iter is not None:
+            self.cg_max_iter = int(cg_max_iter)
+        st = _load().orc_set_params(self._h, self.ks, self.kb, self.density, self.dt,
+                                    *self.gravity, self.cg_tol, self.cg_max_iter)
+        if st != ORC_OK:
+            raise OracleError(st, "set_params")
+
+    MEMBRANE_GAUSS_NEWTON = 0
+    MEMBRANE_EXACT = 1
+    MEMBRANE_TENSION = 2
+
+    def set_membrane_system(self, mode: int):
+        """Stress term of the system matrix's membrane block (reading R9):
+        MEMBRANE_TENSION (default; tension part of the strain), MEMBRANE_EXACT
+        (true Hessian; indefinite under compression) or MEMBRANE_GAUSS_NEWTON."""
+        st = _load().orc_set_membrane_system(self._h, int(mode))
+        if st != ORC_OK:
+            raise OracleError(st, "set_membrane_system")
+
+    # ---------------------------------------------------------------- geometry
+    def geometry(self):
+        """Rest precompute: B = D_m^-1 [T,2,2], triangle areas, lumped vertex areas
+        (reading R6), hinges [H,4], c_e and rest angles (reading R8)."""
+        B = np.zeros((self.nt, 4))
+        at = np.zeros(self.nt)
+        av = np.zeros(self.nv)
+        hv = np.zeros((self.nh, 4), dtype=np.int32)
+        ce = np.zeros(self.nh)
+        th0 = np.zeros(self.nh)
+        _load().orc_get_geometry(self._h, _d(B), _d(at), _d(av), _i(hv), _d(ce), _d(th0))
+        return dict(B=B.reshape(-1, 2, 2), tri_area=at, vert_area=av, hinges=hv, c_e=ce,
+                    theta_rest=th0)
+
+    # ----------------------------------------------------- element-level probes
+    def energy(self, x):
+        """Internal energy E_m + E_b at positions x (Sec. 3.1, readings R7, R8)."""
+        x = _f64(x, (self.nv, 3))
+        em = ctypes.c_double(0)
+        eb = ctypes.c_double(0)
+        e = _load().orc_energy(self._h, _d(x), ctypes.byref(em), ctypes.byref(eb))
+        return e, em.value, eb.value
+
+    def internal_force(self, x):
+        """f = -dE/dx (Sec. 3.1, Eq. 3 right-hand side, internal part)."""
+        x = _f64(x, (self.nv, 3))
+        f = np.zeros((self.nv, 3))
+        _load().orc_internal_force(self._h, _d(x), _d(f))
+        return f
+
+    def _apply(self, fn, x, u):
+        x = _f64(x, (self.nv, 3))
+        u = _f64(u, (self.nv, 3))
+        o = np.zeros((self.nv, 3))
+        fn(self._h, _d(x), _d(u), _d(o))
+        return o
+
+    def ksys_apply(self, x, u):
+        """K_sys u: tension-clamped membrane + Gauss-Newton bending (reading R9)."""
+        return self._apply(_load().orc_ksys_apply, x, u)
+
+    def kexact_apply(self, x, u):
+        """K_exact u: the true Hessian of E (= -df/dx) along u."""
+        return self._apply(_load().orc_kexact_apply, x, u)
+
+    def ksys_assembled_apply(self, x, u):
+        """K_sys u through the assembled block matrix the solver uses."""
+        return self._apply(_load().orc_ksys_assembled_apply, x, u)
+
+    def third(self, x, mu, w):
+        """grad_x [mu^T K_sys(x) w] (the state derivative of the system matrix)."""
+        x = _f64(x, (self.nv, 3))
+        mu = _f64(mu, (self.nv, 3))
+        w = _f64(w, (self.nv, 3))
+        o = np.zeros((self.nv, 3))
+        _load().orc_third(self._h, _d(x), _d(mu), _d(w), _d(o))
+        return o
+
+    # --------------------------------------------------------------- the step
+    def system(self, x, v, F=None):
+        """Dense A = M + h^2 K_sys (pins eliminated) and b of one step (Eq. 4-5)."""
+        n = 3 * self.nv
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        F = _f64(F, (self.nv, 3)) if F is not None else None
+        A = np.zeros((n, n))
+        b = np.zeros(n)
+        _load().orc_system(self._h, _d(x), _d(v), _d(F), _d(A), _d(b))
+        return A, b
+
+    def solve_step(self, x, v, F=None):
+        """Delta v of one step from the oracle's block-Jacobi PCG."""
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        F = _f64(F, (self.nv, 3)) if F is not None else None
+        dv = np.zeros((self.nv, 3))
+        it = ctypes.c_int(0)
+        st = _load().orc_solve_step(self._h, _d(x), _d(v), _d(F), _d(dv), ctypes.byref(it))
+        return dv, it.value, st
+
+    def step(self, x, v, F=None):
+        """One step S_t = PS(S_{t-1}; phi_{t-1}) (Eq. 1, 4, 5). Returns (x, v, dv, iters, status)."""
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        F = _f64(F, (self.nv, 3)) if F is not None else None
+        xo = np.zeros((self.nv, 3))
+        vo = np.zeros((self.nv, 3))
+        dvo = np.zeros((self.nv, 3))
+        it = ctypes.c_int(0)
+        st = _load().orc_step(self._h, _d(x), _d(v), _d(F), _d(xo), _d(vo), _d(dvo),
+                              ctypes.byref(it))
+        return xo, vo, dvo, it.value, st
+
+    def rollout(self, n_steps, x0, v0=None, forces=None, loss_frames=None, check=True):
+        """Positions at the loss frames [n_loss, V, 3], final velocity, CG iterations."""
+        x0 = _f64(x0, (self.nv, 3))
+        v0 = np.zeros((self.nv, 3)) if v0 is None else _f64(v0, (self.nv, 3))
+        forces = _f64(forces, (n_steps, self.nv, 3)) if forces is not None else None
+        frames = np.arange(1, n_steps + 1, dtype=np.int32) if loss_frames is None else \
+            np.ascontiguousarray(loss_frames, dtype=np.int32)
+        xo = np.zeros((frames.size, self.nv, 3))
+        vf = np.zeros((self.nv, 3))
+        iters = np.zeros(n_steps, dtype=np.int32)
+        st = _load().orc_rollout(self._h, int(n_steps), _d(x0), _d(v0), _d(forces), _i(frames),
+                                 int(frames.size), _d(xo), _d(vf), _i(iters))
+        if check and st not in (ORC_OK,):
+            raise OracleError(st, "rollout")
+        return xo, vf, iters, st
+
+    def gradient(self, n_steps, x0, v0, forces, loss_frames, dl_dx, check=True):
+        """Rollout + adjoint: dL/d(k_s, k_b, d), dL/dF [n_steps, V, 3], dL/dx0, dL/dv0."""
+        x0 = _f64(x0, (self.nv, 3))
+        v0 = np.zeros((self.nv, 3)) if v0 is None else _f64(v0, (self.nv, 3))
+        forces = _f64(forces, (n_steps, self.nv, 3)) if forces is not None else None
+        frames = np.ascontiguousarray(loss_frames, dtype=np.int32)
+        dl_dx = _f64(dl_dx, (frames.size, self.nv, 3))
+        gm = np.zeros(3)
+        gF = np.zeros((n_steps, self.nv, 3))
+        gx0 = np.zeros((self.nv, 3))
+        gv0 = np.zeros((self.nv, 3))
+        itf = np.zeros(n_steps, dtype=np.int32)
+        ita = np.zeros(n_steps, dtype=np.int32)
+        st = _load().orc_gradient(self._h, int(n_steps), _d(x0), _d(v0), _d(forces), _i(frames),
+                                  int(frames.size), _d(dl_dx), _d(gm), _d(gF), _d(gx0), _d(gv0),
+                                  _i(itf), _i(ita))
+        if check and st != ORC_OK:
+            raise OracleError(st, "gradient")
+        return dict(material=gm, forces=gF, x0=gx0, v0=gv0, iters_fwd=itf, iters_adj=ita,
+                    status=st)

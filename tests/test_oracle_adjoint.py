@@ -1,0 +1,133 @@
+"""Pins of the oracle's adjoint (the paper's backward pass: implicit differentiation of Eq. 4).
+
+Brute-force central differences of every input entry on a 3x3 sheet, random
+directions on a larger one, the closed-form gradient of the 'only F' model and
+the scale-homogeneity identity of the step.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2203_11938_amd import workloads as W
+
+
+def loss_and_grad(o, steps, x0, v0, F, frames, target):
+    xo, _, _, _ = o.rollout(steps, x0, v0, F, frames)
+    loss = np.sum((xo - target) ** 2)
+    g = o.gradient(steps, x0, v0, F, frames, 2.0 * (xo - target))
+    return loss, g
+
+
+def loss_only(o, steps, x0, v0, F, frames, target):
+    xo, _, _, _ = o.rollout(steps, x0, v0, F, frames)
+    return np.sum((xo - target) ** 2)
+
+
+def small_problem(oracle_mod, n=3, steps=5, seed=0, pins="top2"):
+    rest, tris = W.grid_sheet(n)
+    p = W.pin_set(n, pins)
+    ks, kb, d = 60.0, 2e-3, 0.2
+    o = oracle_mod.Oracle(tris, rest, p, ks, kb, d, dt=0.01, cg_tol=1e-14)
+    g = np.random.default_rng(seed)
+    V = n * n
+    x0 = rest + 0.02 * g.normal(size=rest.shape)
+    v0 = 0.2 * g.normal(size=rest.shape)
+    F = 0.02 * g.normal(size=(steps, V, 3))
+    frames = np.arange(1, steps + 1, dtype=np.int32)
+    target = x0[None] + 0.05 * g.normal(size=(steps, V, 3))
+    return o, (ks, kb, d), x0, v0, F, frames, target
+
+
+def test_adjoint_matches_bruteforce_fd_on_3x3(oracle_mod):
+    # every input entry: 3 material + 27 x0 + 27 v0 + 135 forces, rel <= 1e-6
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod)
+    steps = F.shape[0]
+    _, g = loss_and_grad(o, steps, x0, v0, F, frames, target)
+
+    def L_with(mat_=mat, x0_=x0, v0_=v0, F_=F):
+        o.set_params(*mat_)
+        return loss_only(o, steps, x0_, v0_, F_, frames, target)
+
+    fd_m = np.zeros(3)
+    for k in range(3):
+        hstep = 1e-6 * mat[k]
+        mp = list(mat); mp[k] += hstep
+        mm = list(mat); mm[k] -= hstep
+        fd_m[k] = (L_with(mat_=mp) - L_with(mat_=mm)) / (2 * hstep)
+    o.set_params(*mat)
+    assert np.allclose(g["material"], fd_m, rtol=1e-6, atol=0)
+
+    def fd_array(name, base):
+        out = np.zeros_like(base)
+        hstep = 1e-7
+        for idx in np.ndindex(base.shape):
+            p = base.copy(); p[idx] += hstep
+            m = base.copy(); m[idx] -= hstep
+            kw = {name: p}
+            lp = L_with(**kw)
+            kw = {name: m}
+            lm = L_with(**kw)
+            out[idx] = (lp - lm) / (2 * hstep)
+        return out
+
+    for name, base, key in [("x0_", x0, "x0"), ("v0_", v0, "v0"), ("F_", F, "forces")]:
+        fd = fd_array(name, base)
+        an = g[key]
+        assert np.linalg.norm(an - fd) <= 1e-6 * np.linalg.norm(fd), key
+    # pinned vertices: no velocity gradient, no force gradient
+    assert np.abs(g["v0"][o.pins]).max() == 0.0
+    assert np.abs(g["forces"][:, o.pins]).max() == 0.0
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_adjoint_random_directions_fd(oracle_mod, seed):
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=7, steps=12, seed=seed)
+    steps = F.shape[0]
+    frames = np.array([4, 8, 12], dtype=np.int32)
+    target = target[frames - 1]
+    _, g = loss_and_grad(o, steps, x0, v0, F, frames, target)
+    gen = np.random.default_rng(seed + 10)
+    hstep = 1e-7
+    for _ in range(3):
+        dx, dv, dF = (gen.normal(size=x0.shape), gen.normal(size=v0.shape),
+                      gen.normal(size=F.shape))
+        dm = gen.normal(size=3) * np.array(mat)
+        pred = (np.sum(g["x0"] * dx) + np.sum(g["v0"] * dv) + np.sum(g["forces"] * dF)
+                + np.sum(g["material"] * dm))
+
+        def at(t):
+            o.set_params(*(np.array(mat) + t * dm))
+            return loss_only(o, steps, x0 + t * dx, v0 + t * dv, F + t * dF, frames, target)
+
+        fd = (at(hstep) - at(-hstep)) / (2 * hstep)
+        o.set_params(*mat)
+        assert np.isclose(pred, fd, rtol=1e-6)
+
+
+def test_only_forces_gradient_closed_form(oracle_mod):
+    # k_s = k_b = 0, g = 0: dx_s / dF_r = (h^2 / m)(s - r) I for r < s (0-based force index)
+    n, steps, h, d = 4, 8, 0.01, 0.2
+    rest, tris = W.grid_sheet(n)
+    pins = W.pin_set(n, "corner")
+    o = oracle_mod.Oracle(tris, rest, pins, 0.0, 0.0, d, dt=h, gravity=(0, 0, 0), cg_tol=1e-14)
+    m = d * o.geometry()["vert_area"]
+    s = 6
+    c = np.random.default_rng(4).normal(size=(1, n * n, 3))
+    g = o.gradient(steps, rest, None, np.zeros((steps, n * n, 3)), np.array([s], np.int32), c)
+    free = np.ones(n * n, bool); free[pins] = False
+    for r in range(steps):
+        ref = c[0] * (h * h / m[:, None]) * max(s - r, 0)
+        ref[~free] = 0.0
+        assert np.allclose(g["forces"][r], ref, rtol=1e-12, atol=1e-15)
+    assert np.allclose(g["material"][:2], 0.0, atol=1e-15)
+
+
+def test_homogeneity_identity(oracle_mod):
+    # (k_s, k_b, d, F) -> c (k_s, k_b, d, F) scales A and b alike, so the trajectory is
+    # unchanged: k_s dL/dk_s + k_b dL/dk_b + d dL/dd + <F, dL/dF> = 0
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=6, steps=10, seed=5)
+    _, g = loss_and_grad(o, F.shape[0], x0, v0, F, frames, target)
+    terms = np.array([mat[0] * g["material"][0], mat[1] * g["material"][1],
+                      mat[2] * g["material"][2], np.sum(F * g["forces"])])
+    assert abs(terms.sum()) <= 1e-9 * np.abs(terms).max()
+    assert np.abs(terms).max() > 1e-6

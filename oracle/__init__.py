@@ -169,8 +169,9 @@ class Oracle:
 
     def set_membrane_system(self, mode: int):
         """Stress term of the system matrix's membrane block (reading R9):
-        MEMBRANE_TENSION (default; tension part of the strain), MEMBRANE_EXACT
-        (true Hessian; indefinite under compression) or MEMBRANE_GAUSS_NEWTON."""
+        MEMBRANE_EXACT (default; true Hessian, can be indefinite under
+        compression), MEMBRANE_TENSION (tension part of the strain only) or
+        MEMBRANE_GAUSS_NEWTON."""
         st = _load().orc_set_membrane_system(self._h, int(mode))
         if st != ORC_OK:
             raise OracleError(st, "set_membrane_system")
@@ -213,7 +214,7 @@ class Oracle:
         return o
 
     def ksys_apply(self, x, u):
-        """K_sys u: tension-clamped membrane + Gauss-Newton bending (reading R9)."""
+        """K_sys u: configured membrane block + Gauss-Newton bending (reading R9)."""
         return self._apply(_load().orc_ksys_apply, x, u)
 
     def kexact_apply(self, x, u):

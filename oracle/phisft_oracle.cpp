@@ -20,17 +20,18 @@
 //   R8  bending: hinge energy E_b = k_b * c_e * (theta - theta_rest)^2 with
 //       c_e = 3 |e_rest|^2 / (area_1 + area_2).
 //   R9  the Jacobians are evaluated at the state of time t-1. The system
-//       matrix uses K_sys = membrane Hessian whose stress term keeps only the
-//       tension part G+ of the strain (compressive principal strains clamped
-//       to zero) + Gauss-Newton bending Hessian 2 k_b c_e grad(theta)
-//       grad(theta)^T; both are positive semi-definite, so A = M + h^2 K_sys
-//       is SPD. In pure tension K_sys's membrane block is the exact Hessian.
-//       (The exact Hessian makes A indefinite under compression and the
-//       Gauss-Newton block lets tensioned sheets gain energy; both variants
-//       stay selectable through orc_set_membrane_system for the tests that
-//       show it.) The adjoint uses the true Hessian K_exact wherever the force
-//       itself is differentiated, and the derivative of K_sys (taken where
-//       it exists: off zero principal strains) in the state-derivative term.
+//       matrix uses K_sys = exact membrane Hessian + Gauss-Newton bending
+//       Hessian 2 k_b c_e grad(theta) grad(theta)^T. Under compression the
+//       exact membrane block can make A = M + h^2 K_sys indefinite; the solver
+//       then reports a breakdown. A recorded variant keeps only the tension
+//       part G+ of the strain in the membrane's stress term (compressive
+//       principal strains clamped to zero), which makes A SPD in every state
+//       but is not differentiable where a principal strain is zero; a
+//       Gauss-Newton variant (no stress term) exists for the test showing that
+//       it lets tensioned sheets gain energy. All three are selected through
+//       orc_set_membrane_system. The adjoint uses the true Hessian K_exact
+//       wherever the force itself is differentiated and the derivative of
+//       K_sys in the state-derivative term.
 //   R11 pinned vertices keep v = 0 and x = x_0 (Dirichlet rows/columns).
 //
 // Independence: nothing here is shared with the GPU library. Element stiffness
@@ -288,9 +289,9 @@ struct Problem {
   double grav[3] = {0, 0, -9.81};
   double cg_tol = 1e-12;
   int cg_max_iter = 100000;
-  // Stress term of the system matrix's membrane block: GEO_TENSION (default),
-  // GEO_EXACT (true Hessian, indefinite under compression) or GEO_NONE.
-  int mem_geo = GEO_TENSION;
+  // Stress term of the system matrix's membrane block: GEO_EXACT (default, the
+  // true Hessian), GEO_TENSION (tension part only) or GEO_NONE (Gauss-Newton).
+  int mem_geo = GEO_EXACT;
   std::vector<int> rowptr, col;  // CSR pattern of the vertex blocks
   int last_status = ORC_OK;
 };
@@ -801,8 +802,8 @@ int orc_set_params(void* h, double ks, double kb, double dens, double dt, double
   return ORC_OK;
 }
 
-// Stress term of the system matrix's membrane block: 2 = tension part (default),
-// 1 = exact Hessian, 0 = none (Gauss-Newton).
+// Stress term of the system matrix's membrane block: 1 = exact Hessian (default),
+// 2 = tension part, 0 = none (Gauss-Newton).
 int orc_set_membrane_system(void* h, int geo) {
   if (geo < GEO_NONE || geo > GEO_TENSION) return ORC_E_INVALID;
   static_cast<Problem*>(h)->mem_geo = geo;

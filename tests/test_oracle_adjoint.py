@@ -23,14 +23,15 @@ def loss_only(o, steps, x0, v0, F, frames, target):
     return np.sum((xo - target) ** 2)
 
 
-def small_problem(oracle_mod, n=3, steps=5, seed=0, pins="top2"):
+def small_problem(oracle_mod, n=3, steps=5, seed=0, pins="top2", amp=0.02, membrane=1):
     rest, tris = W.grid_sheet(n)
     p = W.pin_set(n, pins)
     ks, kb, d = 60.0, 2e-3, 0.2
     o = oracle_mod.Oracle(tris, rest, p, ks, kb, d, dt=0.01, cg_tol=1e-14)
+    o.set_membrane_system(membrane)
     g = np.random.default_rng(seed)
     V = n * n
-    x0 = rest + 0.02 * g.normal(size=rest.shape)
+    x0 = rest + amp * g.normal(size=rest.shape)
     v0 = 0.2 * g.normal(size=rest.shape)
     F = 0.02 * g.normal(size=(steps, V, 3))
     frames = np.arange(1, steps + 1, dtype=np.int32)
@@ -38,9 +39,12 @@ def small_problem(oracle_mod, n=3, steps=5, seed=0, pins="top2"):
     return o, (ks, kb, d), x0, v0, F, frames, target
 
 
-def test_adjoint_matches_bruteforce_fd_on_3x3(oracle_mod):
-    # every input entry: 3 material + 27 x0 + 27 v0 + 135 forces, rel <= 1e-6
-    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod)
+@pytest.mark.parametrize("membrane", [1, 2])
+def test_adjoint_matches_bruteforce_fd_on_3x3(oracle_mod, membrane):
+    # every input entry: 3 material + 27 x0 + 27 v0 + 135 forces, rel <= 1e-6, for the
+    # exact (1) and the tension-clamped (2) system membrane block; the crumpled start keeps
+    # principal strains away from the clamp's kink
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, membrane=membrane)
     steps = F.shape[0]
     _, g = loss_and_grad(o, steps, x0, v0, F, frames, target)
 
@@ -79,9 +83,13 @@ def test_adjoint_matches_bruteforce_fd_on_3x3(oracle_mod):
     assert np.abs(g["forces"][:, o.pins]).max() == 0.0
 
 
-@pytest.mark.parametrize("seed", [1, 2])
-def test_adjoint_random_directions_fd(oracle_mod, seed):
-    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=7, steps=12, seed=seed)
+@pytest.mark.parametrize("seed,membrane,amp", [(1, 1, 0.003), (2, 1, 0.003), (1, 2, 0.02),
+                                               (2, 2, 0.02)])
+def test_adjoint_random_directions_fd(oracle_mod, seed, membrane, amp):
+    # exact block from a mildly perturbed start (a strongly crumpled 7x7 sheet makes the
+    # exact system indefinite), tension-clamped block from a crumpled one
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=7, steps=12, seed=seed,
+                                                      amp=amp, membrane=membrane)
     steps = F.shape[0]
     frames = np.array([4, 8, 12], dtype=np.int32)
     target = target[frames - 1]
@@ -125,7 +133,8 @@ def test_only_forces_gradient_closed_form(oracle_mod):
 def test_homogeneity_identity(oracle_mod):
     # (k_s, k_b, d, F) -> c (k_s, k_b, d, F) scales A and b alike, so the trajectory is
     # unchanged: k_s dL/dk_s + k_b dL/dk_b + d dL/dd + <F, dL/dF> = 0
-    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=6, steps=10, seed=5)
+    o, mat, x0, v0, F, frames, target = small_problem(oracle_mod, n=6, steps=10, seed=5,
+                                                      amp=0.003)
     _, g = loss_and_grad(o, F.shape[0], x0, v0, F, frames, target)
     terms = np.array([mat[0] * g["material"][0], mat[1] * g["material"][1],
                       mat[2] * g["material"][2], np.sum(F * g["forces"])])

@@ -182,10 +182,11 @@ def test_ksys_assembled_equals_element_route(oracle_mod):
 
 
 @pytest.mark.parametrize("seed", [15, 16, 17])
-def test_ksys_positive_semidefinite(oracle_mod, seed):
+def test_tension_ksys_positive_semidefinite(oracle_mod, seed):
     # compressed, crumpled states (the exact Hessian's indefiniteness under compression is
     # pinned in closed form by test_tension_clamp_closed_form)
     o, rest = sheet(oracle_mod, 6, kb=1e-4)
+    o.set_membrane_system(o.MEMBRANE_TENSION)
     x = 0.97 * random_state(rest, 0.01, seed)
     g = np.random.default_rng(seed)
     for _ in range(20):
@@ -202,6 +203,8 @@ def test_tension_clamp_closed_form(oracle_mod, s):
     x = s * rest
     u = np.zeros_like(rest); u[:, 2] = rest[:, 0]
     ue = np.sum(u * o.kexact_apply(x, u))
+    assert np.isclose(np.sum(u * o.ksys_apply(x, u)), ue, rtol=1e-12)  # default: exact block
+    o.set_membrane_system(o.MEMBRANE_TENSION)
     us = np.sum(u * o.ksys_apply(x, u))
     assert np.isclose(ue, ks * L * L * (s * s - 1) / 2, rtol=1e-10)
     if s > 1:
@@ -210,18 +213,21 @@ def test_tension_clamp_closed_form(oracle_mod, s):
         assert abs(us) < 1e-10 * abs(ue)
 
 
-def test_ksys_is_exact_hessian_in_pure_tension(oracle_mod):
+def test_tension_ksys_is_exact_hessian_in_pure_tension(oracle_mod):
     o, rest = sheet(oracle_mod, 6, ks=1e3, kb=0.0)
+    o.set_membrane_system(o.MEMBRANE_TENSION)
     x = 1.03 * rest + 1e-4 * np.random.default_rng(18).normal(size=rest.shape)
     u = np.random.default_rng(19).normal(size=rest.shape)
     a, b = o.ksys_apply(x, u), o.kexact_apply(x, u)
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("seed,scale", [(20, 1.0), (21, 0.985), (22, 1.02)])
-def test_third_contraction_matches_fd(oracle_mod, seed, scale):
+def test_third_contraction_matches_fd(oracle_mod, seed, scale, mode):
     # grad_x [mu^T K_sys(x) w] against central differences of the element route
     o, rest = sheet(oracle_mod, 5, kb=5e-3)
+    o.set_membrane_system(mode)
     x = scale * random_state(rest, 0.01, seed)
     g = np.random.default_rng(seed + 7)
     mu, w = g.normal(size=x.shape), g.normal(size=x.shape)

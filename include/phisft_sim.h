@@ -14,9 +14,9 @@
  *         v_t = v_{t-1} + Delta v,   x_t = x_{t-1} + h v_t
  *     with M the lumped mass (density times a third of the incident triangle
  *     areas), f = -dE/dx for E = sum_tri area (k_s/2) |G|_F^2 (Green strain G)
- *     + sum_hinge k_b c_e (theta - theta_rest)^2, and K_sys the positive
- *     semi-definite system stiffness (membrane Hessian with its compressive
- *     stress term removed, Gauss-Newton bending Hessian);
+ *     + sum_hinge k_b c_e (theta - theta_rest)^2, and K_sys the system
+ *     stiffness (membrane Hessian, see sim_membrane_system, plus the
+ *     Gauss-Newton bending Hessian 2 k_b c_e grad(theta) grad(theta)^T);
  *   * the adjoint of that rollout (the paper's backward pass by implicit
  *     differentiation of Eq. 4): gradients of a per-frame loss with respect to
  *     (k_s, k_b, d), the forces F_t and the initial state (x_0, v_0).
@@ -75,6 +75,19 @@ typedef enum {
 
 typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
 
+/* Stress term of the membrane block of the system stiffness K_sys (the
+ * Jacobian of Eq. 5, evaluated at the previous state):
+ *   SIM_MEMBRANE_EXACT    the true Hessian of the stretching energy (default).
+ *                         A = M + h^2 K_sys can become indefinite under
+ *                         compression; CG then reports SIM_E_INDEFINITE.
+ *   SIM_MEMBRANE_TENSION  only the tension part of the strain enters the stress
+ *                         term (compressive principal strains clamped to zero):
+ *                         A is SPD in every state, but the clamp is not
+ *                         differentiable where a principal strain is zero (for
+ *                         instance at the rest state), so gradients taken there
+ *                         depend on rounding. */
+typedef enum { SIM_MEMBRANE_EXACT = 0, SIM_MEMBRANE_TENSION = 1 } sim_membrane_system;
+
 /* Host triangle mesh: tris [n_tris][3] vertex ids, counter-clockwise. */
 typedef struct {
   int32_t n_verts;
@@ -98,6 +111,7 @@ typedef struct {
   double gravity[3];        /* m/s^2                                                    */
   int32_t max_steps;        /* capacity: longest rollout this handle will run           */
   int32_t rows_per_block;   /* solver rows per workgroup (64..256); 0 = tuned choice     */
+  int32_t membrane_system;  /* sim_membrane_system                                      */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -116,7 +130,8 @@ typedef struct {
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32, cg_tol 1e-7, cg_max_iter 20000, store
- * every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block. */
+ * every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
+ * exact membrane Hessian. */
 void sim_default_options(sim_options* opt);
 
 /* Creates a handle for one sheet.
@@ -181,6 +196,10 @@ sim_status sim_get_stats(const sim_t* sim, sim_stats* out);
 /* Per-step CG iteration counts [n_steps][n_instances] of the most recent
  * rollout (forward) and adjoint; either pointer may be NULL. Host memory. */
 sim_status sim_get_cg_iters(const sim_t* sim, int32_t* forward, int32_t* adjoint);
+
+/* Sticky device status of each instance (sim_status values) as of the last
+ * sim_sync_status; out has n_instances entries. Host memory. */
+sim_status sim_get_instance_status(const sim_t* sim, int32_t* out);
 
 const char* sim_status_string(sim_status s);
 const char* sim_last_error(const sim_t* sim);

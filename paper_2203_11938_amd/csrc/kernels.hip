@@ -1,0 +1,1090 @@
+// kernels.hip -- gfx950 kernels of the differentiable cloth step (phi-SfT, Sec. 3.1).
+//
+// Forward step (Eq. 4 with Eq. 5, df/dv = 0), per step:
+//   k_elements      per triangle: deformation gradient F, Green strain G, force and
+//                   the nine 3x3 blocks of the system stiffness; per hinge: dihedral
+//                   angle, its gradient, force and Gauss-Newton weight.
+//   k_assemble      per vertex row, atomic-free: gathers the row's blocks in a fixed
+//                   order into A = M + h^2 K_sys (ELL layout, pins eliminated), the
+//                   right-hand side b = h (f + M g + F_t - h K_sys v) and the inverse
+//                   of the diagonal block (block-Jacobi preconditioner).
+//   k_pcg           persistent preconditioned CG: every workgroup owns a row range,
+//                   keeps its matrix rows in LDS and its vectors in FP64 registers;
+//                   the workgroups of one sheet meet at a counter barrier twice per
+//                   iteration (reductions are fixed-order, so results are bitwise
+//                   reproducible).
+//   k_update        v_t = v_{t-1} + dv, x_t = x_{t-1} + h v_t, pins held.
+// Adjoint step (implicit differentiation of Eq. 4): k_adj_pre, the same assembly and
+// solver (A is symmetric), k_adj_elements (element vector-Jacobian products) and
+// k_adj_rows; k_material_sum reduces the material gradient.
+//
+// Element arithmetic is FP64 regardless of the storage precision T.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+#include "sim_internal.h"
+
+namespace phisft {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+  // xor butterfly: every lane ends with the same, order-fixed sum
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// status[0]: handle-wide word, status[1 + inst]: the instance's word
+__device__ __forceinline__ void set_status(int* status, int inst, int bits) {
+  __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_or(status + 1 + inst, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool finite3(const double* a) {
+  return isfinite(a[0]) && isfinite(a[1]) && isfinite(a[2]);
+}
+
+// forward-mode dual number (value, directional derivative)
+struct dual {
+  double v, d;
+  __device__ dual() : v(0.0), d(0.0) {}
+  __device__ dual(double a) : v(a), d(0.0) {}
+  __device__ dual(double a, double b) : v(a), d(b) {}
+};
+__device__ __forceinline__ dual operator+(dual a, dual b) { return dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ dual operator-(dual a, dual b) { return dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ dual operator-(dual a) { return dual(-a.v, -a.d); }
+__device__ __forceinline__ dual operator*(dual a, dual b) {
+  return dual(a.v * b.v, a.d * b.v + a.v * b.d);
+}
+__device__ __forceinline__ dual operator/(dual a, dual b) {
+  double q = a.v / b.v;
+  return dual(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ dual dsqrt(dual a) {
+  double s = sqrt(a.v);
+  return dual(s, 0.5 * a.d / s);
+}
+__device__ __forceinline__ double dsqrt(double a) { return sqrt(a); }
+
+// ------------------------------------------------------------ element math
+// Triangle (a, b, c) with per-vertex weights w_i (F = sum_i x_i w_i^T):
+// w_b = first row of B, w_c = second row, w_a = -(w_b + w_c).
+struct Tri {
+  double F[3][2];
+  double G[2][2];
+  double w[3][2];
+  double area;
+};
+
+template <typename T>
+__device__ __forceinline__ void tri_load(const Mesh& m, const T* __restrict__ x, int t, Tri& s,
+                                         int v[3]) {
+  const int nt = m.nt, nv = m.nv;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) v[a] = m.tri_v[a * nt + t];
+  double B00 = m.tri_B[t], B01 = m.tri_B[nt + t], B10 = m.tri_B[2 * nt + t],
+         B11 = m.tri_B[3 * nt + t];
+  s.w[1][0] = B00;
+  s.w[1][1] = B01;
+  s.w[2][0] = B10;
+  s.w[2][1] = B11;
+  s.w[0][0] = -(B00 + B10);
+  s.w[0][1] = -(B01 + B11);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double xa = (double)x[r * nv + v[0]];
+    double d1 = (double)x[r * nv + v[1]] - xa;
+    double d2 = (double)x[r * nv + v[2]] - xa;
+    s.F[r][0] = d1 * B00 + d2 * B10;
+    s.F[r][1] = d1 * B01 + d2 * B11;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      s.G[a][b] = 0.5 * (s.F[0][a] * s.F[0][b] + s.F[1][a] * s.F[1][b] + s.F[2][a] * s.F[2][b] -
+                         (a == b ? 1.0 : 0.0));
+  s.area = m.tri_area[t];
+}
+
+// Spectral split of the symmetric strain: eigenvalues l1 >= l2 and the rotation
+// (cs, sn) whose first column is the eigenvector of l1.
+struct Eig2 {
+  double l1, l2, cs, sn;
+};
+__device__ __forceinline__ Eig2 eig2(const double G[2][2]) {
+  double m = 0.5 * (G[0][0] + G[1][1]);
+  double hd = 0.5 * (G[0][0] - G[1][1]);
+  double b = 0.5 * (G[0][1] + G[1][0]);
+  double r = hypot(hd, b);
+  double phi = 0.5 * atan2(b, hd);
+  Eig2 e;
+  e.l1 = m + r;
+  e.l2 = m - r;
+  e.cs = cos(phi);
+  e.sn = sin(phi);
+  return e;
+}
+
+// X' = R^T X R and X = R X' R^T for the eigenbasis rotation.
+__device__ __forceinline__ void to_eig(const Eig2& e, const double X[2][2], double Y[2][2]) {
+  double c = e.cs, s = e.sn;
+  double a = X[0][0], b = 0.5 * (X[0][1] + X[1][0]), d = X[1][1];
+  Y[0][0] = c * c * a + 2.0 * c * s * b + s * s * d;
+  Y[1][1] = s * s * a - 2.0 * c * s * b + c * c * d;
+  Y[0][1] = Y[1][0] = -c * s * a + (c * c - s * s) * b + c * s * d;
+}
+__device__ __forceinline__ void from_eig(const Eig2& e, const double Y[2][2], double X[2][2]) {
+  double c = e.cs, s = e.sn;
+  double a = Y[0][0], b = Y[0][1], d = Y[1][1];
+  X[0][0] = c * c * a - 2.0 * c * s * b + s * s * d;
+  X[1][1] = s * s * a + 2.0 * c * s * b + c * c * d;
+  X[0][1] = X[1][0] = c * s * a + (c * c - s * s) * b - c * s * d;
+}
+
+// Tension part G+ (compressive principal strains clamped to zero).
+__device__ __forceinline__ void tension(const Eig2& e, double Gp[2][2]) {
+  double Y[2][2] = {{e.l1 > 0.0 ? e.l1 : 0.0, 0.0}, {0.0, e.l2 > 0.0 ? e.l2 : 0.0}};
+  from_eig(e, Y, Gp);
+}
+
+// Directional derivative of G -> G+ along the symmetric S (Daleckii-Krein):
+// in the eigenbasis, entry (k,l) is scaled by the divided difference of max(., 0).
+__device__ __forceinline__ void tension_deriv(const Eig2& e, const double S[2][2],
+                                              double Y[2][2]) {
+  double Sp[2][2], Yp[2][2];
+  to_eig(e, S, Sp);
+  double d1 = e.l1 > 0.0 ? 1.0 : 0.0, d2 = e.l2 > 0.0 ? 1.0 : 0.0;
+  double gap = e.l1 - e.l2;
+  double f12 = gap > 0.0 ? ((e.l1 > 0.0 ? e.l1 : 0.0) - (e.l2 > 0.0 ? e.l2 : 0.0)) / gap : d1;
+  Yp[0][0] = d1 * Sp[0][0];
+  Yp[1][1] = d2 * Sp[1][1];
+  Yp[0][1] = Yp[1][0] = f12 * Sp[0][1];
+  from_eig(e, Yp, Y);
+}
+
+// Dihedral angle gradient of hinge (x0, x1 | x2, x3) (Bridson et al. 2003):
+// wings -|e| n_k / |n_k|^2, edge vertices by the lever rule along the edge.
+template <typename S>
+__device__ __forceinline__ void hinge_grad(const S X[4][3], S g[4][3]) {
+  S e[3], a[3], d[3], me[3], n1[3], n2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    e[k] = X[1][k] - X[0][k];
+    a[k] = X[2][k] - X[0][k];
+    me[k] = X[0][k] - X[1][k];
+    d[k] = X[3][k] - X[1][k];
+  }
+  n1[0] = e[1] * a[2] - e[2] * a[1];
+  n1[1] = e[2] * a[0] - e[0] * a[2];
+  n1[2] = e[0] * a[1] - e[1] * a[0];
+  n2[0] = me[1] * d[2] - me[2] * d[1];
+  n2[1] = me[2] * d[0] - me[0] * d[2];
+  n2[2] = me[0] * d[1] - me[1] * d[0];
+  S ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  S le = dsqrt(ee);
+  S q1 = n1[0] * n1[0] + n1[1] * n1[1] + n1[2] * n1[2];
+  S q2 = n2[0] * n2[0] + n2[1] * n2[1] + n2[2] * n2[2];
+  S t1 = (a[0] * e[0] + a[1] * e[1] + a[2] * e[2]) / ee;
+  S t2 = ((X[3][0] - X[0][0]) * e[0] + (X[3][1] - X[0][1]) * e[1] + (X[3][2] - X[0][2]) * e[2]) / ee;
+  S s1 = le / q1, s2 = le / q2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    S w2 = -(s1 * n1[k]);
+    S w3 = -(s2 * n2[k]);
+    g[2][k] = w2;
+    g[3][k] = w3;
+    g[0][k] = -((S(1.0) - t1) * w2) - (S(1.0) - t2) * w3;
+    g[1][k] = -(t1 * w2) - t2 * w3;
+  }
+}
+
+__device__ __forceinline__ double hinge_theta(const double X[4][3]) {
+  double e[3], a[3], d[3], me[3], n1[3], n2[3], c[3];
+  for (int k = 0; k < 3; ++k) {
+    e[k] = X[1][k] - X[0][k];
+    a[k] = X[2][k] - X[0][k];
+    me[k] = X[0][k] - X[1][k];
+    d[k] = X[3][k] - X[1][k];
+  }
+  n1[0] = e[1] * a[2] - e[2] * a[1];
+  n1[1] = e[2] * a[0] - e[0] * a[2];
+  n1[2] = e[0] * a[1] - e[1] * a[0];
+  n2[0] = me[1] * d[2] - me[2] * d[1];
+  n2[1] = me[2] * d[0] - me[0] * d[2];
+  n2[2] = me[0] * d[1] - me[1] * d[0];
+  c[0] = n1[1] * n2[2] - n1[2] * n2[1];
+  c[1] = n1[2] * n2[0] - n1[0] * n2[2];
+  c[2] = n1[0] * n2[1] - n1[1] * n2[0];
+  double le = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  // atan2 is invariant to the common positive scale |n1| |n2|
+  double sn = (c[0] * e[0] + c[1] * e[1] + c[2] * e[2]) / le;
+  double cs = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+  return atan2(sn, cs);
+}
+
+template <typename T>
+__device__ __forceinline__ void hinge_load(const Mesh& m, const T* __restrict__ x, int e, int v[4],
+                                           double X[4][3]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    v[a] = m.hin_v[a * m.nh + e];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[a][k] = (double)x[k * m.nv + v[a]];
+  }
+}
+
+// ------------------------------------------------------ forward: elements
+// Threads [0, nt) take triangles, [nt, nt + nh) hinges.
+template <typename T>
+__global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const T* __restrict__ x,
+                                                  const double* __restrict__ mat, int* status) {
+  int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < m.nt) {
+    const int t = gid, nt = m.nt;
+    Tri s;
+    int v[3];
+    tri_load(m, x, t, s, v);
+    const int inst = m.tri_inst[t];
+    double ak = s.area * mat[3 * inst + 0];
+    // stress term of the system block: G itself (exact Hessian) or its tension part
+    double Gp[2][2];
+    if (m.tension) {
+      tension(eig2(s.G), Gp);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) Gp[p][q] = s.G[p][q];
+    }
+    double aw[3][3];  // a_i = F w_i
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) aw[i][r] = s.F[r][0] * s.w[i][0] + s.F[r][1] * s.w[i][1];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double gw0 = s.G[0][0] * s.w[i][0] + s.G[0][1] * s.w[i][1];
+      double gw1 = s.G[1][0] * s.w[i][0] + s.G[1][1] * s.w[i][1];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double f = -ak * (s.F[r][0] * gw0 + s.F[r][1] * gw1);
+        ok = ok && isfinite(f);
+        el.tri_f[(i * 3 + r) * nt + t] = f;
+      }
+    }
+    double FF[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) FF[r][c] = s.F[r][0] * s.F[c][0] + s.F[r][1] * s.F[c][1];
+    // K_ij = area k_s [ (w_i^T G' w_j) I + 1/2 (w_i . w_j) F F^T + 1/2 (F w_j)(F w_i)^T ]
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double gij = s.w[i][0] * (Gp[0][0] * s.w[j][0] + Gp[0][1] * s.w[j][1]) +
+                     s.w[i][1] * (Gp[1][0] * s.w[j][0] + Gp[1][1] * s.w[j][1]);
+        double cij = s.w[i][0] * s.w[j][0] + s.w[i][1] * s.w[j][1];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double k = ak * ((r == c ? gij : 0.0) + 0.5 * cij * FF[r][c] + 0.5 * aw[j][r] * aw[i][c]);
+            el.tri_K[((i * 3 + j) * 9 + r * 3 + c) * nt + t] = k;
+          }
+      }
+    if (!ok) set_status(status, inst, ST_NONFINITE);
+  } else if (gid < m.nt + m.nh) {
+    const int e = gid - m.nt, nh = m.nh;
+    int v[4];
+    double X[4][3], g[4][3];
+    hinge_load(m, x, e, v, X);
+    double th = hinge_theta(X);
+    hinge_grad<double>(X, g);
+    double w = 2.0 * mat[3 * m.hin_inst[e] + 1] * m.hin_ce[e];
+    double s = w * (th - m.hin_rest[e]);
+    bool ok = isfinite(s);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        el.hin_g[(a * 3 + k) * nh + e] = g[a][k];
+        el.hin_f[(a * 3 + k) * nh + e] = -s * g[a][k];
+        ok = ok && isfinite(g[a][k]);
+      }
+    el.hin_w[e] = w;
+    if (!ok) set_status(status, m.hin_inst[e], ST_NONFINITE);
+  }
+}
+
+// ----------------------------------------------------- forward: assembly
+// Sum of the stiffness contributions of slot s (fixed order).
+__device__ __forceinline__ void slot_block(const Mesh& m, const Elem& el, int s, double K[9]) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) K[q] = 0.0;
+  const int nt = m.nt, nh = m.nh;
+  for (int c = m.slot_ptr[s]; c < m.slot_ptr[s + 1]; ++c) {
+    int ref = m.slot_ref[c];
+    if (ref >= 0) {
+      int t = ref / 9, ab = ref - 9 * (ref / 9);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) K[q] += el.tri_K[(ab * 9 + q) * nt + t];
+    } else {
+      int r2 = -ref - 1;
+      int e = r2 >> 4, a = (r2 >> 2) & 3, b = r2 & 3;
+      double w = el.hin_w[e];
+      double ga[3], gb[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ga[k] = el.hin_g[(a * 3 + k) * nh + e];
+        gb[k] = el.hin_g[(b * 3 + k) * nh + e];
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) K[r * 3 + q] += w * ga[r] * gb[q];
+    }
+  }
+}
+
+__device__ __forceinline__ bool inv3(const double a[9], double o[9]) {
+  double c00 = a[4] * a[8] - a[5] * a[7];
+  double c01 = a[5] * a[6] - a[3] * a[8];
+  double c02 = a[3] * a[7] - a[4] * a[6];
+  double det = a[0] * c00 + a[1] * c01 + a[2] * c02;
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  double id = 1.0 / det;
+  o[0] = c00 * id;
+  o[1] = (a[2] * a[7] - a[1] * a[8]) * id;
+  o[2] = (a[1] * a[5] - a[2] * a[4]) * id;
+  o[3] = c01 * id;
+  o[4] = (a[0] * a[8] - a[2] * a[6]) * id;
+  o[5] = (a[2] * a[3] - a[0] * a[5]) * id;
+  o[6] = c02 * id;
+  o[7] = (a[1] * a[6] - a[0] * a[7]) * id;
+  o[8] = (a[0] * a[4] - a[1] * a[3]) * id;
+  return true;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nv = m.nv;
+  if (i >= nv) return;
+  const int inst = m.vert_inst[i];
+  const double mass = a.mat[3 * inst + 2] * m.varea[i];
+  const bool pin_i = m.pinned[i] != 0;
+  const double h = a.h, h2 = a.h * a.h;
+  double kv[3] = {0.0, 0.0, 0.0}, diag[9];
+  for (int k = 0; k < m.maxnz; ++k) {
+    const int s = k * nv + i;
+    const int j = m.ell_col[s];
+    double Ab[9];
+    if (j < 0) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Ab[q] = 0.0;
+    } else {
+      double K[9];
+      slot_block(m, el, s, K);
+      const bool pin_j = m.pinned[j] != 0;
+      if (a.want_rhs && !pin_j) {
+        double vj[3] = {(double)a.v[j], (double)a.v[nv + j], (double)a.v[2 * nv + j]};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) kv[r] += K[r * 3] * vj[0] + K[r * 3 + 1] * vj[1] + K[r * 3 + 2] * vj[2];
+      }
+      if (pin_i || pin_j) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ab[q] = (i == j && (q % 4) == 0) ? 1.0 : 0.0;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ab[q] = h2 * K[q];
+        if (i == j) {
+          Ab[0] += mass;
+          Ab[4] += mass;
+          Ab[8] += mass;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a.A[(size_t)(k * 9 + q) * nv + i] = (T)Ab[q];
+    if (j == i) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) diag[q] = Ab[q];
+    }
+  }
+  // block-Jacobi inverse of the stored (rounded) diagonal block
+  double dr[9], Ji[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) dr[q] = (double)(T)diag[q];
+  if (!inv3(dr, Ji)) {
+    set_status(a.status, inst, ST_INDEFINITE);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Ji[q] = (q % 4) == 0 ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) a.Jinv[q * nv + i] = (T)Ji[q];
+  if (!a.want_rhs) return;
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
+    int ref = m.vinc_ref[c];
+    if (ref >= 0) {
+      int t = ref / 3, va = ref - 3 * (ref / 3);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) f[r] += el.tri_f[(va * 3 + r) * m.nt + t];
+    } else {
+      int r2 = -ref - 1;
+      int e = r2 >> 2, va = r2 & 3;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) f[r] += el.hin_f[(va * 3 + r) * m.nh + e];
+    }
+  }
+  double b[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double fe = a.forces ? (double)a.forces[r * nv + i] : 0.0;
+    b[r] = pin_i ? 0.0 : h * (f[r] + mass * a.g[r] + fe - h * kv[r]);
+    a.b[r * nv + i] = b[r];
+  }
+  if (!finite3(b)) set_status(a.status, inst, ST_NONFINITE);
+}
+
+// ------------------------------------------------------- persistent PCG
+// Cluster barrier of the workgroups of one sheet: monotone arrival counter,
+// bounded wait (every wave reaches the exit even if a peer never arrives).
+constexpr int kSpinLimit = 1 << 25;
+
+__device__ __forceinline__ bool cluster_barrier(int* ctr, int nwg, int& epoch, int* abort_flag,
+                                                int* status, int inst) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    epoch += 1;
+    const int target = epoch * nwg;
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1, spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit ||
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        set_status(status, inst, ST_TIMEOUT);
+        break;
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Fixed-order sum of two values over the cluster's workgroups via the partial
+// array red[slot][wg][2]; every workgroup obtains the identical result.
+__device__ __forceinline__ bool cluster_sum2(double a0, double a1, double* red, int slot, int nwg_all,
+                                             int wg, int iw0, int nwg, int* ctr, int& epoch,
+                                             int* abort_flag, int* status, int inst,
+                                             double out[2]) {
+  __shared__ double s_part[2][4];
+  __shared__ double s_out[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if (lane == 0) {
+    s_part[0][wave] = a0;
+    s_part[1][wave] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = 0; q < nwaves; ++q) {
+      t0 += s_part[0][q];
+      t1 += s_part[1][q];
+    }
+    double* dst = red + ((size_t)slot * nwg_all + wg) * 2;
+    dst[0] = t0;
+    dst[1] = t1;
+  }
+  bool ok = cluster_barrier(ctr, nwg, epoch, abort_flag, status, inst);
+  if (wave == 0) {
+    double t0 = 0.0, t1 = 0.0;
+    for (int q = lane; q < nwg; q += 64) {
+      const double* src = red + ((size_t)slot * nwg_all + iw0 + q) * 2;
+      t0 += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      t1 += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    if (lane == 0) {
+      s_out[0] = t0;
+      s_out[1] = t1;
+    }
+  }
+  __syncthreads();
+  out[0] = s_out[0];
+  out[1] = s_out[1];
+  return ok;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int wg = blockIdx.x;
+  const int inst = plan.wg_inst[wg];
+  const int row0 = plan.wg_row0[wg];
+  const int nrows = plan.wg_nrows[wg];
+  const int iw0 = plan.inst_wg0[inst], nwg = plan.inst_nwg[inst];
+  const int tid = threadIdx.x, R = blockDim.x;
+  const int nv = m.nv, maxnz = m.maxnz;
+  const bool act = tid < nrows;
+  const int i = row0 + (act ? tid : 0);
+  int* ctr = w.barrier + inst;
+  int epoch = 0;
+
+  // matrix rows of this workgroup -> LDS ([slot][entry][row], conflict-free)
+  T* Al = reinterpret_cast<T*>(lds_raw);
+  int* Cl = reinterpret_cast<int*>(Al + (size_t)maxnz * 9 * R);
+  for (int k = 0; k < maxnz; ++k) {
+    int j = act ? m.ell_col[k * nv + i] : -1;
+    Cl[k * R + tid] = j < 0 ? i : j;
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+      Al[(k * 9 + q) * R + tid] = j < 0 ? T(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+  }
+
+  double J[9], x[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0}, z[3] = {0.0, 0.0, 0.0};
+  double p[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 9; ++q) J[q] = act ? (double)a.Jinv[q * nv + i] : 0.0;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) z[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
+  double* zb = w.zbuf;
+  double* pb0 = w.pbuf;
+  double* pb1 = w.pbuf + 3 * (size_t)nv;
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      zb[c * nv + i] = z[c];
+      pb1[c * nv + i] = 0.0;
+    }
+  }
+  double sums[2];
+  bool ok = cluster_sum2(r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
+                         r[0] * z[0] + r[1] * z[1] + r[2] * z[2], w.red, 1, plan.nwg, wg, iw0, nwg,
+                         ctr, epoch, w.abort_flag, a.status, inst, sums);
+  const double bnorm = sqrt(sums[0]);
+  double rz = sums[1], rr = sums[0], beta = 0.0;
+  int it = 0;
+  int flag = 0;
+  if (!isfinite(bnorm) || !isfinite(rz)) flag = ST_NONFINITE;
+  bool done = !ok || flag != 0 || bnorm == 0.0;
+  while (!done) {
+    if (it >= a.max_iter) {
+      flag = ST_NOT_CONVERGED;
+      break;
+    }
+    double* pcur = (it & 1) ? pb1 : pb0;
+    const double* pprev = (it & 1) ? pb0 : pb1;
+    // p_it = z_it + beta p_{it-1}; neighbours' entries are formed the same way
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p[c] = z[c] + beta * p[c];
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pcur[c * nv + i] = p[c];
+    }
+    double q3[3] = {0.0, 0.0, 0.0};
+    if (act) {
+      for (int k = 0; k < maxnz; ++k) {
+        const int j = Cl[k * R + tid];
+        double pj[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pj[c] = zb[c * nv + j] + beta * pprev[c * nv + j];
+        const T* blk = Al + (size_t)k * 9 * R + tid;
+#pragma unroll
+        for (int rr3 = 0; rr3 < 3; ++rr3)
+          q3[rr3] += (double)blk[(rr3 * 3) * R] * pj[0] + (double)blk[(rr3 * 3 + 1) * R] * pj[1] +
+                     (double)blk[(rr3 * 3 + 2) * R] * pj[2];
+      }
+    }
+    ok = cluster_sum2(p[0] * q3[0] + p[1] * q3[1] + p[2] * q3[2], 0.0, w.red, 0, plan.nwg, wg, iw0,
+                      nwg, ctr, epoch, w.abort_flag, a.status, inst, sums);
+    const double pq = sums[0];
+    if (!ok) break;
+    if (!isfinite(pq)) {
+      flag = ST_NONFINITE;
+      break;
+    }
+    if (!(pq > 0.0)) {
+      flag = ST_INDEFINITE;
+      break;
+    }
+    const double alpha = rz / pq;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] += alpha * p[c];
+      r[c] -= alpha * q3[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) zb[c * nv + i] = z[c];
+    }
+    ok = cluster_sum2(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
+                      w.red, 1, plan.nwg, wg, iw0, nwg, ctr, epoch, w.abort_flag, a.status, inst,
+                      sums);
+    ++it;
+    rr = sums[1];
+    if (!ok) break;
+    if (!isfinite(sums[0]) || !isfinite(rr)) {
+      flag = ST_NONFINITE;
+      break;
+    }
+    if (sqrt(rr) <= a.tol * bnorm) break;
+    beta = sums[0] / rz;
+    rz = sums[0];
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.sol[c * nv + i] = x[c];
+  }
+  if (wg == iw0 && tid == 0) {
+    if (flag) set_status(a.status, inst, flag);
+    if (a.iters) a.iters[inst] = it;
+    if (a.resid) a.resid[inst] = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+  }
+}
+
+// ---------------------------------------------------------- forward: update
+template <typename T>
+__global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ pinned,
+                                                const int* __restrict__ vert_inst,
+                                                const T* __restrict__ xp, const T* __restrict__ vp,
+                                                const double* __restrict__ dv, double h,
+                                                T* __restrict__ xn, T* __restrict__ vn,
+                                                T* __restrict__ xout, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  const bool pin = pinned[i] != 0;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double v = pin ? 0.0 : (double)vp[c * nv + i] + dv[c * nv + i];
+    double xx = (double)xp[c * nv + i] + h * v;
+    ok = ok && isfinite(xx) && isfinite(v);
+    vn[c * nv + i] = (T)v;
+    xn[c * nv + i] = (T)xx;
+    if (xout) xout[c * nv + i] = (T)xx;
+  }
+  if (!ok) set_status(status, vert_inst[i], ST_NONFINITE);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_init_state(int nv, const int* __restrict__ pinned,
+                                                    const int* __restrict__ vert_inst,
+                                                    const T* __restrict__ x0,
+                                                    const T* __restrict__ v0, T* __restrict__ xs,
+                                                    T* __restrict__ vs, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T xx = x0[c * nv + i];
+    T v = (v0 && !pinned[i]) ? v0[c * nv + i] : T(0);
+    ok = ok && isfinite((double)xx) && isfinite((double)v);
+    xs[c * nv + i] = xx;
+    vs[c * nv + i] = v;
+  }
+  if (!ok) set_status(status, vert_inst[i], ST_NONFINITE);
+}
+
+// ---------------------------------------------------------------- adjoint
+// gx += dL/dx_s (if s is a loss frame); u = mask(gv + h gx)
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_pre(int nv, const int* __restrict__ pinned,
+                                                 const int* __restrict__ vert_inst,
+                                                 const T* __restrict__ dl, double h,
+                                                 double* __restrict__ gx,
+                                                 const double* __restrict__ gv,
+                                                 double* __restrict__ u, int* status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double g = gx[c * nv + i];
+    if (dl) {
+      double d = (double)dl[c * nv + i];
+      ok = ok && isfinite(d);
+      g += d;
+      gx[c * nv + i] = g;
+    }
+    u[c * nv + i] = pinned[i] ? 0.0 : gv[c * nv + i] + h * g;
+  }
+  if (!ok) set_status(status, vert_inst[i], ST_NONFINITE);
+}
+
+// Element vector-Jacobian products of one adjoint step at x_{s-1}, with the
+// adjoint solution mu and the new velocity v_s:
+//   ag = -h K_exact mu - h^2 grad_x(mu^T K_sys(x) v_s)   (state gradient)
+//   ak = K_sys mu                                         (velocity gradient)
+//   acc_ks += mu . (h f_m/k_s - h^2 (K_sys,m/k_s) v_s), acc_kb likewise.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T> a) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nv = m.nv;
+  const double h = a.h, h2 = a.h * a.h;
+  if (gid < m.nt) {
+    const int t = gid, nt = m.nt;
+    Tri s;
+    int v[3];
+    tri_load(m, a.x, t, s, v);
+    const double ks = a.mat[3 * m.tri_inst[t] + 0];
+    double mu[3][3], vv[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mu[i][c] = a.mu[c * nv + v[i]];
+        vv[i][c] = (double)a.vs[c * nv + v[i]];
+      }
+    double dFm[3][2], dFv[3][2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        dFm[r][c] = mu[0][r] * s.w[0][c] + mu[1][r] * s.w[1][c] + mu[2][r] * s.w[2][c];
+        dFv[r][c] = vv[0][r] * s.w[0][c] + vv[1][r] * s.w[1][c] + vv[2][r] * s.w[2][c];
+      }
+    // S3 = sym(F^T dF_mu), S2 = sym(F^T dF_v), S1 = sym(dF_mu^T dF_v)
+    double S1[2][2], S2[2][2], S3[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        double fm = 0, mf = 0, fv = 0, vf = 0, mv = 0, vm = 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          fm += s.F[r][p] * dFm[r][q];
+          mf += dFm[r][p] * s.F[r][q];
+          fv += s.F[r][p] * dFv[r][q];
+          vf += dFv[r][p] * s.F[r][q];
+          mv += dFm[r][p] * dFv[r][q];
+          vm += dFv[r][p] * dFm[r][q];
+        }
+        S3[p][q] = 0.5 * (fm + mf);
+        S2[p][q] = 0.5 * (fv + vf);
+        S1[p][q] = 0.5 * (mv + vm);
+      }
+    // stress term of K_sys and its derivative along S1
+    double Gp[2][2], Y[2][2];
+    if (m.tension) {
+      Eig2 eg = eig2(s.G);
+      tension(eg, Gp);
+      tension_deriv(eg, S1, Y);
+    } else {
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          Gp[p][q] = s.G[p][q];
+          Y[p][q] = S1[p][q];
+        }
+    }
+    // 3x2 matrices, all without the area * k_s factor
+    double Qe[3][2], Qs[3][2], Qt[3][2], Pf[3][2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double fs3 = s.F[r][0] * S3[0][c] + s.F[r][1] * S3[1][c];
+        Qe[r][c] = dFm[r][0] * s.G[0][c] + dFm[r][1] * s.G[1][c] + fs3;
+        Qs[r][c] = dFm[r][0] * Gp[0][c] + dFm[r][1] * Gp[1][c] + fs3;
+        Qt[r][c] = s.F[r][0] * Y[0][c] + s.F[r][1] * Y[1][c] + dFm[r][0] * S2[0][c] +
+                   dFm[r][1] * S2[1][c] + dFv[r][0] * S3[0][c] + dFv[r][1] * S3[1][c];
+        Pf[r][c] = s.F[r][0] * s.G[0][c] + s.F[r][1] * s.G[1][c];
+      }
+    const double A = s.area, ak = s.area * ks;
+    double part = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        double qe = Qe[r][0] * s.w[i][0] + Qe[r][1] * s.w[i][1];
+        double qs = Qs[r][0] * s.w[i][0] + Qs[r][1] * s.w[i][1];
+        double qt = Qt[r][0] * s.w[i][0] + Qt[r][1] * s.w[i][1];
+        double pf = Pf[r][0] * s.w[i][0] + Pf[r][1] * s.w[i][1];
+        el.tri_ag[(i * 3 + r) * nt + t] = -h * ak * qe - h2 * ak * qt;
+        el.tri_ak[(i * 3 + r) * nt + t] = ak * qs;
+        // unit-stiffness force -A pf, unit-stiffness K_sys mu = A qs (symmetric: v.K mu)
+        part += mu[i][r] * (-h * A * pf) - h2 * vv[i][r] * (A * qs);
+      }
+    el.acc_ks[t] += part;
+  } else if (gid < m.nt + m.nh) {
+    const int e = gid - m.nt, nh = m.nh;
+    int v[4];
+    double X[4][3], g[4][3], mu[4][3], vv[4][3];
+    hinge_load(m, a.x, e, v, X);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        mu[i][c] = a.mu[c * nv + v[i]];
+        vv[i][c] = (double)a.vs[c * nv + v[i]];
+      }
+    const double th = hinge_theta(X);
+    hinge_grad<double>(X, g);
+    const double ce = m.hin_ce[e];
+    const double wgt = 2.0 * a.mat[3 * m.hin_inst[e] + 1] * ce;
+    const double dth = th - m.hin_rest[e];
+    double gm = 0.0, gv = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        gm += g[i][c] * mu[i][c];
+        gv += g[i][c] * vv[i][c];
+      }
+    // y = (h dth + h^2 gv) mu + h^2 gm v; Hess(theta) y by one dual pass of grad(theta)
+    const double cm = h * dth + h2 * gv, cv = h2 * gm;
+    dual Xd[4][3], gd[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Xd[i][c] = dual(X[i][c], cm * mu[i][c] + cv * vv[i][c]);
+    hinge_grad<dual>(Xd, gd);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        el.hin_ag[(i * 3 + c) * nh + e] = -wgt * (h * gm * g[i][c] + gd[i][c].d);
+        el.hin_ak[(i * 3 + c) * nh + e] = wgt * gm * g[i][c];
+      }
+    el.acc_kb[e] += -2.0 * ce * gm * (h * dth + h2 * gv);
+  }
+}
+
+// Per-vertex completion of one adjoint step: gather the element products,
+// gx -= ..., gv = mask(u - h^2 K_sys mu), dL/dF_{s-1} = h mu, density partial.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nv = m.nv;
+  if (i >= nv) return;
+  const double h = a.h, h2 = a.h * a.h;
+  double ag[3] = {0.0, 0.0, 0.0}, ak[3] = {0.0, 0.0, 0.0};
+  for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
+    int ref = m.vinc_ref[c];
+    if (ref >= 0) {
+      int t = ref / 3, va = ref - 3 * (ref / 3);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        ag[r] += el.tri_ag[(va * 3 + r) * m.nt + t];
+        ak[r] += el.tri_ak[(va * 3 + r) * m.nt + t];
+      }
+    } else {
+      int r2 = -ref - 1;
+      int e = r2 >> 2, va = r2 & 3;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        ag[r] += el.hin_ag[(va * 3 + r) * m.nh + e];
+        ak[r] += el.hin_ak[(va * 3 + r) * m.nh + e];
+      }
+    }
+  }
+  const bool pin = m.pinned[i] != 0;
+  const double varea = m.varea[i];
+  double dpart = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double mu = a.mu[r * nv + i];
+    a.gx[r * nv + i] += ag[r];
+    a.gv[r * nv + i] = pin ? 0.0 : a.u[r * nv + i] - h2 * ak[r];
+    if (a.dl_dF) a.dl_dF[r * nv + i] = (T)(h * mu);
+    const double dv = pin ? 0.0 : (double)a.vs[r * nv + i] - (double)a.vp[r * nv + i];
+    dpart += mu * (h * varea * a.g[r] - varea * dv);
+  }
+  el.acc_d[i] += dpart;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_final(int nv, const double* __restrict__ gx,
+                                                   const double* __restrict__ gv,
+                                                   T* __restrict__ dx0, T* __restrict__ dv0) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * nv) return;
+  if (dx0) dx0[k] = (T)gx[k];
+  if (dv0) dv0[k] = (T)gv[k];
+}
+
+// One workgroup per sheet: fixed-order sums of the per-element partials.
+__global__ void __launch_bounds__(256) k_material_sum(Mesh m, Elem el, double* __restrict__ out) {
+  __shared__ double s_part[3][4];
+  const int inst = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  const int toff = m.inst_toff[inst], nt = m.inst_nt[inst];
+  const int hoff = m.inst_hoff[inst], nh = m.inst_nh[inst];
+  const int voff = m.inst_voff[inst], nv = m.inst_nv[inst];
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) t0 += el.acc_ks[toff + k];
+  for (int k = threadIdx.x; k < nh; k += blockDim.x) t1 += el.acc_kb[hoff + k];
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) t2 += el.acc_d[voff + k];
+  t0 = wave_sum(t0);
+  t1 = wave_sum(t1);
+  t2 = wave_sum(t2);
+  if (lane == 0) {
+    s_part[0][wave] = t0;
+    s_part[1][wave] = t1;
+    s_part[2][wave] = t2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nwaves = (blockDim.x + 63) >> 6;
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+    for (int q = 0; q < nwaves; ++q) {
+      r0 += s_part[0][q];
+      r1 += s_part[1][q];
+      r2 += s_part[2][q];
+    }
+    out[3 * inst + 0] = r0;
+    out[3 * inst + 1] = r1;
+    out[3 * inst + 2] = r2;
+  }
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+__global__ void k_fill_double(double* p, long n, double v) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
+// --------------------------------------------------------------- launchers
+static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
+void launch_fill_int(int* p, int n, int v, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+}
+void launch_fill_double(double* p, long n, double v, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_fill_double, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+}
+
+template <typename T>
+void launch_elements(const Mesh& m, const Elem& el, const T* x, const double* mat, int* status,
+                     hipStream_t st) {
+  long n = (long)m.nt + m.nh;
+  hipLaunchKernelGGL(k_elements<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, mat,
+                     status);
+}
+
+template <typename T>
+void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_assemble<T>, dim3(blocks_for(m.nv, 128)), dim3(128), 0, st, m, el, a);
+}
+
+template <typename T>
+size_t pcg_lds_bytes(int maxnz, int rows) {
+  return (size_t)maxnz * rows * (9 * sizeof(T) + sizeof(int));
+}
+
+template <typename T>
+hipError_t pcg_prepare(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pcg<T>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T>
+hipError_t pcg_occupancy(int rows, size_t lds, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<T>, rows, lds);
+}
+
+template <typename T>
+void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<T>& a,
+                hipStream_t st) {
+  size_t lds = pcg_lds_bytes<T>(m.maxnz, plan.rows);
+  launch_fill_int(w.barrier, m.ninst, 0, st);
+  launch_fill_int(w.abort_flag, 1, 0, st);
+  hipLaunchKernelGGL(k_pcg<T>, dim3(plan.nwg), dim3(plan.rows), lds, st, m, plan, w, a);
+}
+
+template <typename T>
+void launch_update(int nv, const int* pinned, const int* vert_inst, const T* xp, const T* vp,
+                   const double* dv, double h, T* xn, T* vn, T* xout, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_update<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
+                     vert_inst, xp, vp, dv, h, xn, vn, xout, status);
+}
+
+template <typename T>
+void launch_init_state(int nv, const int* pinned, const int* vert_inst, const T* x0, const T* v0,
+                       T* xs, T* vs, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_state<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
+                     vert_inst, x0, v0, xs, vs, status);
+}
+
+template <typename T>
+void launch_adj_pre(int nv, const int* pinned, const int* vert_inst, const T* dl, double h,
+                    double* gx, const double* gv, double* u, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_pre<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
+                     vert_inst, dl, h, gx, gv, u, status);
+}
+
+template <typename T>
+void launch_adj_elements(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st) {
+  long n = (long)m.nt + m.nh;
+  hipLaunchKernelGGL(k_adj_elements<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, a);
+}
+
+template <typename T>
+void launch_adj_rows(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_rows<T>, dim3(blocks_for(m.nv, 256)), dim3(256), 0, st, m, el, a);
+}
+
+template <typename T>
+void launch_adj_final(int nv, const double* gx, const double* gv, T* dx0, T* dv0, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_final<T>, dim3(blocks_for(3L * nv, 256)), dim3(256), 0, st, nv, gx, gv,
+                     dx0, dv0);
+}
+
+void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_material_sum, dim3(m.ninst), dim3(256), 0, st, m, el, out);
+}
+
+#define PHISFT_INSTANTIATE(T)                                                                    \
+  template void launch_elements<T>(const Mesh&, const Elem&, const T*, const double*, int*,      \
+                                   hipStream_t);                                                 \
+  template void launch_assemble<T>(const Mesh&, const Elem&, const AssembleArgs<T>&,             \
+                                   hipStream_t);                                                 \
+  template size_t pcg_lds_bytes<T>(int, int);                                                    \
+  template hipError_t pcg_prepare<T>(size_t);                                                    \
+  template hipError_t pcg_occupancy<T>(int, size_t, int*);                                       \
+  template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&,                 \
+                              const PcgArgs<T>&, hipStream_t);                                   \
+  template void launch_update<T>(int, const int*, const int*, const T*, const T*, const double*, \
+                                 double, T*, T*, T*, int*, hipStream_t);                         \
+  template void launch_init_state<T>(int, const int*, const int*, const T*, const T*, T*, T*,    \
+                                     int*, hipStream_t);                                         \
+  template void launch_adj_pre<T>(int, const int*, const int*, const T*, double, double*,        \
+                                  const double*, double*, int*, hipStream_t);                    \
+  template void launch_adj_elements<T>(const Mesh&, const Elem&, const AdjArgs<T>&,              \
+                                       hipStream_t);                                             \
+  template void launch_adj_rows<T>(const Mesh&, const Elem&, const AdjArgs<T>&, hipStream_t);   \
+  template void launch_adj_final<T>(int, const double*, const double*, T*, T*, hipStream_t);
+
+PHISFT_INSTANTIATE(float)
+PHISFT_INSTANTIATE(double)
+
+}  // namespace phisft

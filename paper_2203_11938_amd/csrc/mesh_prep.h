@@ -1,0 +1,46 @@
+// mesh_prep.h -- host-side preparation of a (batch of) cloth sheet(s): rest
+// geometry, hinges, block sparsity pattern, element-to-block maps, solver plan.
+#pragma once
+
+#include <string>
+#include <vector>
+
+namespace phisft {
+
+struct HostSheet {
+  int nv = 0, nt = 0;
+  std::vector<int> tris;      // [nt][3]
+  std::vector<double> rest;   // [nv][3]
+  std::vector<int> pins;
+  double mat[3] = {0, 0, 0};  // k_s, k_b, d
+};
+
+// Concatenated, validated layout (global indices). Field meaning as in Mesh.
+struct HostLayout {
+  int nv = 0, nt = 0, nh = 0, ninst = 0, maxnz = 0;
+  std::vector<double> varea;
+  std::vector<int> pinned, vert_inst, vinc_ptr, vinc_ref, ell_col, slot_ptr, slot_ref, diag_k;
+  std::vector<int> tri_v;
+  std::vector<double> tri_B, tri_area;
+  std::vector<int> tri_inst;
+  std::vector<int> hin_v;
+  std::vector<double> hin_ce, hin_rest;
+  std::vector<int> hin_inst;
+  std::vector<int> inst_voff, inst_nv, inst_toff, inst_nt, inst_hoff, inst_nh;
+  std::vector<double> mat;    // [ninst][3] create-time materials
+};
+
+struct HostPlan {
+  int rows = 0, nwg = 0;
+  std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg;
+};
+
+// Returns 0 on success, -1 (invalid argument) or -2 (mesh error) with a message.
+int build_layout(const std::vector<HostSheet>& sheets, HostLayout& out, std::string& err);
+
+// Checks every index table against its bounds (run before any upload).
+bool check_layout(const HostLayout& L, std::string& err);
+
+HostPlan make_plan(const HostLayout& L, int rows);
+
+}  // namespace phisft

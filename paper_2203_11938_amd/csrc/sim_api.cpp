@@ -1,0 +1,665 @@
+// sim_api.cpp -- the C ABI (include/phisft_sim.h): handles, workspace, and the
+// step sequencing of rollout and adjoint on the caller's HIP stream.
+//
+// Rollout: for s = 1..n, one linearised backward-Euler step (Sec. 3.1, Eq. 4-5):
+// element pass, row assembly, persistent PCG, update. States are kept either
+// for every step or every k-th step (checkpoints); the adjoint walks the steps
+// backwards (implicit differentiation of Eq. 4), recomputing each checkpoint
+// segment forward first when checkpoints are used. The recomputation runs the
+// same kernels on the same inputs, so it reproduces the forward states bitwise.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/phisft_sim.h"
+#include "kernels.h"
+#include "mesh_prep.h"
+#include "sim_internal.h"
+
+using namespace phisft;
+
+struct sim_s {
+  HostLayout L;
+  HostPlan plan_h;
+  int prec = SIM_FP32;
+  size_t tsize = 4;
+  double h = 0.01;
+  double grav[3] = {0.0, 0.0, -9.81};
+  double cg_tol = 1e-7;
+  int cg_max_iter = 20000;
+  int ckpt = 0;
+  int max_steps = 0;
+
+  std::vector<void*> allocs;
+  Mesh mesh{};
+  Elem el{};
+  SolverPlan plan{};
+  SolverWork sw{};
+  void* A = nullptr;
+  void* Jinv = nullptr;
+  double* rhs = nullptr;
+  double* sol = nullptr;
+  double* mat_default = nullptr;
+  double* gx = nullptr;
+  double* gv = nullptr;
+  int* status = nullptr;
+  int* it_fwd = nullptr;   // [max_steps][ninst]
+  int* it_rec = nullptr;
+  int* it_adj = nullptr;
+  double* res_fwd = nullptr;
+  double* res_adj = nullptr;
+  double* res_rec = nullptr;
+  // state storage: each state is x [3][nv] followed by v [3][nv]
+  void* traj = nullptr;    // store-all: max_steps + 1 states
+  void* ckpts = nullptr;   // checkpoints: max_steps / k + 1 states
+  void* tmp = nullptr;     // checkpoints: 2 rolling states + 1 final
+  void* seg = nullptr;     // checkpoints: k recomputed states
+
+  // most recent rollout
+  bool have_rollout = false;
+  int n_steps = 0;
+  std::vector<int> frames;
+  const void* forces = nullptr;
+  const double* material = nullptr;
+  hipStream_t stream = nullptr;
+
+  sim_stats stats{};
+  std::vector<int> inst_status;
+  std::string err;
+};
+
+namespace {
+
+sim_status bits_to_status(int bits) {
+  if (bits & ST_TIMEOUT) return SIM_E_HIP;
+  if (bits & ST_NONFINITE) return SIM_E_NONFINITE;
+  if (bits & ST_INDEFINITE) return SIM_E_INDEFINITE;
+  if (bits & ST_NOT_CONVERGED) return SIM_E_NOT_CONVERGED;
+  return SIM_OK;
+}
+
+sim_status hip_fail(sim_t* s, hipError_t e, const char* where) {
+  if (s) s->err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SIM_E_NOMEM : SIM_E_HIP;
+}
+
+#define HIPCHECK(s, call)                                \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail((s), e_, #call); \
+  } while (0)
+
+template <typename V>
+sim_status upload(sim_t* s, const std::vector<V>& h, const V** out) {
+  void* d = nullptr;
+  size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(V);
+  HIPCHECK(s, hipMalloc(&d, bytes));
+  s->allocs.push_back(d);
+  if (!h.empty()) HIPCHECK(s, hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  *out = static_cast<const V*>(d);
+  return SIM_OK;
+}
+
+sim_status alloc(sim_t* s, size_t bytes, void** out) {
+  void* d = nullptr;
+  HIPCHECK(s, hipMalloc(&d, std::max<size_t>(bytes, 8)));
+  s->allocs.push_back(d);
+  *out = d;
+  return SIM_OK;
+}
+
+#define TRY(x)                      \
+  do {                              \
+    sim_status st_ = (x);           \
+    if (st_ != SIM_OK) return st_;  \
+  } while (0)
+
+size_t state_bytes(const sim_t* s) { return 6 * (size_t)s->L.nv * s->tsize; }
+
+char* state_at(void* base, const sim_t* s, long k) {
+  return static_cast<char*>(base) + (size_t)k * state_bytes(s);
+}
+
+// State of step index k (0..n) during the forward pass of an n-step rollout.
+char* fwd_state(sim_t* s, int k, int n) {
+  if (s->ckpt == 0) return state_at(s->traj, s, k);
+  if (k % s->ckpt == 0) return state_at(s->ckpts, s, k / s->ckpt);
+  if (k == n) return state_at(s->tmp, s, 2);
+  return state_at(s->tmp, s, k % 2);
+}
+
+// State of step index k during the adjoint sweep over the segment that starts at c0.
+char* adj_state(sim_t* s, int k, int c0, int n) {
+  if (s->ckpt == 0) return state_at(s->traj, s, k);
+  if (k % s->ckpt == 0) return state_at(s->ckpts, s, k / s->ckpt);
+  if (k == n) return state_at(s->tmp, s, 2);
+  return state_at(s->seg, s, k - c0);
+}
+
+sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, const sim_options* opt) {
+  sim_options o;
+  sim_default_options(&o);
+  if (opt) o = *opt;
+  if (!(dt > 0.0) || !std::isfinite(dt)) {
+    s->err = "dt must be positive";
+    return SIM_E_INVALID;
+  }
+  if ((o.precision != SIM_FP32 && o.precision != SIM_FP64) || !(o.cg_tol > 0.0) ||
+      o.cg_max_iter < 1 || o.checkpoint_every < 0 || o.max_steps < 1 ||
+      !(o.rows_per_block == 0 || o.rows_per_block == 64 || o.rows_per_block == 128 ||
+        o.rows_per_block == 256) ||
+      (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION)) {
+    s->err = "invalid options";
+    return SIM_E_INVALID;
+  }
+  s->prec = o.precision;
+  s->tsize = o.precision == SIM_FP64 ? 8 : 4;
+  s->h = dt;
+  for (int k = 0; k < 3; ++k) s->grav[k] = o.gravity[k];
+  s->cg_tol = o.cg_tol;
+  s->cg_max_iter = o.cg_max_iter;
+  s->ckpt = o.checkpoint_every;
+  s->max_steps = o.max_steps;
+
+  int rc = build_layout(sheets, s->L, s->err);
+  if (rc != 0) return rc == -1 ? SIM_E_INVALID : SIM_E_MESH;
+  if (!check_layout(s->L, s->err)) return SIM_E_MESH;
+  HostLayout& L = s->L;
+
+  // solver launch shape: rows per workgroup bounded by the LDS budget and co-residency
+  int dev = 0, ncu = 0;
+  HIPCHECK(s, hipGetDevice(&dev));
+  HIPCHECK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const size_t lds_cap = 160 * 1024 - 1024;
+  std::vector<int> cands;
+  if (o.rows_per_block) cands.push_back(o.rows_per_block);
+  else cands = {128, 256, 64};
+  bool placed = false;
+  for (int rows : cands) {
+    size_t lds = s->prec == SIM_FP64 ? pcg_lds_bytes<double>(L.maxnz, rows)
+                                     : pcg_lds_bytes<float>(L.maxnz, rows);
+    if (lds > lds_cap) continue;
+    hipError_t e = s->prec == SIM_FP64 ? pcg_prepare<double>(lds) : pcg_prepare<float>(lds);
+    if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
+    int per_cu = 0;
+    e = s->prec == SIM_FP64 ? pcg_occupancy<double>(rows, lds, &per_cu)
+                            : pcg_occupancy<float>(rows, lds, &per_cu);
+    if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
+    HostPlan P = make_plan(L, rows);
+    if ((long)per_cu * ncu >= P.nwg) {
+      s->plan_h = P;
+      placed = true;
+      break;
+    }
+  }
+  if (!placed) {
+    s->err = "mesh too large for the co-resident solver (rows per block / LDS)";
+    return SIM_E_INVALID;
+  }
+
+  // ---- upload geometry and tables
+  Mesh& m = s->mesh;
+  m.nv = L.nv;
+  m.nt = L.nt;
+  m.nh = L.nh;
+  m.ninst = L.ninst;
+  m.maxnz = L.maxnz;
+  m.tension = o.membrane_system == SIM_MEMBRANE_TENSION ? 1 : 0;
+  TRY(upload(s, L.varea, &m.varea));
+  TRY(upload(s, L.pinned, &m.pinned));
+  TRY(upload(s, L.vert_inst, &m.vert_inst));
+  TRY(upload(s, L.vinc_ptr, &m.vinc_ptr));
+  TRY(upload(s, L.vinc_ref, &m.vinc_ref));
+  TRY(upload(s, L.ell_col, &m.ell_col));
+  TRY(upload(s, L.slot_ptr, &m.slot_ptr));
+  TRY(upload(s, L.slot_ref, &m.slot_ref));
+  TRY(upload(s, L.diag_k, &m.diag_k));
+  TRY(upload(s, L.tri_v, &m.tri_v));
+  TRY(upload(s, L.tri_B, &m.tri_B));
+  TRY(upload(s, L.tri_area, &m.tri_area));
+  TRY(upload(s, L.tri_inst, &m.tri_inst));
+  TRY(upload(s, L.hin_v, &m.hin_v));
+  TRY(upload(s, L.hin_ce, &m.hin_ce));
+  TRY(upload(s, L.hin_rest, &m.hin_rest));
+  TRY(upload(s, L.hin_inst, &m.hin_inst));
+  TRY(upload(s, L.inst_voff, &m.inst_voff));
+  TRY(upload(s, L.inst_nv, &m.inst_nv));
+  TRY(upload(s, L.inst_toff, &m.inst_toff));
+  TRY(upload(s, L.inst_nt, &m.inst_nt));
+  TRY(upload(s, L.inst_hoff, &m.inst_hoff));
+  TRY(upload(s, L.inst_nh, &m.inst_nh));
+  const double* md = nullptr;
+  TRY(upload(s, L.mat, &md));
+  s->mat_default = const_cast<double*>(md);
+
+  SolverPlan& p = s->plan;
+  p.nwg = s->plan_h.nwg;
+  p.rows = s->plan_h.rows;
+  TRY(upload(s, s->plan_h.wg_inst, &p.wg_inst));
+  TRY(upload(s, s->plan_h.wg_row0, &p.wg_row0));
+  TRY(upload(s, s->plan_h.wg_nrows, &p.wg_nrows));
+  TRY(upload(s, s->plan_h.inst_wg0, &p.inst_wg0));
+  TRY(upload(s, s->plan_h.inst_nwg, &p.inst_nwg));
+
+  // ---- workspace
+  const size_t nv = L.nv, nt = L.nt, nh = L.nh, ni = L.ninst, ts = s->tsize;
+  void* q = nullptr;
+  Elem& el = s->el;
+  TRY(alloc(s, 9 * nt * 8, &q)); el.tri_f = (double*)q;
+  TRY(alloc(s, 81 * nt * 8, &q)); el.tri_K = (double*)q;
+  TRY(alloc(s, 12 * nh * 8, &q)); el.hin_g = (double*)q;
+  TRY(alloc(s, 12 * nh * 8, &q)); el.hin_f = (double*)q;
+  TRY(alloc(s, nh * 8, &q)); el.hin_w = (double*)q;
+  TRY(alloc(s, 9 * nt * 8, &q)); el.tri_ag = (double*)q;
+  TRY(alloc(s, 9 * nt * 8, &q)); el.tri_ak = (double*)q;
+  TRY(alloc(s, 12 * nh * 8, &q)); el.hin_ag = (double*)q;
+  TRY(alloc(s, 12 * nh * 8, &q)); el.hin_ak = (double*)q;
+  TRY(alloc(s, nt * 8, &q)); el.acc_ks = (double*)q;
+  TRY(alloc(s, nh * 8, &q)); el.acc_kb = (double*)q;
+  TRY(alloc(s, nv * 8, &q)); el.acc_d = (double*)q;
+  TRY(alloc(s, (size_t)L.maxnz * 9 * nv * ts, &s->A));
+  TRY(alloc(s, 9 * nv * ts, &s->Jinv));
+  TRY(alloc(s, 3 * nv * 8, &q)); s->rhs = (double*)q;
+  TRY(alloc(s, 3 * nv * 8, &q)); s->sol = (double*)q;
+  TRY(alloc(s, 3 * nv * 8, &q)); s->gx = (double*)q;
+  TRY(alloc(s, 3 * nv * 8, &q)); s->gv = (double*)q;
+  TRY(alloc(s, 3 * nv * 8, &q)); s->sw.zbuf = (double*)q;
+  TRY(alloc(s, 6 * nv * 8, &q)); s->sw.pbuf = (double*)q;
+  TRY(alloc(s, 4 * (size_t)p.nwg * 8, &q)); s->sw.red = (double*)q;
+  TRY(alloc(s, ni * 4, &q)); s->sw.barrier = (int*)q;
+  TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
+  TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
+  const size_t st = (size_t)s->max_steps * ni;
+  TRY(alloc(s, st * 4, &q)); s->it_fwd = (int*)q;
+  TRY(alloc(s, st * 4, &q)); s->it_rec = (int*)q;
+  TRY(alloc(s, st * 4, &q)); s->it_adj = (int*)q;
+  TRY(alloc(s, st * 8, &q)); s->res_fwd = (double*)q;
+  TRY(alloc(s, st * 8, &q)); s->res_rec = (double*)q;
+  TRY(alloc(s, st * 8, &q)); s->res_adj = (double*)q;
+  if (s->ckpt == 0) {
+    TRY(alloc(s, (size_t)(s->max_steps + 1) * state_bytes(s), &s->traj));
+  } else {
+    TRY(alloc(s, (size_t)(s->max_steps / s->ckpt + 1) * state_bytes(s), &s->ckpts));
+    TRY(alloc(s, 3 * state_bytes(s), &s->tmp));
+    TRY(alloc(s, (size_t)s->ckpt * state_bytes(s), &s->seg));
+  }
+  HIPCHECK(s, hipMemset(s->status, 0, 4 * (ni + 1)));
+  HIPCHECK(s, hipMemset(s->it_fwd, 0, st * 4));
+  HIPCHECK(s, hipMemset(s->it_rec, 0, st * 4));
+  HIPCHECK(s, hipMemset(s->it_adj, 0, st * 4));
+  HIPCHECK(s, hipDeviceSynchronize());
+  s->stats.n_instances = L.ninst;
+  s->stats.rows_per_block = p.rows;
+  s->stats.blocks = p.nwg;
+  return SIM_OK;
+}
+
+// ---------------------------------------------------------- step sequences
+template <typename T>
+void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* mat, T* xout,
+                  int* iters, double* resid, hipStream_t st) {
+  const int nv = s->L.nv;
+  const T* xp = reinterpret_cast<const T*>(sp);
+  const T* vp = xp + 3 * (size_t)nv;
+  T* xn = reinterpret_cast<T*>(sn);
+  T* vn = xn + 3 * (size_t)nv;
+  launch_elements<T>(s->mesh, s->el, xp, mat, s->status, st);
+  AssembleArgs<T> a{};
+  a.v = vp;
+  a.forces = F;
+  a.mat = mat;
+  a.h = s->h;
+  for (int k = 0; k < 3; ++k) a.g[k] = s->grav[k];
+  a.want_rhs = 1;
+  a.A = static_cast<T*>(s->A);
+  a.Jinv = static_cast<T*>(s->Jinv);
+  a.b = s->rhs;
+  a.status = s->status;
+  launch_assemble<T>(s->mesh, s->el, a, st);
+  PcgArgs<T> c{};
+  c.A = a.A;
+  c.Jinv = a.Jinv;
+  c.rhs = s->rhs;
+  c.sol = s->sol;
+  c.tol = s->cg_tol;
+  c.max_iter = s->cg_max_iter;
+  c.iters = iters;
+  c.resid = resid;
+  c.status = s->status;
+  launch_pcg<T>(s->mesh, s->plan, s->sw, c, st);
+  launch_update<T>(nv, s->mesh.pinned, s->mesh.vert_inst, xp, vp, s->sol, s->h, xn, vn, xout,
+                   s->status, st);
+}
+
+template <typename T>
+const T* force_slice(const sim_t* s, int step) {
+  if (!s->forces) return nullptr;
+  return static_cast<const T*>(s->forces) + (size_t)(step - 1) * 3 * s->L.nv;
+}
+
+template <typename T>
+sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x_out,
+                        hipStream_t st) {
+  const int nv = s->L.nv, ni = s->L.ninst;
+  char* s0 = fwd_state(s, 0, n);
+  launch_init_state<T>(nv, s->mesh.pinned, s->mesh.vert_inst, static_cast<const T*>(x0),
+                       static_cast<const T*>(v0),
+                       reinterpret_cast<T*>(s0), reinterpret_cast<T*>(s0) + 3 * (size_t)nv,
+                       s->status, st);
+  size_t f = 0;
+  for (int k = 1; k <= n; ++k) {
+    T* xo = nullptr;
+    if (f < s->frames.size() && s->frames[f] == k) {
+      xo = static_cast<T*>(x_out) + f * 3 * (size_t)nv;
+      ++f;
+    }
+    forward_step<T>(s, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
+                    s->material, xo, s->it_fwd + (size_t)(k - 1) * ni,
+                    s->res_fwd + (size_t)(k - 1) * ni, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "rollout launch");
+  return SIM_OK;
+}
+
+template <typename T>
+void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, T* dlF,
+                  hipStream_t st) {
+  const int nv = s->L.nv, ni = s->L.ninst;
+  const T* xp = reinterpret_cast<const T*>(sp);
+  const T* vp = xp + 3 * (size_t)nv;
+  const T* vs = reinterpret_cast<const T*>(sn) + 3 * (size_t)nv;
+  double* u = s->rhs;  // the adjoint right-hand side reuses the forward rhs buffer
+  launch_adj_pre<T>(nv, s->mesh.pinned, s->mesh.vert_inst, dl, s->h, s->gx, s->gv, u, s->status,
+                    st);
+  launch_elements<T>(s->mesh, s->el, xp, s->material, s->status, st);
+  AssembleArgs<T> a{};
+  a.v = vp;
+  a.forces = nullptr;
+  a.mat = s->material;
+  a.h = s->h;
+  for (int q = 0; q < 3; ++q) a.g[q] = s->grav[q];
+  a.want_rhs = 0;
+  a.A = static_cast<T*>(s->A);
+  a.Jinv = static_cast<T*>(s->Jinv);
+  a.b = nullptr;
+  a.status = s->status;
+  launch_assemble<T>(s->mesh, s->el, a, st);
+  PcgArgs<T> c{};
+  c.A = a.A;
+  c.Jinv = a.Jinv;
+  c.rhs = u;
+  c.sol = s->sol;
+  c.tol = s->cg_tol;
+  c.max_iter = s->cg_max_iter;
+  c.iters = s->it_adj + (size_t)(k - 1) * ni;
+  c.resid = s->res_adj + (size_t)(k - 1) * ni;
+  c.status = s->status;
+  launch_pcg<T>(s->mesh, s->plan, s->sw, c, st);
+  AdjArgs<T> j{};
+  j.x = xp;
+  j.vp = vp;
+  j.vs = vs;
+  j.mu = s->sol;
+  j.u = u;
+  j.mat = s->material;
+  j.h = s->h;
+  for (int q = 0; q < 3; ++q) j.g[q] = s->grav[q];
+  j.gx = s->gx;
+  j.gv = s->gv;
+  j.dl_dF = dlF;
+  launch_adj_elements<T>(s->mesh, s->el, j, st);
+  launch_adj_rows<T>(s->mesh, s->el, j, st);
+}
+
+template <typename T>
+sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF, void* dl_dx0,
+                        void* dl_dv0, hipStream_t st) {
+  const int nv = s->L.nv, ni = s->L.ninst, n = s->n_steps;
+  launch_fill_double(s->gx, 3L * nv, 0.0, st);
+  launch_fill_double(s->gv, 3L * nv, 0.0, st);
+  launch_fill_double(s->el.acc_ks, s->L.nt, 0.0, st);
+  launch_fill_double(s->el.acc_kb, s->L.nh, 0.0, st);
+  launch_fill_double(s->el.acc_d, nv, 0.0, st);
+  const T* dl = static_cast<const T*>(dl_dx);
+  int f = (int)s->frames.size() - 1;
+  const int k = s->ckpt == 0 ? n : s->ckpt;
+  const int nseg = (n + k - 1) / k;
+  for (int c = nseg - 1; c >= 0; --c) {
+    const int c0 = c * k, c1 = std::min(n, c0 + k);
+    if (s->ckpt != 0) {
+      // recompute the interior states of the segment from its checkpoint
+      for (int q = c0 + 1; q < c1; ++q)
+        forward_step<T>(s, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
+                        s->material, nullptr, s->it_rec + (size_t)(q - 1) * ni,
+                        s->res_rec + (size_t)(q - 1) * ni, st);
+    }
+    for (int q = c1; q > c0; --q) {
+      const T* dlq = nullptr;
+      if (f >= 0 && s->frames[f] == q) {
+        dlq = dl + (size_t)f * 3 * nv;
+        --f;
+      }
+      T* dlF = dl_dF ? static_cast<T*>(dl_dF) + (size_t)(q - 1) * 3 * nv : nullptr;
+      adjoint_step<T>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), dlq, dlF, st);
+    }
+  }
+  launch_adj_final<T>(nv, s->gx, s->gv, static_cast<T*>(dl_dx0), static_cast<T*>(dl_dv0), st);
+  if (dl_dmat) launch_material_sum(s->mesh, s->el, static_cast<double*>(dl_dmat), st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "adjoint launch");
+  return SIM_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+void sim_default_options(sim_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SIM_FP32;
+  o->cg_tol = 1e-7;
+  o->cg_max_iter = 20000;
+  o->checkpoint_every = 0;
+  o->gravity[0] = 0.0;
+  o->gravity[1] = 0.0;
+  o->gravity[2] = -9.81;
+  o->max_steps = 1000;
+  o->rows_per_block = 0;
+  o->membrane_system = SIM_MEMBRANE_EXACT;
+}
+
+sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,
+                            const int32_t* const* pins, const int32_t* n_pins,
+                            const sim_material* mats, double dt, const sim_options* opt,
+                            sim_t** out) {
+  if (!out) return SIM_E_INVALID;
+  *out = nullptr;
+  if (n < 1 || !meshes || !rest_pos || !mats) return SIM_E_INVALID;
+  std::vector<HostSheet> sheets(n);
+  for (int b = 0; b < n; ++b) {
+    const sim_mesh& m = meshes[b];
+    if (m.n_verts < 3 || m.n_tris < 1 || !m.tris || !rest_pos[b]) return SIM_E_INVALID;
+    int np = n_pins ? n_pins[b] : 0;
+    if (np < 0 || (np > 0 && (!pins || !pins[b]))) return SIM_E_INVALID;
+    HostSheet& s = sheets[b];
+    s.nv = m.n_verts;
+    s.nt = m.n_tris;
+    s.tris.assign(m.tris, m.tris + 3 * (size_t)m.n_tris);
+    s.rest.assign(rest_pos[b], rest_pos[b] + 3 * (size_t)m.n_verts);
+    if (np > 0) s.pins.assign(pins[b], pins[b] + np);
+    s.mat[0] = mats[b].stretch;
+    s.mat[1] = mats[b].bend;
+    s.mat[2] = mats[b].density;
+    if (!std::isfinite(s.mat[0]) || !std::isfinite(s.mat[1]) || !std::isfinite(s.mat[2]) ||
+        !(s.mat[2] > 0.0))
+      return SIM_E_INVALID;
+  }
+  sim_t* s = new (std::nothrow) sim_t();
+  if (!s) return SIM_E_NOMEM;
+  sim_status st = setup(s, sheets, dt, opt);
+  if (st != SIM_OK) {
+    std::fprintf(stderr, "sim_create: %s\n", s->err.c_str());
+    sim_destroy(s);
+    return st;
+  }
+  *out = s;
+  return SIM_OK;
+}
+
+sim_status sim_create(const sim_mesh* mesh, const double* rest_pos, const int32_t* pins,
+                      int32_t n_pins, const sim_material* mat, double dt, const sim_options* opt,
+                      sim_t** out) {
+  if (!mesh || !mat) return SIM_E_INVALID;
+  const double* rp[1] = {rest_pos};
+  const int32_t* pp[1] = {pins};
+  int32_t np[1] = {n_pins};
+  return sim_create_batch(1, mesh, rp, pp, np, mat, dt, opt, out);
+}
+
+sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0,
+                       const void* forces, const void* material, const int32_t* loss_frames,
+                       int32_t n_loss, void* x_out, void* stream) {
+  if (!s) return SIM_E_INVALID;
+  if (n_steps < 1 || n_steps > s->max_steps || !x0 || n_loss < 0 || (n_loss > 0 && (!loss_frames || !x_out))) {
+    s->err = "invalid rollout arguments";
+    return SIM_E_INVALID;
+  }
+  int prev = 0;
+  for (int k = 0; k < n_loss; ++k) {
+    if (loss_frames[k] <= prev || loss_frames[k] > n_steps) {
+      s->err = "loss frames must be strictly increasing within 1..n_steps";
+      return SIM_E_INVALID;
+    }
+    prev = loss_frames[k];
+  }
+  s->have_rollout = false;
+  s->n_steps = n_steps;
+  s->frames.assign(loss_frames, loss_frames + n_loss);
+  s->forces = forces;
+  s->material = material ? static_cast<const double*>(material) : s->mat_default;
+  s->stream = static_cast<hipStream_t>(stream);
+  sim_status st = s->prec == SIM_FP64
+                      ? rollout_impl<double>(s, n_steps, x0, v0, x_out, s->stream)
+                      : rollout_impl<float>(s, n_steps, x0, v0, x_out, s->stream);
+  if (st == SIM_OK) s->have_rollout = true;
+  return st;
+}
+
+sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl_dforces,
+                       void* dl_dx0, void* dl_dv0, void* stream) {
+  if (!s) return SIM_E_INVALID;
+  if (!s->have_rollout) {
+    s->err = "sim_adjoint needs a preceding sim_rollout";
+    return SIM_E_STATE;
+  }
+  if (!s->frames.empty() && !dl_dx) {
+    s->err = "dl_dx is required when the rollout has loss frames";
+    return SIM_E_INVALID;
+  }
+  s->stream = static_cast<hipStream_t>(stream);
+  return s->prec == SIM_FP64
+             ? adjoint_impl<double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, s->stream)
+             : adjoint_impl<float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, s->stream);
+}
+
+sim_status sim_sync_status(sim_t* s) {
+  if (!s) return SIM_E_INVALID;
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "hipStreamSynchronize");
+  const int ni = s->L.ninst;
+  std::vector<int> words(ni + 1, 0);
+  e = hipMemcpy(words.data(), s->status, 4 * (ni + 1), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(s, e, "status readback");
+  e = hipMemset(s->status, 0, 4 * (ni + 1));
+  if (e != hipSuccess) return hip_fail(s, e, "status reset");
+  s->inst_status.assign(ni, SIM_OK);
+  for (int b = 0; b < ni; ++b) s->inst_status[b] = bits_to_status(words[1 + b]);
+  const int bits = words[0];
+  // statistics of the most recent calls
+  const int n = s->n_steps;
+  std::vector<int> itf((size_t)n * ni), itr((size_t)n * ni), ita((size_t)n * ni);
+  std::vector<double> rf((size_t)n * ni), ra((size_t)n * ni);
+  if (n > 0) {
+    (void)hipMemcpy(itf.data(), s->it_fwd, itf.size() * 4, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(itr.data(), s->it_rec, itr.size() * 4, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(ita.data(), s->it_adj, ita.size() * 4, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(rf.data(), s->res_fwd, rf.size() * 8, hipMemcpyDeviceToHost);
+    (void)hipMemcpy(ra.data(), s->res_adj, ra.size() * 8, hipMemcpyDeviceToHost);
+  }
+  sim_stats& S = s->stats;
+  S.n_steps = n;
+  S.cg_iters_forward = S.cg_iters_recompute = S.cg_iters_adjoint = 0;
+  S.cg_iters_max = 0;
+  S.max_rel_residual = 0.0;
+  for (size_t q = 0; q < itf.size(); ++q) {
+    S.cg_iters_forward += itf[q];
+    S.cg_iters_recompute += itr[q];
+    S.cg_iters_adjoint += ita[q];
+    S.cg_iters_max = std::max(S.cg_iters_max, std::max(itf[q], ita[q]));
+    S.max_rel_residual = std::max(S.max_rel_residual, std::max(rf[q], ra[q]));
+  }
+  sim_status st = bits_to_status(bits);
+  if (bits & ST_TIMEOUT) s->err = "solver workgroups timed out at a cluster barrier";
+  S.device_status = st;
+  return st;
+}
+
+sim_status sim_get_instance_status(const sim_t* s, int32_t* out) {
+  if (!s || !out) return SIM_E_INVALID;
+  for (int b = 0; b < s->L.ninst; ++b)
+    out[b] = b < (int)s->inst_status.size() ? s->inst_status[b] : SIM_OK;
+  return SIM_OK;
+}
+
+sim_status sim_get_stats(const sim_t* s, sim_stats* out) {
+  if (!s || !out) return SIM_E_INVALID;
+  *out = s->stats;
+  return SIM_OK;
+}
+
+sim_status sim_get_cg_iters(const sim_t* s, int32_t* forward, int32_t* adjoint) {
+  if (!s) return SIM_E_INVALID;
+  const size_t cnt = (size_t)s->n_steps * s->L.ninst;
+  if (cnt == 0) return SIM_OK;
+  if (forward && hipMemcpy(forward, s->it_fwd, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return SIM_E_HIP;
+  if (adjoint && hipMemcpy(adjoint, s->it_adj, cnt * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return SIM_E_HIP;
+  return SIM_OK;
+}
+
+const char* sim_status_string(sim_status st) {
+  switch (st) {
+    case SIM_OK: return "ok";
+    case SIM_E_INVALID: return "invalid argument";
+    case SIM_E_MESH: return "invalid mesh";
+    case SIM_E_NOMEM: return "out of memory";
+    case SIM_E_HIP: return "HIP runtime error";
+    case SIM_E_NOT_CONVERGED: return "CG did not converge within cg_max_iter";
+    case SIM_E_INDEFINITE: return "CG breakdown (system not positive definite)";
+    case SIM_E_NONFINITE: return "non-finite value";
+    case SIM_E_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* sim_last_error(const sim_t* s) { return s ? s->err.c_str() : ""; }
+
+void sim_destroy(sim_t* s) {
+  if (!s) return;
+  if (!s->allocs.empty()) (void)hipDeviceSynchronize();
+  for (void* p : s->allocs) (void)hipFree(p);
+  delete s;
+}
+
+}  // extern "C"

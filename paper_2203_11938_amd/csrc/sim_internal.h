@@ -1,0 +1,98 @@
+// sim_internal.h -- device-side data layout shared by the host runtime and the kernels.
+//
+// All per-instance arrays of a handle are concatenated (vertices, triangles,
+// hinges) and indexed globally. Geometry is stored in FP64; the state
+// trajectory, the assembled system matrix and its block-Jacobi inverse are
+// stored in the handle's precision T (float or double); element intermediates
+// and all solver vectors are FP64.
+#pragma once
+
+#include <cstdint>
+
+namespace phisft {
+
+// Sticky device status bits. A status array holds the handle-wide word at
+// index 0 and one word per instance after it.
+enum : int {
+  ST_NOT_CONVERGED = 1,
+  ST_INDEFINITE = 2,
+  ST_NONFINITE = 4,
+  ST_TIMEOUT = 8,  // a solver workgroup waited too long at a cluster barrier
+};
+
+// Element reference encodings (slot contributions and vertex incidences):
+//   triangle block (t, a, b): t * 9 + a * 3 + b          (>= 0)
+//   hinge block    (e, a, b): -(e * 16 + a * 4 + b) - 1   (< 0)
+//   triangle vertex (t, a):   t * 3 + a                   (>= 0)
+//   hinge vertex    (e, a):   -(e * 4 + a) - 1            (< 0)
+
+struct Mesh {
+  int nv, nt, nh, ninst, maxnz;
+  int tension;                  // 1: tension-clamped membrane block in K_sys, 0: exact Hessian
+  // vertices
+  const double* varea;          // [nv] lumped area (a third of incident triangle areas)
+  const int* pinned;            // [nv] 1 = Dirichlet vertex
+  const int* vert_inst;         // [nv]
+  const int* vinc_ptr;          // [nv+1] incident element vertices
+  const int* vinc_ref;          // encoded (t,a) / (e,a)
+  const int* ell_col;           // [maxnz][nv] block columns (padding: own row, zero block)
+  const int* slot_ptr;          // [maxnz*nv+1] contributions of slot s = k*nv + i
+  const int* slot_ref;          // encoded (t,a,b) / (e,a,b)
+  const int* diag_k;            // [nv] slot index of the diagonal block
+  // triangles
+  const int* tri_v;             // [3][nt] global vertex ids (a, b, c), CCW
+  const double* tri_B;          // [4][nt] inverse rest frame B = D_m^-1, row-major
+  const double* tri_area;       // [nt] rest area
+  const int* tri_inst;          // [nt]
+  // hinges: edge (v0, v1), wings v2 (triangle v0 v1 v2) and v3 (triangle v1 v0 v3)
+  const int* hin_v;             // [4][nh]
+  const double* hin_ce;         // [nh] 3 |e|^2 / (A1 + A2)
+  const double* hin_rest;       // [nh] rest dihedral angle
+  const int* hin_inst;          // [nh]
+  // instances
+  const int* inst_voff;
+  const int* inst_nv;
+  const int* inst_toff;
+  const int* inst_nt;
+  const int* inst_hoff;
+  const int* inst_nh;
+};
+
+// Per-step element scratch (FP64).
+struct Elem {
+  double* tri_f;    // [9][nt]  force on (a, b, c)
+  double* tri_K;    // [81][nt] system stiffness blocks (a,b) row-major 3x3
+  double* hin_g;    // [12][nh] grad theta
+  double* hin_f;    // [12][nh] bending force
+  double* hin_w;    // [nh]     2 k_b c_e
+  // adjoint
+  double* tri_ag;   // [9][nt]  state-gradient contribution
+  double* tri_ak;   // [9][nt]  K_sys mu contribution
+  double* hin_ag;   // [12][nh]
+  double* hin_ak;   // [12][nh]
+  double* acc_ks;   // [nt] dL/dk_s partial sums over steps
+  double* acc_kb;   // [nh]
+  double* acc_d;    // [nv]
+};
+
+// Persistent solver launch description.
+struct SolverPlan {
+  int nwg;                 // workgroups of the launch
+  int rows;                // rows per workgroup (= block size)
+  const int* wg_inst;      // [nwg]
+  const int* wg_row0;      // [nwg]
+  const int* wg_nrows;     // [nwg]
+  const int* inst_wg0;     // [ninst]
+  const int* inst_nwg;     // [ninst]
+};
+
+// Solver scratch (device).
+struct SolverWork {
+  double* zbuf;            // [3][nv]
+  double* pbuf;            // [2][3][nv]
+  double* red;             // [2][nwg][2] per-workgroup partial sums
+  int* barrier;            // [ninst] arrival counters (zeroed before each launch)
+  int* abort_flag;         // [1]
+};
+
+}  // namespace phisft

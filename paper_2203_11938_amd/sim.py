@@ -1,0 +1,330 @@
+"""ctypes binding of ``libphisft_sim.so`` (C ABI in ``include/phisft_sim.h``).
+
+Argument marshalling only: every step of the rollout and of the adjoint runs in
+the HIP kernels of the library. PyTorch supplies device memory and the stream.
+If the library is missing this module raises -- there is no CPU fallback.
+
+Device tensors at the boundary are structure-of-arrays ``[..., 3, V]`` in the
+handle's precision (float32 for FP32, float64 for FP64); material arrays are
+float64 ``[n_instances, 3]`` = (k_s, k_b, d).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphisft_sim.so")
+
+SIM_OK = 0
+SIM_E_INVALID = -1
+SIM_E_MESH = -2
+SIM_E_NOMEM = -3
+SIM_E_HIP = -4
+SIM_E_NOT_CONVERGED = -5
+SIM_E_INDEFINITE = -6
+SIM_E_NONFINITE = -7
+SIM_E_STATE = -8
+SIM_FP32 = 0
+SIM_FP64 = 1
+SIM_MEMBRANE_EXACT = 0
+SIM_MEMBRANE_TENSION = 1
+
+
+class SimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("n_tris", ctypes.c_int32),
+                ("tris", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("stretch", ctypes.c_double), ("bend", ctypes.c_double),
+                ("density", ctypes.c_double)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double),
+                ("cg_max_iter", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
+                ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
+                ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int32), ("n_instances", ctypes.c_int32),
+                ("cg_iters_forward", ctypes.c_int64), ("cg_iters_recompute", ctypes.c_int64),
+                ("cg_iters_adjoint", ctypes.c_int64), ("cg_iters_max", ctypes.c_int32),
+                ("max_rel_residual", ctypes.c_double), ("device_status", ctypes.c_int32),
+                ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout", "sim_adjoint",
+           "sim_sync_status", "sim_get_stats", "sim_get_cg_iters", "sim_get_instance_status",
+           "sim_status_string", "sim_last_error", "sim_destroy")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the simulator has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    sig = {
+        "sim_default_options": (None, [ctypes.POINTER(_Options)]),
+        "sim_create": (i32, [ctypes.POINTER(_Mesh), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(i32), i32, ctypes.POINTER(_Material), ctypes.c_double,
+                             ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
+        "sim_create_batch": (i32, [i32, ctypes.POINTER(_Mesh),
+                                   ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.POINTER(ctypes.POINTER(i32)), ctypes.POINTER(i32),
+                                   ctypes.POINTER(_Material), ctypes.c_double,
+                                   ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
+        "sim_rollout": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp, vp]),
+        "sim_adjoint": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "sim_sync_status": (i32, [vp]),
+        "sim_get_stats": (i32, [vp, ctypes.POINTER(_Stats)]),
+        "sim_get_cg_iters": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "sim_get_instance_status": (i32, [vp, ctypes.POINTER(i32)]),
+        "sim_status_string": (ctypes.c_char_p, [i32]),
+        "sim_last_error": (ctypes.c_char_p, [vp]),
+        "sim_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class Sheet:
+    """One sheet's host description: triangles [T,3], rest positions [V,3], pins."""
+    tris: np.ndarray
+    rest: np.ndarray
+    pins: Sequence[int]
+    stretch: float
+    bend: float
+    density: float
+
+
+class Simulator:
+    """A handle of the library over one or several sheets (batched when several).
+
+    ``dt`` is the step h [s]; ``precision`` "fp32" or "fp64"; ``cg_tol`` the
+    relative residual at which each CG solve stops; ``checkpoint_every`` k > 0
+    keeps every k-th state and recomputes the rest in the adjoint; ``membrane``
+    selects the system matrix's membrane block ("exact" Hessian or "tension").
+    """
+
+    def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
+                 cg_tol: float = 1e-7, cg_max_iter: int = 20000, checkpoint_every: int = 0,
+                 max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
+                 membrane: str = "exact"):
+        lib = load_library()
+        self._lib = lib
+        self._h = None
+        opt = _Options()
+        lib.sim_default_options(ctypes.byref(opt))
+        opt.precision = SIM_FP64 if precision == "fp64" else SIM_FP32
+        opt.cg_tol = cg_tol
+        opt.cg_max_iter = cg_max_iter
+        opt.checkpoint_every = checkpoint_every
+        opt.max_steps = max_steps
+        opt.gravity[:] = list(gravity)
+        opt.rows_per_block = rows_per_block
+        if membrane not in ("exact", "tension"):
+            raise ValueError("membrane must be 'exact' or 'tension'")
+        opt.membrane_system = SIM_MEMBRANE_TENSION if membrane == "tension" else SIM_MEMBRANE_EXACT
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        n = len(sheets)
+        keep = []
+        meshes = (_Mesh * n)()
+        rests = (ctypes.POINTER(ctypes.c_double) * n)()
+        pins = (ctypes.POINTER(ctypes.c_int32) * n)()
+        npins = (ctypes.c_int32 * n)()
+        mats = (_Material * n)()
+        self.sizes = []
+        for b, s in enumerate(sheets):
+            tr = np.ascontiguousarray(s.tris, dtype=np.int32).reshape(-1, 3)
+            rp = np.ascontiguousarray(s.rest, dtype=np.float64).reshape(-1, 3)
+            pn = np.ascontiguousarray(np.asarray(s.pins, dtype=np.int32).reshape(-1))
+            keep += [tr, rp, pn]
+            meshes[b].n_verts = rp.shape[0]
+            meshes[b].n_tris = tr.shape[0]
+            meshes[b].tris = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            rests[b] = rp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            pins[b] = pn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if pn.size else None
+            npins[b] = pn.size
+            mats[b] = _Material(s.stretch, s.bend, s.density)
+            self.sizes.append(rp.shape[0])
+        h = ctypes.c_void_p()
+        st = lib.sim_create_batch(n, meshes, rests, pins, npins, mats, dt, ctypes.byref(opt),
+                                  ctypes.byref(h))
+        if st != SIM_OK:
+            raise SimError(st, "sim_create_batch: " + lib.sim_status_string(st).decode())
+        self._h = h
+        self.n_instances = n
+        self.n_verts = int(sum(self.sizes))
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(int)
+        self.dt = dt
+        self.max_steps = max_steps
+        self.n_steps = 0
+        self.n_loss = 0
+
+    def close(self):
+        if self._h is not None:
+            self._lib.sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != SIM_OK:
+            msg = self._lib.sim_last_error(self._h).decode() if self._h else ""
+            raise SimError(st, f"{what}: {self._lib.sim_status_string(st).decode()} {msg}")
+
+    def _need(self, t: Optional[torch.Tensor], shape, name: str, dtype=None):
+        if t is None:
+            return None
+        dtype = dtype or self.dtype
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor of shape "
+                             f"{tuple(shape)}, got {t.dtype} {tuple(t.shape)} "
+                             f"{'cuda' if t.is_cuda else 'cpu'}")
+        return t
+
+    def rollout(self, n_steps: int, x0: torch.Tensor, v0: Optional[torch.Tensor] = None,
+                forces: Optional[torch.Tensor] = None, material: Optional[torch.Tensor] = None,
+                loss_frames: Optional[Sequence[int]] = None, x_out: Optional[torch.Tensor] = None):
+        """Run ``n_steps`` steps. Returns positions at the loss frames [n_loss, 3, V]."""
+        V = self.n_verts
+        frames = np.arange(1, n_steps + 1, dtype=np.int32) if loss_frames is None else \
+            np.ascontiguousarray(loss_frames, dtype=np.int32)
+        self._need(x0, (3, V), "x0")
+        self._need(v0, (3, V), "v0")
+        self._need(forces, (n_steps, 3, V), "forces")
+        self._need(material, (self.n_instances, 3), "material", torch.float64)
+        if x_out is None:
+            x_out = torch.empty((frames.size, 3, V), dtype=self.dtype, device=x0.device)
+        self._need(x_out, (frames.size, 3, V), "x_out")
+        st = self._lib.sim_rollout(self._h, int(n_steps), _ptr(x0), _ptr(v0), _ptr(forces),
+                                   _ptr(material),
+                                   frames.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   int(frames.size), _ptr(x_out), _stream())
+        self._check(st, "sim_rollout")
+        # the adjoint re-reads these; keep them alive
+        self._keep = (forces, material)
+        self.n_steps = n_steps
+        self.n_loss = int(frames.size)
+        self.loss_frames = frames
+        return x_out
+
+    def adjoint(self, dl_dx: torch.Tensor, want_forces: bool = True, want_x0: bool = True,
+                want_v0: bool = True, want_material: bool = True):
+        """Gradients of the loss whose frame gradients are ``dl_dx`` [n_loss, 3, V]."""
+        V = self.n_verts
+        self._need(dl_dx, (self.n_loss, 3, V), "dl_dx")
+        dev = dl_dx.device
+        g_mat = torch.empty((self.n_instances, 3), dtype=torch.float64, device=dev) if want_material else None
+        g_F = torch.empty((self.n_steps, 3, V), dtype=self.dtype, device=dev) if want_forces else None
+        g_x0 = torch.empty((3, V), dtype=self.dtype, device=dev) if want_x0 else None
+        g_v0 = torch.empty((3, V), dtype=self.dtype, device=dev) if want_v0 else None
+        st = self._lib.sim_adjoint(self._h, _ptr(dl_dx), _ptr(g_mat), _ptr(g_F), _ptr(g_x0),
+                                   _ptr(g_v0), _stream())
+        self._check(st, "sim_adjoint")
+        return dict(material=g_mat, forces=g_F, x0=g_x0, v0=g_v0)
+
+    def sync(self, allow_not_converged: bool = False) -> int:
+        """Wait for the stream; raise on a sticky device error."""
+        st = self._lib.sim_sync_status(self._h)
+        if st == SIM_E_NOT_CONVERGED and allow_not_converged:
+            return st
+        self._check(st, "device status")
+        return st
+
+    def status(self) -> int:
+        return self._lib.sim_sync_status(self._h)
+
+    def stats(self) -> dict:
+        s = _Stats()
+        self._check(self._lib.sim_get_stats(self._h, ctypes.byref(s)), "sim_get_stats")
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def instance_status(self) -> np.ndarray:
+        out = np.zeros(self.n_instances, dtype=np.int32)
+        self._check(self._lib.sim_get_instance_status(self._h, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int32))), "sim_get_instance_status")
+        return out
+
+    def cg_iters(self):
+        n = self.n_steps * self.n_instances
+        f = np.zeros(n, dtype=np.int32)
+        a = np.zeros(n, dtype=np.int32)
+        self._check(self._lib.sim_get_cg_iters(self._h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                               a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                    "sim_get_cg_iters")
+        return f.reshape(self.n_steps, self.n_instances), a.reshape(self.n_steps, self.n_instances)
+
+
+class ClothRollout(torch.autograd.Function):
+    """Differentiable rollout: (material, forces, x0, v0) -> positions at the loss frames.
+
+    User-facing layout is vertex-major: forces [n_steps, V, 3], x0/v0 [V, 3],
+    output [n_loss, V, 3]; material [n_instances, 3] float64. The backward pass
+    is the library's adjoint; double backward is not supported.
+    """
+
+    @staticmethod
+    def forward(ctx, sim: Simulator, n_steps: int, loss_frames, material, forces, x0, v0):
+        soa = lambda t: None if t is None else t.transpose(-1, -2).contiguous()
+        xo = sim.rollout(n_steps, soa(x0), soa(v0), soa(forces), material.contiguous(),
+                         loss_frames)
+        sim.sync(allow_not_converged=True)
+        ctx.sim = sim
+        ctx.has_forces = forces is not None
+        ctx.has_v0 = v0 is not None
+        return xo.transpose(-1, -2).contiguous()
+
+    @staticmethod
+    def backward(ctx, g):
+        sim = ctx.sim
+        r = sim.adjoint(g.transpose(-1, -2).contiguous(), want_forces=ctx.has_forces)
+        sim.sync(allow_not_converged=True)
+        aos = lambda t: None if t is None else t.transpose(-1, -2).contiguous()
+        return (None, None, None, r["material"], aos(r["forces"]), aos(r["x0"]),
+                aos(r["v0"]) if ctx.has_v0 else None)
+
+
+def rollout(sim: Simulator, n_steps: int, material, x0, v0=None, forces=None, loss_frames=None):
+    """Differentiable rollout through the library (see ClothRollout)."""
+    return ClothRollout.apply(sim, n_steps, loss_frames, material, forces, x0, v0)

@@ -1,0 +1,163 @@
+"""Benchmark: one full gradient (rollout + adjoint) of the differentiable cloth step.
+
+Workload (headline): a 64x64-vertex sheet (0.5 m, 7938 triangles), 100 steps of
+0.01 s, top corners pinned, per-step Gaussian wind load 0.05 N/m^2, material
+k_s 1e3 N/m, k_b 1e-4 N m, d 0.1 kg/m^2, FP32 state with FP64 solver vectors,
+CG tolerance 1e-7, every state stored. Loss: summed squared distance to a target
+rollout (material scaled by seeded factors). A benchmark "step" is one gradient.
+
+Prints one JSON line with the throughput in vertex-steps/s (vertices x simulated
+steps / wall time of rollout + adjoint, inputs resident on the GPU), the roofline
+of the dominant kernel (the persistent PCG) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def solver_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_2203_11938_amd", "csrc", "kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """Per-launch HBM bytes of the solver from the committed rocprofv3 counter
+    summary, or None if absent or taken on a different kernel source."""
+    p = os.path.join(ROOT, "profiles", f"k_pcg_{workload}_counters.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha256_16") != solver_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, inst, sample_steps: int):
+    import numpy as np
+    import oracle
+    o = oracle.Oracle(inst.tris, inst.rest, inst.pins, *inst.material.as_tuple(), dt=w.dt,
+                      cg_tol=w.cg_tol)
+    frames = np.arange(1, sample_steps + 1, dtype=np.int32)
+    F = inst.forces[:sample_steps] if inst.forces is not None else None
+    xo, _, _, _ = o.rollout(sample_steps, inst.x0, inst.v0, F, frames)
+    tgt = inst.x0[None] + 0.01
+    t0 = time.perf_counter()
+    o.gradient(sample_steps, inst.x0, inst.v0, F, frames, 2.0 * (xo - tgt))
+    dt = time.perf_counter() - t0
+    return dict(value=inst.n_verts * sample_steps / dt, unit="vertex-steps/s", cores=1,
+                kind="oracle",
+                sample=f"first {sample_steps} of the {w.steps} steps of the same sheet, rollout "
+                       f"+ adjoint in one single-threaded FP64 call ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed gradients")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="H")
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the simulator has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+
+    w = W.workload(args.workload)
+    insts = W.make_instances(w)
+    dev = torch.device("cuda:0")
+    print(f"bench: workload {w.name}, {len(insts)} sheet(s), {w.steps} steps", file=sys.stderr,
+          flush=True)
+    sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
+    sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
+                      checkpoint_every=w.checkpoint_every, max_steps=w.steps)
+    dt = sim.dtype
+    V = sim.n_verts
+    x0 = torch.tensor(W.to_soa(np.concatenate([i.x0 for i in insts])), dtype=dt, device=dev)
+    v0 = torch.tensor(W.to_soa(np.concatenate([i.v0 for i in insts])), dtype=dt, device=dev)
+    F = torch.tensor(W.to_soa(np.concatenate([i.forces for i in insts], axis=1)), dtype=dt,
+                     device=dev)
+    frames = w.loss_frames()
+    # target: rollout of the same sheets with the seeded material factors (untimed)
+    mat_t = torch.tensor(np.array([np.array(i.material.as_tuple()) * i.target_factors
+                                   for i in insts]), dtype=torch.float64, device=dev)
+    tgt = sim.rollout(w.steps, x0, v0, F, mat_t, frames).clone()
+    sim.sync(allow_not_converged=True)
+
+    def gradient():
+        xo = sim.rollout(w.steps, x0, v0, F, None, frames)
+        g = sim.adjoint((2.0 * (xo - tgt)).contiguous())
+        return g
+
+    for _ in range(args.warmup):
+        gradient()
+        sim.sync(allow_not_converged=True)
+    sim.set_timing(True)
+    iters = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gradient()
+        sim.sync(allow_not_converged=True)
+        st = sim.stats()
+        iters += st["cg_iters_forward"] + st["cg_iters_adjoint"] + st["cg_iters_recompute"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = sim.stats()
+    ms = 1e3 * wall / args.steps
+    value = V * w.steps * args.steps / wall
+
+    # roofline of the solver: algorithmic bytes per CG iteration -- the operator read once
+    # (9 entries + a 4 B column index per non-zero 3x3 block, in the stored precision) plus
+    # 192 B per vertex for one pass over the solver vectors
+    msize = 8 if sim.matrix_precision == "fp64" else 4
+    b_iter = (9 * msize + 4) * st["nnz_blocks"] + 192 * V
+    launches = st["solver_launches"]
+    avg_ms = st["solver_ms"] / max(launches, 1)
+    bytes_per_launch = b_iter * iters / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w.name)
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else round(traffic, 1),
+                kernel="k_pcg", avg_launch_ms=round(avg_ms, 4),
+                cg_iters_per_launch=round(iters / max(launches, 1), 1),
+                solver_share_of_wall=round(st["solver_ms"] / (wall * 1e3), 3))
+
+    out = dict(metric="vertex-steps/s forward+adjoint (ms per gradient, 100-step 64x64 sheet)",
+               value=round(value, 1), unit="vertex-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+               config=dict(workload=f"{w.name}: {w.n}x{w.n} sheet, {w.steps} steps of "
+                           f"{w.dt} s, rollout + adjoint", vertices=V, sim_steps=w.steps,
+                           cg_tol=w.cg_tol, cg_iters_per_gradient=iters // args.steps,
+                           solver_blocks=st["blocks"], rows_per_block=st["rows_per_block"],
+                           matrix_precision=sim.matrix_precision, bytes_per_cg_iter=b_iter),
+               roofline=roof)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

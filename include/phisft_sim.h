@@ -103,7 +103,9 @@ typedef struct {
 } sim_material;
 
 typedef struct {
-  int32_t precision;        /* sim_precision; storage type of state, matrix, forces     */
+  int32_t precision;        /* sim_precision of the caller's device arrays; the state
+                               trajectory, element arithmetic and solver vectors are
+                               always FP64                                              */
   double cg_tol;            /* stop at ||r||_2 <= cg_tol * ||b||_2 (relative residual)  */
   int32_t cg_max_iter;      /* cap per solve                                            */
   int32_t checkpoint_every; /* k > 0: keep every k-th state, recompute in the adjoint;
@@ -112,6 +114,10 @@ typedef struct {
   int32_t max_steps;        /* capacity: longest rollout this handle will run           */
   int32_t rows_per_block;   /* solver rows per workgroup (64..256); 0 = tuned choice     */
   int32_t membrane_system;  /* sim_membrane_system                                      */
+  int32_t matrix_precision; /* sim_precision of the stored system matrix and its
+                               block-Jacobi inverse (default SIM_FP64; SIM_FP32 halves
+                               the solver's operand but bounds the solution's relative
+                               accuracy near cond(A) * 6e-8)                            */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -127,11 +133,14 @@ typedef struct {
   int32_t device_status;      /* sticky device status (sim_status value) */
   int32_t rows_per_block;     /* solver launch shape in use */
   int32_t blocks;             /* solver workgroups per launch */
+  int64_t nnz_blocks;         /* non-zero 3x3 blocks of the system matrix */
+  int64_t solver_launches;    /* timed solver launches since timing was enabled */
+  double solver_ms;           /* their summed duration (HIP events on the call's stream) */
 } sim_stats;
 
-/* Fills *opt with the defaults: FP32, cg_tol 1e-7, cg_max_iter 20000, store
- * every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
- * exact membrane Hessian. */
+/* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,
+ * store every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
+ * exact membrane Hessian, FP64 system matrix. */
 void sim_default_options(sim_options* opt);
 
 /* Creates a handle for one sheet.
@@ -189,6 +198,11 @@ sim_status sim_adjoint(sim_t* sim, const void* dl_dx, void* dl_dmaterial, void* 
  * (SIM_OK, SIM_E_NOT_CONVERGED, SIM_E_INDEFINITE or SIM_E_NONFINITE) or a HIP
  * error; clears it for the next call. */
 sim_status sim_sync_status(sim_t* sim);
+
+/* enable != 0: bracket every solver launch with HIP events on the call's stream
+ * and accumulate their durations in sim_stats (solver_launches, solver_ms) at
+ * each sim_sync_status; enable = 0 stops timing and clears the totals. */
+sim_status sim_set_timing(sim_t* sim, int32_t enable);
 
 /* Copies the statistics of the most recent calls (valid after sim_sync_status). */
 sim_status sim_get_stats(const sim_t* sim, sim_stats* out);

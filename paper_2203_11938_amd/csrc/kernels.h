@@ -7,24 +7,24 @@
 
 namespace phisft {
 
-template <typename T>
+template <typename T, typename TM>
 struct AssembleArgs {
-  const T* v;          // [3][nv] velocity v_{t-1} (zero on pins)
+  const double* v;     // [3][nv] velocity v_{t-1} (zero on pins)
   const T* forces;     // [3][nv] corrective forces of the step, or nullptr
   const double* mat;   // [ninst][3] (k_s, k_b, d)
   double h;
   double g[3];
   int want_rhs;        // 0: matrix and preconditioner only (adjoint re-assembly)
-  T* A;                // [maxnz][9][nv]
-  T* Jinv;             // [9][nv]
+  TM* A;               // [maxnz][9][nv]
+  TM* Jinv;            // [9][nv]
   double* b;           // [3][nv]
   int* status;
 };
 
-template <typename T>
+template <typename TM>
 struct PcgArgs {
-  const T* A;
-  const T* Jinv;
+  const TM* A;
+  const TM* Jinv;
   const double* rhs;   // [3][nv]
   double* sol;         // [3][nv]
   double tol;
@@ -36,9 +36,9 @@ struct PcgArgs {
 
 template <typename T>
 struct AdjArgs {
-  const T* x;          // x_{s-1}
-  const T* vp;         // v_{s-1}
-  const T* vs;         // v_s
+  const double* x;     // x_{s-1}
+  const double* vp;    // v_{s-1}
+  const double* vs;    // v_s
   const double* mu;    // adjoint solution of step s
   const double* u;     // its right-hand side
   const double* mat;
@@ -52,26 +52,26 @@ struct AdjArgs {
 void launch_fill_int(int* p, int n, int v, hipStream_t st);
 void launch_fill_double(double* p, long n, double v, hipStream_t st);
 
-template <typename T>
-void launch_elements(const Mesh& m, const Elem& el, const T* x, const double* mat, int* status,
+void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* mat, int* status,
                      hipStream_t st);
-template <typename T>
-void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T>& a, hipStream_t st);
-template <typename T>
+template <typename T, typename TM>
+void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
+template <typename TM>
 size_t pcg_lds_bytes(int maxnz, int rows);
-template <typename T>
+template <typename TM>
 hipError_t pcg_prepare(size_t lds);
-template <typename T>
+template <typename TM>
 hipError_t pcg_occupancy(int rows, size_t lds, int* blocks_per_cu);
-template <typename T>
-void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<T>& a,
+template <typename TM>
+void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
                 hipStream_t st);
 template <typename T>
-void launch_update(int nv, const int* pinned, const int* vert_inst, const T* xp, const T* vp,
-                   const double* dv, double h, T* xn, T* vn, T* xout, int* status, hipStream_t st);
+void launch_update(int nv, const int* pinned, const int* vert_inst, const double* xp,
+                   const double* vp, const double* dv, double h, double* xn, double* vn, T* xout,
+                   int* status, hipStream_t st);
 template <typename T>
 void launch_init_state(int nv, const int* pinned, const int* vert_inst, const T* x0, const T* v0,
-                       T* xs, T* vs, int* status, hipStream_t st);
+                       double* xs, double* vs, int* status, hipStream_t st);
 template <typename T>
 void launch_adj_pre(int nv, const int* pinned, const int* vert_inst, const T* dl, double h,
                     double* gx, const double* gv, double* u, int* status, hipStream_t st);

@@ -8,17 +8,19 @@
 //                   order into A = M + h^2 K_sys (ELL layout, pins eliminated), the
 //                   right-hand side b = h (f + M g + F_t - h K_sys v) and the inverse
 //                   of the diagonal block (block-Jacobi preconditioner).
-//   k_pcg           persistent preconditioned CG: every workgroup owns a row range,
-//                   keeps its matrix rows in LDS and its vectors in FP64 registers;
-//                   the workgroups of one sheet meet at a counter barrier twice per
-//                   iteration (reductions are fixed-order, so results are bitwise
-//                   reproducible).
+//   k_pcg           persistent preconditioned pipelined CG: every workgroup owns a
+//                   row range, keeps its matrix rows in LDS and its vectors in FP64
+//                   registers; the workgroups of one sheet meet at one counter
+//                   barrier per iteration (reductions are fixed-order, so results
+//                   are bitwise reproducible).
 //   k_update        v_t = v_{t-1} + dv, x_t = x_{t-1} + h v_t, pins held.
 // Adjoint step (implicit differentiation of Eq. 4): k_adj_pre, the same assembly and
 // solver (A is symmetric), k_adj_elements (element vector-Jacobian products) and
 // k_adj_rows; k_material_sum reduces the material gradient.
 //
-// Element arithmetic is FP64 regardless of the storage precision T.
+// The state trajectory (x, v), element arithmetic and solver vectors are FP64 in
+// every precision mode; T (float or double) is the type of the system matrix, its
+// block-Jacobi inverse and the caller's input/output arrays.
 
 #include <hip/hip_runtime.h>
 
@@ -79,8 +81,7 @@ struct Tri {
   double area;
 };
 
-template <typename T>
-__device__ __forceinline__ void tri_load(const Mesh& m, const T* __restrict__ x, int t, Tri& s,
+__device__ __forceinline__ void tri_load(const Mesh& m, const double* __restrict__ x, int t, Tri& s,
                                          int v[3]) {
   const int nt = m.nt, nv = m.nv;
 #pragma unroll
@@ -95,9 +96,9 @@ __device__ __forceinline__ void tri_load(const Mesh& m, const T* __restrict__ x,
   s.w[0][1] = -(B01 + B11);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    double xa = (double)x[r * nv + v[0]];
-    double d1 = (double)x[r * nv + v[1]] - xa;
-    double d2 = (double)x[r * nv + v[2]] - xa;
+    double xa = x[r * nv + v[0]];
+    double d1 = x[r * nv + v[1]] - xa;
+    double d2 = x[r * nv + v[2]] - xa;
     s.F[r][0] = d1 * B00 + d2 * B10;
     s.F[r][1] = d1 * B01 + d2 * B11;
   }
@@ -226,21 +227,19 @@ __device__ __forceinline__ double hinge_theta(const double X[4][3]) {
   return atan2(sn, cs);
 }
 
-template <typename T>
-__device__ __forceinline__ void hinge_load(const Mesh& m, const T* __restrict__ x, int e, int v[4],
-                                           double X[4][3]) {
+__device__ __forceinline__ void hinge_load(const Mesh& m, const double* __restrict__ x, int e,
+                                           int v[4], double X[4][3]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     v[a] = m.hin_v[a * m.nh + e];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) X[a][k] = (double)x[k * m.nv + v[a]];
+    for (int k = 0; k < 3; ++k) X[a][k] = x[k * m.nv + v[a]];
   }
 }
 
 // ------------------------------------------------------ forward: elements
 // Threads [0, nt) take triangles, [nt, nt + nh) hinges.
-template <typename T>
-__global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const T* __restrict__ x,
+__global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double* __restrict__ x,
                                                   const double* __restrict__ mat, int* status) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid < m.nt) {
@@ -371,8 +370,8 @@ __device__ __forceinline__ bool inv3(const double a[9], double o[9]) {
   return true;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<T> a) {
+template <typename T, typename TM>
+__global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<T, TM> a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nv = m.nv;
   if (i >= nv) return;
@@ -393,7 +392,7 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
       slot_block(m, el, s, K);
       const bool pin_j = m.pinned[j] != 0;
       if (a.want_rhs && !pin_j) {
-        double vj[3] = {(double)a.v[j], (double)a.v[nv + j], (double)a.v[2 * nv + j]};
+        double vj[3] = {a.v[j], a.v[nv + j], a.v[2 * nv + j]};
 #pragma unroll
         for (int r = 0; r < 3; ++r) kv[r] += K[r * 3] * vj[0] + K[r * 3 + 1] * vj[1] + K[r * 3 + 2] * vj[2];
       }
@@ -411,7 +410,7 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
       }
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) a.A[(size_t)(k * 9 + q) * nv + i] = (T)Ab[q];
+    for (int q = 0; q < 9; ++q) a.A[(size_t)(k * 9 + q) * nv + i] = (TM)Ab[q];
     if (j == i) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) diag[q] = Ab[q];
@@ -420,14 +419,14 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   // block-Jacobi inverse of the stored (rounded) diagonal block
   double dr[9], Ji[9];
 #pragma unroll
-  for (int q = 0; q < 9; ++q) dr[q] = (double)(T)diag[q];
+  for (int q = 0; q < 9; ++q) dr[q] = (double)(TM)diag[q];
   if (!inv3(dr, Ji)) {
     set_status(a.status, inst, ST_INDEFINITE);
 #pragma unroll
     for (int q = 0; q < 9; ++q) Ji[q] = (q % 4) == 0 ? 1.0 : 0.0;
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) a.Jinv[q * nv + i] = (T)Ji[q];
+  for (int q = 0; q < 9; ++q) a.Jinv[q * nv + i] = (TM)Ji[q];
   if (!a.want_rhs) return;
   double f[3] = {0.0, 0.0, 0.0};
   for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
@@ -483,54 +482,85 @@ __device__ __forceinline__ bool cluster_barrier(int* ctr, int nwg, int& epoch, i
   return s_ok != 0;
 }
 
-// Fixed-order sum of two values over the cluster's workgroups via the partial
-// array red[slot][wg][2]; every workgroup obtains the identical result.
-__device__ __forceinline__ bool cluster_sum2(double a0, double a1, double* red, int slot, int nwg_all,
+// Fixed-order sum of three values over the cluster's workgroups via the partial
+// array red[slot][wg][3]; every workgroup obtains the identical result. The
+// cluster barrier inside also publishes every store made before the call.
+__device__ __forceinline__ bool cluster_sum3(const double a[3], double* red, int slot, int nwg_all,
                                              int wg, int iw0, int nwg, int* ctr, int& epoch,
                                              int* abort_flag, int* status, int inst,
-                                             double out[2]) {
-  __shared__ double s_part[2][4];
-  __shared__ double s_out[2];
+                                             double out[3]) {
+  __shared__ double s_part[3][4];
+  __shared__ double s_out[3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
-  a0 = wave_sum(a0);
-  a1 = wave_sum(a1);
+  double v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = wave_sum(a[k]);
   if (lane == 0) {
-    s_part[0][wave] = a0;
-    s_part[1][wave] = a1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s_part[k][wave] = v[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t0 = 0.0, t1 = 0.0;
-    for (int q = 0; q < nwaves; ++q) {
-      t0 += s_part[0][q];
-      t1 += s_part[1][q];
+    double* dst = red + ((size_t)slot * nwg_all + wg) * 3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double t = 0.0;
+      for (int q = 0; q < nwaves; ++q) t += s_part[k][q];
+      dst[k] = t;
     }
-    double* dst = red + ((size_t)slot * nwg_all + wg) * 2;
-    dst[0] = t0;
-    dst[1] = t1;
   }
   bool ok = cluster_barrier(ctr, nwg, epoch, abort_flag, status, inst);
   if (wave == 0) {
-    double t0 = 0.0, t1 = 0.0;
+    double t[3] = {0.0, 0.0, 0.0};
     for (int q = lane; q < nwg; q += 64) {
-      const double* src = red + ((size_t)slot * nwg_all + iw0 + q) * 2;
-      t0 += __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      t1 += __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double* src = red + ((size_t)slot * nwg_all + iw0 + q) * 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        t[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    t0 = wave_sum(t0);
-    t1 = wave_sum(t1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t[k] = wave_sum(t[k]);
     if (lane == 0) {
-      s_out[0] = t0;
-      s_out[1] = t1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s_out[k] = t[k];
     }
   }
   __syncthreads();
-  out[0] = s_out[0];
-  out[1] = s_out[1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = s_out[k];
   return ok;
 }
 
+// y = A v for this thread's row: blocks from LDS, v gathered from global [3][nv].
+template <typename T>
+__device__ __forceinline__ void row_spmv(const T* __restrict__ Al, const int* __restrict__ Cl, int R,
+                                         int tid, int maxnz, int nv, const double* __restrict__ v,
+                                         double y[3]) {
+  y[0] = y[1] = y[2] = 0.0;
+  for (int k = 0; k < maxnz; ++k) {
+    const int j = Cl[k * R + tid];
+    const double v0 = v[j], v1 = v[nv + j], v2 = v[2 * nv + j];
+    const T* blk = Al + (size_t)k * 9 * R + tid;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      y[r] += (double)blk[(r * 3) * R] * v0 + (double)blk[(r * 3 + 1) * R] * v1 +
+              (double)blk[(r * 3 + 2) * R] * v2;
+  }
+}
+
+constexpr int kMaxRestarts = 16;
+
+// Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
+// reduction per iteration, (r,u), (w,u), (r,r), whose cluster barrier also
+// publishes m = M^-1 w for the iteration's single SpMV n = A m. Vectors per row:
+// x, r, u = M^-1 r, w = A u, z, q, s, p (recurrences of the method), all FP64.
+// The recursively updated residual drifts from b - A x (rounding), so
+// convergence is accepted only on a true residual: when the recursive residual
+// meets the tolerance the recurrences restart from b - A x and the test is
+// repeated. A step denominator <= 0 also triggers a restart; at a fresh start
+// the denominator is u^T A u, so a non-positive value there is reported as an
+// indefinite system.
 template <typename T>
 __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -557,101 +587,123 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       Al[(k * 9 + q) * R + tid] = j < 0 ? T(0) : a.A[(size_t)(k * 9 + q) * nv + i];
   }
 
-  double J[9], x[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0}, z[3] = {0.0, 0.0, 0.0};
-  double p[3] = {0.0, 0.0, 0.0};
+  double J[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) J[q] = act ? (double)a.Jinv[q * nv + i] : 0.0;
+  auto prec = [&](const double in[3], double out[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = J[3 * c] * in[0] + J[3 * c + 1] * in[1] + J[3 * c + 2] * in[2];
+  };
+  double x[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0}, u[3], wv[3];
+  double mm[3], nn[3], z[3] = {0.0, 0.0, 0.0}, q3[3] = {0.0, 0.0, 0.0};
+  double sv[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
   if (act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i];
   }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) z[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
-  double* zb = w.zbuf;
-  double* pb0 = w.pbuf;
-  double* pb1 = w.pbuf + 3 * (size_t)nv;
+  prec(r, u);
+  // w_0 = A u_0 needs the neighbours' u_0
+  double* ub = w.zbuf;
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      zb[c * nv + i] = z[c];
-      pb1[c * nv + i] = 0.0;
-    }
+    for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
   }
-  double sums[2];
-  bool ok = cluster_sum2(r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
-                         r[0] * z[0] + r[1] * z[1] + r[2] * z[2], w.red, 1, plan.nwg, wg, iw0, nwg,
-                         ctr, epoch, w.abort_flag, a.status, inst, sums);
-  const double bnorm = sqrt(sums[0]);
-  double rz = sums[1], rr = sums[0], beta = 0.0;
-  int it = 0;
-  int flag = 0;
-  if (!isfinite(bnorm) || !isfinite(rz)) flag = ST_NONFINITE;
-  bool done = !ok || flag != 0 || bnorm == 0.0;
-  while (!done) {
+  bool ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst);
+  if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, ub, wv);
+  else wv[0] = wv[1] = wv[2] = 0.0;
+
+  double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
+  int it = 0, flag = 0, fresh = 1, restarts = 0;
+  // Restart the recurrences from the true residual r = b - A x (x published through a
+  // slot of pbuf no workgroup reads in this phase): two cluster barriers.
+  auto restart = [&]() -> bool {
+    double* xb = w.pbuf + (size_t)((it + 1) & 1) * 3 * nv;
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xb[c * nv + i] = x[c];
+    }
+    if (!cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst)) return false;
+    if (act) {
+      double ax[3];
+      row_spmv(Al, Cl, R, tid, maxnz, nv, xb, ax);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
+    }
+    prec(r, u);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
+    }
+    if (!cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst)) return false;
+    if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, ub, wv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
+    fresh = 1;
+    ++restarts;
+    return true;
+  };
+  while (ok) {
+    double* mb = w.pbuf + (size_t)(it & 1) * 3 * nv;
+    prec(wv, mm);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mb[c * nv + i] = mm[c];
+    }
+    const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
+                           wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
+                           r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
+    double sums[3];
+    ok = cluster_sum3(loc, w.red, it & 1, plan.nwg, wg, iw0, nwg, ctr, epoch, w.abort_flag,
+                      a.status, inst, sums);
+    if (!ok) break;
+    const double gamma = sums[0], delta = sums[1];
+    rr = sums[2];
+    if (it == 0) bnorm = sqrt(rr);
+    if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rr)) {
+      flag = ST_NONFINITE;
+      break;
+    }
+    if (bnorm == 0.0) break;
+    if (sqrt(rr) <= a.tol * bnorm) {
+      // accept only a true residual: right after a (re)start r = b - A x exactly
+      if (fresh || restarts >= kMaxRestarts) break;
+      ok = restart();
+      continue;
+    }
     if (it >= a.max_iter) {
       flag = ST_NOT_CONVERGED;
       break;
     }
-    double* pcur = (it & 1) ? pb1 : pb0;
-    const double* pprev = (it & 1) ? pb0 : pb1;
-    // p_it = z_it + beta p_{it-1}; neighbours' entries are formed the same way
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p[c] = z[c] + beta * p[c];
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) pcur[c * nv + i] = p[c];
-    }
-    double q3[3] = {0.0, 0.0, 0.0};
-    if (act) {
-      for (int k = 0; k < maxnz; ++k) {
-        const int j = Cl[k * R + tid];
-        double pj[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pj[c] = zb[c * nv + j] + beta * pprev[c * nv + j];
-        const T* blk = Al + (size_t)k * 9 * R + tid;
-#pragma unroll
-        for (int rr3 = 0; rr3 < 3; ++rr3)
-          q3[rr3] += (double)blk[(rr3 * 3) * R] * pj[0] + (double)blk[(rr3 * 3 + 1) * R] * pj[1] +
-                     (double)blk[(rr3 * 3 + 2) * R] * pj[2];
+    if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, mb, nn);
+    else nn[0] = nn[1] = nn[2] = 0.0;
+    const double beta = fresh ? 0.0 : gamma / gamma_prev;
+    const double denom = fresh ? delta : delta - beta * gamma / alpha_prev;
+    if (!(denom > 0.0)) {
+      // Right after a (re)start denom = u^T A u: A is not positive definite. Later, the
+      // recurrences have drifted (rounding): restart them from the true residual.
+      if (fresh || restarts >= kMaxRestarts) {
+        flag = ST_INDEFINITE;
+        break;
       }
+      ok = restart();
+      continue;
     }
-    ok = cluster_sum2(p[0] * q3[0] + p[1] * q3[1] + p[2] * q3[2], 0.0, w.red, 0, plan.nwg, wg, iw0,
-                      nwg, ctr, epoch, w.abort_flag, a.status, inst, sums);
-    const double pq = sums[0];
-    if (!ok) break;
-    if (!isfinite(pq)) {
-      flag = ST_NONFINITE;
-      break;
-    }
-    if (!(pq > 0.0)) {
-      flag = ST_INDEFINITE;
-      break;
-    }
-    const double alpha = rz / pq;
+    fresh = 0;
+    const double alpha = gamma / denom;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      z[c] = nn[c] + beta * z[c];
+      q3[c] = mm[c] + beta * q3[c];
+      sv[c] = wv[c] + beta * sv[c];
+      p[c] = u[c] + beta * p[c];
       x[c] += alpha * p[c];
-      r[c] -= alpha * q3[c];
+      r[c] -= alpha * sv[c];
+      u[c] -= alpha * q3[c];
+      wv[c] -= alpha * z[c];
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) zb[c * nv + i] = z[c];
-    }
-    ok = cluster_sum2(r[0] * z[0] + r[1] * z[1] + r[2] * z[2], r[0] * r[0] + r[1] * r[1] + r[2] * r[2],
-                      w.red, 1, plan.nwg, wg, iw0, nwg, ctr, epoch, w.abort_flag, a.status, inst,
-                      sums);
+    gamma_prev = gamma;
+    alpha_prev = alpha;
     ++it;
-    rr = sums[1];
-    if (!ok) break;
-    if (!isfinite(sums[0]) || !isfinite(rr)) {
-      flag = ST_NONFINITE;
-      break;
-    }
-    if (sqrt(rr) <= a.tol * bnorm) break;
-    beta = sums[0] / rz;
-    rz = sums[0];
   }
   if (act) {
 #pragma unroll
@@ -668,9 +720,10 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ pinned,
                                                 const int* __restrict__ vert_inst,
-                                                const T* __restrict__ xp, const T* __restrict__ vp,
+                                                const double* __restrict__ xp,
+                                                const double* __restrict__ vp,
                                                 const double* __restrict__ dv, double h,
-                                                T* __restrict__ xn, T* __restrict__ vn,
+                                                double* __restrict__ xn, double* __restrict__ vn,
                                                 T* __restrict__ xout, int* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
@@ -678,11 +731,11 @@ __global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ 
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double v = pin ? 0.0 : (double)vp[c * nv + i] + dv[c * nv + i];
-    double xx = (double)xp[c * nv + i] + h * v;
+    double v = pin ? 0.0 : vp[c * nv + i] + dv[c * nv + i];
+    double xx = xp[c * nv + i] + h * v;
     ok = ok && isfinite(xx) && isfinite(v);
-    vn[c * nv + i] = (T)v;
-    xn[c * nv + i] = (T)xx;
+    vn[c * nv + i] = v;
+    xn[c * nv + i] = xx;
     if (xout) xout[c * nv + i] = (T)xx;
   }
   if (!ok) set_status(status, vert_inst[i], ST_NONFINITE);
@@ -692,16 +745,17 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_init_state(int nv, const int* __restrict__ pinned,
                                                     const int* __restrict__ vert_inst,
                                                     const T* __restrict__ x0,
-                                                    const T* __restrict__ v0, T* __restrict__ xs,
-                                                    T* __restrict__ vs, int* status) {
+                                                    const T* __restrict__ v0,
+                                                    double* __restrict__ xs,
+                                                    double* __restrict__ vs, int* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    T xx = x0[c * nv + i];
-    T v = (v0 && !pinned[i]) ? v0[c * nv + i] : T(0);
-    ok = ok && isfinite((double)xx) && isfinite((double)v);
+    double xx = (double)x0[c * nv + i];
+    double v = (v0 && !pinned[i]) ? (double)v0[c * nv + i] : 0.0;
+    ok = ok && isfinite(xx) && isfinite(v);
     xs[c * nv + i] = xx;
     vs[c * nv + i] = v;
   }
@@ -756,7 +810,7 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mu[i][c] = a.mu[c * nv + v[i]];
-        vv[i][c] = (double)a.vs[c * nv + v[i]];
+        vv[i][c] = a.vs[c * nv + v[i]];
       }
     double dFm[3][2], dFv[3][2];
 #pragma unroll
@@ -840,7 +894,7 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mu[i][c] = a.mu[c * nv + v[i]];
-        vv[i][c] = (double)a.vs[c * nv + v[i]];
+        vv[i][c] = a.vs[c * nv + v[i]];
       }
     const double th = hinge_theta(X);
     hinge_grad<double>(X, g);
@@ -911,7 +965,7 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
     a.gx[r * nv + i] += ag[r];
     a.gv[r * nv + i] = pin ? 0.0 : a.u[r * nv + i] - h2 * ak[r];
     if (a.dl_dF) a.dl_dF[r * nv + i] = (T)(h * mu);
-    const double dv = pin ? 0.0 : (double)a.vs[r * nv + i] - (double)a.vp[r * nv + i];
+    const double dv = pin ? 0.0 : a.vs[r * nv + i] - a.vp[r * nv + i];
     dpart += mu * (h * varea * a.g[r] - varea * dv);
   }
   el.acc_d[i] += dpart;
@@ -983,17 +1037,16 @@ void launch_fill_double(double* p, long n, double v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_double, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
 }
 
-template <typename T>
-void launch_elements(const Mesh& m, const Elem& el, const T* x, const double* mat, int* status,
+void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* mat, int* status,
                      hipStream_t st) {
   long n = (long)m.nt + m.nh;
-  hipLaunchKernelGGL(k_elements<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, mat,
+  hipLaunchKernelGGL(k_elements, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, mat,
                      status);
 }
 
-template <typename T>
-void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_assemble<T>, dim3(blocks_for(m.nv, 128)), dim3(128), 0, st, m, el, a);
+template <typename T, typename TM>
+void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_assemble<T, TM>), dim3(blocks_for(m.nv, 128)), dim3(128), 0, st, m, el, a);
 }
 
 template <typename T>
@@ -1022,15 +1075,16 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
 }
 
 template <typename T>
-void launch_update(int nv, const int* pinned, const int* vert_inst, const T* xp, const T* vp,
-                   const double* dv, double h, T* xn, T* vn, T* xout, int* status, hipStream_t st) {
+void launch_update(int nv, const int* pinned, const int* vert_inst, const double* xp,
+                   const double* vp, const double* dv, double h, double* xn, double* vn, T* xout,
+                   int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_update<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
                      vert_inst, xp, vp, dv, h, xn, vn, xout, status);
 }
 
 template <typename T>
 void launch_init_state(int nv, const int* pinned, const int* vert_inst, const T* x0, const T* v0,
-                       T* xs, T* vs, int* status, hipStream_t st) {
+                       double* xs, double* vs, int* status, hipStream_t st) {
   hipLaunchKernelGGL(k_init_state<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
                      vert_inst, x0, v0, xs, vs, status);
 }
@@ -1063,20 +1117,24 @@ void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t
   hipLaunchKernelGGL(k_material_sum, dim3(m.ninst), dim3(256), 0, st, m, el, out);
 }
 
+#define PHISFT_INSTANTIATE_ASM(T, TM)                                                             \
+  template void launch_assemble<T, TM>(const Mesh&, const Elem&, const AssembleArgs<T, TM>&,     \
+                                       hipStream_t);
+PHISFT_INSTANTIATE_ASM(float, float)
+PHISFT_INSTANTIATE_ASM(float, double)
+PHISFT_INSTANTIATE_ASM(double, float)
+PHISFT_INSTANTIATE_ASM(double, double)
+
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template void launch_elements<T>(const Mesh&, const Elem&, const T*, const double*, int*,      \
-                                   hipStream_t);                                                 \
-  template void launch_assemble<T>(const Mesh&, const Elem&, const AssembleArgs<T>&,             \
-                                   hipStream_t);                                                 \
   template size_t pcg_lds_bytes<T>(int, int);                                                    \
   template hipError_t pcg_prepare<T>(size_t);                                                    \
   template hipError_t pcg_occupancy<T>(int, size_t, int*);                                       \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&,                 \
                               const PcgArgs<T>&, hipStream_t);                                   \
-  template void launch_update<T>(int, const int*, const int*, const T*, const T*, const double*, \
-                                 double, T*, T*, T*, int*, hipStream_t);                         \
-  template void launch_init_state<T>(int, const int*, const int*, const T*, const T*, T*, T*,    \
-                                     int*, hipStream_t);                                         \
+  template void launch_update<T>(int, const int*, const int*, const double*, const double*,      \
+                                 const double*, double, double*, double*, T*, int*, hipStream_t); \
+  template void launch_init_state<T>(int, const int*, const int*, const T*, const T*, double*,   \
+                                     double*, int*, hipStream_t);                                \
   template void launch_adj_pre<T>(int, const int*, const int*, const T*, double, double*,        \
                                   const double*, double*, int*, hipStream_t);                    \
   template void launch_adj_elements<T>(const Mesh&, const Elem&, const AdjArgs<T>&,              \

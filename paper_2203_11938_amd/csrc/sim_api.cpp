@@ -28,8 +28,10 @@ using namespace phisft;
 struct sim_s {
   HostLayout L;
   HostPlan plan_h;
-  int prec = SIM_FP32;
+  int prec = SIM_FP32;   // caller arrays
+  int mprec = SIM_FP64;  // system matrix and block-Jacobi inverse
   size_t tsize = 4;
+  size_t msize = 8;
   double h = 0.01;
   double grav[3] = {0.0, 0.0, -9.81};
   double cg_tol = 1e-7;
@@ -72,6 +74,10 @@ struct sim_s {
 
   sim_stats stats{};
   std::vector<int> inst_status;
+  // solver timing: event pairs recorded around each solver launch
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
   std::string err;
 };
 
@@ -121,7 +127,8 @@ sim_status alloc(sim_t* s, size_t bytes, void** out) {
     if (st_ != SIM_OK) return st_;  \
   } while (0)
 
-size_t state_bytes(const sim_t* s) { return 6 * (size_t)s->L.nv * s->tsize; }
+// states are FP64 in every precision mode: x [3][nv] then v [3][nv]
+size_t state_bytes(const sim_t* s) { return 6 * (size_t)s->L.nv * sizeof(double); }
 
 char* state_at(void* base, const sim_t* s, long k) {
   return static_cast<char*>(base) + (size_t)k * state_bytes(s);
@@ -155,12 +162,15 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       o.cg_max_iter < 1 || o.checkpoint_every < 0 || o.max_steps < 1 ||
       !(o.rows_per_block == 0 || o.rows_per_block == 64 || o.rows_per_block == 128 ||
         o.rows_per_block == 256) ||
-      (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION)) {
+      (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
+      (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64)) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
   s->prec = o.precision;
   s->tsize = o.precision == SIM_FP64 ? 8 : 4;
+  s->mprec = o.matrix_precision;
+  s->msize = o.matrix_precision == SIM_FP64 ? 8 : 4;
   s->h = dt;
   for (int k = 0; k < 3; ++k) s->grav[k] = o.gravity[k];
   s->cg_tol = o.cg_tol;
@@ -178,19 +188,19 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   HIPCHECK(s, hipGetDevice(&dev));
   HIPCHECK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const size_t lds_cap = 160 * 1024 - 1024;
+  // largest feasible block first: fewer workgroups meet faster at the per-iteration barrier
   std::vector<int> cands;
   if (o.rows_per_block) cands.push_back(o.rows_per_block);
-  else cands = {128, 256, 64};
+  else cands = {256, 224, 192, 160, 128, 96, 64};
   bool placed = false;
   for (int rows : cands) {
-    size_t lds = s->prec == SIM_FP64 ? pcg_lds_bytes<double>(L.maxnz, rows)
-                                     : pcg_lds_bytes<float>(L.maxnz, rows);
+    const bool m64 = s->mprec == SIM_FP64;
+    size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows) : pcg_lds_bytes<float>(L.maxnz, rows);
     if (lds > lds_cap) continue;
-    hipError_t e = s->prec == SIM_FP64 ? pcg_prepare<double>(lds) : pcg_prepare<float>(lds);
+    hipError_t e = m64 ? pcg_prepare<double>(lds) : pcg_prepare<float>(lds);
     if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
     int per_cu = 0;
-    e = s->prec == SIM_FP64 ? pcg_occupancy<double>(rows, lds, &per_cu)
-                            : pcg_occupancy<float>(rows, lds, &per_cu);
+    e = m64 ? pcg_occupancy<double>(rows, lds, &per_cu) : pcg_occupancy<float>(rows, lds, &per_cu);
     if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
     HostPlan P = make_plan(L, rows);
     if ((long)per_cu * ncu >= P.nwg) {
@@ -264,15 +274,15 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, nt * 8, &q)); el.acc_ks = (double*)q;
   TRY(alloc(s, nh * 8, &q)); el.acc_kb = (double*)q;
   TRY(alloc(s, nv * 8, &q)); el.acc_d = (double*)q;
-  TRY(alloc(s, (size_t)L.maxnz * 9 * nv * ts, &s->A));
-  TRY(alloc(s, 9 * nv * ts, &s->Jinv));
+  TRY(alloc(s, (size_t)L.maxnz * 9 * nv * s->msize, &s->A));
+  TRY(alloc(s, 9 * nv * s->msize, &s->Jinv));
   TRY(alloc(s, 3 * nv * 8, &q)); s->rhs = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->sol = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->gx = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->gv = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->sw.zbuf = (double*)q;
   TRY(alloc(s, 6 * nv * 8, &q)); s->sw.pbuf = (double*)q;
-  TRY(alloc(s, 4 * (size_t)p.nwg * 8, &q)); s->sw.red = (double*)q;
+  TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q)); s->sw.red = (double*)q;
   TRY(alloc(s, ni * 4, &q)); s->sw.barrier = (int*)q;
   TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
   TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
@@ -298,32 +308,57 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->stats.n_instances = L.ninst;
   s->stats.rows_per_block = p.rows;
   s->stats.blocks = p.nwg;
+  long nnzb = 0;
+  for (int c : L.ell_col) nnzb += c >= 0;
+  s->stats.nnz_blocks = nnzb;
   return SIM_OK;
 }
 
+// Solver launch bracketed by timing events when timing is enabled.
+template <typename TM>
+void timed_pcg(sim_t* s, const PcgArgs<TM>& c, hipStream_t st) {
+  if (s->timing) {
+    if (s->ev_used + 2 > s->ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        s->ev.push_back(e);
+      }
+    }
+    if (s->ev_used + 2 <= s->ev.size()) {
+      (void)hipEventRecord(s->ev[s->ev_used], st);
+      launch_pcg<TM>(s->mesh, s->plan, s->sw, c, st);
+      (void)hipEventRecord(s->ev[s->ev_used + 1], st);
+      s->ev_used += 2;
+      return;
+    }
+  }
+  launch_pcg<TM>(s->mesh, s->plan, s->sw, c, st);
+}
+
 // ---------------------------------------------------------- step sequences
-template <typename T>
+template <typename T, typename TM>
 void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* mat, T* xout,
                   int* iters, double* resid, hipStream_t st) {
   const int nv = s->L.nv;
-  const T* xp = reinterpret_cast<const T*>(sp);
-  const T* vp = xp + 3 * (size_t)nv;
-  T* xn = reinterpret_cast<T*>(sn);
-  T* vn = xn + 3 * (size_t)nv;
-  launch_elements<T>(s->mesh, s->el, xp, mat, s->status, st);
-  AssembleArgs<T> a{};
+  const double* xp = reinterpret_cast<const double*>(sp);
+  const double* vp = xp + 3 * (size_t)nv;
+  double* xn = reinterpret_cast<double*>(sn);
+  double* vn = xn + 3 * (size_t)nv;
+  launch_elements(s->mesh, s->el, xp, mat, s->status, st);
+  AssembleArgs<T, TM> a{};
   a.v = vp;
   a.forces = F;
   a.mat = mat;
   a.h = s->h;
   for (int k = 0; k < 3; ++k) a.g[k] = s->grav[k];
   a.want_rhs = 1;
-  a.A = static_cast<T*>(s->A);
-  a.Jinv = static_cast<T*>(s->Jinv);
+  a.A = static_cast<TM*>(s->A);
+  a.Jinv = static_cast<TM*>(s->Jinv);
   a.b = s->rhs;
   a.status = s->status;
-  launch_assemble<T>(s->mesh, s->el, a, st);
-  PcgArgs<T> c{};
+  launch_assemble<T, TM>(s->mesh, s->el, a, st);
+  PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
   c.rhs = s->rhs;
@@ -333,7 +368,7 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   c.iters = iters;
   c.resid = resid;
   c.status = s->status;
-  launch_pcg<T>(s->mesh, s->plan, s->sw, c, st);
+  timed_pcg<TM>(s, c, st);
   launch_update<T>(nv, s->mesh.pinned, s->mesh.vert_inst, xp, vp, s->sol, s->h, xn, vn, xout,
                    s->status, st);
 }
@@ -344,14 +379,14 @@ const T* force_slice(const sim_t* s, int step) {
   return static_cast<const T*>(s->forces) + (size_t)(step - 1) * 3 * s->L.nv;
 }
 
-template <typename T>
+template <typename T, typename TM>
 sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x_out,
                         hipStream_t st) {
   const int nv = s->L.nv, ni = s->L.ninst;
   char* s0 = fwd_state(s, 0, n);
   launch_init_state<T>(nv, s->mesh.pinned, s->mesh.vert_inst, static_cast<const T*>(x0),
                        static_cast<const T*>(v0),
-                       reinterpret_cast<T*>(s0), reinterpret_cast<T*>(s0) + 3 * (size_t)nv,
+                       reinterpret_cast<double*>(s0), reinterpret_cast<double*>(s0) + 3 * (size_t)nv,
                        s->status, st);
   size_t f = 0;
   for (int k = 1; k <= n; ++k) {
@@ -360,7 +395,7 @@ sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x
       xo = static_cast<T*>(x_out) + f * 3 * (size_t)nv;
       ++f;
     }
-    forward_step<T>(s, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
+    forward_step<T, TM>(s, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
                     s->material, xo, s->it_fwd + (size_t)(k - 1) * ni,
                     s->res_fwd + (size_t)(k - 1) * ni, st);
   }
@@ -369,30 +404,30 @@ sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x
   return SIM_OK;
 }
 
-template <typename T>
+template <typename T, typename TM>
 void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, T* dlF,
                   hipStream_t st) {
   const int nv = s->L.nv, ni = s->L.ninst;
-  const T* xp = reinterpret_cast<const T*>(sp);
-  const T* vp = xp + 3 * (size_t)nv;
-  const T* vs = reinterpret_cast<const T*>(sn) + 3 * (size_t)nv;
+  const double* xp = reinterpret_cast<const double*>(sp);
+  const double* vp = xp + 3 * (size_t)nv;
+  const double* vs = reinterpret_cast<const double*>(sn) + 3 * (size_t)nv;
   double* u = s->rhs;  // the adjoint right-hand side reuses the forward rhs buffer
   launch_adj_pre<T>(nv, s->mesh.pinned, s->mesh.vert_inst, dl, s->h, s->gx, s->gv, u, s->status,
                     st);
-  launch_elements<T>(s->mesh, s->el, xp, s->material, s->status, st);
-  AssembleArgs<T> a{};
+  launch_elements(s->mesh, s->el, xp, s->material, s->status, st);
+  AssembleArgs<T, TM> a{};
   a.v = vp;
   a.forces = nullptr;
   a.mat = s->material;
   a.h = s->h;
   for (int q = 0; q < 3; ++q) a.g[q] = s->grav[q];
   a.want_rhs = 0;
-  a.A = static_cast<T*>(s->A);
-  a.Jinv = static_cast<T*>(s->Jinv);
+  a.A = static_cast<TM*>(s->A);
+  a.Jinv = static_cast<TM*>(s->Jinv);
   a.b = nullptr;
   a.status = s->status;
-  launch_assemble<T>(s->mesh, s->el, a, st);
-  PcgArgs<T> c{};
+  launch_assemble<T, TM>(s->mesh, s->el, a, st);
+  PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
   c.rhs = u;
@@ -402,7 +437,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   c.iters = s->it_adj + (size_t)(k - 1) * ni;
   c.resid = s->res_adj + (size_t)(k - 1) * ni;
   c.status = s->status;
-  launch_pcg<T>(s->mesh, s->plan, s->sw, c, st);
+  timed_pcg<TM>(s, c, st);
   AdjArgs<T> j{};
   j.x = xp;
   j.vp = vp;
@@ -419,7 +454,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   launch_adj_rows<T>(s->mesh, s->el, j, st);
 }
 
-template <typename T>
+template <typename T, typename TM>
 sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF, void* dl_dx0,
                         void* dl_dv0, hipStream_t st) {
   const int nv = s->L.nv, ni = s->L.ninst, n = s->n_steps;
@@ -437,7 +472,7 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
     if (s->ckpt != 0) {
       // recompute the interior states of the segment from its checkpoint
       for (int q = c0 + 1; q < c1; ++q)
-        forward_step<T>(s, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
+        forward_step<T, TM>(s, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
                         s->material, nullptr, s->it_rec + (size_t)(q - 1) * ni,
                         s->res_rec + (size_t)(q - 1) * ni, st);
     }
@@ -448,7 +483,7 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
         --f;
       }
       T* dlF = dl_dF ? static_cast<T*>(dl_dF) + (size_t)(q - 1) * 3 * nv : nullptr;
-      adjoint_step<T>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), dlq, dlF, st);
+      adjoint_step<T, TM>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), dlq, dlF, st);
     }
   }
   launch_adj_final<T>(nv, s->gx, s->gv, static_cast<T*>(dl_dx0), static_cast<T*>(dl_dv0), st);
@@ -476,6 +511,7 @@ void sim_default_options(sim_options* o) {
   o->max_steps = 1000;
   o->rows_per_block = 0;
   o->membrane_system = SIM_MEMBRANE_EXACT;
+  o->matrix_precision = SIM_FP64;
 }
 
 sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,
@@ -548,9 +584,13 @@ sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0
   s->forces = forces;
   s->material = material ? static_cast<const double*>(material) : s->mat_default;
   s->stream = static_cast<hipStream_t>(stream);
-  sim_status st = s->prec == SIM_FP64
-                      ? rollout_impl<double>(s, n_steps, x0, v0, x_out, s->stream)
-                      : rollout_impl<float>(s, n_steps, x0, v0, x_out, s->stream);
+  sim_status st;
+  if (s->prec == SIM_FP64)
+    st = s->mprec == SIM_FP64 ? rollout_impl<double, double>(s, n_steps, x0, v0, x_out, s->stream)
+                              : rollout_impl<double, float>(s, n_steps, x0, v0, x_out, s->stream);
+  else
+    st = s->mprec == SIM_FP64 ? rollout_impl<float, double>(s, n_steps, x0, v0, x_out, s->stream)
+                              : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, s->stream);
   if (st == SIM_OK) s->have_rollout = true;
   return st;
 }
@@ -567,9 +607,17 @@ sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl
     return SIM_E_INVALID;
   }
   s->stream = static_cast<hipStream_t>(stream);
-  return s->prec == SIM_FP64
-             ? adjoint_impl<double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, s->stream)
-             : adjoint_impl<float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, s->stream);
+  if (s->prec == SIM_FP64)
+    return s->mprec == SIM_FP64
+               ? adjoint_impl<double, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
+                                              s->stream)
+               : adjoint_impl<double, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
+                                             s->stream);
+  return s->mprec == SIM_FP64
+             ? adjoint_impl<float, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
+                                           s->stream)
+             : adjoint_impl<float, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
+                                          s->stream);
 }
 
 sim_status sim_sync_status(sim_t* s) {
@@ -608,10 +656,27 @@ sim_status sim_sync_status(sim_t* s) {
     S.cg_iters_max = std::max(S.cg_iters_max, std::max(itf[q], ita[q]));
     S.max_rel_residual = std::max(S.max_rel_residual, std::max(rf[q], ra[q]));
   }
+  for (size_t q = 0; q + 1 < s->ev_used; q += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1]) == hipSuccess) {
+      S.solver_ms += ms;
+      S.solver_launches += 1;
+    }
+  }
+  s->ev_used = 0;
   sim_status st = bits_to_status(bits);
   if (bits & ST_TIMEOUT) s->err = "solver workgroups timed out at a cluster barrier";
   S.device_status = st;
   return st;
+}
+
+sim_status sim_set_timing(sim_t* s, int32_t enable) {
+  if (!s) return SIM_E_INVALID;
+  s->timing = enable != 0;
+  s->ev_used = 0;
+  s->stats.solver_ms = 0.0;
+  s->stats.solver_launches = 0;
+  return SIM_OK;
 }
 
 sim_status sim_get_instance_status(const sim_t* s, int32_t* out) {
@@ -658,6 +723,7 @@ const char* sim_last_error(const sim_t* s) { return s ? s->err.c_str() : ""; }
 void sim_destroy(sim_t* s) {
   if (!s) return;
   if (!s->allocs.empty()) (void)hipDeviceSynchronize();
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   for (void* p : s->allocs) (void)hipFree(p);
   delete s;
 }

@@ -88,9 +88,9 @@ struct SolverPlan {
 
 // Solver scratch (device).
 struct SolverWork {
-  double* zbuf;            // [3][nv]
-  double* pbuf;            // [2][3][nv]
-  double* red;             // [2][nwg][2] per-workgroup partial sums
+  double* zbuf;            // [3][nv]     preconditioned initial residual, gathered once
+  double* pbuf;            // [2][3][nv]  m = M^-1 w of even / odd iterations
+  double* red;             // [2][nwg][3] per-workgroup partial sums
   int* barrier;            // [ninst] arrival counters (zeroed before each launch)
   int* abort_flag;         // [1]
 };

@@ -57,7 +57,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double),
                 ("cg_max_iter", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
-                ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32)]
+                ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
+                ("matrix_precision", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -65,13 +66,16 @@ class _Stats(ctypes.Structure):
                 ("cg_iters_forward", ctypes.c_int64), ("cg_iters_recompute", ctypes.c_int64),
                 ("cg_iters_adjoint", ctypes.c_int64), ("cg_iters_max", ctypes.c_int32),
                 ("max_rel_residual", ctypes.c_double), ("device_status", ctypes.c_int32),
-                ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+                ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
+                ("solver_ms", ctypes.c_double)]
 
 
 _lib = None
 
 EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout", "sim_adjoint",
-           "sim_sync_status", "sim_get_stats", "sim_get_cg_iters", "sim_get_instance_status",
+           "sim_sync_status", "sim_set_timing", "sim_get_stats", "sim_get_cg_iters",
+           "sim_get_instance_status",
            "sim_status_string", "sim_last_error", "sim_destroy")
 
 
@@ -98,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "sim_rollout": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp, vp]),
         "sim_adjoint": (i32, [vp, vp, vp, vp, vp, vp, vp]),
         "sim_sync_status": (i32, [vp]),
+        "sim_set_timing": (i32, [vp, i32]),
         "sim_get_stats": (i32, [vp, ctypes.POINTER(_Stats)]),
         "sim_get_cg_iters": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "sim_get_instance_status": (i32, [vp, ctypes.POINTER(i32)]),
@@ -144,7 +149,7 @@ class Simulator:
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
                  cg_tol: float = 1e-7, cg_max_iter: int = 20000, checkpoint_every: int = 0,
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
-                 membrane: str = "exact"):
+                 membrane: str = "exact", matrix_precision: str = "fp64"):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -160,6 +165,8 @@ class Simulator:
         if membrane not in ("exact", "tension"):
             raise ValueError("membrane must be 'exact' or 'tension'")
         opt.membrane_system = SIM_MEMBRANE_TENSION if membrane == "tension" else SIM_MEMBRANE_EXACT
+        opt.matrix_precision = SIM_FP32 if matrix_precision == "fp32" else SIM_FP64
+        self.matrix_precision = matrix_precision
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         n = len(sheets)
@@ -271,6 +278,9 @@ class Simulator:
             return st
         self._check(st, "device status")
         return st
+
+    def set_timing(self, enable: bool):
+        self._check(self._lib.sim_set_timing(self._h, 1 if enable else 0), "sim_set_timing")
 
     def status(self) -> int:
         return self._lib.sim_sync_status(self._h)

@@ -9,7 +9,7 @@ separates arithmetic from bugs.
 import numpy as np
 import pytest
 
-from gpu_common import gpu_run, make_sim, note, oracle_reference, rel, targets
+from gpu_common import as_given, gpu_run, make_sim, note, oracle_reference, rel, targets
 from paper_2203_11938_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def test_c1_fp64_rollout():
 @pytest.mark.parametrize("precision,tol_x,tol_g", [("fp64", 1e-9, 1e-7), ("fp32", 1e-5, 1e-4)])
 def test_c2_parity(precision, tol_x, tol_g):
     w = W.workload("C2", precision=precision)
-    inst = W.make_instances(w)[0]
+    inst = as_given(W.make_instances(w)[0], precision)
     note(f"C2: 32x32, 100 steps, {precision}")
     tgt = targets(w)
     ref = oracle_reference(w, inst, tgt)

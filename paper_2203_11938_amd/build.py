@@ -25,12 +25,13 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def build_library(verbose: bool = False, jobs: int = 3) -> str:
-    build_dir = os.path.join(HERE, "_build")
+def build_library(verbose: bool = False, jobs: int = 3, out: str = LIB, defines=(),
+                  build_dir: str = "") -> str:
+    build_dir = build_dir or os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     cc = hipcc()
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(ROOT, 'include')}",
-              f"-I{CSRC}"]
+              f"-I{CSRC}"] + [f"-D{d}" for d in defines]
     hip_flags = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
                  "-packed-fp32-ops"]
     procs, objs = [], []
@@ -51,13 +52,13 @@ def build_library(verbose: bool = False, jobs: int = 3) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -58,10 +58,14 @@ template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
 template <typename TM>
 size_t pcg_lds_bytes(int maxnz, int rows);
+// threads of a solver block: its rows rounded up to whole 64-lane wavefronts
+inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
+// Rows may couple at most this many vertices (grid sheets: 13).
+constexpr int kMaxRowBlocks = 32;
 template <typename TM>
-hipError_t pcg_prepare(size_t lds);
+hipError_t pcg_prepare(size_t lds, int maxnz);
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int* blocks_per_cu);
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int* blocks_per_cu);
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
                 hipStream_t st);

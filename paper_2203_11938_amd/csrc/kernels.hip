@@ -482,15 +482,9 @@ __device__ __forceinline__ bool cluster_barrier(int* ctr, int nwg, int& epoch, i
   return s_ok != 0;
 }
 
-// Fixed-order sum of three values over the cluster's workgroups via the partial
-// array red[slot][wg][3]; every workgroup obtains the identical result. The
-// cluster barrier inside also publishes every store made before the call.
-__device__ __forceinline__ bool cluster_sum3(const double a[3], double* red, int slot, int nwg_all,
-                                             int wg, int iw0, int nwg, int* ctr, int& epoch,
-                                             int* abort_flag, int* status, int inst,
-                                             double out[3]) {
+// Fixed-order workgroup sum of three values; thread 0 stores them at dst.
+__device__ __forceinline__ void publish3(const double a[3], double* dst) {
   __shared__ double s_part[3][4];
-  __shared__ double s_out[3];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
   double v[3];
@@ -502,7 +496,6 @@ __device__ __forceinline__ bool cluster_sum3(const double a[3], double* red, int
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double* dst = red + ((size_t)slot * nwg_all + wg) * 3;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       double t = 0.0;
@@ -510,46 +503,104 @@ __device__ __forceinline__ bool cluster_sum3(const double a[3], double* red, int
       dst[k] = t;
     }
   }
-  bool ok = cluster_barrier(ctr, nwg, epoch, abort_flag, status, inst);
-  if (wave == 0) {
-    double t[3] = {0.0, 0.0, 0.0};
-    for (int q = lane; q < nwg; q += 64) {
-      const double* src = red + ((size_t)slot * nwg_all + iw0 + q) * 3;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        t[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) t[k] = wave_sum(t[k]);
-    if (lane == 0) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s_out[k] = t[k];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 3; ++k) out[k] = s_out[k];
-  return ok;
 }
 
-// y = A v for this thread's row: blocks from LDS, v gathered from global [3][nv].
-template <typename T>
-__device__ __forceinline__ void row_spmv(const T* __restrict__ Al, const int* __restrict__ Cl, int R,
-                                         int tid, int maxnz, int nv, const double* __restrict__ v,
-                                         double y[3]) {
-  y[0] = y[1] = y[2] = 0.0;
-  for (int k = 0; k < maxnz; ++k) {
-    const int j = Cl[k * R + tid];
-    const double v0 = v[j], v1 = v[nv + j], v2 = v[2 * nv + j];
-    const T* blk = Al + (size_t)k * 9 * R + tid;
+// After a cluster barrier: fixed-order sum of the cluster's partials (wave 0),
+// left in s_out; the caller synchronises the workgroup before reading it.
+__device__ __forceinline__ void collect3(const double* red_slot, int iw0, int nwg, double* s_out) {
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) != 0) return;
+  double t[3] = {0.0, 0.0, 0.0};
+  for (int q = lane; q < nwg; q += 64) {
+    const double* src = red_slot + (size_t)(iw0 + q) * 3;
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-      y[r] += (double)blk[(r * 3) * R] * v0 + (double)blk[(r * 3 + 1) * R] * v1 +
-              (double)blk[(r * 3 + 2) * R] * v2;
+    for (int k = 0; k < 3; ++k)
+      t[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[k] = wave_sum(t[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s_out[k] = t[k];
+  }
+}
+
+#ifndef SCHED_BARRIER
+#define SCHED_BARRIER 1
+#endif
+#ifndef GATHER_CHUNK
+#define GATHER_CHUNK 8
+#endif
+// neighbours gathered per batch of independent loads
+constexpr int kChunk = GATHER_CHUNK;
+
+// Gather kChunk of the row's neighbour values of v, starting at slot k0 ([3][nv] in
+// global memory; entries of rows owned by this workgroup from the LDS copy vl
+// [3][R] when vl is given). All loads are issued before any is used.
+__device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int tid, int k0,
+                                       int maxnz, int nv, int row0, int nrows,
+                                       const double* __restrict__ vg,
+                                       const double* __restrict__ vl, double g[3][kChunk]) {
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+    if (k0 + k < maxnz) {
+      const int j = Cl[(k0 + k) * R + tid];
+      const int lj = j - row0;
+      if (vl != nullptr && (unsigned)lj < (unsigned)nrows) {
+        g[0][k] = vl[lj];
+        g[1][k] = vl[R + lj];
+        g[2][k] = vl[2 * R + lj];
+      } else {
+        g[0][k] = vg[j];
+        g[1][k] = vg[nv + j];
+        g[2][k] = vg[2 * nv + j];
+      }
+    } else {
+      g[0][k] = g[1][k] = g[2][k] = 0.0;
+    }
+  }
+}
+
+// y += (blocks k0..k0+kChunk-1 of the row) * g. The scheduling barriers keep each
+// block's LDS loads next to their use instead of hoisting them all into registers.
+template <typename TM>
+__device__ __forceinline__ void applynb(const TM* __restrict__ Al, int R, int tid, int k0,
+                                        int maxnz, const double g[3][kChunk], double y[3]) {
+#pragma unroll
+  for (int k = 0; k < kChunk; ++k) {
+#if SCHED_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+    if (k0 + k < maxnz) {
+      const TM* blk = Al + (size_t)(k0 + k) * 9 * R + tid;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        y[r] += (double)blk[(r * 3) * R] * g[0][k] + (double)blk[(r * 3 + 1) * R] * g[1][k] +
+                (double)blk[(r * 3 + 2) * R] * g[2][k];
+    }
+  }
+}
+
+// y = A v for this thread's row, v from global memory (and LDS when vl is given).
+template <typename TM>
+__device__ __forceinline__ void spmv_row(const TM* __restrict__ Al, const int* __restrict__ Cl,
+                                         int R, int tid, int maxnz, int nv, int row0, int nrows,
+                                         const double* __restrict__ vg,
+                                         const double* __restrict__ vl, double y[3]) {
+  y[0] = y[1] = y[2] = 0.0;
+  for (int k0 = 0; k0 < maxnz; k0 += kChunk) {
+    double g[3][kChunk];
+    loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, vg, vl, g);
+    applynb<TM>(Al, R, tid, k0, maxnz, g, y);
   }
 }
 
 constexpr int kMaxRestarts = 16;
+#ifndef LOCAL_GATHER
+#define LOCAL_GATHER 1
+#endif
+// neighbours owned by the same workgroup are read from its LDS copy of m
+constexpr bool kLocalGather = LOCAL_GATHER;
 
 // Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
 // reduction per iteration, (r,u), (w,u), (r,r), whose cluster barrier also
@@ -561,47 +612,65 @@ constexpr int kMaxRestarts = 16;
 // repeated. A step denominator <= 0 also triggers a restart; at a fresh start
 // the denominator is u^T A u, so a non-positive value there is reported as an
 // indefinite system.
-template <typename T>
-__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<T> a) {
+// LDS: two copies of m [parity][3][row] (neighbours inside the workgroup are read
+// from there, the others from global memory), the workgroup's matrix rows
+// [slot][entry][row] and their columns [slot][row].
+#ifdef PHISFT_PHASES
+// per-workgroup accumulated wall-clock ticks of the solver phases (tuning builds only)
+__device__ unsigned long long g_phase[512][6];
+#define PHASE_T(v) const unsigned long long v = wall_clock64()
+#define PHASE_ADD(k, d) ph[k] += (d)
+#else
+#define PHASE_T(v)
+#define PHASE_ADD(k, d)
+#endif
+
+template <typename TM>
+__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<TM> a) {
+#ifdef PHISFT_PHASES
+  unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
+#endif
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ double s_out[3];
   const int wg = blockIdx.x;
   const int inst = plan.wg_inst[wg];
   const int row0 = plan.wg_row0[wg];
   const int nrows = plan.wg_nrows[wg];
   const int iw0 = plan.inst_wg0[inst], nwg = plan.inst_nwg[inst];
-  const int tid = threadIdx.x, R = blockDim.x;
+  // R rows per workgroup (the LDS stride); the block has R rounded up to whole
+  // wavefronts so every lane of every wave exists for the cross-lane reductions
+  const int tid = threadIdx.x, R = plan.rows;
   const int nv = m.nv, maxnz = m.maxnz;
   const bool act = tid < nrows;
   const int i = row0 + (act ? tid : 0);
   int* ctr = w.barrier + inst;
   int epoch = 0;
 
-  // matrix rows of this workgroup -> LDS ([slot][entry][row], conflict-free)
-  T* Al = reinterpret_cast<T*>(lds_raw);
-  int* Cl = reinterpret_cast<int*>(Al + (size_t)maxnz * 9 * R);
-  for (int k = 0; k < maxnz; ++k) {
-    int j = act ? m.ell_col[k * nv + i] : -1;
-    Cl[k * R + tid] = j < 0 ? i : j;
+  double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][R]
+  TM* Al = reinterpret_cast<TM*>(mL + 6 * (size_t)R);              // [maxnz][9][R]
+  int* Cl = reinterpret_cast<int*>(Al + (size_t)maxnz * 9 * R);    // [maxnz][R]
+  if (act) {
+    for (int k = 0; k < maxnz; ++k) {
+      int j = m.ell_col[k * nv + i];
+      Cl[k * R + tid] = j < 0 ? i : j;
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
-      Al[(k * 9 + q) * R + tid] = j < 0 ? T(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+      for (int q = 0; q < 9; ++q)
+        Al[(k * 9 + q) * R + tid] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+    }
   }
 
   double J[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) J[q] = act ? (double)a.Jinv[q * nv + i] : 0.0;
-  auto prec = [&](const double in[3], double out[3]) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) out[c] = J[3 * c] * in[0] + J[3 * c + 1] * in[1] + J[3 * c + 2] * in[2];
-  };
-  double x[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0}, u[3], wv[3];
+  double x[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0}, u[3], wv[3] = {0.0, 0.0, 0.0};
   double mm[3], nn[3], z[3] = {0.0, 0.0, 0.0}, q3[3] = {0.0, 0.0, 0.0};
   double sv[3] = {0.0, 0.0, 0.0}, p[3] = {0.0, 0.0, 0.0};
   if (act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i];
   }
-  prec(r, u);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
   // w_0 = A u_0 needs the neighbours' u_0
   double* ub = w.zbuf;
   if (act) {
@@ -609,55 +678,72 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
   }
   bool ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst);
-  if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, ub, wv);
-  else wv[0] = wv[1] = wv[2] = 0.0;
+  if (act) spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 
   double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
-  // Restart the recurrences from the true residual r = b - A x (x published through a
-  // slot of pbuf no workgroup reads in this phase): two cluster barriers.
-  auto restart = [&]() -> bool {
-    double* xb = w.pbuf + (size_t)((it + 1) & 1) * 3 * nv;
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) xb[c * nv + i] = x[c];
-    }
-    if (!cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst)) return false;
-    if (act) {
-      double ax[3];
-      row_spmv(Al, Cl, R, tid, maxnz, nv, xb, ax);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
-    }
-    prec(r, u);
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
-    }
-    if (!cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst)) return false;
-    if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, ub, wv);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
-    fresh = 1;
-    ++restarts;
-    return true;
-  };
+  bool restart = false;
   while (ok) {
-    double* mb = w.pbuf + (size_t)(it & 1) * 3 * nv;
-    prec(wv, mm);
+    if (restart) {
+      // Restart the recurrences from the true residual r = b - A x (x published
+      // through the pbuf slot that no workgroup reads in this phase).
+      restart = false;
+      double* xb = w.pbuf + (size_t)((it + 1) & 1) * 3 * nv;
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xb[c * nv + i] = x[c];
+      }
+      if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
+      if (act) {
+        double ax[3];
+        spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
+      }
+      if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
+      if (act) spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
+      fresh = 1;
+      ++restarts;
+    }
+    const int par = it & 1;
+    double* mb = w.pbuf + (size_t)par * 3 * nv;
+    double* ml = mL + (size_t)par * 3 * R;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) mb[c * nv + i] = mm[c];
+      for (int c = 0; c < 3; ++c) {
+        mb[c * nv + i] = mm[c];
+        ml[c * R + tid] = mm[c];
+      }
     }
     const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
-    double sums[3];
-    ok = cluster_sum3(loc, w.red, it & 1, plan.nwg, wg, iw0, nwg, ctr, epoch, w.abort_flag,
-                      a.status, inst, sums);
-    if (!ok) break;
-    const double gamma = sums[0], delta = sums[1];
-    rr = sums[2];
+    double* red_slot = w.red + (size_t)par * plan.nwg * 3;
+    PHASE_T(t0);
+    publish3(loc, red_slot + (size_t)wg * 3);
+    PHASE_T(t1);
+    if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
+    PHASE_T(t2);
+    // issue the first kChunk loads of the SpMV gather and the partial-sum loads together
+    double g[3][kChunk];
+    if (act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
+    collect3(red_slot, iw0, nwg, s_out);
+    __syncthreads();
+    const double gamma = s_out[0], delta = s_out[1];
+    rr = s_out[2];
+    __syncthreads();  // s_out is rewritten by the next collect3
+    PHASE_T(t3);
     if (it == 0) bnorm = sqrt(rr);
     if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rr)) {
       flag = ST_NONFINITE;
@@ -667,15 +753,26 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     if (sqrt(rr) <= a.tol * bnorm) {
       // accept only a true residual: right after a (re)start r = b - A x exactly
       if (fresh || restarts >= kMaxRestarts) break;
-      ok = restart();
+      restart = true;
       continue;
     }
     if (it >= a.max_iter) {
       flag = ST_NOT_CONVERGED;
       break;
     }
-    if (act) row_spmv(Al, Cl, R, tid, maxnz, nv, mb, nn);
-    else nn[0] = nn[1] = nn[2] = 0.0;
+    nn[0] = nn[1] = nn[2] = 0.0;
+    if (act) {
+      applynb<TM>(Al, R, tid, 0, maxnz, g, nn);
+      for (int k0 = kChunk; k0 < maxnz; k0 += kChunk) {
+        loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
+        applynb<TM>(Al, R, tid, k0, maxnz, g, nn);
+      }
+    }
+    PHASE_T(t4);
+    PHASE_ADD(0, t1 - t0);
+    PHASE_ADD(1, t2 - t1);
+    PHASE_ADD(2, t3 - t2);
+    PHASE_ADD(3, t4 - t3);
     const double beta = fresh ? 0.0 : gamma / gamma_prev;
     const double denom = fresh ? delta : delta - beta * gamma / alpha_prev;
     if (!(denom > 0.0)) {
@@ -685,7 +782,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
         flag = ST_INDEFINITE;
         break;
       }
-      ok = restart();
+      restart = true;
       continue;
     }
     fresh = 0;
@@ -709,6 +806,12 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.sol[c * nv + i] = x[c];
   }
+#ifdef PHISFT_PHASES
+  if (tid == 0 && wg < 512) {
+    for (int k = 0; k < 4; ++k) g_phase[wg][k] += ph[k];
+    g_phase[wg][4] += it;
+  }
+#endif
   if (wg == iw0 && tid == 0) {
     if (flag) set_status(a.status, inst, flag);
     if (a.iters) a.iters[inst] = it;
@@ -1049,29 +1152,33 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
   hipLaunchKernelGGL((k_assemble<T, TM>), dim3(blocks_for(m.nv, 128)), dim3(128), 0, st, m, el, a);
 }
 
-template <typename T>
+template <typename TM>
 size_t pcg_lds_bytes(int maxnz, int rows) {
-  return (size_t)maxnz * rows * (9 * sizeof(T) + sizeof(int));
+  return (size_t)maxnz * rows * (9 * sizeof(TM) + sizeof(int)) + 6 * sizeof(double) * rows;
 }
 
-template <typename T>
-hipError_t pcg_prepare(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pcg<T>),
+template <typename TM>
+hipError_t pcg_prepare(size_t lds, int maxnz) {
+  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pcg<TM>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename T>
-hipError_t pcg_occupancy(int rows, size_t lds, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<T>, rows, lds);
+template <typename TM>
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int* blocks_per_cu) {
+  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM>,
+                                                      pcg_threads(rows), lds);
 }
 
-template <typename T>
-void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<T>& a,
+template <typename TM>
+void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
                 hipStream_t st) {
-  size_t lds = pcg_lds_bytes<T>(m.maxnz, plan.rows);
+  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows);
   launch_fill_int(w.barrier, m.ninst, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
-  hipLaunchKernelGGL(k_pcg<T>, dim3(plan.nwg), dim3(plan.rows), lds, st, m, plan, w, a);
+  hipLaunchKernelGGL(k_pcg<TM>, dim3(plan.nwg), dim3(pcg_threads(plan.rows)), lds, st, m, plan, w,
+                     a);
 }
 
 template <typename T>
@@ -1127,8 +1234,8 @@ PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
   template size_t pcg_lds_bytes<T>(int, int);                                                    \
-  template hipError_t pcg_prepare<T>(size_t);                                                    \
-  template hipError_t pcg_occupancy<T>(int, size_t, int*);                                       \
+  template hipError_t pcg_prepare<T>(size_t, int);                                               \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, int*);                                  \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&,                 \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_update<T>(int, const int*, const int*, const double*, const double*,      \
@@ -1146,3 +1253,15 @@ PHISFT_INSTANTIATE(float)
 PHISFT_INSTANTIATE(double)
 
 }  // namespace phisft
+
+#ifdef PHISFT_PHASES
+extern "C" int phisft_read_phases(unsigned long long* out, int reset) {
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(phisft::g_phase), sizeof(phisft::g_phase)) != hipSuccess)
+    return -1;
+  if (reset) {
+    static unsigned long long zero[512][6];
+    if (hipMemcpyToSymbol(HIP_SYMBOL(phisft::g_phase), zero, sizeof(zero)) != hipSuccess) return -1;
+  }
+  return 0;
+}
+#endif

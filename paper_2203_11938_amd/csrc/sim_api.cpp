@@ -182,6 +182,10 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   if (rc != 0) return rc == -1 ? SIM_E_INVALID : SIM_E_MESH;
   if (!check_layout(s->L, s->err)) return SIM_E_MESH;
   HostLayout& L = s->L;
+  if (L.maxnz > kMaxRowBlocks) {
+    s->err = "a vertex couples to more than 32 vertices (valence too high for the solver)";
+    return SIM_E_MESH;
+  }
 
   // solver launch shape: rows per workgroup bounded by the LDS budget and co-residency
   int dev = 0, ncu = 0;
@@ -191,16 +195,17 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   // largest feasible block first: fewer workgroups meet faster at the per-iteration barrier
   std::vector<int> cands;
   if (o.rows_per_block) cands.push_back(o.rows_per_block);
-  else cands = {256, 224, 192, 160, 128, 96, 64};
+  else cands = {256, 224, 192, 160, 152, 128, 96, 64};
   bool placed = false;
   for (int rows : cands) {
     const bool m64 = s->mprec == SIM_FP64;
     size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows) : pcg_lds_bytes<float>(L.maxnz, rows);
     if (lds > lds_cap) continue;
-    hipError_t e = m64 ? pcg_prepare<double>(lds) : pcg_prepare<float>(lds);
+    hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz) : pcg_prepare<float>(lds, L.maxnz);
     if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
     int per_cu = 0;
-    e = m64 ? pcg_occupancy<double>(rows, lds, &per_cu) : pcg_occupancy<float>(rows, lds, &per_cu);
+    e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, &per_cu)
+            : pcg_occupancy<float>(rows, lds, L.maxnz, &per_cu);
     if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
     HostPlan P = make_plan(L, rows);
     if ((long)per_cu * ncu >= P.nwg) {

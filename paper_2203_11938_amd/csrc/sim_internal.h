@@ -78,7 +78,7 @@ struct Elem {
 // Persistent solver launch description.
 struct SolverPlan {
   int nwg;                 // workgroups of the launch
-  int rows;                // rows per workgroup (= block size)
+  int rows;                // rows per workgroup (LDS stride; block = rows rounded up to 64)
   const int* wg_inst;      // [nwg]
   const int* wg_row0;      // [nwg]
   const int* wg_nrows;     // [nwg]

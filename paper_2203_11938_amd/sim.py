@@ -20,7 +20,8 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libphisft_sim.so")
+# PHISFT_SIM_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PHISFT_SIM_LIB") or os.path.join(HERE, "libphisft_sim.so")
 
 SIM_OK = 0
 SIM_E_INVALID = -1

@@ -133,6 +133,8 @@ typedef struct {
   int32_t device_status;      /* sticky device status (sim_status value) */
   int32_t rows_per_block;     /* solver launch shape in use */
   int32_t blocks;             /* solver workgroups per launch */
+  int32_t solver_lds_matrix;  /* 1: matrix rows held in LDS, 0: streamed from memory */
+  int32_t solver_launches_per_solve; /* batches split into sets of co-resident sheets */
   int64_t nnz_blocks;         /* non-zero 3x3 blocks of the system matrix */
   int64_t solver_launches;    /* timed solver launches since timing was enabled */
   double solver_ms;           /* their summed duration (HIP events on the call's stream) */

@@ -66,6 +66,7 @@ def _load():
         "orc_hinge_theta_grad": (None, [D, D]),
         "orc_system": (c_int, [P, D, D, D, D, D]),
         "orc_solve_step": (c_int, [P, D, D, D, D, I]),
+        "orc_step_residual": (c_int, [P, D, D, D, D, D, D]),
         "orc_step": (c_int, [P, D, D, D, D, D, D, I]),
         "orc_rollout": (c_int, [P, c_int, D, D, D, I, c_int, D, D, I]),
         "orc_gradient": (c_int, [P, c_int, D, D, D, I, c_int, D, D, D, D, D, I, I]),
@@ -255,6 +256,18 @@ class Oracle:
         it = ctypes.c_int(0)
         st = _load().orc_solve_step(self._h, _d(x), _d(v), _d(F), _d(dv), ctypes.byref(it))
         return dv, it.value, st
+
+    def step_residual(self, x, v, F, dv):
+        """r = b - A dv of the step from (x, v) (Eq. 4-5), and ||b||. Returns (r, ||b||, status)."""
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        F = _f64(F, (self.nv, 3)) if F is not None else None
+        dv = _f64(dv, (self.nv, 3))
+        r = np.zeros((self.nv, 3))
+        bn = ctypes.c_double(0.0)
+        st = _load().orc_step_residual(self._h, _d(x), _d(v), _d(F), _d(dv), _d(r),
+                                       ctypes.byref(bn))
+        return r, bn.value, st
 
     def step(self, x, v, F=None):
         """One step S_t = PS(S_{t-1}; phi_{t-1}) (Eq. 1, 4, 5). Returns (x, v, dv, iters, status)."""

@@ -901,6 +901,30 @@ int orc_solve_step(void* h, const double* x, const double* v, const double* F, d
   return pcg(*P, A, b.data(), dv, iters);
 }
 
+// Residual r = b - A dv of one step's system (Eq. 4-5) for a given increment dv,
+// and ||b||: how well dv solves the step, without forming a dense matrix.
+int orc_step_residual(void* h, const double* x, const double* v, const double* F,
+                      const double* dv, double* r, double* bnorm) {
+  Problem* P = static_cast<Problem*>(h);
+  int n = 3 * P->nv;
+  std::vector<double> vm(v, v + n);
+  for (int i = 0; i < P->nv; ++i)
+    if (P->pinned[i])
+      for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
+  std::vector<double> K, A, b(n), Adv(n);
+  assemble_ksys(*P, x, K);
+  system_matrix(*P, K, A);
+  step_rhs(*P, x, vm.data(), F, K, b.data());
+  csr_apply(*P, A, dv, Adv.data());
+  double bn = 0.0;
+  for (int k = 0; k < n; ++k) {
+    r[k] = b[k] - Adv[k];
+    bn += b[k] * b[k];
+  }
+  *bnorm = std::sqrt(bn);
+  return all_finite(r, n) ? ORC_OK : ORC_E_NONFINITE;
+}
+
 // One full step from (x, v) with force slice F (may be NULL).
 int orc_step(void* h, const double* x, const double* v, const double* F, double* xo, double* vo,
              double* dvo, int* iters) {

@@ -57,15 +57,15 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows);
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix);
 // threads of a solver block: its rows rounded up to whole 64-lane wavefronts
 inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 // Rows may couple at most this many vertices (grid sheets: 13).
 constexpr int kMaxRowBlocks = 32;
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz);
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix);
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int* blocks_per_cu);
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, int* blocks_per_cu);
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
                 hipStream_t st);

@@ -453,30 +453,79 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
 }
 
 // ------------------------------------------------------- persistent PCG
-// Cluster barrier of the workgroups of one sheet: monotone arrival counter,
-// bounded wait (every wave reaches the exit even if a peer never arrives).
 constexpr int kSpinLimit = 1 << 25;
+// Cluster barrier of the workgroups of one sheet. Counters live in 128-byte slots
+// of w.barrier: slot inst is the sheet's root counter; a sheet with more than
+// kBarrierGroup workgroups also has per-group arrival counters and release flags
+// (slots from plan.inst_grp0). Arrival is counted per group; the last arriver of a
+// group adds the group to the root, waits for all groups, then releases its group.
+// Every wait is bounded: a timeout sets the abort flag, which ends all waits.
+struct Barrier {
+  int* root;
+  int* gctr;   // nullptr: flat barrier
+  int* gflag;
+  int ngroups;
+  int gsize;   // members of this workgroup's group (flat: workgroups of the sheet)
+  int epoch;
+};
 
-__device__ __forceinline__ bool cluster_barrier(int* ctr, int nwg, int& epoch, int* abort_flag,
-                                                int* status, int inst) {
+__device__ __forceinline__ bool bounded_wait_ge(int* addr, int target, int* abort_flag) {
+  int spins = 0;
+  while (__hip_atomic_load(addr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit ||
+        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ Barrier make_barrier(const SolverPlan& plan, const SolverWork& w, int inst,
+                                                int wg, int iw0, int nwg) {
+  Barrier b;
+  b.root = w.barrier + (size_t)inst * kBarrierSlot;
+  b.epoch = 0;
+  if (nwg <= kBarrierGroup) {
+    b.gctr = b.gflag = nullptr;
+    b.ngroups = 1;
+    b.gsize = nwg;
+  } else {
+    const int gi = (wg - iw0) / kBarrierGroup;
+    b.ngroups = (nwg + kBarrierGroup - 1) / kBarrierGroup;
+    b.gsize = min(kBarrierGroup, nwg - gi * kBarrierGroup);
+    const int slot = plan.inst_grp0[inst] + 2 * gi;
+    b.gctr = w.barrier + (size_t)slot * kBarrierSlot;
+    b.gflag = w.barrier + (size_t)(slot + 1) * kBarrierSlot;
+  }
+  return b;
+}
+
+__device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int* status,
+                                                int inst) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    epoch += 1;
-    const int target = epoch * nwg;
-    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    int ok = 1, spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit ||
-          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        ok = 0;
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        set_status(status, inst, ST_TIMEOUT);
-        break;
+    b.epoch += 1;
+    const int e = b.epoch;
+    bool ok;
+    if (b.gctr == nullptr) {
+      __hip_atomic_fetch_add(b.root, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      ok = bounded_wait_ge(b.root, e * b.gsize, abort_flag);
+    } else {
+      const int old = __hip_atomic_fetch_add(b.gctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == e * b.gsize - 1) {  // last arriver of the group
+        __hip_atomic_fetch_add(b.root, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        ok = bounded_wait_ge(b.root, e * b.ngroups, abort_flag);
+        __hip_atomic_store(b.gflag, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        ok = bounded_wait_ge(b.gflag, e, abort_flag);
       }
     }
-    s_ok = ok;
+    if (!ok) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      set_status(status, inst, ST_TIMEOUT);
+    }
+    s_ok = ok ? 1 : 0;
   }
   __syncthreads();
   return s_ok != 0;
@@ -563,8 +612,10 @@ __device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int ti
 
 // y += (blocks k0..k0+kChunk-1 of the row) * g. The scheduling barriers keep each
 // block's LDS loads next to their use instead of hoisting them all into registers.
+// The matrix is read at A[((k * 9 + e) * stride) + idx]: the LDS copy (stride R,
+// idx = thread) or the assembled ELL array in global memory (stride nv, idx = row).
 template <typename TM>
-__device__ __forceinline__ void applynb(const TM* __restrict__ Al, int R, int tid, int k0,
+__device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, int idx, int k0,
                                         int maxnz, const double g[3][kChunk], double y[3]) {
 #pragma unroll
   for (int k = 0; k < kChunk; ++k) {
@@ -572,26 +623,28 @@ __device__ __forceinline__ void applynb(const TM* __restrict__ Al, int R, int ti
     __builtin_amdgcn_sched_barrier(0);
 #endif
     if (k0 + k < maxnz) {
-      const TM* blk = Al + (size_t)(k0 + k) * 9 * R + tid;
+      const TM* blk = Am + (size_t)(k0 + k) * 9 * stride + idx;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        y[r] += (double)blk[(r * 3) * R] * g[0][k] + (double)blk[(r * 3 + 1) * R] * g[1][k] +
-                (double)blk[(r * 3 + 2) * R] * g[2][k];
+        y[r] += (double)blk[(size_t)(r * 3) * stride] * g[0][k] +
+                (double)blk[(size_t)(r * 3 + 1) * stride] * g[1][k] +
+                (double)blk[(size_t)(r * 3 + 2) * stride] * g[2][k];
     }
   }
 }
 
 // y = A v for this thread's row, v from global memory (and LDS when vl is given).
 template <typename TM>
-__device__ __forceinline__ void spmv_row(const TM* __restrict__ Al, const int* __restrict__ Cl,
-                                         int R, int tid, int maxnz, int nv, int row0, int nrows,
+__device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
+                                         const int* __restrict__ Cl, int R, int tid, int maxnz,
+                                         int nv, int row0, int nrows,
                                          const double* __restrict__ vg,
                                          const double* __restrict__ vl, double y[3]) {
   y[0] = y[1] = y[2] = 0.0;
   for (int k0 = 0; k0 < maxnz; k0 += kChunk) {
     double g[3][kChunk];
     loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, vg, vl, g);
-    applynb<TM>(Al, R, tid, k0, maxnz, g, y);
+    applynb<TM>(Am, stride, idx, k0, maxnz, g, y);
   }
 }
 
@@ -613,8 +666,9 @@ constexpr bool kLocalGather = LOCAL_GATHER;
 // the denominator is u^T A u, so a non-positive value there is reported as an
 // indefinite system.
 // LDS: two copies of m [parity][3][row] (neighbours inside the workgroup are read
-// from there, the others from global memory), the workgroup's matrix rows
-// [slot][entry][row] and their columns [slot][row].
+// from there, the others from global memory), the rows' block columns
+// [slot][row] and, when LDS_MATRIX, the workgroup's matrix rows [slot][entry][row]
+// (otherwise the assembled matrix is streamed from global memory each SpMV).
 #ifdef PHISFT_PHASES
 // per-workgroup accumulated wall-clock ticks of the solver phases (tuning builds only)
 __device__ unsigned long long g_phase[512][6];
@@ -625,14 +679,14 @@ __device__ unsigned long long g_phase[512][6];
 #define PHASE_ADD(k, d)
 #endif
 
-template <typename TM>
+template <typename TM, bool LDS_MATRIX>
 __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<TM> a) {
 #ifdef PHISFT_PHASES
   unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
 #endif
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double s_out[3];
-  const int wg = blockIdx.x;
+  const int wg = plan.wg_base + blockIdx.x;
   const int inst = plan.wg_inst[wg];
   const int row0 = plan.wg_row0[wg];
   const int nrows = plan.wg_nrows[wg];
@@ -643,19 +697,24 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   const int nv = m.nv, maxnz = m.maxnz;
   const bool act = tid < nrows;
   const int i = row0 + (act ? tid : 0);
-  int* ctr = w.barrier + inst;
-  int epoch = 0;
+  Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
 
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][R]
-  TM* Al = reinterpret_cast<TM*>(mL + 6 * (size_t)R);              // [maxnz][9][R]
-  int* Cl = reinterpret_cast<int*>(Al + (size_t)maxnz * 9 * R);    // [maxnz][R]
+  int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)R);            // [maxnz][R]
+  TM* Al = reinterpret_cast<TM*>(Cl + (size_t)maxnz * R);          // [maxnz][9][R] (LDS mode)
+  // matrix operand: LDS copy, or the assembled ELL array read in place
+  const TM* Am = LDS_MATRIX ? Al : a.A;
+  const int As = LDS_MATRIX ? R : nv;
+  const int Ai = LDS_MATRIX ? tid : i;
   if (act) {
     for (int k = 0; k < maxnz; ++k) {
       int j = m.ell_col[k * nv + i];
       Cl[k * R + tid] = j < 0 ? i : j;
+      if (LDS_MATRIX) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q)
-        Al[(k * 9 + q) * R + tid] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+        for (int q = 0; q < 9; ++q)
+          Al[(k * 9 + q) * R + tid] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+      }
     }
   }
 
@@ -677,8 +736,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
     for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
   }
-  bool ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst);
-  if (act) spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+  bool ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
+  if (act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 
   double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
@@ -693,10 +752,10 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
         for (int c = 0; c < 3; ++c) xb[c * nv + i] = x[c];
       }
-      if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
+      if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       if (act) {
         double ax[3];
-        spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
+        spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -707,8 +766,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
         for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
       }
-      if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
-      if (act) spmv_row<TM>(Al, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+      if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      if (act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -733,7 +792,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     PHASE_T(t0);
     publish3(loc, red_slot + (size_t)wg * 3);
     PHASE_T(t1);
-    if (!(ok = cluster_barrier(ctr, nwg, epoch, w.abort_flag, a.status, inst))) break;
+    if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
     // issue the first kChunk loads of the SpMV gather and the partial-sum loads together
     double g[3][kChunk];
@@ -762,10 +821,10 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     }
     nn[0] = nn[1] = nn[2] = 0.0;
     if (act) {
-      applynb<TM>(Al, R, tid, 0, maxnz, g, nn);
+      applynb<TM>(Am, As, Ai, 0, maxnz, g, nn);
       for (int k0 = kChunk; k0 < maxnz; k0 += kChunk) {
         loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
-        applynb<TM>(Al, R, tid, k0, maxnz, g, nn);
+        applynb<TM>(Am, As, Ai, k0, maxnz, g, nn);
       }
     }
     PHASE_T(t4);
@@ -1153,32 +1212,52 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
 }
 
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows) {
-  return (size_t)maxnz * rows * (9 * sizeof(TM) + sizeof(int)) + 6 * sizeof(double) * rows;
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix) {
+  return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
+         6 * sizeof(double) * rows;
 }
 
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz) {
-  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pcg<TM>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static const void* pcg_entry(bool lds_matrix) {
+  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true>)
+                    : reinterpret_cast<const void*>(&k_pcg<TM, false>);
 }
 
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int* blocks_per_cu) {
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix) {
   if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM>,
+  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <typename TM>
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, int* blocks_per_cu) {
+  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
+  if (lds_matrix)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true>,
+                                                        pcg_threads(rows), lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false>,
                                                       pcg_threads(rows), lds);
 }
 
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
                 hipStream_t st) {
-  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows);
-  launch_fill_int(w.barrier, m.ninst, 0, st);
+  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0);
+  launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
-  hipLaunchKernelGGL(k_pcg<TM>, dim3(plan.nwg), dim3(pcg_threads(plan.rows)), lds, st, m, plan, w,
-                     a);
+  // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
+  for (int g = 0; g < plan.ngroups; ++g) {
+    SolverPlan pg = plan;
+    pg.wg_base = plan.group_wg0_host[g];
+    const int n = plan.group_wg0_host[g + 1] - pg.wg_base;
+    if (plan.lds_matrix)
+      hipLaunchKernelGGL((k_pcg<TM, true>), dim3(n), dim3(pcg_threads(plan.rows)), lds, st, m, pg,
+                         w, a);
+    else
+      hipLaunchKernelGGL((k_pcg<TM, false>), dim3(n), dim3(pcg_threads(plan.rows)), lds, st, m,
+                         pg, w, a);
+  }
 }
 
 template <typename T>
@@ -1233,9 +1312,9 @@ PHISFT_INSTANTIATE_ASM(double, float)
 PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template size_t pcg_lds_bytes<T>(int, int);                                                    \
-  template hipError_t pcg_prepare<T>(size_t, int);                                               \
-  template hipError_t pcg_occupancy<T>(int, size_t, int, int*);                                  \
+  template size_t pcg_lds_bytes<T>(int, int, bool);                                              \
+  template hipError_t pcg_prepare<T>(size_t, int, bool);                                         \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, int*);                            \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&,                 \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_update<T>(int, const int*, const int*, const double*, const double*,      \

@@ -312,14 +312,17 @@ bool check_layout(const HostLayout& L, std::string& err) {
   return true;
 }
 
-HostPlan make_plan(const HostLayout& L, int rows) {
+HostPlan make_plan(const HostLayout& L, int rows, int group) {
   HostPlan P;
   P.rows = rows;
+  int slot = L.ninst;  // root counters first
   for (int b = 0; b < L.ninst; ++b) {
     int n = L.inst_nv[b];
     int k = (n + rows - 1) / rows;
     P.inst_wg0.push_back(P.nwg);
     P.inst_nwg.push_back(k);
+    P.inst_grp0.push_back(slot);
+    if (k > group) slot += 2 * ((k + group - 1) / group);
     for (int w = 0; w < k; ++w) {
       P.wg_inst.push_back(b);
       P.wg_row0.push_back(L.inst_voff[b] + w * rows);
@@ -327,7 +330,24 @@ HostPlan make_plan(const HostLayout& L, int rows) {
     }
     P.nwg += k;
   }
+  P.barrier_slots = slot;
   return P;
+}
+
+bool group_plan(HostPlan& P, int capacity, int max_groups) {
+  P.group_wg0.assign(1, 0);
+  int used = 0;
+  for (size_t b = 0; b < P.inst_nwg.size(); ++b) {
+    const int k = P.inst_nwg[b];
+    if (k > capacity) return false;
+    if (used + k > capacity) {
+      P.group_wg0.push_back(P.inst_wg0[b]);
+      used = 0;
+    }
+    used += k;
+  }
+  P.group_wg0.push_back(P.nwg);
+  return (int)P.group_wg0.size() - 1 <= max_groups;
 }
 
 }  // namespace phisft

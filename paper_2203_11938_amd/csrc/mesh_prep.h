@@ -31,9 +31,15 @@ struct HostLayout {
 };
 
 struct HostPlan {
-  int rows = 0, nwg = 0;
-  std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg;
+  int rows = 0, nwg = 0, lds_matrix = 1;
+  int barrier_slots = 0;   // root slots + group counter/flag slots
+  std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
+  std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets
 };
+
+// Splits the sheets (in order) into solver launches of at most `capacity`
+// co-resident workgroups; false if one sheet alone exceeds it.
+bool group_plan(HostPlan& P, int capacity, int max_groups);
 
 // Returns 0 on success, -1 (invalid argument) or -2 (mesh error) with a message.
 int build_layout(const std::vector<HostSheet>& sheets, HostLayout& out, std::string& err);
@@ -41,6 +47,6 @@ int build_layout(const std::vector<HostSheet>& sheets, HostLayout& out, std::str
 // Checks every index table against its bounds (run before any upload).
 bool check_layout(const HostLayout& L, std::string& err);
 
-HostPlan make_plan(const HostLayout& L, int rows);
+HostPlan make_plan(const HostLayout& L, int rows, int group);
 
 }  // namespace phisft

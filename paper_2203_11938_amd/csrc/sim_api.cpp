@@ -192,30 +192,39 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   HIPCHECK(s, hipGetDevice(&dev));
   HIPCHECK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const size_t lds_cap = 160 * 1024 - 1024;
-  // largest feasible block first: fewer workgroups meet faster at the per-iteration barrier
+  // Largest feasible block first (fewer workgroups meet faster at the per-iteration
+  // barrier); matrix rows in LDS when they fit, else streamed from global memory.
+  // A plan needing fewer solver launches wins; then LDS-resident rows; then larger blocks.
   std::vector<int> cands;
   if (o.rows_per_block) cands.push_back(o.rows_per_block);
   else cands = {256, 224, 192, 160, 152, 128, 96, 64};
   bool placed = false;
-  for (int rows : cands) {
-    const bool m64 = s->mprec == SIM_FP64;
-    size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows) : pcg_lds_bytes<float>(L.maxnz, rows);
-    if (lds > lds_cap) continue;
-    hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz) : pcg_prepare<float>(lds, L.maxnz);
-    if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
-    int per_cu = 0;
-    e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, &per_cu)
-            : pcg_occupancy<float>(rows, lds, L.maxnz, &per_cu);
-    if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
-    HostPlan P = make_plan(L, rows);
-    if ((long)per_cu * ncu >= P.nwg) {
-      s->plan_h = P;
-      placed = true;
-      break;
+  int best_groups = 1 << 30;
+  for (int mode = 1; mode >= 0; --mode) {
+    for (int rows : cands) {
+      const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
+      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm)
+                       : pcg_lds_bytes<float>(L.maxnz, rows, lm);
+      if (lds > lds_cap) continue;
+      hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm) : pcg_prepare<float>(lds, L.maxnz, lm);
+      if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
+      int per_cu = 0;
+      e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, &per_cu)
+              : pcg_occupancy<float>(rows, lds, L.maxnz, lm, &per_cu);
+      if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
+      HostPlan P = make_plan(L, rows, kBarrierGroup);
+      P.lds_matrix = mode;
+      if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
+      const int ng = (int)P.group_wg0.size() - 1;
+      if (ng < best_groups) {
+        s->plan_h = P;
+        best_groups = ng;
+        placed = true;
+      }
     }
   }
   if (!placed) {
-    s->err = "mesh too large for the co-resident solver (rows per block / LDS)";
+    s->err = "mesh too large for the co-resident solver";
     return SIM_E_INVALID;
   }
 
@@ -257,6 +266,11 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   SolverPlan& p = s->plan;
   p.nwg = s->plan_h.nwg;
   p.rows = s->plan_h.rows;
+  p.lds_matrix = s->plan_h.lds_matrix;
+  p.wg_base = 0;
+  p.ngroups = (int)s->plan_h.group_wg0.size() - 1;
+  for (int g = 0; g <= p.ngroups; ++g) p.group_wg0_host[g] = s->plan_h.group_wg0[g];
+  TRY(upload(s, s->plan_h.inst_grp0, &p.inst_grp0));
   TRY(upload(s, s->plan_h.wg_inst, &p.wg_inst));
   TRY(upload(s, s->plan_h.wg_row0, &p.wg_row0));
   TRY(upload(s, s->plan_h.wg_nrows, &p.wg_nrows));
@@ -288,7 +302,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, 3 * nv * 8, &q)); s->sw.zbuf = (double*)q;
   TRY(alloc(s, 6 * nv * 8, &q)); s->sw.pbuf = (double*)q;
   TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q)); s->sw.red = (double*)q;
-  TRY(alloc(s, ni * 4, &q)); s->sw.barrier = (int*)q;
+  s->sw.barrier_ints = s->plan_h.barrier_slots * kBarrierSlot;
+  TRY(alloc(s, (size_t)s->sw.barrier_ints * 4, &q)); s->sw.barrier = (int*)q;
   TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
   TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
   const size_t st = (size_t)s->max_steps * ni;
@@ -313,6 +328,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->stats.n_instances = L.ninst;
   s->stats.rows_per_block = p.rows;
   s->stats.blocks = p.nwg;
+  s->stats.solver_lds_matrix = p.lds_matrix;
+  s->stats.solver_launches_per_solve = p.ngroups;
   long nnzb = 0;
   for (int c : L.ell_col) nnzb += c >= 0;
   s->stats.nnz_blocks = nnzb;

@@ -75,15 +75,27 @@ struct Elem {
   double* acc_d;    // [nv]
 };
 
+// Cluster-barrier layout: counters 128 bytes apart; sheets with more than
+// kBarrierGroup workgroups arrive in groups of that size.
+constexpr int kBarrierSlot = 32;   // ints per counter slot
+constexpr int kBarrierGroup = 16;
+
+constexpr int kMaxSolverGroups = 64;
+
 // Persistent solver launch description.
 struct SolverPlan {
-  int nwg;                 // workgroups of the launch
+  int nwg;                 // workgroups over all solver groups
+  int wg_base;             // first workgroup of the current launch
+  int ngroups;             // launches per solve: sets of whole sheets that fit co-resident
+  int group_wg0_host[kMaxSolverGroups + 1];  // workgroup ranges of the groups
+  int lds_matrix;          // 1: matrix rows copied to LDS; 0: streamed from global memory
   int rows;                // rows per workgroup (LDS stride; block = rows rounded up to 64)
   const int* wg_inst;      // [nwg]
   const int* wg_row0;      // [nwg]
   const int* wg_nrows;     // [nwg]
   const int* inst_wg0;     // [ninst]
   const int* inst_nwg;     // [ninst]
+  const int* inst_grp0;    // [ninst] first group slot (counter, flag pairs) of the sheet
 };
 
 // Solver scratch (device).
@@ -91,7 +103,8 @@ struct SolverWork {
   double* zbuf;            // [3][nv]     preconditioned initial residual, gathered once
   double* pbuf;            // [2][3][nv]  m = M^-1 w of even / odd iterations
   double* red;             // [2][nwg][3] per-workgroup partial sums
-  int* barrier;            // [ninst] arrival counters (zeroed before each launch)
+  int* barrier;            // counter slots: [ninst] roots, then group counter/flag pairs
+  int barrier_ints;        // ints to zero before each launch
   int* abort_flag;         // [1]
 };
 

@@ -68,6 +68,7 @@ class _Stats(ctypes.Structure):
                 ("cg_iters_adjoint", ctypes.c_int64), ("cg_iters_max", ctypes.c_int32),
                 ("max_rel_residual", ctypes.c_double), ("device_status", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("solver_lds_matrix", ctypes.c_int32), ("solver_launches_per_solve", ctypes.c_int32),
                 ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
                 ("solver_ms", ctypes.c_double)]
 

@@ -30,6 +30,16 @@ def test_pcg_matches_library_solve(oracle_mod):
     assert np.linalg.norm(dv.ravel() - ref) <= 1e-10 * np.linalg.norm(ref)
     # pinned rows are Dirichlet: zero increment
     assert np.abs(dv[inst.pins]).max() == 0.0
+    # the sparse step residual: b - A dv for the library's solution is at rounding
+    # level, for zero it is b, and it is affine in dv with slope -A
+    r, bn, st = o.step_residual(x, vf, F, ref.reshape(-1, 3))
+    assert st == 0 and abs(bn - np.linalg.norm(b)) <= 1e-14 * bn
+    assert np.linalg.norm(r) <= 1e-12 * bn
+    r0, _, _ = o.step_residual(x, vf, F, np.zeros_like(x))
+    assert np.array_equal(r0.ravel(), b)
+    d = np.random.default_rng(2).normal(size=x.shape)
+    r1, _, _ = o.step_residual(x, vf, F, d)
+    assert np.allclose(r1.ravel(), b - A @ d.ravel(), rtol=0, atol=1e-12 * np.abs(A @ d.ravel()).max())
 
 
 @pytest.mark.parametrize("n,steps", [(3, 30), (9, 20)])

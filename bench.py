@@ -36,7 +36,7 @@ def solver_source_hash() -> str:
 def measured_traffic(workload: str):
     """Per-launch HBM bytes of the solver from the committed rocprofv3 counter
     summary, or None if absent or taken on a different kernel source."""
-    p = os.path.join(ROOT, "profiles", f"k_pcg_{workload}_counters.json")
+    p = os.path.join(ROOT, "profiles", f"k_pcg_{workload}_counters.txt")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -69,8 +69,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed gradients")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="H")
-    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--cpu-sample-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run three plain device copies of MIB MiB (untimed), the "
+                         "known-size reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the simulator has no "
@@ -84,6 +87,16 @@ def main():
     w = W.workload(args.workload)
     insts = W.make_instances(w)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copies of {args.calibrate_copy} MiB done", file=sys.stderr,
+              flush=True)
+        del a, b
     print(f"bench: workload {w.name}, {len(insts)} sheet(s), {w.steps} steps", file=sys.stderr,
           flush=True)
     sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
@@ -142,10 +155,11 @@ def main():
                 cg_iters_per_launch=round(iters / max(launches, 1), 1),
                 solver_share_of_wall=round(st["solver_ms"] / (wall * 1e3), 3))
 
-    out = dict(metric="vertex-steps/s forward+adjoint (ms per gradient, 100-step 64x64 sheet)",
+    out = dict(metric="vertex-steps/s forward+adjoint (ms per gradient, 100-step 64\u00d764 "
+                      "sheet); % HBM peak",
                value=round(value, 1), unit="vertex-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+               scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                config=dict(workload=f"{w.name}: {w.n}x{w.n} sheet, {w.steps} steps of "
                            f"{w.dt} s, rollout + adjoint", vertices=V, sim_steps=w.steps,
                            cg_tol=w.cg_tol, cg_iters_per_gradient=iters // args.steps,

@@ -118,6 +118,13 @@ typedef struct {
                                block-Jacobi inverse (default SIM_FP64; SIM_FP32 halves
                                the solver's operand but bounds the solution's relative
                                accuracy near cond(A) * 6e-8)                            */
+  int32_t coarse_size;      /* vertices per aggregate of the solver's coarse space
+                               (default 64; 0 = block-Jacobi preconditioner only).
+                               The preconditioner adds P A_c^-1 P^T, where P holds the
+                               six rigid motions of every aggregate of nearby vertices
+                               and A_c = P^T A P is factored per step; a sheet with
+                               more than 128 aggregates uses larger ones. The solution
+                               still meets cg_tol on the true residual.                 */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -138,11 +145,13 @@ typedef struct {
   int64_t nnz_blocks;         /* non-zero 3x3 blocks of the system matrix */
   int64_t solver_launches;    /* timed solver launches since timing was enabled */
   double solver_ms;           /* their summed duration (HIP events on the call's stream) */
+  int32_t coarse_aggregates;  /* aggregates of the coarse space over all sheets (0: none) */
+  int32_t coarse_max_dim;     /* largest per-sheet coarse dimension (6 x aggregates) */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,
  * store every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
- * exact membrane Hessian, FP64 system matrix. */
+ * exact membrane Hessian, FP64 system matrix, aggregates of 64 vertices. */
 void sim_default_options(sim_options* opt);
 
 /* Creates a handle for one sheet.

@@ -57,34 +57,43 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix);
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc);
 // threads of a solver block: its rows rounded up to whole 64-lane wavefronts
 inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 // Rows may couple at most this many vertices (grid sheets: 13).
 constexpr int kMaxRowBlocks = 32;
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix);
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse);
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, int* blocks_per_cu);
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse,
+                         int* blocks_per_cu);
 template <typename TM>
-void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
-                hipStream_t st);
+void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
+                const PcgArgs<TM>& a, hipStream_t st);
+// Coarse operator of the step at positions x and assembled matrix A: frames,
+// Galerkin product, Cholesky factorisation and inverse (no-op without a coarse space).
+template <typename TM>
+void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
+                         long long coarse_doubles, hipStream_t st);
+// Sets the LDS size of the inverse kernel; fails when max_nc is too large.
+hipError_t coarse_prepare(int max_nc);
+// Caller-layout arrays (x0, v0, x_out, dL/dx) are indexed through m.vold.
 template <typename T>
-void launch_update(int nv, const int* pinned, const int* vert_inst, const double* xp,
-                   const double* vp, const double* dv, double h, double* xn, double* vn, T* xout,
-                   int* status, hipStream_t st);
+void launch_update(const Mesh& m, const double* xp, const double* vp, const double* dv, double h,
+                   double* xn, double* vn, T* xout, int* status, hipStream_t st);
 template <typename T>
-void launch_init_state(int nv, const int* pinned, const int* vert_inst, const T* x0, const T* v0,
-                       double* xs, double* vs, int* status, hipStream_t st);
+void launch_init_state(const Mesh& m, const T* x0, const T* v0, double* xs, double* vs,
+                       int* status, hipStream_t st);
 template <typename T>
-void launch_adj_pre(int nv, const int* pinned, const int* vert_inst, const T* dl, double h,
-                    double* gx, const double* gv, double* u, int* status, hipStream_t st);
+void launch_adj_pre(const Mesh& m, const T* dl, double h, double* gx, const double* gv, double* u,
+                    int* status, hipStream_t st);
 template <typename T>
 void launch_adj_elements(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st);
 template <typename T>
 void launch_adj_rows(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st);
 template <typename T>
-void launch_adj_final(int nv, const double* gx, const double* gv, T* dx0, T* dv0, hipStream_t st);
+void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0, T* dv0,
+                      hipStream_t st);
 void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st);
 
 }  // namespace phisft

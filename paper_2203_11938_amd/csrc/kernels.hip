@@ -445,11 +445,293 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   double b[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    double fe = a.forces ? (double)a.forces[r * nv + i] : 0.0;
+    double fe = a.forces ? (double)a.forces[r * nv + m.vold[i]] : 0.0;
     b[r] = pin_i ? 0.0 : h * (f[r] + mass * a.g[r] + fe - h * kv[r]);
     a.b[r * nv + i] = b[r];
   }
   if (!finite3(b)) set_status(a.status, inst, ST_NONFINITE);
+}
+
+// ------------------------------------------------- coarse space (once per step)
+// Two-level additive preconditioner M^-1 = B^-1 + P A_c^-1 P^T. Per step: the
+// aggregate frames at x_{t-1}, the Galerkin product A_c = P^T A P (dense per
+// sheet), its Cholesky factorisation and its inverse. The PCG applies A_c^-1 as a
+// dense product with the rows of the inverse that its workgroup needs.
+
+// One wavefront per aggregate: centroid of the free vertices at x and the offsets
+// x_i - c of its members (zero on pinned members and where rotations are unused).
+__global__ void __launch_bounds__(64) k_coarse_frame(Mesh m, Coarse c, const double* __restrict__ x) {
+  const int a = blockIdx.x, lane = threadIdx.x, nv = m.nv;
+  const int v0 = c.agg_v0[a], v1 = c.agg_v0[a + 1];
+  double s[3] = {0.0, 0.0, 0.0}, cnt = 0.0;
+  for (int i = v0 + lane; i < v1; i += 64) {
+    if (m.pinned[i]) continue;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[k] += x[k * nv + i];
+    cnt += 1.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = wave_sum(s[k]);
+  cnt = wave_sum(cnt);
+  const bool rot = c.agg_modes[a] == 6;
+  for (int i = v0 + lane; i < v1; i += 64) {
+    const bool use = rot && !m.pinned[i];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c.crel[k * nv + i] = use ? x[k * nv + i] - s[k] / cnt : 0.0;
+  }
+}
+
+// [r]x, the matrix of v -> r x v (row-major)
+__device__ __forceinline__ void skew(const double r[3], double R[9]) {
+  R[0] = 0.0;   R[1] = -r[2]; R[2] = r[1];
+  R[3] = r[2];  R[4] = 0.0;   R[5] = -r[0];
+  R[6] = -r[1]; R[7] = r[0];  R[8] = 0.0;
+}
+
+__device__ __forceinline__ void mul33(const double* A, const double* B, double* C) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) C[r * 3 + q] = A[r * 3] * B[q] + A[r * 3 + 1] * B[3 + q] + A[r * 3 + 2] * B[6 + q];
+}
+
+// One wavefront per aggregate pair (a <= b): the 6x6 block sum over its matrix
+// slots of P_i^T A_ij P_j with P_i = [I | -[r_i]x], i.e.
+//   [[A, -A R_j], [R_i A, -R_i A R_j]];
+// written at (a, b) and, transposed, at (b, a). Unused modes give zero rows and
+// columns (their unit diagonal is set by k_coarse_dead).
+template <typename TM>
+__global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const TM* __restrict__ A) {
+  const int p = blockIdx.x, lane = threadIdx.x, nv = m.nv;
+  const int a = c.pair_a[p], b = c.pair_b[p];
+  double acc[36];
+#pragma unroll
+  for (int e = 0; e < 36; ++e) acc[e] = 0.0;
+  for (int t = c.pair_ptr[p] + lane; t < c.pair_ptr[p + 1]; t += 64) {
+    const int s = c.pair_slot[t];
+    const int k = s / nv, i = s - k * nv, j = m.ell_col[s];
+    double Ab[9], Ri[9], Rj[9], AR[9], RA[9], RAR[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Ab[q] = (double)A[(size_t)(k * 9 + q) * nv + i];
+    const double ri[3] = {c.crel[i], c.crel[nv + i], c.crel[2 * nv + i]};
+    const double rj[3] = {c.crel[j], c.crel[nv + j], c.crel[2 * nv + j]};
+    skew(ri, Ri);
+    skew(rj, Rj);
+    mul33(Ab, Rj, AR);
+    mul33(Ri, Ab, RA);
+    mul33(RA, Rj, RAR);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        acc[r * 6 + q] += Ab[r * 3 + q];
+        acc[r * 6 + 3 + q] -= AR[r * 3 + q];
+        acc[(3 + r) * 6 + q] += RA[r * 3 + q];
+        acc[(3 + r) * 6 + 3 + q] -= RAR[r * 3 + q];
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < 36; ++e) acc[e] = wave_sum(acc[e]);
+  const int inst = c.agg_inst[a];
+  const int nc = c.inst_nc[inst];
+  double* M = c.mat + c.inst_coff[inst];
+  const int la = a - c.inst_agg0[inst], lb = b - c.inst_agg0[inst];
+  const int ma = c.agg_modes[a], mb = c.agg_modes[b];
+#pragma unroll
+  for (int e = 0; e < 36; ++e) {
+    if (lane == e) {
+      const int r = e / 6, q = e % 6;
+      const double val = (r < ma && q < mb) ? acc[e] : 0.0;
+      M[(size_t)(6 * la + r) * nc + 6 * lb + q] = val;
+      if (a != b) M[(size_t)(6 * lb + q) * nc + 6 * la + r] = val;
+    }
+  }
+}
+
+// Unit diagonal for the unused modes of every aggregate.
+__global__ void __launch_bounds__(256) k_coarse_dead(Coarse c) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= c.nagg) return;
+  const int inst = c.agg_inst[a], nc = c.inst_nc[inst], la = a - c.inst_agg0[inst];
+  double* M = c.mat + c.inst_coff[inst];
+  for (int q = c.agg_modes[a]; q < 6; ++q) M[(size_t)(6 * la + q) * nc + 6 * la + q] = 1.0;
+}
+
+// One workgroup per sheet: right-looking Cholesky A_c = L L^T in 32x32 tiles (each
+// tile factored or updated in LDS), in place; L^T is mirrored into the upper
+// triangle for the row-wise reads of the inverse. A non-positive or non-finite
+// pivot leaves ok = 0 (the coarse correction is then skipped for the step).
+__global__ void __launch_bounds__(256) k_coarse_factor(Coarse c) {
+  constexpr int T = kCoarseTile;
+  __shared__ double D[T][T + 1];
+  __shared__ double P1[T][T + 1];
+  __shared__ double P2[T][T + 1];
+  __shared__ int s_fail;
+  const int inst = blockIdx.x, tid = threadIdx.x;
+  const int n = c.inst_nc[inst];
+  if (n == 0) return;
+  double* M = c.mat + c.inst_coff[inst];
+  const int nt = (n + T - 1) / T;
+  if (tid == 0) s_fail = 0;
+  for (int K = 0; K < nt; ++K) {
+    const int k0 = K * T, kb = min(T, n - k0);
+    __syncthreads();
+    for (int e = tid; e < T * T; e += blockDim.x) {
+      const int r = e / T, q = e % T;
+      D[r][q] = (r < kb && q < kb) ? M[(size_t)(k0 + r) * n + k0 + q] : 0.0;
+    }
+    __syncthreads();
+    // diagonal tile
+    for (int j = 0; j < kb; ++j) {
+      if (tid == 0) {
+        const double d = D[j][j];
+        if (!(d > 0.0) || !isfinite(d)) s_fail = 1;
+        D[j][j] = d > 0.0 ? sqrt(d) : 1.0;
+      }
+      __syncthreads();
+      if (s_fail) break;
+      if (tid > j && tid < kb) D[tid][j] /= D[j][j];
+      __syncthreads();
+      for (int e = tid; e < T * T; e += blockDim.x) {
+        const int r = e / T, q = e % T;
+        if (q > j && q <= r && r < kb) D[r][q] -= D[r][j] * D[q][j];
+      }
+      __syncthreads();
+    }
+    if (s_fail) break;
+    for (int e = tid; e < T * T; e += blockDim.x) {
+      const int r = e / T, q = e % T;
+      if (r < kb && q <= r) {
+        M[(size_t)(k0 + r) * n + k0 + q] = D[r][q];
+        M[(size_t)(k0 + q) * n + k0 + r] = D[r][q];
+      }
+    }
+    // panel: L_IK = A_IK L_KK^-T. First Li = L_KK^-1 (lower; one column per thread,
+    // down the column), then every panel row is a product with Li^T.
+    for (int e = tid; e < T * T; e += blockDim.x) P1[e / T][e % T] = 0.0;
+    __syncthreads();
+    if (tid < kb) {
+      const int cc = tid;
+      P1[cc][cc] = 1.0 / D[cc][cc];
+      for (int r = cc + 1; r < kb; ++r) {
+        double acc = 0.0;
+        for (int q = cc; q < r; ++q) acc += D[r][q] * P1[q][cc];
+        P1[r][cc] = -acc / D[r][r];
+      }
+    }
+    __syncthreads();
+    for (int i = k0 + kb + tid; i < n; i += blockDim.x) {
+      double av[T];
+#pragma unroll
+      for (int q = 0; q < T; ++q) av[q] = q < kb ? M[(size_t)i * n + k0 + q] : 0.0;
+      for (int q = 0; q < kb; ++q) {
+        double y = 0.0;
+#pragma unroll
+        for (int p = 0; p < T; ++p) y += av[p] * P1[q][p];
+        M[(size_t)i * n + k0 + q] = y;
+        M[(size_t)(k0 + q) * n + i] = y;
+      }
+    }
+    __syncthreads();
+    // trailing update of the lower tiles: A_IJ -= L_IK L_JK^T, K < J <= I
+    for (int I = K + 1; I < nt; ++I) {
+      const int i0 = I * T, ib = min(T, n - i0);
+      for (int e = tid; e < T * T; e += blockDim.x) {
+        const int r = e / T, q = e % T;
+        P1[r][q] = (r < ib && q < kb) ? M[(size_t)(i0 + r) * n + k0 + q] : 0.0;
+      }
+      for (int J = K + 1; J <= I; ++J) {
+        const int j0 = J * T, jb = min(T, n - j0);
+        __syncthreads();
+        for (int e = tid; e < T * T; e += blockDim.x) {
+          const int r = e / T, q = e % T;
+          P2[r][q] = (r < jb && q < kb) ? M[(size_t)(j0 + r) * n + k0 + q] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < T * T; e += blockDim.x) {
+          const int r = e / T, q = e % T;
+          if (r < ib && q < jb && (I != J || q <= r)) {
+            double acc = 0.0;
+#pragma unroll 8
+            for (int p = 0; p < T; ++p) acc += P1[r][p] * P2[q][p];
+            M[(size_t)(i0 + r) * n + j0 + q] -= acc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) c.ok[inst] = s_fail ? 0 : 1;
+}
+
+// Columns col0 .. col0+15 of A_c^-1 = L^-T L^-1 (one workgroup per task): blocked
+// forward and back substitution over 32-row tiles with the right-hand sides in
+// LDS [n][16]; the small triangular solves run in one wavefront, one column per
+// lane. Written as rows of the (symmetric) inverse.
+__global__ void __launch_bounds__(256) k_coarse_inverse(Coarse c) {
+  constexpr int T = kCoarseTile, NC = kInvCols;
+  extern __shared__ __align__(16) unsigned char inv_lds[];
+  double* Y = reinterpret_cast<double*>(inv_lds);
+  const int task = blockIdx.x, tid = threadIdx.x;
+  const int inst = c.inv_inst[task], col0 = c.inv_col0[task];
+  if (!c.ok[inst]) return;
+  const int n = c.inst_nc[inst];
+  const double* M = c.mat + c.inst_coff[inst];
+  double* X = c.inv + c.inst_coff[inst];
+  const int ncol = min(NC, n - col0);
+  const int nt = (n + T - 1) / T;
+  for (int e = tid; e < n * NC; e += blockDim.x) {
+    const int r = e / NC, q = e % NC;
+    Y[e] = (q < ncol && r == col0 + q) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // forward: L Y = E
+  for (int I = 0; I < nt; ++I) {
+    const int i0 = I * T, ib = min(T, n - i0);
+    for (int e = tid; e < ib * NC; e += blockDim.x) {
+      const int r = e / NC, q = e % NC;
+      const double* Lr = M + (size_t)(i0 + r) * n;
+      double acc = Y[(i0 + r) * NC + q];
+      for (int k = 0; k < i0; ++k) acc -= Lr[k] * Y[k * NC + q];
+      Y[(i0 + r) * NC + q] = acc;
+    }
+    __syncthreads();
+    if (tid < NC) {
+      for (int r = 0; r < ib; ++r) {
+        const double* Lr = M + (size_t)(i0 + r) * n + i0;
+        double v = Y[(i0 + r) * NC + tid];
+        for (int k = 0; k < r; ++k) v -= Lr[k] * Y[(i0 + k) * NC + tid];
+        Y[(i0 + r) * NC + tid] = v / Lr[r];
+      }
+    }
+    __syncthreads();
+  }
+  // back: L^T X = Y (L^T rows are the mirrored upper triangle)
+  for (int I = nt - 1; I >= 0; --I) {
+    const int i0 = I * T, ib = min(T, n - i0);
+    for (int e = tid; e < ib * NC; e += blockDim.x) {
+      const int r = e / NC, q = e % NC;
+      const double* Ur = M + (size_t)(i0 + r) * n;
+      double acc = Y[(i0 + r) * NC + q];
+      for (int k = i0 + ib; k < n; ++k) acc -= Ur[k] * Y[k * NC + q];
+      Y[(i0 + r) * NC + q] = acc;
+    }
+    __syncthreads();
+    if (tid < NC) {
+      for (int r = ib - 1; r >= 0; --r) {
+        const double* Ur = M + (size_t)(i0 + r) * n + i0;
+        double v = Y[(i0 + r) * NC + tid];
+        for (int k = r + 1; k < ib; ++k) v -= Ur[k] * Y[(i0 + k) * NC + tid];
+        Y[(i0 + r) * NC + tid] = v / Ur[r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < ncol * n; e += blockDim.x) {
+    const int q = e / n, r = e % n;
+    X[(size_t)(col0 + q) * n + r] = Y[r * NC + q];
+  }
 }
 
 // ------------------------------------------------------- persistent PCG
@@ -679,8 +961,85 @@ __device__ unsigned long long g_phase[512][6];
 #define PHASE_ADD(k, d)
 #endif
 
-template <typename TM, bool LDS_MATRIX>
-__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, PcgArgs<TM> a) {
+// Coarse restriction of this thread's row vector y: per-aggregate sums of
+// (y, r_i x y) = P_i^T y over the workgroup's rows, published as
+// part[wg][k][0..5] (k: aggregate minus the workgroup's first aggregate). Fixed
+// order: a butterfly per wavefront, then the wavefronts in order.
+__device__ __forceinline__ void coarse_restrict(const Coarse& c, int wg, int row0,
+                                                int nrows, int wa0, int wna, int kloc, bool live,
+                                                const double r[3], const double y[3]) {
+  __shared__ double s_wp[4][kMaxWgAgg][6];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  for (int e = tid; e < 4 * kMaxWgAgg * 6; e += blockDim.x) (&s_wp[0][0][0])[e] = 0.0;
+  double v[6];
+  v[0] = y[0];
+  v[1] = y[1];
+  v[2] = y[2];
+  v[3] = r[1] * y[2] - r[2] * y[1];
+  v[4] = r[2] * y[0] - r[0] * y[2];
+  v[5] = r[0] * y[1] - r[1] * y[0];
+  __syncthreads();
+  const int f = wave * 64;
+  if (f < nrows) {
+    const int l = min(nrows, f + 64) - 1;
+    const int kf = c.vert_agg[row0 + f] - wa0, kl = c.vert_agg[row0 + l] - wa0;
+    for (int k = kf; k <= kl; ++k) {
+      const bool mine = live && kloc == k;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double t = wave_sum(mine ? v[q] : 0.0);
+        if (lane == 0) s_wp[wave][k][q] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < wna * 6; e += blockDim.x) {
+    const int k = e / 6, q = e - k * 6;
+    double t = 0.0;
+    for (int w = 0; w < nwaves; ++w) t += s_wp[w][k][q];
+    c.part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
+  }
+}
+
+// After the cluster barrier that publishes the partial sums: the sheet's coarse
+// residual w_c (LDS), e = rows of A_c^-1 w_c for this workgroup's aggregates (LDS),
+// and y += P_i e on this thread's row. Skipped when the step's factorisation failed.
+__device__ __forceinline__ void coarse_correct(const Coarse& c, int inst, int wa0, int wna, int kloc,
+                                               bool live, const double r[3], double y[3],
+                                               double* s_wc, double* s_e) {
+  if (!c.ok[inst]) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int nc = c.inst_nc[inst], ag0 = c.inst_agg0[inst];
+  for (int e = tid; e < nc; e += blockDim.x) {
+    const int t = e / 6, q = e - t * 6, a = ag0 + t;
+    const int w0 = c.agg_wg0[a], w1 = w0 + c.agg_nwg[a];
+    double sum = 0.0;
+    for (int w = w0; w < w1; ++w) sum += c.part[((size_t)w * kMaxWgAgg + (a - c.wg_agg0[w])) * 6 + q];
+    s_wc[e] = sum;
+  }
+  __syncthreads();
+  const double* inv = c.inv + c.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * nc;
+  for (int row = wave; row < 6 * wna; row += nwaves) {
+    const double* ir = inv + (size_t)row * nc;
+    double acc = 0.0;
+    for (int col = lane; col < nc; col += 64) acc += ir[col] * s_wc[col];
+    acc = wave_sum(acc);
+    if (lane == 0) s_e[row] = acc;
+  }
+  __syncthreads();
+  if (live) {
+    const double* e = s_e + 6 * kloc;
+    y[0] += e[0] + (e[4] * r[2] - e[5] * r[1]);
+    y[1] += e[1] + (e[5] * r[0] - e[3] * r[2]);
+    y[2] += e[2] + (e[3] * r[1] - e[4] * r[0]);
+  }
+}
+
+template <typename TM, bool LDS_MATRIX, bool COARSE>
+__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
+                                             PcgArgs<TM> a) {
 #ifdef PHISFT_PHASES
   unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
 #endif
@@ -702,6 +1061,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][R]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)R);            // [maxnz][R]
   TM* Al = reinterpret_cast<TM*>(Cl + (size_t)maxnz * R);          // [maxnz][9][R] (LDS mode)
+  double* s_wc = reinterpret_cast<double*>(Al + (LDS_MATRIX ? (size_t)maxnz * 9 * R : 0));
+  double* s_e = s_wc + cs.max_nc;                                  // [kMaxWgAgg][6]
   // matrix operand: LDS copy, or the assembled ELL array read in place
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
@@ -717,6 +1078,20 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       }
     }
   }
+  // coarse-space data of this row
+  int wa0 = 0, wna = 0, kloc = 0;
+  bool live = false;
+  double cr[3] = {0.0, 0.0, 0.0};
+  if (COARSE) {
+    wa0 = cs.wg_agg0[wg];
+    wna = cs.wg_nagg[wg];
+    if (act) {
+      kloc = cs.vert_agg[i] - wa0;
+      live = m.pinned[i] == 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cr[c] = cs.crel[c * nv + i];
+    }
+  }
 
   double J[9];
 #pragma unroll
@@ -730,14 +1105,20 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
+  bool ok = true;
+  if (COARSE) {
+    coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, r);
+    ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
+    if (ok) coarse_correct(cs, inst, wa0, wna, kloc, live, cr, u, s_wc, s_e);
+  }
   // w_0 = A u_0 needs the neighbours' u_0
   double* ub = w.zbuf;
   if (act) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
   }
-  bool ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
-  if (act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+  if (ok) ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
+  if (ok && act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 
   double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
@@ -762,6 +1143,11 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
+      if (COARSE) {
+        coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, r);
+        if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+        coarse_correct(cs, inst, wa0, wna, kloc, live, cr, u, s_wc, s_e);
+      }
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
@@ -778,13 +1164,14 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     double* ml = mL + (size_t)par * 3 * R;
 #pragma unroll
     for (int c = 0; c < 3; ++c) mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
-    if (act) {
+    if (!COARSE && act) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mb[c * nv + i] = mm[c];
         ml[c * R + tid] = mm[c];
       }
     }
+    if (COARSE) coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, wv);
     const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
@@ -796,7 +1183,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     PHASE_T(t2);
     // issue the first kChunk loads of the SpMV gather and the partial-sum loads together
     double g[3][kChunk];
-    if (act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
+    if (!COARSE && act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
     collect3(red_slot, iw0, nwg, s_out);
     __syncthreads();
     const double gamma = s_out[0], delta = s_out[1];
@@ -818,6 +1205,19 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     if (it >= a.max_iter) {
       flag = ST_NOT_CONVERGED;
       break;
+    }
+    if (COARSE) {
+      // m = M^-1 w needs the coarse correction before it is published for the SpMV
+      coarse_correct(cs, inst, wa0, wna, kloc, live, cr, mm, s_wc, s_e);
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          mb[c * nv + i] = mm[c];
+          ml[c * R + tid] = mm[c];
+        }
+      }
+      if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      if (act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
     }
     nn[0] = nn[1] = nn[2] = 0.0;
     if (act) {
@@ -882,6 +1282,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 template <typename T>
 __global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ pinned,
                                                 const int* __restrict__ vert_inst,
+                                                const int* __restrict__ vold,
                                                 const double* __restrict__ xp,
                                                 const double* __restrict__ vp,
                                                 const double* __restrict__ dv, double h,
@@ -898,7 +1299,7 @@ __global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ 
     ok = ok && isfinite(xx) && isfinite(v);
     vn[c * nv + i] = v;
     xn[c * nv + i] = xx;
-    if (xout) xout[c * nv + i] = (T)xx;
+    if (xout) xout[c * nv + vold[i]] = (T)xx;
   }
   if (!ok) set_status(status, vert_inst[i], ST_NONFINITE);
 }
@@ -906,17 +1307,19 @@ __global__ void __launch_bounds__(256) k_update(int nv, const int* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) k_init_state(int nv, const int* __restrict__ pinned,
                                                     const int* __restrict__ vert_inst,
+                                                    const int* __restrict__ vold,
                                                     const T* __restrict__ x0,
                                                     const T* __restrict__ v0,
                                                     double* __restrict__ xs,
                                                     double* __restrict__ vs, int* status) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
+  const int o = vold[i];
   bool ok = true;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double xx = (double)x0[c * nv + i];
-    double v = (v0 && !pinned[i]) ? (double)v0[c * nv + i] : 0.0;
+    double xx = (double)x0[c * nv + o];
+    double v = (v0 && !pinned[i]) ? (double)v0[c * nv + o] : 0.0;
     ok = ok && isfinite(xx) && isfinite(v);
     xs[c * nv + i] = xx;
     vs[c * nv + i] = v;
@@ -929,6 +1332,7 @@ __global__ void __launch_bounds__(256) k_init_state(int nv, const int* __restric
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_pre(int nv, const int* __restrict__ pinned,
                                                  const int* __restrict__ vert_inst,
+                                                 const int* __restrict__ vold,
                                                  const T* __restrict__ dl, double h,
                                                  double* __restrict__ gx,
                                                  const double* __restrict__ gv,
@@ -940,7 +1344,7 @@ __global__ void __launch_bounds__(256) k_adj_pre(int nv, const int* __restrict__
   for (int c = 0; c < 3; ++c) {
     double g = gx[c * nv + i];
     if (dl) {
-      double d = (double)dl[c * nv + i];
+      double d = (double)dl[c * nv + vold[i]];
       ok = ok && isfinite(d);
       g += d;
       gx[c * nv + i] = g;
@@ -1126,7 +1530,7 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
     const double mu = a.mu[r * nv + i];
     a.gx[r * nv + i] += ag[r];
     a.gv[r * nv + i] = pin ? 0.0 : a.u[r * nv + i] - h2 * ak[r];
-    if (a.dl_dF) a.dl_dF[r * nv + i] = (T)(h * mu);
+    if (a.dl_dF) a.dl_dF[r * nv + m.vold[i]] = (T)(h * mu);
     const double dv = pin ? 0.0 : a.vs[r * nv + i] - a.vp[r * nv + i];
     dpart += mu * (h * varea * a.g[r] - varea * dv);
   }
@@ -1134,13 +1538,16 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_final(int nv, const double* __restrict__ gx,
+__global__ void __launch_bounds__(256) k_adj_final(int nv, const int* __restrict__ vold,
+                                                   const double* __restrict__ gx,
                                                    const double* __restrict__ gv,
                                                    T* __restrict__ dx0, T* __restrict__ dv0) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 3 * nv) return;
-  if (dx0) dx0[k] = (T)gx[k];
-  if (dv0) dv0[k] = (T)gv[k];
+  const int c = k / nv, i = k - c * nv;
+  const int o = c * nv + vold[i];
+  if (dx0) dx0[o] = (T)gx[k];
+  if (dv0) dv0[o] = (T)gv[k];
 }
 
 // One workgroup per sheet: fixed-order sums of the per-element partials.
@@ -1212,74 +1619,106 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
 }
 
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix) {
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc) {
   return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
-         6 * sizeof(double) * rows;
+         6 * sizeof(double) * rows +
+         (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 6 * kMaxWgAgg) : 0);
 }
 
 template <typename TM>
-static const void* pcg_entry(bool lds_matrix) {
-  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true>)
-                    : reinterpret_cast<const void*>(&k_pcg<TM, false>);
+static const void* pcg_entry(bool lds_matrix, bool coarse) {
+  if (coarse)
+    return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, true>)
+                      : reinterpret_cast<const void*>(&k_pcg<TM, false, true>);
+  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, false>)
+                    : reinterpret_cast<const void*>(&k_pcg<TM, false, false>);
 }
 
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix) {
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse) {
   if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix, coarse),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, int* blocks_per_cu) {
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse,
+                         int* blocks_per_cu) {
   if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  if (lds_matrix)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true>,
-                                                        pcg_threads(rows), lds);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false>,
-                                                      pcg_threads(rows), lds);
+  const int nt = pcg_threads(rows);
+  if (coarse)
+    return lds_matrix ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true, true>, nt, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false, true>, nt, lds);
+  return lds_matrix ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true, false>, nt, lds)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false, false>, nt, lds);
 }
 
 template <typename TM>
-void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const PcgArgs<TM>& a,
-                hipStream_t st) {
-  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0);
+void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
+                const PcgArgs<TM>& a, hipStream_t st) {
+  const bool coarse = cs.nagg > 0;
+  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0);
   launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
   for (int g = 0; g < plan.ngroups; ++g) {
     SolverPlan pg = plan;
     pg.wg_base = plan.group_wg0_host[g];
-    const int n = plan.group_wg0_host[g + 1] - pg.wg_base;
-    if (plan.lds_matrix)
-      hipLaunchKernelGGL((k_pcg<TM, true>), dim3(n), dim3(pcg_threads(plan.rows)), lds, st, m, pg,
-                         w, a);
-    else
-      hipLaunchKernelGGL((k_pcg<TM, false>), dim3(n), dim3(pcg_threads(plan.rows)), lds, st, m,
-                         pg, w, a);
+    const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base), block(pcg_threads(plan.rows));
+    if (coarse) {
+      if (plan.lds_matrix)
+        hipLaunchKernelGGL((k_pcg<TM, true, true>), grid, block, lds, st, m, pg, w, cs, a);
+      else
+        hipLaunchKernelGGL((k_pcg<TM, false, true>), grid, block, lds, st, m, pg, w, cs, a);
+    } else {
+      if (plan.lds_matrix)
+        hipLaunchKernelGGL((k_pcg<TM, true, false>), grid, block, lds, st, m, pg, w, cs, a);
+      else
+        hipLaunchKernelGGL((k_pcg<TM, false, false>), grid, block, lds, st, m, pg, w, cs, a);
+    }
   }
 }
 
-template <typename T>
-void launch_update(int nv, const int* pinned, const int* vert_inst, const double* xp,
-                   const double* vp, const double* dv, double h, double* xn, double* vn, T* xout,
-                   int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_update<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
-                     vert_inst, xp, vp, dv, h, xn, vn, xout, status);
+hipError_t coarse_prepare(int max_nc) {
+  const size_t lds = (size_t)std::max(max_nc, 1) * kInvCols * sizeof(double);
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_inverse),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename TM>
+void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
+                         long long coarse_doubles, hipStream_t st) {
+  if (c.nagg == 0) return;
+  hipLaunchKernelGGL(k_coarse_frame, dim3(c.nagg), dim3(64), 0, st, m, c, x);
+  launch_fill_double(c.mat, coarse_doubles, 0.0, st);
+  if (c.npair > 0)
+    hipLaunchKernelGGL((k_coarse_assemble<TM>), dim3(c.npair), dim3(64), 0, st, m, c, A);
+  hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg, 256)), dim3(256), 0, st, c);
+  hipLaunchKernelGGL(k_coarse_factor, dim3(m.ninst), dim3(256), 0, st, c);
+  const size_t lds = (size_t)c.max_nc * kInvCols * sizeof(double);
+  if (c.ninv > 0) hipLaunchKernelGGL(k_coarse_inverse, dim3(c.ninv), dim3(256), lds, st, c);
 }
 
 template <typename T>
-void launch_init_state(int nv, const int* pinned, const int* vert_inst, const T* x0, const T* v0,
-                       double* xs, double* vs, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_state<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
-                     vert_inst, x0, v0, xs, vs, status);
+void launch_update(const Mesh& m, const double* xp, const double* vp, const double* dv, double h,
+                   double* xn, double* vn, T* xout, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_update<T>, dim3(blocks_for(m.nv, 256)), dim3(256), 0, st, m.nv, m.pinned,
+                     m.vert_inst, m.vold, xp, vp, dv, h, xn, vn, xout, status);
 }
 
 template <typename T>
-void launch_adj_pre(int nv, const int* pinned, const int* vert_inst, const T* dl, double h,
-                    double* gx, const double* gv, double* u, int* status, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_pre<T>, dim3(blocks_for(nv, 256)), dim3(256), 0, st, nv, pinned,
-                     vert_inst, dl, h, gx, gv, u, status);
+void launch_init_state(const Mesh& m, const T* x0, const T* v0, double* xs, double* vs,
+                       int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_state<T>, dim3(blocks_for(m.nv, 256)), dim3(256), 0, st, m.nv,
+                     m.pinned, m.vert_inst, m.vold, x0, v0, xs, vs, status);
+}
+
+template <typename T>
+void launch_adj_pre(const Mesh& m, const T* dl, double h, double* gx, const double* gv, double* u,
+                    int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_pre<T>, dim3(blocks_for(m.nv, 256)), dim3(256), 0, st, m.nv, m.pinned,
+                     m.vert_inst, m.vold, dl, h, gx, gv, u, status);
 }
 
 template <typename T>
@@ -1294,9 +1733,10 @@ void launch_adj_rows(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStre
 }
 
 template <typename T>
-void launch_adj_final(int nv, const double* gx, const double* gv, T* dx0, T* dv0, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_final<T>, dim3(blocks_for(3L * nv, 256)), dim3(256), 0, st, nv, gx, gv,
-                     dx0, dv0);
+void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0, T* dv0,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_final<T>, dim3(blocks_for(3L * m.nv, 256)), dim3(256), 0, st, m.nv,
+                     m.vold, gx, gv, dx0, dv0);
 }
 
 void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st) {
@@ -1312,21 +1752,24 @@ PHISFT_INSTANTIATE_ASM(double, float)
 PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template size_t pcg_lds_bytes<T>(int, int, bool);                                              \
-  template hipError_t pcg_prepare<T>(size_t, int, bool);                                         \
-  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, int*);                            \
-  template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&,                 \
+  template size_t pcg_lds_bytes<T>(int, int, bool, int);                                         \
+  template hipError_t pcg_prepare<T>(size_t, int, bool, bool);                                   \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int*);                      \
+  template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
-  template void launch_update<T>(int, const int*, const int*, const double*, const double*,      \
-                                 const double*, double, double*, double*, T*, int*, hipStream_t); \
-  template void launch_init_state<T>(int, const int*, const int*, const T*, const T*, double*,   \
-                                     double*, int*, hipStream_t);                                \
-  template void launch_adj_pre<T>(int, const int*, const int*, const T*, double, double*,        \
-                                  const double*, double*, int*, hipStream_t);                    \
+  template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \
+                                       long long, hipStream_t);                                  \
+  template void launch_update<T>(const Mesh&, const double*, const double*, const double*,        \
+                                 double, double*, double*, T*, int*, hipStream_t);               \
+  template void launch_init_state<T>(const Mesh&, const T*, const T*, double*, double*, int*,    \
+                                     hipStream_t);                                               \
+  template void launch_adj_pre<T>(const Mesh&, const T*, double, double*, const double*,         \
+                                  double*, int*, hipStream_t);                                   \
   template void launch_adj_elements<T>(const Mesh&, const Elem&, const AdjArgs<T>&,              \
                                        hipStream_t);                                             \
   template void launch_adj_rows<T>(const Mesh&, const Elem&, const AdjArgs<T>&, hipStream_t);   \
-  template void launch_adj_final<T>(int, const double*, const double*, T*, T*, hipStream_t);
+  template void launch_adj_final<T>(const Mesh&, const double*, const double*, T*, T*,       \
+                                    hipStream_t);
 
 PHISFT_INSTANTIATE(float)
 PHISFT_INSTANTIATE(double)

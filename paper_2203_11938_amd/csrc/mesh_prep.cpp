@@ -42,14 +42,117 @@ double rest_angle(const double* x0, const double* x1, const double* x2, const do
 
 inline uint64_t edge_key(int i, int j) { return ((uint64_t)(uint32_t)i << 32) | (uint32_t)j; }
 
+// Recursive coordinate bisection: orders ids[lo, hi) so that every run of `leaf`
+// consecutive vertices counted from lo is a compact patch of the rest shape. Each
+// split is along the longest side of the bounding box, at a multiple of `leaf`.
+void rcb(const std::vector<double>& rest, std::vector<int>& ids, int lo, int hi, int leaf) {
+  const int n = hi - lo;
+  if (n <= leaf) {
+    std::sort(ids.begin() + lo, ids.begin() + hi);
+    return;
+  }
+  const int k = (n + leaf - 1) / leaf;
+  const int mid = lo + (k / 2) * leaf;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int q = lo; q < hi; ++q)
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = std::min(mn[c], rest[3 * (size_t)ids[q] + c]);
+      mx[c] = std::max(mx[c], rest[3 * (size_t)ids[q] + c]);
+    }
+  int ax = 0;
+  for (int c = 1; c < 3; ++c)
+    if (mx[c] - mn[c] > mx[ax] - mn[ax]) ax = c;
+  std::nth_element(ids.begin() + lo, ids.begin() + mid, ids.begin() + hi, [&](int a, int b) {
+    const double xa = rest[3 * (size_t)a + ax], xb = rest[3 * (size_t)b + ax];
+    return xa < xb || (xa == xb && a < b);
+  });
+  rcb(rest, ids, lo, mid, leaf);
+  rcb(rest, ids, mid, hi, leaf);
+}
+
+// Coarse modes an aggregate supports: rigid motions (6) when its free vertices are
+// at least three and not collinear, translations (3) with one or two free vertices
+// (or collinear ones), none when every vertex is pinned.
+int aggregate_modes(const std::vector<double>& rest, const std::vector<int>& pinned, int voff,
+                    int v0, int v1) {
+  std::vector<int> fr;  // sheet-local ids (rest is the sheet's, pinned is global)
+  for (int i = v0; i < v1; ++i)
+    if (!pinned[voff + i]) fr.push_back(i);
+  if (fr.empty()) return 0;
+  if (fr.size() < 3) return 3;
+  const double* p0 = &rest[3 * (size_t)fr[0]];
+  double far2 = 0.0, d[3];
+  int f = fr[0];
+  for (int i : fr) {
+    vsub(&rest[3 * (size_t)i], p0, d);
+    if (vdot(d, d) > far2) {
+      far2 = vdot(d, d);
+      f = i;
+    }
+  }
+  if (!(far2 > 0.0)) return 3;
+  double e[3], c[3], best = 0.0;
+  vsub(&rest[3 * (size_t)f], p0, e);
+  for (int i : fr) {
+    vsub(&rest[3 * (size_t)i], p0, d);
+    vcross(d, e, c);
+    best = std::max(best, std::sqrt(vdot(c, c)) / far2);
+  }
+  return best > 1e-6 ? 6 : 3;
+}
+
 }  // namespace
 
-int build_layout(const std::vector<HostSheet>& sheets, HostLayout& L, std::string& err) {
+int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_aggs,
+                 HostLayout& L, std::string& err) {
   L = HostLayout();
-  L.ninst = (int)sheets.size();
+  L.ninst = (int)sheets_in.size();
   if (L.ninst < 1) {
     err = "no sheets";
     return -1;
+  }
+  if (agg_size < 0 || max_aggs < 1) {
+    err = "invalid coarse-space size";
+    return -1;
+  }
+  // ---- renumber every sheet's vertices (compact runs); indices are checked first
+  std::vector<HostSheet> sheets(sheets_in.size());
+  std::vector<std::vector<int>> order(sheets_in.size());
+  std::vector<int> leaf(sheets_in.size());
+  for (size_t b = 0; b < sheets_in.size(); ++b) {
+    const HostSheet& s = sheets_in[b];
+    if (s.nv < 3 || s.nt < 1 || (int)s.tris.size() != 3 * s.nt || (int)s.rest.size() != 3 * s.nv) {
+      err = "sheet sizes do not match its arrays";
+      return -1;
+    }
+    for (int v : s.tris)
+      if (v < 0 || v >= s.nv) {
+        err = "triangle vertex id out of range";
+        return -2;
+      }
+    for (int p : s.pins)
+      if (p < 0 || p >= s.nv) {
+        err = "pin index out of range";
+        return -1;
+      }
+    const int base = agg_size > 0 ? agg_size : 64;
+    leaf[b] = std::max(base, (s.nv + max_aggs - 1) / max_aggs);
+    std::vector<int>& ids = order[b];
+    ids.resize(s.nv);
+    for (int i = 0; i < s.nv; ++i) ids[i] = i;
+    rcb(s.rest, ids, 0, s.nv, leaf[b]);
+    std::vector<int> inv(s.nv);
+    for (int q = 0; q < s.nv; ++q) inv[ids[q]] = q;
+    HostSheet& t = sheets[b];
+    t.nv = s.nv;
+    t.nt = s.nt;
+    t.rest.resize(s.rest.size());
+    for (int q = 0; q < s.nv; ++q)
+      for (int c = 0; c < 3; ++c) t.rest[3 * (size_t)q + c] = s.rest[3 * (size_t)ids[q] + c];
+    t.tris.resize(s.tris.size());
+    for (size_t k = 0; k < s.tris.size(); ++k) t.tris[k] = inv[s.tris[k]];
+    for (int p : s.pins) t.pins.push_back(inv[p]);
+    for (int k = 0; k < 3; ++k) t.mat[k] = s.mat[k];
   }
   // ---- sizes and offsets
   for (const HostSheet& s : sheets) {
@@ -266,6 +369,80 @@ int build_layout(const std::vector<HostSheet>& sheets, HostLayout& L, std::strin
     for (int a = 0; a < 3; ++a) L.vinc_ref[vf[L.tri_v[a * (size_t)L.nt + t]]++] = t * 3 + a;
   for (int e = 0; e < L.nh; ++e)
     for (int a = 0; a < 4; ++a) L.vinc_ref[vf[hv[4 * (size_t)e + a]]++] = -(e * 4 + a) - 1;
+
+  // ---- internal -> caller vertex order
+  L.vold.assign(nv, 0);
+  for (int b = 0; b < L.ninst; ++b)
+    for (int q = 0; q < L.inst_nv[b]; ++q) L.vold[L.inst_voff[b] + q] = L.inst_voff[b] + order[b][q];
+
+  // ---- aggregates and the coarse pattern
+  L.vert_agg.assign(nv, -1);
+  L.agg_v0.clear();
+  for (int b = 0; b < L.ninst; ++b) {
+    L.inst_agg0.push_back(L.nagg);
+    if (agg_size == 0) {
+      L.inst_nagg.push_back(0);
+      L.inst_nc.push_back(0);
+      L.inst_coff.push_back(L.coarse_doubles);
+      continue;
+    }
+    const int n = L.inst_nv[b], voff = L.inst_voff[b];
+    const int k = (n + leaf[b] - 1) / leaf[b];
+    for (int a = 0; a < k; ++a) {
+      const int v0 = voff + a * leaf[b], v1 = std::min(voff + n, v0 + leaf[b]);
+      L.agg_v0.push_back(v0);
+      L.agg_inst.push_back(b);
+      L.agg_modes.push_back(aggregate_modes(sheets[b].rest, L.pinned, voff, v0 - voff, v1 - voff));
+      for (int i = v0; i < v1; ++i) L.vert_agg[i] = L.nagg;
+      ++L.nagg;
+    }
+    L.inst_nagg.push_back(k);
+    L.inst_nc.push_back(6 * k);
+    L.inst_coff.push_back(L.coarse_doubles);
+    L.coarse_doubles += 36LL * k * k;
+    L.max_nc = std::max(L.max_nc, 6 * k);
+  }
+  L.agg_v0.push_back(nv);
+  if (agg_size > 0) {
+    std::vector<std::vector<int>> bucket;   // per pair
+    std::unordered_map<uint64_t, int> pid;
+    for (int i = 0; i < nv; ++i) {
+      if (L.pinned[i]) continue;
+      for (int k = 0; k < mz; ++k) {
+        const int j = L.ell_col[(size_t)k * nv + i];
+        if (j < 0 || L.pinned[j]) continue;
+        const int a = L.vert_agg[i], c = L.vert_agg[j];
+        if (a > c) continue;
+        const uint64_t key = edge_key(a, c);
+        auto it = pid.find(key);
+        int q;
+        if (it == pid.end()) {
+          q = (int)bucket.size();
+          pid[key] = q;
+          bucket.emplace_back();
+        } else {
+          q = it->second;
+        }
+        bucket[q].push_back(k * nv + i);
+      }
+    }
+    std::vector<std::pair<uint64_t, int>> keys(pid.begin(), pid.end());
+    std::sort(keys.begin(), keys.end());
+    L.pair_ptr.assign(1, 0);
+    for (auto& kv : keys) {
+      L.pair_a.push_back((int)(kv.first >> 32));
+      L.pair_b.push_back((int)(kv.first & 0xffffffffu));
+      auto& v = bucket[kv.second];
+      std::sort(v.begin(), v.end(), [&](int x, int y) {
+        const int ix = x % nv, iy = y % nv;
+        return ix < iy || (ix == iy && x < y);
+      });
+      L.pair_slot.insert(L.pair_slot.end(), v.begin(), v.end());
+      L.pair_ptr.push_back((int)L.pair_slot.size());
+    }
+  } else {
+    L.pair_ptr.assign(1, 0);
+  }
   return 0;
 }
 
@@ -309,6 +486,39 @@ bool check_layout(const HostLayout& L, std::string& err) {
     if (L.tri_inst[t] < 0 || L.tri_inst[t] >= L.ninst) return bad("triangle instance");
   for (int e = 0; e < nh; ++e)
     if (L.hin_inst[e] < 0 || L.hin_inst[e] >= L.ninst) return bad("hinge instance");
+  // vertex order is a permutation within each sheet
+  if ((int)L.vold.size() != nv) return bad("vertex order size");
+  std::vector<char> seen(nv, 0);
+  for (int i = 0; i < nv; ++i) {
+    const int o = L.vold[i];
+    if (o < 0 || o >= nv || seen[o] || L.vert_inst[o] != L.vert_inst[i]) return bad("vertex order");
+    seen[o] = 1;
+  }
+  // aggregates: consecutive runs covering their sheets
+  if ((int)L.agg_v0.size() != L.nagg + 1 || (int)L.agg_modes.size() != L.nagg) return bad("aggregates");
+  for (int a = 0; a < L.nagg; ++a) {
+    if (L.agg_v0[a] < 0 || L.agg_v0[a + 1] <= L.agg_v0[a] || L.agg_v0[a + 1] > nv) return bad("aggregate range");
+    for (int i = L.agg_v0[a]; i < L.agg_v0[a + 1]; ++i)
+      if (L.vert_agg[i] != a || L.vert_inst[i] != L.agg_inst[a]) return bad("aggregate member");
+  }
+  for (int b = 0; b < L.ninst; ++b) {
+    if (L.inst_nagg[b] > 0 && (L.agg_v0[L.inst_agg0[b]] != L.inst_voff[b] ||
+                               L.agg_v0[L.inst_agg0[b] + L.inst_nagg[b]] != L.inst_voff[b] + L.inst_nv[b]))
+      return bad("aggregates of a sheet");
+    if (L.inst_nc[b] != 6 * L.inst_nagg[b]) return bad("coarse size");
+  }
+  if (L.pair_ptr.size() != L.pair_a.size() + 1 || L.pair_ptr.back() != (int)L.pair_slot.size())
+    return bad("coarse pairs");
+  for (size_t q = 0; q < L.pair_a.size(); ++q) {
+    const int a = L.pair_a[q], c = L.pair_b[q];
+    if (a < 0 || c < a || c >= L.nagg || L.agg_inst[a] != L.agg_inst[c]) return bad("coarse pair");
+    for (int t = L.pair_ptr[q]; t < L.pair_ptr[q + 1]; ++t) {
+      const int sl = L.pair_slot[t];
+      if (sl < 0 || sl >= L.maxnz * nv) return bad("coarse pair slot");
+      const int i = sl % nv, j = L.ell_col[sl];
+      if (j < 0 || L.vert_agg[i] != a || L.vert_agg[j] != c) return bad("coarse pair slot");
+    }
+  }
   return true;
 }
 
@@ -331,6 +541,26 @@ HostPlan make_plan(const HostLayout& L, int rows, int group) {
     P.nwg += k;
   }
   P.barrier_slots = slot;
+  // workgroup / aggregate overlaps (both are runs of consecutive vertices)
+  if (L.nagg > 0) {
+    P.wg_agg0.resize(P.nwg);
+    P.wg_nagg.resize(P.nwg);
+    for (int w = 0; w < P.nwg; ++w) {
+      const int r0 = P.wg_row0[w], r1 = r0 + P.wg_nrows[w] - 1;
+      P.wg_agg0[w] = L.vert_agg[r0];
+      P.wg_nagg[w] = L.vert_agg[r1] - L.vert_agg[r0] + 1;
+      P.max_wg_agg = std::max(P.max_wg_agg, P.wg_nagg[w]);
+    }
+    P.agg_wg0.resize(L.nagg);
+    P.agg_nwg.resize(L.nagg);
+    for (int a = 0; a < L.nagg; ++a) {
+      const int b = L.agg_inst[a], voff = L.inst_voff[b];
+      const int w0 = P.inst_wg0[b] + (L.agg_v0[a] - voff) / rows;
+      const int w1 = P.inst_wg0[b] + (L.agg_v0[a + 1] - 1 - voff) / rows;
+      P.agg_wg0[a] = w0;
+      P.agg_nwg[a] = w1 - w0 + 1;
+    }
+  }
   return P;
 }
 

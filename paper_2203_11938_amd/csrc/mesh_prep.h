@@ -28,6 +28,19 @@ struct HostLayout {
   std::vector<int> hin_inst;
   std::vector<int> inst_voff, inst_nv, inst_toff, inst_nt, inst_hoff, inst_nh;
   std::vector<double> mat;    // [ninst][3] create-time materials
+  // vertex order: internal index -> caller's (global) index
+  std::vector<int> vold;
+  // coarse space: aggregates are runs of consecutive internal vertices of one sheet
+  int nagg = 0, max_nc = 0;
+  std::vector<int> agg_v0;     // [nagg+1] first vertex
+  std::vector<int> agg_inst;   // [nagg]
+  std::vector<int> agg_modes;  // [nagg] 6 (rigid motions), 3 (translations) or 0
+  std::vector<int> vert_agg;   // [nv]
+  std::vector<int> inst_agg0, inst_nagg, inst_nc;  // [ninst]; nc = 6 * aggregates
+  std::vector<long long> inst_coff;                 // [ninst] offset of the dense nc x nc blocks
+  long long coarse_doubles = 0;
+  // aggregate pairs (a <= b, adjacent) and the matrix slots s = k*nv + i (i in a, col in b)
+  std::vector<int> pair_a, pair_b, pair_ptr, pair_slot;
 };
 
 struct HostPlan {
@@ -35,6 +48,10 @@ struct HostPlan {
   int barrier_slots = 0;   // root slots + group counter/flag slots
   std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
   std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets
+  // overlap of workgroup row ranges and aggregates (both are runs of vertices)
+  int max_wg_agg = 0;
+  std::vector<int> wg_agg0, wg_nagg;   // [nwg] first aggregate touched, count
+  std::vector<int> agg_wg0, agg_nwg;   // [nagg] first workgroup touching, count
 };
 
 // Splits the sheets (in order) into solver launches of at most `capacity`
@@ -42,7 +59,12 @@ struct HostPlan {
 bool group_plan(HostPlan& P, int capacity, int max_groups);
 
 // Returns 0 on success, -1 (invalid argument) or -2 (mesh error) with a message.
-int build_layout(const std::vector<HostSheet>& sheets, HostLayout& out, std::string& err);
+// Vertices of every sheet are renumbered by recursive coordinate bisection of the
+// rest positions into compact runs of `agg_size` vertices (the aggregates of the
+// coarse space; 0: no coarse space, runs of 64 still order the vertices). A sheet
+// with more than max_aggs runs uses proportionally larger ones.
+int build_layout(const std::vector<HostSheet>& sheets, int agg_size, int max_aggs,
+                 HostLayout& out, std::string& err);
 
 // Checks every index table against its bounds (run before any upload).
 bool check_layout(const HostLayout& L, std::string& err);

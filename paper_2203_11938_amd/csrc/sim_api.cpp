@@ -44,6 +44,7 @@ struct sim_s {
   Elem el{};
   SolverPlan plan{};
   SolverWork sw{};
+  Coarse coarse{};
   void* A = nullptr;
   void* Jinv = nullptr;
   double* rhs = nullptr;
@@ -82,6 +83,9 @@ struct sim_s {
 };
 
 namespace {
+
+// aggregates per sheet at most (coarse dimension 6 x 128 = 768)
+constexpr int kCoarseMaxAggs = 128;
 
 sim_status bits_to_status(int bits) {
   if (bits & ST_TIMEOUT) return SIM_E_HIP;
@@ -163,7 +167,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       !(o.rows_per_block == 0 || o.rows_per_block == 64 || o.rows_per_block == 128 ||
         o.rows_per_block == 256) ||
       (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
-      (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64)) {
+      (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
+      !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20)))) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
@@ -178,7 +183,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->ckpt = o.checkpoint_every;
   s->max_steps = o.max_steps;
 
-  int rc = build_layout(sheets, s->L, s->err);
+  int rc = build_layout(sheets, o.coarse_size, kCoarseMaxAggs, s->L, s->err);
   if (rc != 0) return rc == -1 ? SIM_E_INVALID : SIM_E_MESH;
   if (!check_layout(s->L, s->err)) return SIM_E_MESH;
   HostLayout& L = s->L;
@@ -191,7 +196,13 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   int dev = 0, ncu = 0;
   HIPCHECK(s, hipGetDevice(&dev));
   HIPCHECK(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const size_t lds_cap = 160 * 1024 - 1024;
+  const bool coarse = L.nagg > 0;
+  // dynamic LDS budget: 160 KB less the kernel's static buffers
+  const size_t lds_cap = 160 * 1024 - (coarse ? 4096 : 1024);
+  if (coarse) {
+    hipError_t e = coarse_prepare(L.max_nc);
+    if (e != hipSuccess) return hip_fail(s, e, "coarse inverse LDS attribute");
+  }
   // Largest feasible block first (fewer workgroups meet faster at the per-iteration
   // barrier); matrix rows in LDS when they fit, else streamed from global memory.
   // A plan needing fewer solver launches wins; then LDS-resident rows; then larger blocks.
@@ -203,17 +214,20 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   for (int mode = 1; mode >= 0; --mode) {
     for (int rows : cands) {
       const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
-      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm)
-                       : pcg_lds_bytes<float>(L.maxnz, rows, lm);
+      const int cnc = coarse ? L.max_nc : 0;
+      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc)
+                       : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc);
       if (lds > lds_cap) continue;
-      hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm) : pcg_prepare<float>(lds, L.maxnz, lm);
+      hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse)
+                         : pcg_prepare<float>(lds, L.maxnz, lm, coarse);
       if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
       int per_cu = 0;
-      e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, &per_cu)
-              : pcg_occupancy<float>(rows, lds, L.maxnz, lm, &per_cu);
+      e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, &per_cu)
+              : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, &per_cu);
       if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
       HostPlan P = make_plan(L, rows, kBarrierGroup);
       P.lds_matrix = mode;
+      if (P.max_wg_agg > kMaxWgAgg) continue;
       if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
       const int ng = (int)P.group_wg0.size() - 1;
       if (ng < best_groups) {
@@ -226,6 +240,15 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   if (!placed) {
     s->err = "mesh too large for the co-resident solver";
     return SIM_E_INVALID;
+  }
+  {
+    // the LDS attribute of the chosen solver variant (the search set it per candidate)
+    const bool lm = s->plan_h.lds_matrix != 0;
+    const int cnc = coarse ? L.max_nc : 0;
+    hipError_t e = s->mprec == SIM_FP64
+        ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, s->plan_h.rows, lm, cnc), L.maxnz, lm, coarse)
+        : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, s->plan_h.rows, lm, cnc), L.maxnz, lm, coarse);
+    if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   }
 
   // ---- upload geometry and tables
@@ -259,6 +282,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(upload(s, L.inst_nt, &m.inst_nt));
   TRY(upload(s, L.inst_hoff, &m.inst_hoff));
   TRY(upload(s, L.inst_nh, &m.inst_nh));
+  TRY(upload(s, L.vold, &m.vold));
   const double* md = nullptr;
   TRY(upload(s, L.mat, &md));
   s->mat_default = const_cast<double*>(md);
@@ -277,8 +301,41 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(upload(s, s->plan_h.inst_wg0, &p.inst_wg0));
   TRY(upload(s, s->plan_h.inst_nwg, &p.inst_nwg));
 
+  // ---- coarse space
+  Coarse& cs = s->coarse;
+  cs.nagg = L.nagg;
+  cs.max_nc = L.max_nc;
+  if (coarse) {
+    TRY(upload(s, L.agg_v0, &cs.agg_v0));
+    TRY(upload(s, L.agg_inst, &cs.agg_inst));
+    TRY(upload(s, L.agg_modes, &cs.agg_modes));
+    TRY(upload(s, L.vert_agg, &cs.vert_agg));
+    TRY(upload(s, L.inst_agg0, &cs.inst_agg0));
+    TRY(upload(s, L.inst_nagg, &cs.inst_nagg));
+    TRY(upload(s, L.inst_nc, &cs.inst_nc));
+    TRY(upload(s, L.inst_coff, &cs.inst_coff));
+    cs.npair = (int)L.pair_a.size();
+    TRY(upload(s, L.pair_a, &cs.pair_a));
+    TRY(upload(s, L.pair_b, &cs.pair_b));
+    TRY(upload(s, L.pair_ptr, &cs.pair_ptr));
+    TRY(upload(s, L.pair_slot, &cs.pair_slot));
+    std::vector<int> ti, tc;
+    for (int b = 0; b < L.ninst; ++b)
+      for (int c0 = 0; c0 < L.inst_nc[b]; c0 += kInvCols) {
+        ti.push_back(b);
+        tc.push_back(c0);
+      }
+    cs.ninv = (int)ti.size();
+    TRY(upload(s, ti, &cs.inv_inst));
+    TRY(upload(s, tc, &cs.inv_col0));
+    TRY(upload(s, s->plan_h.wg_agg0, &cs.wg_agg0));
+    TRY(upload(s, s->plan_h.wg_nagg, &cs.wg_nagg));
+    TRY(upload(s, s->plan_h.agg_wg0, &cs.agg_wg0));
+    TRY(upload(s, s->plan_h.agg_nwg, &cs.agg_nwg));
+  }
+
   // ---- workspace
-  const size_t nv = L.nv, nt = L.nt, nh = L.nh, ni = L.ninst, ts = s->tsize;
+  const size_t nv = L.nv, nt = L.nt, nh = L.nh, ni = L.ninst;
   void* q = nullptr;
   Elem& el = s->el;
   TRY(alloc(s, 9 * nt * 8, &q)); el.tri_f = (double*)q;
@@ -305,6 +362,13 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->sw.barrier_ints = s->plan_h.barrier_slots * kBarrierSlot;
   TRY(alloc(s, (size_t)s->sw.barrier_ints * 4, &q)); s->sw.barrier = (int*)q;
   TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
+  if (coarse) {
+    TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
+    TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.mat = (double*)q;
+    TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.inv = (double*)q;
+    TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
+    TRY(alloc(s, (size_t)p.nwg * kMaxWgAgg * 6 * 8, &q)); cs.part = (double*)q;
+  }
   TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
   const size_t st = (size_t)s->max_steps * ni;
   TRY(alloc(s, st * 4, &q)); s->it_fwd = (int*)q;
@@ -333,6 +397,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   long nnzb = 0;
   for (int c : L.ell_col) nnzb += c >= 0;
   s->stats.nnz_blocks = nnzb;
+  s->stats.coarse_aggregates = L.nagg;
+  s->stats.coarse_max_dim = L.max_nc;
   return SIM_OK;
 }
 
@@ -349,13 +415,13 @@ void timed_pcg(sim_t* s, const PcgArgs<TM>& c, hipStream_t st) {
     }
     if (s->ev_used + 2 <= s->ev.size()) {
       (void)hipEventRecord(s->ev[s->ev_used], st);
-      launch_pcg<TM>(s->mesh, s->plan, s->sw, c, st);
+      launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);
       (void)hipEventRecord(s->ev[s->ev_used + 1], st);
       s->ev_used += 2;
       return;
     }
   }
-  launch_pcg<TM>(s->mesh, s->plan, s->sw, c, st);
+  launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);
 }
 
 // ---------------------------------------------------------- step sequences
@@ -380,6 +446,7 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   a.b = s->rhs;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -391,8 +458,7 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   c.resid = resid;
   c.status = s->status;
   timed_pcg<TM>(s, c, st);
-  launch_update<T>(nv, s->mesh.pinned, s->mesh.vert_inst, xp, vp, s->sol, s->h, xn, vn, xout,
-                   s->status, st);
+  launch_update<T>(s->mesh, xp, vp, s->sol, s->h, xn, vn, xout, s->status, st);
 }
 
 template <typename T>
@@ -406,8 +472,7 @@ sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x
                         hipStream_t st) {
   const int nv = s->L.nv, ni = s->L.ninst;
   char* s0 = fwd_state(s, 0, n);
-  launch_init_state<T>(nv, s->mesh.pinned, s->mesh.vert_inst, static_cast<const T*>(x0),
-                       static_cast<const T*>(v0),
+  launch_init_state<T>(s->mesh, static_cast<const T*>(x0), static_cast<const T*>(v0),
                        reinterpret_cast<double*>(s0), reinterpret_cast<double*>(s0) + 3 * (size_t)nv,
                        s->status, st);
   size_t f = 0;
@@ -434,8 +499,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   const double* vp = xp + 3 * (size_t)nv;
   const double* vs = reinterpret_cast<const double*>(sn) + 3 * (size_t)nv;
   double* u = s->rhs;  // the adjoint right-hand side reuses the forward rhs buffer
-  launch_adj_pre<T>(nv, s->mesh.pinned, s->mesh.vert_inst, dl, s->h, s->gx, s->gv, u, s->status,
-                    st);
+  launch_adj_pre<T>(s->mesh, dl, s->h, s->gx, s->gv, u, s->status, st);
   launch_elements(s->mesh, s->el, xp, s->material, s->status, st);
   AssembleArgs<T, TM> a{};
   a.v = vp;
@@ -449,6 +513,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   a.b = nullptr;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -508,7 +573,7 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
       adjoint_step<T, TM>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), dlq, dlF, st);
     }
   }
-  launch_adj_final<T>(nv, s->gx, s->gv, static_cast<T*>(dl_dx0), static_cast<T*>(dl_dv0), st);
+  launch_adj_final<T>(s->mesh, s->gx, s->gv, static_cast<T*>(dl_dx0), static_cast<T*>(dl_dv0), st);
   if (dl_dmat) launch_material_sum(s->mesh, s->el, static_cast<double*>(dl_dmat), st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(s, e, "adjoint launch");
@@ -534,6 +599,7 @@ void sim_default_options(sim_options* o) {
   o->rows_per_block = 0;
   o->membrane_system = SIM_MEMBRANE_EXACT;
   o->matrix_precision = SIM_FP64;
+  o->coarse_size = 64;
 }
 
 sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,

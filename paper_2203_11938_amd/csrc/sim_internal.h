@@ -56,6 +56,7 @@ struct Mesh {
   const int* inst_nt;
   const int* inst_hoff;
   const int* inst_nh;
+  const int* vold;              // [nv] caller's index of each vertex (I/O arrays use it)
 };
 
 // Per-step element scratch (FP64).
@@ -73,6 +74,48 @@ struct Elem {
   double* acc_ks;   // [nt] dL/dk_s partial sums over steps
   double* acc_kb;   // [nh]
   double* acc_d;    // [nv]
+};
+
+// Coarse space of the two-level preconditioner M^-1 = B^-1 + P A_c^-1 P^T (B: the
+// 3x3 block diagonal of A). An aggregate is a run of consecutive vertices of one
+// sheet; its six modes are the rigid motions t + w x (x_i - c) about its centroid c
+// at the step's positions (P_i = 0 on pinned vertices; an aggregate with fewer than
+// three free, non-collinear vertices keeps translations only, one without free
+// vertices keeps none). A_c = P^T A P is dense per sheet (nc = 6 x aggregates).
+constexpr int kMaxWgAgg = 16;     // aggregates overlapping one solver workgroup
+constexpr int kCoarseTile = 32;   // Cholesky tile
+constexpr int kInvCols = 16;      // right-hand sides per inverse workgroup
+
+struct Coarse {
+  int nagg;                    // 0: no coarse space
+  int max_nc;
+  const int* agg_v0;           // [nagg+1]
+  const int* agg_inst;         // [nagg]
+  const int* agg_modes;        // [nagg] 6, 3 or 0
+  const int* vert_agg;         // [nv]
+  const int* inst_agg0;        // [ninst]
+  const int* inst_nagg;        // [ninst]
+  const int* inst_nc;          // [ninst]
+  const long long* inst_coff;  // [ninst] offset of the sheet's nc x nc blocks
+  int npair;
+  const int* pair_a;           // [npair] aggregate pairs a <= b of one sheet
+  const int* pair_b;
+  const int* pair_ptr;         // [npair+1]
+  const int* pair_slot;        // matrix slots k*nv + i, i in a, column in b
+  int ninv;                    // inverse tasks (sheet, first column)
+  const int* inv_inst;
+  const int* inv_col0;
+  // solver-plan overlaps
+  const int* wg_agg0;          // [nwg]
+  const int* wg_nagg;          // [nwg]
+  const int* agg_wg0;          // [nagg]
+  const int* agg_nwg;          // [nagg]
+  // per-step data
+  double* crel;                // [3][nv] x_i - c (zero where the rotations are not used)
+  double* mat;                 // A_c, then its Cholesky factor (L lower, L^T upper)
+  double* inv;                 // A_c^-1 (symmetric, row-major)
+  int* ok;                     // [ninst] 1 when this step's factorisation succeeded
+  double* part;                // [nwg][kMaxWgAgg][6] restriction partial sums
 };
 
 // Cluster-barrier layout: counters 128 bytes apart; sheets with more than

@@ -59,7 +59,7 @@ class _Options(ctypes.Structure):
                 ("cg_max_iter", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
-                ("matrix_precision", ctypes.c_int32)]
+                ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -70,7 +70,8 @@ class _Stats(ctypes.Structure):
                 ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
                 ("solver_lds_matrix", ctypes.c_int32), ("solver_launches_per_solve", ctypes.c_int32),
                 ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
-                ("solver_ms", ctypes.c_double)]
+                ("solver_ms", ctypes.c_double), ("coarse_aggregates", ctypes.c_int32),
+                ("coarse_max_dim", ctypes.c_int32)]
 
 
 _lib = None
@@ -151,7 +152,8 @@ class Simulator:
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
                  cg_tol: float = 1e-7, cg_max_iter: int = 20000, checkpoint_every: int = 0,
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
-                 membrane: str = "exact", matrix_precision: str = "fp64"):
+                 membrane: str = "exact", matrix_precision: str = "fp64",
+                 coarse_size: Optional[int] = None):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -168,6 +170,8 @@ class Simulator:
             raise ValueError("membrane must be 'exact' or 'tension'")
         opt.membrane_system = SIM_MEMBRANE_TENSION if membrane == "tension" else SIM_MEMBRANE_EXACT
         opt.matrix_precision = SIM_FP32 if matrix_precision == "fp32" else SIM_FP64
+        if coarse_size is not None:
+            opt.coarse_size = coarse_size
         self.matrix_precision = matrix_precision
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32

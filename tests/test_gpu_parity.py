@@ -92,10 +92,12 @@ def test_batch_matches_single_instances():
     insts = W.make_instances(w)
     note("batch: 4 sheets (16..40 per side), 15 steps, batched vs one by one")
     tgts = [i.x0[None].repeat(w.steps, axis=0) + 0.02 for i in insts]
-    batched = gpu_run(make_sim(w, insts), w, insts, tgts)
+    # the same rows per solver workgroup on both sides, so that every reduction of a
+    # sheet runs over the same partition
+    batched = gpu_run(make_sim(w, insts, rows_per_block=128), w, insts, tgts)
     off = np.concatenate([[0], np.cumsum([i.n_verts for i in insts])])
     for b, inst in enumerate(insts):
-        single = gpu_run(make_sim(w, [inst]), w, [inst], [tgts[b]])
+        single = gpu_run(make_sim(w, [inst], rows_per_block=128), w, [inst], [tgts[b]])
         sl = slice(off[b], off[b + 1])
         assert np.array_equal(batched["x"][:, sl], single["x"]), b
         assert np.array_equal(batched["forces"][:, sl], single["forces"]), b

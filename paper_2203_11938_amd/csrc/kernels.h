@@ -71,12 +71,12 @@ template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
                 const PcgArgs<TM>& a, hipStream_t st);
 // Coarse operator of the step at positions x and assembled matrix A: frames,
-// Galerkin product, Cholesky factorisation and inverse (no-op without a coarse space).
+// Galerkin product and its in-place blocked Gauss-Jordan inverse (host arrays
+// gja_count / gjb_count: tasks of each pivot step). No-op without a coarse space.
 template <typename TM>
 void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
-                         long long coarse_doubles, hipStream_t st);
-// Sets the LDS size of the inverse kernel; fails when max_nc is too large.
-hipError_t coarse_prepare(int max_nc);
+                         long long coarse_doubles, const int* gja_count, const int* gjb_count,
+                         hipStream_t st);
 // Caller-layout arrays (x0, v0, x_out, dL/dx) are indexed through m.vold.
 template <typename T>
 void launch_update(const Mesh& m, const double* xp, const double* vp, const double* dv, double h,

@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const 
 #pragma unroll
   for (int e = 0; e < 36; ++e) acc[e] = wave_sum(acc[e]);
   const int inst = c.agg_inst[a];
-  const int nc = c.inst_nc[inst];
+  const int np = c.inst_np[inst];
   double* M = c.mat + c.inst_coff[inst];
   const int la = a - c.inst_agg0[inst], lb = b - c.inst_agg0[inst];
   const int ma = c.agg_modes[a], mb = c.agg_modes[b];
@@ -542,195 +542,186 @@ __global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const 
     if (lane == e) {
       const int r = e / 6, q = e % 6;
       const double val = (r < ma && q < mb) ? acc[e] : 0.0;
-      M[(size_t)(6 * la + r) * nc + 6 * lb + q] = val;
-      if (a != b) M[(size_t)(6 * lb + q) * nc + 6 * la + r] = val;
+      M[(size_t)(6 * la + r) * np + 6 * lb + q] = val;
+      if (a != b) M[(size_t)(6 * lb + q) * np + 6 * la + r] = val;
     }
   }
 }
 
-// Unit diagonal for the unused modes of every aggregate.
-__global__ void __launch_bounds__(256) k_coarse_dead(Coarse c) {
+// Unit diagonal for the unused modes of every aggregate and for the padding rows
+// of every sheet (threads past the aggregates handle the sheets).
+__global__ void __launch_bounds__(256) k_coarse_dead(Coarse c, int ninst) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= c.nagg) return;
-  const int inst = c.agg_inst[a], nc = c.inst_nc[inst], la = a - c.inst_agg0[inst];
-  double* M = c.mat + c.inst_coff[inst];
-  for (int q = c.agg_modes[a]; q < 6; ++q) M[(size_t)(6 * la + q) * nc + 6 * la + q] = 1.0;
+  if (a < c.nagg) {
+    const int inst = c.agg_inst[a], np = c.inst_np[inst], la = a - c.inst_agg0[inst];
+    double* M = c.mat + c.inst_coff[inst];
+    for (int q = c.agg_modes[a]; q < 6; ++q) M[(size_t)(6 * la + q) * np + 6 * la + q] = 1.0;
+  } else if (a < c.nagg + ninst) {
+    const int inst = a - c.nagg, np = c.inst_np[inst];
+    double* M = c.mat + c.inst_coff[inst];
+    for (int r = c.inst_nc[inst]; r < np; ++r) M[(size_t)r * np + r] = 1.0;
+  }
 }
 
-// One workgroup per sheet: right-looking Cholesky A_c = L L^T in 32x32 tiles (each
-// tile factored or updated in LDS), in place; L^T is mirrored into the upper
-// triangle for the row-wise reads of the inverse. A non-positive or non-finite
-// pivot leaves ok = 0 (the coarse correction is then skipped for the step).
-__global__ void __launch_bounds__(256) k_coarse_factor(Coarse c) {
-  constexpr int T = kCoarseTile;
-  __shared__ double D[T][T + 1];
-  __shared__ double P1[T][T + 1];
-  __shared__ double P2[T][T + 1];
-  __shared__ int s_fail;
-  const int inst = blockIdx.x, tid = threadIdx.x;
-  const int n = c.inst_nc[inst];
-  if (n == 0) return;
-  double* M = c.mat + c.inst_coff[inst];
-  const int nt = (n + T - 1) / T;
-  if (tid == 0) s_fail = 0;
-  for (int K = 0; K < nt; ++K) {
-    const int k0 = K * T, kb = min(T, n - k0);
-    __syncthreads();
-    for (int e = tid; e < T * T; e += blockDim.x) {
-      const int r = e / T, q = e % T;
-      D[r][q] = (r < kb && q < kb) ? M[(size_t)(k0 + r) * n + k0 + q] : 0.0;
-    }
-    __syncthreads();
-    // diagonal tile
-    for (int j = 0; j < kb; ++j) {
-      if (tid == 0) {
-        const double d = D[j][j];
-        if (!(d > 0.0) || !isfinite(d)) s_fail = 1;
-        D[j][j] = d > 0.0 ? sqrt(d) : 1.0;
-      }
-      __syncthreads();
-      if (s_fail) break;
-      if (tid > j && tid < kb) D[tid][j] /= D[j][j];
-      __syncthreads();
-      for (int e = tid; e < T * T; e += blockDim.x) {
-        const int r = e / T, q = e % T;
-        if (q > j && q <= r && r < kb) D[r][q] -= D[r][j] * D[q][j];
-      }
-      __syncthreads();
-    }
-    if (s_fail) break;
-    for (int e = tid; e < T * T; e += blockDim.x) {
-      const int r = e / T, q = e % T;
-      if (r < kb && q <= r) {
-        M[(size_t)(k0 + r) * n + k0 + q] = D[r][q];
-        M[(size_t)(k0 + q) * n + k0 + r] = D[r][q];
-      }
-    }
-    // panel: L_IK = A_IK L_KK^-T. First Li = L_KK^-1 (lower; one column per thread,
-    // down the column), then every panel row is a product with Li^T.
-    for (int e = tid; e < T * T; e += blockDim.x) P1[e / T][e % T] = 0.0;
-    __syncthreads();
-    if (tid < kb) {
-      const int cc = tid;
-      P1[cc][cc] = 1.0 / D[cc][cc];
-      for (int r = cc + 1; r < kb; ++r) {
-        double acc = 0.0;
-        for (int q = cc; q < r; ++q) acc += D[r][q] * P1[q][cc];
-        P1[r][cc] = -acc / D[r][r];
-      }
-    }
-    __syncthreads();
-    for (int i = k0 + kb + tid; i < n; i += blockDim.x) {
-      double av[T];
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  int2 t = *reinterpret_cast<int2*>(&v);
+  t.x = __builtin_amdgcn_readlane(t.x, l);
+  t.y = __builtin_amdgcn_readlane(t.y, l);
+  return *reinterpret_cast<double*>(&t);
+}
+
+// In-place Gauss-Jordan inverse of a 32x32 symmetric positive definite tile held one
+// row per lane (lanes 0..31 of the wavefront; other lanes compute nothing useful).
+// No pivoting: every pivot of an SPD matrix is positive; false if one is not.
+__device__ __forceinline__ bool gj_tile_inverse(double (&a)[kGjTile], int lane) {
+  bool good = true;
 #pragma unroll
-      for (int q = 0; q < T; ++q) av[q] = q < kb ? M[(size_t)i * n + k0 + q] : 0.0;
-      for (int q = 0; q < kb; ++q) {
-        double y = 0.0;
+  for (int p = 0; p < kGjTile; ++p) {
+    double row[kGjTile];
 #pragma unroll
-        for (int p = 0; p < T; ++p) y += av[p] * P1[q][p];
-        M[(size_t)i * n + k0 + q] = y;
-        M[(size_t)(k0 + q) * n + i] = y;
-      }
-    }
-    __syncthreads();
-    // trailing update of the lower tiles: A_IJ -= L_IK L_JK^T, K < J <= I
-    for (int I = K + 1; I < nt; ++I) {
-      const int i0 = I * T, ib = min(T, n - i0);
-      for (int e = tid; e < T * T; e += blockDim.x) {
-        const int r = e / T, q = e % T;
-        P1[r][q] = (r < ib && q < kb) ? M[(size_t)(i0 + r) * n + k0 + q] : 0.0;
-      }
-      for (int J = K + 1; J <= I; ++J) {
-        const int j0 = J * T, jb = min(T, n - j0);
-        __syncthreads();
-        for (int e = tid; e < T * T; e += blockDim.x) {
-          const int r = e / T, q = e % T;
-          P2[r][q] = (r < jb && q < kb) ? M[(size_t)(j0 + r) * n + k0 + q] : 0.0;
-        }
-        __syncthreads();
-        for (int e = tid; e < T * T; e += blockDim.x) {
-          const int r = e / T, q = e % T;
-          if (r < ib && q < jb && (I != J || q <= r)) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int p = 0; p < T; ++p) acc += P1[r][p] * P2[q][p];
-            M[(size_t)(i0 + r) * n + j0 + q] -= acc;
-          }
-        }
-      }
-      __syncthreads();
+    for (int j = 0; j < kGjTile; ++j) row[j] = readlane_d(a[j], p);
+    const double piv = row[p];
+    good = good && piv > 0.0 && isfinite(piv);
+    const double d = 1.0 / piv;
+    const double f = a[p];
+#pragma unroll
+    for (int j = 0; j < kGjTile; ++j) {
+      const double sj = j == p ? d : row[j] * d;   // scaled pivot row
+      a[j] = lane == p ? sj : (j == p ? -f * d : a[j] - f * sj);
     }
   }
-  __syncthreads();
-  if (tid == 0) c.ok[inst] = s_fail ? 0 : 1;
+  return good;
 }
 
-// Columns col0 .. col0+15 of A_c^-1 = L^-T L^-1 (one workgroup per task): blocked
-// forward and back substitution over 32-row tiles with the right-hand sides in
-// LDS [n][16]; the small triangular solves run in one wavefront, one column per
-// lane. Written as rows of the (symmetric) inverse.
-__global__ void __launch_bounds__(256) k_coarse_inverse(Coarse c) {
-  constexpr int T = kCoarseTile, NC = kInvCols;
-  extern __shared__ __align__(16) unsigned char inv_lds[];
-  double* Y = reinterpret_cast<double*>(inv_lds);
-  const int task = blockIdx.x, tid = threadIdx.x;
-  const int inst = c.inv_inst[task], col0 = c.inv_col0[task];
-  if (!c.ok[inst]) return;
-  const int n = c.inst_nc[inst];
+// Inverse of the sheet's first pivot tile (one wavefront per sheet).
+__global__ void __launch_bounds__(64) k_gj_pivot0(Coarse c) {
+  const int inst = blockIdx.x, lane = threadIdx.x;
+  const int np = c.inst_np[inst];
+  if (np == 0) return;
   const double* M = c.mat + c.inst_coff[inst];
-  double* X = c.inv + c.inst_coff[inst];
-  const int ncol = min(NC, n - col0);
-  const int nt = (n + T - 1) / T;
-  for (int e = tid; e < n * NC; e += blockDim.x) {
-    const int r = e / NC, q = e % NC;
-    Y[e] = (q < ncol && r == col0 + q) ? 1.0 : 0.0;
+  double a[kGjTile];
+#pragma unroll
+  for (int j = 0; j < kGjTile; ++j) a[j] = lane < kGjTile ? M[(size_t)lane * np + j] : 0.0;
+  const bool good = gj_tile_inverse(a, lane);
+  double* P = c.gj_pinv + (size_t)inst * kGjTile * kGjTile;
+  if (lane < kGjTile) {
+#pragma unroll
+    for (int j = 0; j < kGjTile; ++j) P[lane * kGjTile + j] = a[j];
+  }
+  if (lane == 0) c.ok[inst] = good ? 1 : 0;
+}
+
+// 32x32 tile product in LDS: each of the 256 threads forms 4 entries of X Y.
+__device__ __forceinline__ void tile_mul4(const double (*X)[kGjTile + 1], const double (*Y)[kGjTile + 1],
+                                          double out[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + k * 256, r = e / kGjTile, q = e % kGjTile;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int p = 0; p < kGjTile; ++p) acc += X[r][p] * Y[p][q];
+    out[k] = acc;
+  }
+}
+
+// Step K, first half: column multipliers C_t = A_tK Pinv (t != K) and a copy R_j of
+// the pivot row tiles A_Kj. One 256-thread workgroup per task.
+__global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
+  constexpr int T = kGjTile;
+  __shared__ double X[T][T + 1], Y[T][T + 1];
+  const int task = c.gja_ptr[K] + blockIdx.x, tid = threadIdx.x;
+  const int inst = c.gja_inst[task], t = c.gja_t[task];
+  if (!c.ok[inst]) return;
+  const int np = c.inst_np[inst];
+  const double* M = c.mat + c.inst_coff[inst];
+  double* C = c.gj_c + c.inst_boff[inst];
+  double* Rr = c.gj_r + c.inst_boff[inst];
+  if (t < 0) {
+    const int j = -t - 1;
+    for (int e = tid; e < T * T; e += 256) {
+      const int r = e / T, q = e % T;
+      Rr[(size_t)r * np + j * T + q] = M[(size_t)(K * T + r) * np + j * T + q];
+    }
+    return;
+  }
+  const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
+  for (int e = tid; e < T * T; e += 256) {
+    const int r = e / T, q = e % T;
+    X[r][q] = M[(size_t)(t * T + r) * np + K * T + q];
+    Y[r][q] = P[r * T + q];
   }
   __syncthreads();
-  // forward: L Y = E
-  for (int I = 0; I < nt; ++I) {
-    const int i0 = I * T, ib = min(T, n - i0);
-    for (int e = tid; e < ib * NC; e += blockDim.x) {
-      const int r = e / NC, q = e % NC;
-      const double* Lr = M + (size_t)(i0 + r) * n;
-      double acc = Y[(i0 + r) * NC + q];
-      for (int k = 0; k < i0; ++k) acc -= Lr[k] * Y[k * NC + q];
-      Y[(i0 + r) * NC + q] = acc;
-    }
-    __syncthreads();
-    if (tid < NC) {
-      for (int r = 0; r < ib; ++r) {
-        const double* Lr = M + (size_t)(i0 + r) * n + i0;
-        double v = Y[(i0 + r) * NC + tid];
-        for (int k = 0; k < r; ++k) v -= Lr[k] * Y[(i0 + k) * NC + tid];
-        Y[(i0 + r) * NC + tid] = v / Lr[r];
-      }
-    }
-    __syncthreads();
+  double o[4];
+  tile_mul4(X, Y, o);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + k * 256, r = e / T, q = e % T;
+    C[(size_t)(t * T + r) * T + q] = o[k];
   }
-  // back: L^T X = Y (L^T rows are the mirrored upper triangle)
-  for (int I = nt - 1; I >= 0; --I) {
-    const int i0 = I * T, ib = min(T, n - i0);
-    for (int e = tid; e < ib * NC; e += blockDim.x) {
-      const int r = e / NC, q = e % NC;
-      const double* Ur = M + (size_t)(i0 + r) * n;
-      double acc = Y[(i0 + r) * NC + q];
-      for (int k = i0 + ib; k < n; ++k) acc -= Ur[k] * Y[k * NC + q];
-      Y[(i0 + r) * NC + q] = acc;
+}
+
+// Step K, second half: every tile (i, j) of the sheet:
+//   i, j != K: A_ij -= C_i R_j;   i = K: A_Kj = Pinv R_j;   j = K: A_iK = -C_i;
+//   (K, K): Pinv. The tile (K+1, K+1) then inverts itself as the next pivot.
+__global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
+  constexpr int T = kGjTile;
+  __shared__ double X[T][T + 1], Y[T][T + 1];
+  const int task = c.gjb_ptr[K] + blockIdx.x, tid = threadIdx.x;
+  const int inst = c.gjb_inst[task], ij = c.gjb_ij[task];
+  if (!c.ok[inst]) return;
+  const int i = ij >> 16, j = ij & 0xffff;
+  const int np = c.inst_np[inst], nb = np / T;
+  double* M = c.mat + c.inst_coff[inst];
+  const double* C = c.gj_c + c.inst_boff[inst];
+  const double* Rr = c.gj_r + c.inst_boff[inst];
+  const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
+  double o[4];
+  if (i != K && j == K) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + k * 256, r = e / T, q = e % T;
+      M[(size_t)(i * T + r) * np + K * T + q] = -C[(size_t)(i * T + r) * T + q];
     }
-    __syncthreads();
-    if (tid < NC) {
-      for (int r = ib - 1; r >= 0; --r) {
-        const double* Ur = M + (size_t)(i0 + r) * n + i0;
-        double v = Y[(i0 + r) * NC + tid];
-        for (int k = r + 1; k < ib; ++k) v -= Ur[k] * Y[(i0 + k) * NC + tid];
-        Y[(i0 + r) * NC + tid] = v / Ur[r];
-      }
-    }
-    __syncthreads();
+    return;
   }
-  for (int e = tid; e < ncol * n; e += blockDim.x) {
-    const int q = e / n, r = e % n;
-    X[(size_t)(col0 + q) * n + r] = Y[r * NC + q];
+  if (i == K && j == K) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + k * 256, r = e / T, q = e % T;
+      M[(size_t)(K * T + r) * np + K * T + q] = P[r * T + q];
+    }
+    return;
+  }
+  for (int e = tid; e < T * T; e += 256) {
+    const int r = e / T, q = e % T;
+    X[r][q] = i == K ? P[r * T + q] : C[(size_t)(i * T + r) * T + q];
+    Y[r][q] = Rr[(size_t)r * np + j * T + q];
+  }
+  __syncthreads();
+  tile_mul4(X, Y, o);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = tid + k * 256, r = e / T, q = e % T;
+    double* dst = M + (size_t)(i * T + r) * np + j * T + q;
+    const double v = i == K ? o[k] : *dst - o[k];
+    *dst = v;
+    if (i == K + 1 && j == K + 1) X[r][q] = v;
+  }
+  if (i == K + 1 && j == K + 1 && K + 1 < nb) {
+    __syncthreads();
+    if (tid < 64) {
+      double a[T];
+#pragma unroll
+      for (int q = 0; q < T; ++q) a[q] = tid < T ? X[tid][q] : 0.0;
+      const bool good = gj_tile_inverse(a, tid);
+      double* Pn = c.gj_pinv + ((size_t)((K + 1) & 1) * ninst + inst) * T * T;
+      if (tid < T) {
+#pragma unroll
+        for (int q = 0; q < T; ++q) Pn[tid * T + q] = a[q];
+      }
+      if (tid == 0 && !good) c.ok[inst] = 0;
+    }
   }
 }
 
@@ -1020,9 +1011,10 @@ __device__ __forceinline__ void coarse_correct(const Coarse& c, int inst, int wa
     s_wc[e] = sum;
   }
   __syncthreads();
-  const double* inv = c.inv + c.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * nc;
+  const int np = c.inst_np[inst];
+  const double* inv = c.mat + c.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;
   for (int row = wave; row < 6 * wna; row += nwaves) {
-    const double* ir = inv + (size_t)row * nc;
+    const double* ir = inv + (size_t)row * np;
     double acc = 0.0;
     for (int col = lane; col < nc; col += 64) acc += ir[col] * s_wc[col];
     acc = wave_sum(acc);
@@ -1679,25 +1671,24 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
   }
 }
 
-hipError_t coarse_prepare(int max_nc) {
-  const size_t lds = (size_t)std::max(max_nc, 1) * kInvCols * sizeof(double);
-  if (lds > 150 * 1024) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_inverse),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
 template <typename TM>
 void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
-                         long long coarse_doubles, hipStream_t st) {
+                         long long coarse_doubles, const int* gja_count, const int* gjb_count,
+                         hipStream_t st) {
   if (c.nagg == 0) return;
   hipLaunchKernelGGL(k_coarse_frame, dim3(c.nagg), dim3(64), 0, st, m, c, x);
   launch_fill_double(c.mat, coarse_doubles, 0.0, st);
   if (c.npair > 0)
     hipLaunchKernelGGL((k_coarse_assemble<TM>), dim3(c.npair), dim3(64), 0, st, m, c, A);
-  hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg, 256)), dim3(256), 0, st, c);
-  hipLaunchKernelGGL(k_coarse_factor, dim3(m.ninst), dim3(256), 0, st, c);
-  const size_t lds = (size_t)c.max_nc * kInvCols * sizeof(double);
-  if (c.ninv > 0) hipLaunchKernelGGL(k_coarse_inverse, dim3(c.ninv), dim3(256), lds, st, c);
+  hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst, 256)), dim3(256), 0, st, c,
+                     m.ninst);
+  hipLaunchKernelGGL(k_gj_pivot0, dim3(m.ninst), dim3(64), 0, st, c);
+  for (int K = 0; K < c.max_nb; ++K) {
+    if (gja_count[K] > 0)
+      hipLaunchKernelGGL(k_gj_cols, dim3(gja_count[K]), dim3(256), 0, st, c, K, m.ninst);
+    if (gjb_count[K] > 0)
+      hipLaunchKernelGGL(k_gj_update, dim3(gjb_count[K]), dim3(256), 0, st, c, K, m.ninst);
+  }
 }
 
 template <typename T>
@@ -1758,7 +1749,7 @@ PHISFT_INSTANTIATE_ASM(double, double)
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \
-                                       long long, hipStream_t);                                  \
+                                       long long, const int*, const int*, hipStream_t);          \
   template void launch_update<T>(const Mesh&, const double*, const double*, const double*,        \
                                  double, double*, double*, T*, int*, hipStream_t);               \
   template void launch_init_state<T>(const Mesh&, const T*, const T*, double*, double*, int*,    \

@@ -383,6 +383,7 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
     if (agg_size == 0) {
       L.inst_nagg.push_back(0);
       L.inst_nc.push_back(0);
+      L.inst_np.push_back(0);
       L.inst_coff.push_back(L.coarse_doubles);
       continue;
     }
@@ -397,9 +398,11 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
       ++L.nagg;
     }
     L.inst_nagg.push_back(k);
+    const int np = (6 * k + 31) / 32 * 32;  // stored with an identity block up to 32 | np
     L.inst_nc.push_back(6 * k);
+    L.inst_np.push_back(np);
     L.inst_coff.push_back(L.coarse_doubles);
-    L.coarse_doubles += 36LL * k * k;
+    L.coarse_doubles += (long long)np * np;
     L.max_nc = std::max(L.max_nc, 6 * k);
   }
   L.agg_v0.push_back(nv);
@@ -505,7 +508,8 @@ bool check_layout(const HostLayout& L, std::string& err) {
     if (L.inst_nagg[b] > 0 && (L.agg_v0[L.inst_agg0[b]] != L.inst_voff[b] ||
                                L.agg_v0[L.inst_agg0[b] + L.inst_nagg[b]] != L.inst_voff[b] + L.inst_nv[b]))
       return bad("aggregates of a sheet");
-    if (L.inst_nc[b] != 6 * L.inst_nagg[b]) return bad("coarse size");
+    if (L.inst_nc[b] != 6 * L.inst_nagg[b] || L.inst_np[b] < L.inst_nc[b] || L.inst_np[b] % 32 != 0)
+      return bad("coarse size");
   }
   if (L.pair_ptr.size() != L.pair_a.size() + 1 || L.pair_ptr.back() != (int)L.pair_slot.size())
     return bad("coarse pairs");

@@ -37,7 +37,8 @@ struct HostLayout {
   std::vector<int> agg_modes;  // [nagg] 6 (rigid motions), 3 (translations) or 0
   std::vector<int> vert_agg;   // [nv]
   std::vector<int> inst_agg0, inst_nagg, inst_nc;  // [ninst]; nc = 6 * aggregates
-  std::vector<long long> inst_coff;                 // [ninst] offset of the dense nc x nc blocks
+  std::vector<int> inst_np;                         // [ninst] nc rounded up to 32 (stored size)
+  std::vector<long long> inst_coff;                 // [ninst] offset of the dense np x np blocks
   long long coarse_doubles = 0;
   // aggregate pairs (a <= b, adjacent) and the matrix slots s = k*nv + i (i in a, col in b)
   std::vector<int> pair_a, pair_b, pair_ptr, pair_slot;

@@ -45,6 +45,8 @@ struct sim_s {
   SolverPlan plan{};
   SolverWork sw{};
   Coarse coarse{};
+  long long gj_doubles = 0;               // per-sheet [np][32] blocks of the inversion
+  std::vector<int> gja_count, gjb_count;  // inversion tasks per pivot step
   void* A = nullptr;
   void* Jinv = nullptr;
   double* rhs = nullptr;
@@ -199,10 +201,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   const bool coarse = L.nagg > 0;
   // dynamic LDS budget: 160 KB less the kernel's static buffers
   const size_t lds_cap = 160 * 1024 - (coarse ? 4096 : 1024);
-  if (coarse) {
-    hipError_t e = coarse_prepare(L.max_nc);
-    if (e != hipSuccess) return hip_fail(s, e, "coarse inverse LDS attribute");
-  }
   // Largest feasible block first (fewer workgroups meet faster at the per-iteration
   // barrier); matrix rows in LDS when they fit, else streamed from global memory.
   // A plan needing fewer solver launches wins; then LDS-resident rows; then larger blocks.
@@ -319,15 +317,46 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(upload(s, L.pair_b, &cs.pair_b));
     TRY(upload(s, L.pair_ptr, &cs.pair_ptr));
     TRY(upload(s, L.pair_slot, &cs.pair_slot));
-    std::vector<int> ti, tc;
-    for (int b = 0; b < L.ninst; ++b)
-      for (int c0 = 0; c0 < L.inst_nc[b]; c0 += kInvCols) {
-        ti.push_back(b);
-        tc.push_back(c0);
+    TRY(upload(s, L.inst_np, &cs.inst_np));
+    // blocked Gauss-Jordan task lists per pivot tile K
+    int max_nb = 0;
+    for (int b = 0; b < L.ninst; ++b) max_nb = std::max(max_nb, L.inst_np[b] / kGjTile);
+    cs.max_nb = max_nb;
+    std::vector<int> aptr(1, 0), ainst, at, bptr(1, 0), binst, bij;
+    for (int K = 0; K < max_nb; ++K) {
+      for (int b = 0; b < L.ninst; ++b) {
+        const int nb = L.inst_np[b] / kGjTile;
+        if (nb <= K) continue;
+        for (int t = 0; t < nb; ++t) {
+          if (t == K) continue;
+          ainst.push_back(b);
+          at.push_back(t);
+          ainst.push_back(b);
+          at.push_back(-t - 1);
+        }
+        for (int i = 0; i < nb; ++i)
+          for (int j = 0; j < nb; ++j) {
+            binst.push_back(b);
+            bij.push_back(i * 65536 + j);
+          }
       }
-    cs.ninv = (int)ti.size();
-    TRY(upload(s, ti, &cs.inv_inst));
-    TRY(upload(s, tc, &cs.inv_col0));
+      aptr.push_back((int)ainst.size());
+      bptr.push_back((int)binst.size());
+      s->gja_count.push_back(aptr[K + 1] - aptr[K]);
+      s->gjb_count.push_back(bptr[K + 1] - bptr[K]);
+    }
+    TRY(upload(s, aptr, &cs.gja_ptr));
+    TRY(upload(s, ainst, &cs.gja_inst));
+    TRY(upload(s, at, &cs.gja_t));
+    TRY(upload(s, bptr, &cs.gjb_ptr));
+    TRY(upload(s, binst, &cs.gjb_inst));
+    TRY(upload(s, bij, &cs.gjb_ij));
+    std::vector<long long> boff;
+    for (int b = 0; b < L.ninst; ++b) {
+      boff.push_back(s->gj_doubles);
+      s->gj_doubles += (long long)kGjTile * L.inst_np[b];
+    }
+    TRY(upload(s, boff, &cs.inst_boff));
     TRY(upload(s, s->plan_h.wg_agg0, &cs.wg_agg0));
     TRY(upload(s, s->plan_h.wg_nagg, &cs.wg_nagg));
     TRY(upload(s, s->plan_h.agg_wg0, &cs.agg_wg0));
@@ -365,7 +394,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   if (coarse) {
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.mat = (double*)q;
-    TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.inv = (double*)q;
+    TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_c = (double*)q;
+    TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
+    TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
     TRY(alloc(s, (size_t)p.nwg * kMaxWgAgg * 6 * 8, &q)); cs.part = (double*)q;
   }
@@ -446,7 +477,8 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   a.b = s->rhs;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
-  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
+                          s->gjb_count.data(), st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -513,7 +545,8 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   a.b = nullptr;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
-  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
+                          s->gjb_count.data(), st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;

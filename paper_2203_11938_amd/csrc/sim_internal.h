@@ -83,28 +83,33 @@ struct Elem {
 // three free, non-collinear vertices keeps translations only, one without free
 // vertices keeps none). A_c = P^T A P is dense per sheet (nc = 6 x aggregates).
 constexpr int kMaxWgAgg = 16;     // aggregates overlapping one solver workgroup
-constexpr int kCoarseTile = 32;   // Cholesky tile
-constexpr int kInvCols = 16;      // right-hand sides per inverse workgroup
+constexpr int kGjTile = 32;       // tile of the blocked Gauss-Jordan inversion
 
 struct Coarse {
   int nagg;                    // 0: no coarse space
   int max_nc;
+  int max_nb;                  // largest number of 32-tiles per side
   const int* agg_v0;           // [nagg+1]
   const int* agg_inst;         // [nagg]
   const int* agg_modes;        // [nagg] 6, 3 or 0
   const int* vert_agg;         // [nv]
   const int* inst_agg0;        // [ninst]
   const int* inst_nagg;        // [ninst]
-  const int* inst_nc;          // [ninst]
-  const long long* inst_coff;  // [ninst] offset of the sheet's nc x nc blocks
+  const int* inst_nc;          // [ninst] coarse dimension (6 x aggregates)
+  const int* inst_np;          // [ninst] stored dimension: nc rounded up to 32 (identity pad)
+  const long long* inst_coff;  // [ninst] offset of the sheet's np x np matrix
   int npair;
   const int* pair_a;           // [npair] aggregate pairs a <= b of one sheet
   const int* pair_b;
   const int* pair_ptr;         // [npair+1]
   const int* pair_slot;        // matrix slots k*nv + i, i in a, column in b
-  int ninv;                    // inverse tasks (sheet, first column)
-  const int* inv_inst;
-  const int* inv_col0;
+  // blocked Gauss-Jordan task lists, per pivot tile K (ptr arrays have max_nb + 1 entries)
+  const int* gja_ptr;          // column multipliers / pivot-row copies of step K
+  const int* gja_inst;
+  const int* gja_t;            // >= 0: C_t = A_tK Pinv; < 0: R_j = A_Kj with j = -t - 1
+  const int* gjb_ptr;          // tile updates of step K
+  const int* gjb_inst;
+  const int* gjb_ij;           // i * 65536 + j
   // solver-plan overlaps
   const int* wg_agg0;          // [nwg]
   const int* wg_nagg;          // [nwg]
@@ -112,9 +117,12 @@ struct Coarse {
   const int* agg_nwg;          // [nagg]
   // per-step data
   double* crel;                // [3][nv] x_i - c (zero where the rotations are not used)
-  double* mat;                 // A_c, then its Cholesky factor (L lower, L^T upper)
-  double* inv;                 // A_c^-1 (symmetric, row-major)
-  int* ok;                     // [ninst] 1 when this step's factorisation succeeded
+  double* mat;                 // A_c, inverted in place
+  double* gj_c;                // per sheet [np][32] column multipliers
+  double* gj_r;                // per sheet [32][np] pivot-row copy
+  double* gj_pinv;             // [2][ninst][32][32] inverse pivot tiles
+  const long long* inst_boff;  // [ninst] offset of the sheet's gj_c / gj_r blocks (32 np)
+  int* ok;                     // [ninst] 1 when this step's inversion succeeded
   double* part;                // [nwg][kMaxWgAgg][6] restriction partial sums
 };
 

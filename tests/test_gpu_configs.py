@@ -223,8 +223,6 @@ def test_c4_tension_variant_runs_every_sheet():
     s.close()
 
 
-@pytest.mark.skip(reason="200x200 solves take 7,000-11,000 block-Jacobi PCG iterations and an "
-                  "adjoint solve can reach the iteration cap; enabled with the stronger preconditioner")
 def test_c5_large_sheet_full_size():
     w = W.workload("C5")
     inst = W.make_instances(w)[0]

@@ -63,6 +63,45 @@ def cpu_baseline(w, inst, sample_steps: int):
                        f"+ adjoint in one single-threaded FP64 call ({dt:.1f} s)")
 
 
+def sequential_comparison(w, insts, batched_ms, steps, membrane):
+    """The same gradient with one handle per sheet, launched one after the other
+    on the same stream (warm-up excluded); returns the wall times and the ratio."""
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+    dev = torch.device("cuda:0")
+    runs = []
+    for inst in insts:
+        sim = S.Simulator([S.Sheet(inst.tris, inst.rest, inst.pins, *inst.material.as_tuple())],
+                          dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
+                          checkpoint_every=w.checkpoint_every, max_steps=w.steps,
+                          membrane=membrane)
+        dt = sim.dtype
+        x0 = torch.tensor(W.to_soa(inst.x0), dtype=dt, device=dev)
+        F = torch.tensor(W.to_soa(inst.forces), dtype=dt, device=dev)
+        tgt = (x0[None].repeat(len(w.loss_frames()), 1, 1) + 0.01).contiguous()
+        runs.append((sim, x0, F, tgt))
+
+    def all_gradients():
+        for sim, x0, F, tgt in runs:
+            xo = sim.rollout(w.steps, x0, None, F, None, w.loss_frames())
+            sim.adjoint((2.0 * (xo - tgt)).contiguous())
+        for sim, *_ in runs:
+            sim.status()
+
+    all_gradients()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        all_gradients()
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t0) / steps
+    for sim, *_ in runs:
+        sim.close()
+    return dict(sheets=len(insts), batched_ms=round(batched_ms, 3), sequential_ms=round(seq_ms, 3),
+                speedup=round(seq_ms / batched_ms, 2))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +110,11 @@ def main():
     ap.add_argument("--workload", default="H")
     ap.add_argument("--cpu-sample-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--membrane", default="exact", choices=["exact", "tension"],
+                    help="membrane block of the step matrix")
+    ap.add_argument("--sequential", action="store_true",
+                    help="batched workloads: also time one handle per sheet, run back to back, "
+                         "and report the batched speed-up")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (untimed), the "
                          "known-size reference for scaling HBM byte counters")
@@ -101,7 +145,8 @@ def main():
           flush=True)
     sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
     sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
-                      checkpoint_every=w.checkpoint_every, max_steps=w.steps)
+                      checkpoint_every=w.checkpoint_every, max_steps=w.steps,
+                      membrane=args.membrane)
     dt = sim.dtype
     V = sim.n_verts
     x0 = torch.tensor(W.to_soa(np.concatenate([i.x0 for i in insts])), dtype=dt, device=dev)
@@ -113,7 +158,7 @@ def main():
     mat_t = torch.tensor(np.array([np.array(i.material.as_tuple()) * i.target_factors
                                    for i in insts]), dtype=torch.float64, device=dev)
     tgt = sim.rollout(w.steps, x0, v0, F, mat_t, frames).clone()
-    sim.sync(allow_not_converged=True)
+    sim.status()
 
     def gradient():
         xo = sim.rollout(w.steps, x0, v0, F, None, frames)
@@ -122,19 +167,20 @@ def main():
 
     for _ in range(args.warmup):
         gradient()
-        sim.sync(allow_not_converged=True)
+        sim.status()
     sim.set_timing(True)
     iters = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         gradient()
-        sim.sync(allow_not_converged=True)
+        sim.status()
         st = sim.stats()
         iters += st["cg_iters_forward"] + st["cg_iters_adjoint"] + st["cg_iters_recompute"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = sim.stats()
+    sides = [int(round(np.sqrt(i.n_verts))) for i in insts]
     ms = 1e3 * wall / args.steps
     value = V * w.steps * args.steps / wall
 
@@ -160,12 +206,20 @@ def main():
                value=round(value, 1), unit="vertex-steps/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload=f"{w.name}: {w.n}x{w.n} sheet, {w.steps} steps of "
-                           f"{w.dt} s, rollout + adjoint", vertices=V, sim_steps=w.steps,
+               config=dict(workload=(f"{w.name}: {w.n}x{w.n} sheet" if len(insts) == 1 else
+                                     f"{w.name}: {len(insts)} sheets of {min(sides)}..{max(sides)} per side") +
+                           f", {w.steps} steps of {w.dt} s, rollout + adjoint",
+                           sheets=len(insts), vertices=V, sim_steps=w.steps,
                            cg_tol=w.cg_tol, cg_iters_per_gradient=iters // args.steps,
                            solver_blocks=st["blocks"], rows_per_block=st["rows_per_block"],
-                           matrix_precision=sim.matrix_precision, bytes_per_cg_iter=b_iter),
+                           matrix_precision=sim.matrix_precision, membrane=args.membrane,
+                           coarse_aggregates=st["coarse_aggregates"],
+                           coarse_max_dim=st["coarse_max_dim"], bytes_per_cg_iter=b_iter,
+                           device_status=S.status_name(sim.status())),
                roofline=roof)
+    if args.sequential and len(insts) > 1:
+        out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
+                                                             args.membrane)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps)

@@ -121,6 +121,11 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
+def status_name(code: int) -> str:
+    """The library's name for a status code."""
+    return load_library().sim_status_string(int(code)).decode()
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 

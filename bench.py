@@ -45,6 +45,26 @@ def measured_traffic(workload: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def block_pattern_size(tris, nv: int) -> int:
+    """Non-zero 3x3 blocks of a sheet's step matrix: vertex pairs sharing a triangle,
+    the two wing vertices of every interior edge, and the diagonal."""
+    import numpy as np
+    t = np.asarray(tris, dtype=np.int64)
+    pairs = [t[:, [a, b]] for a in range(3) for b in range(3)]
+    # interior edges: directed edge (i, j) of one triangle and (j, i) of another
+    e = np.concatenate([t[:, [0, 1, 2]], t[:, [1, 2, 0]], t[:, [2, 0, 1]]])  # (i, j, opposite)
+    key = e[:, 0] * nv + e[:, 1]
+    rev = e[:, 1] * nv + e[:, 0]
+    order = np.argsort(key)
+    pos = np.searchsorted(key[order], rev)
+    pos = np.minimum(pos, len(key) - 1)
+    hit = key[order][pos] == rev
+    wings = np.stack([e[hit, 2], e[order][pos][hit, 2]], axis=1)
+    pairs += [wings, wings[:, ::-1]]
+    allp = np.concatenate(pairs)
+    return int(np.unique(allp[:, 0] * nv + allp[:, 1]).size)
+
+
 def cpu_baseline(w, inst, sample_steps: int):
     import numpy as np
     import oracle
@@ -170,6 +190,7 @@ def main():
         sim.status()
     sim.set_timing(True)
     iters = 0
+    sheet_iters = np.zeros(len(insts))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -177,6 +198,10 @@ def main():
         sim.status()
         st = sim.stats()
         iters += st["cg_iters_forward"] + st["cg_iters_adjoint"] + st["cg_iters_recompute"]
+        fwd, adj = sim.cg_iters()
+        sheet_iters += fwd.sum(axis=0) + adj.sum(axis=0)
+        if len(insts) == 1:
+            sheet_iters += st["cg_iters_recompute"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = sim.stats()
@@ -189,9 +214,13 @@ def main():
     # 192 B per vertex for one pass over the solver vectors
     msize = 8 if sim.matrix_precision == "fp64" else 4
     b_iter = (9 * msize + 4) * st["nnz_blocks"] + 192 * V
+    # a batched launch iterates every sheet on its own: weight each sheet's iterations
+    # with its own bytes per iteration
+    sheet_b = np.array([(9 * msize + 4) * block_pattern_size(i.tris, i.n_verts) + 192 * i.n_verts
+                        for i in insts], dtype=np.float64)
     launches = st["solver_launches"]
     avg_ms = st["solver_ms"] / max(launches, 1)
-    bytes_per_launch = b_iter * iters / max(launches, 1)
+    bytes_per_launch = float(np.dot(sheet_b, sheet_iters)) / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(w.name)
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",

@@ -883,17 +883,19 @@ __device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int ti
   }
 }
 
-// y += (blocks k0..k0+kChunk-1 of the row) * g. The scheduling barriers keep each
-// block's LDS loads next to their use instead of hoisting them all into registers.
+// y += (blocks k0..k0+kChunk-1 of the row) * g. With SB (matrix in LDS) scheduling
+// barriers keep each block's LDS loads next to their use instead of hoisting them all
+// into registers; a matrix streamed from memory is left to the scheduler so that its
+// loads are issued early.
 // The matrix is read at A[((k * 9 + e) * stride) + idx]: the LDS copy (stride R,
 // idx = thread) or the assembled ELL array in global memory (stride nv, idx = row).
-template <typename TM>
+template <typename TM, bool SB>
 __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, int idx, int k0,
                                         int maxnz, const double g[3][kChunk], double y[3]) {
 #pragma unroll
   for (int k = 0; k < kChunk; ++k) {
 #if SCHED_BARRIER
-    __builtin_amdgcn_sched_barrier(0);
+    if (SB) __builtin_amdgcn_sched_barrier(0);
 #endif
     if (k0 + k < maxnz) {
       const TM* blk = Am + (size_t)(k0 + k) * 9 * stride + idx;
@@ -907,7 +909,7 @@ __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, i
 }
 
 // y = A v for this thread's row, v from global memory (and LDS when vl is given).
-template <typename TM>
+template <typename TM, bool SB>
 __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
                                          const int* __restrict__ Cl, int R, int tid, int maxnz,
                                          int nv, int row0, int nrows,
@@ -917,7 +919,7 @@ __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, 
   for (int k0 = 0; k0 < maxnz; k0 += kChunk) {
     double g[3][kChunk];
     loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, vg, vl, g);
-    applynb<TM>(Am, stride, idx, k0, maxnz, g, y);
+    applynb<TM, SB>(Am, stride, idx, k0, maxnz, g, y);
   }
 }
 
@@ -944,7 +946,7 @@ constexpr bool kLocalGather = LOCAL_GATHER;
 // (otherwise the assembled matrix is streamed from global memory each SpMV).
 #ifdef PHISFT_PHASES
 // per-workgroup accumulated wall-clock ticks of the solver phases (tuning builds only)
-__device__ unsigned long long g_phase[512][6];
+__device__ unsigned long long g_phase[512][8];
 #define PHASE_T(v) const unsigned long long v = wall_clock64()
 #define PHASE_ADD(k, d) ph[k] += (d)
 #else
@@ -956,8 +958,8 @@ __device__ unsigned long long g_phase[512][6];
 // (y, r_i x y) = P_i^T y over the workgroup's rows, published as
 // part[wg][k][0..5] (k: aggregate minus the workgroup's first aggregate). Fixed
 // order: a butterfly per wavefront, then the wavefronts in order.
-__device__ __forceinline__ void coarse_restrict(const Coarse& c, int wg, int row0,
-                                                int nrows, int wa0, int wna, int kloc, bool live,
+__device__ __forceinline__ void coarse_restrict(double* __restrict__ part, int wg, int wna,
+                                                int kf, int kl, int kloc, bool live,
                                                 const double r[3], const double y[3]) {
   __shared__ double s_wp[4][kMaxWgAgg][6];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -971,54 +973,76 @@ __device__ __forceinline__ void coarse_restrict(const Coarse& c, int wg, int row
   v[4] = r[2] * y[0] - r[0] * y[2];
   v[5] = r[0] * y[1] - r[1] * y[0];
   __syncthreads();
-  const int f = wave * 64;
-  if (f < nrows) {
-    const int l = min(nrows, f + 64) - 1;
-    const int kf = c.vert_agg[row0 + f] - wa0, kl = c.vert_agg[row0 + l] - wa0;
-    for (int k = kf; k <= kl; ++k) {
-      const bool mine = live && kloc == k;
+  for (int k = kf; k <= kl; ++k) {   // this wavefront's aggregates (empty if it has no rows)
+    const bool mine = live && kloc == k;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double t = wave_sum(mine ? v[q] : 0.0);
-        if (lane == 0) s_wp[wave][k][q] = t;
-      }
+    for (int q = 0; q < 6; ++q) {
+      const double t = wave_sum(mine ? v[q] : 0.0);
+      if (lane == 0) s_wp[wave][k][q] = t;
     }
   }
   __syncthreads();
   for (int e = tid; e < wna * 6; e += blockDim.x) {
-    const int k = e / 6, q = e - k * 6;
+    const int k = e / 6, q = e % 6;
     double t = 0.0;
     for (int w = 0; w < nwaves; ++w) t += s_wp[w][k][q];
-    c.part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
+    part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
   }
 }
 
+// Per-launch constants of a workgroup's coarse correction.
+struct CoarseRow {
+  const double* X;       // rows of A_c^-1 of the workgroup's aggregates (stride np)
+  const double* part;    // restriction partial sums
+  int nc, np, nrow, ok;
+};
+
 // After the cluster barrier that publishes the partial sums: the sheet's coarse
-// residual w_c (LDS), e = rows of A_c^-1 w_c for this workgroup's aggregates (LDS),
-// and y += P_i e on this thread's row. Skipped when the step's factorisation failed.
-__device__ __forceinline__ void coarse_correct(const Coarse& c, int inst, int wa0, int wna, int kloc,
-                                               bool live, const double r[3], double y[3],
-                                               double* s_wc, double* s_e) {
-  if (!c.ok[inst]) return;
+// residual w_c (into LDS), then e = the rows of A_c^-1 belonging to this
+// workgroup's aggregates times w_c (one row per lane, the columns split over the
+// wavefronts, w_c read as LDS broadcasts; no cross-lane reductions), then
+// y += P_i e on this thread's row. Fixed summation order throughout. Skipped when
+// the step's inversion failed.
+__device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, bool live,
+                                               const double r[3], double y[3],
+                                               const int* s_pidx, double* s_wc, double* s_red,
+                                               double* s_e) {
+  constexpr int NR = 6 * kMaxWgAgg;
+  if (!cr_.ok) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
-  const int nc = c.inst_nc[inst], ag0 = c.inst_agg0[inst];
-  for (int e = tid; e < nc; e += blockDim.x) {
-    const int t = e / 6, q = e - t * 6, a = ag0 + t;
-    const int w0 = c.agg_wg0[a], w1 = w0 + c.agg_nwg[a];
-    double sum = 0.0;
-    for (int w = w0; w < w1; ++w) sum += c.part[((size_t)w * kMaxWgAgg + (a - c.wg_agg0[w])) * 6 + q];
-    s_wc[e] = sum;
+  const int nc = cr_.nc, np = cr_.np, nrow = cr_.nrow;
+  for (int col = tid; col < nc; col += blockDim.x) {
+    const int t = col / 6, q = col - 6 * t;
+    double wc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxAggWg; ++k) {
+      const int pi = s_pidx[t * kMaxAggWg + k];
+      if (pi >= 0) wc += cr_.part[(size_t)pi * 6 + q];
+    }
+    s_wc[col] = wc;
   }
   __syncthreads();
-  const int np = c.inst_np[inst];
-  const double* inv = c.mat + c.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;
-  for (int row = wave; row < 6 * wna; row += nwaves) {
-    const double* ir = inv + (size_t)row * np;
-    double acc = 0.0;
-    for (int col = lane; col < nc; col += 64) acc += ir[col] * s_wc[col];
-    acc = wave_sum(acc);
-    if (lane == 0) s_e[row] = acc;
+  const int chunk = (nc + nwaves - 1) / nwaves;
+  const int c0 = wave * chunk, c1 = min(nc, c0 + chunk);
+  if (lane < nrow) {
+    const double* __restrict__ xr = cr_.X + (size_t)lane * np;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int col = c0;
+    for (; col + 4 <= c1; col += 4) {
+      a0 += xr[col] * s_wc[col];
+      a1 += xr[col + 1] * s_wc[col + 1];
+      a2 += xr[col + 2] * s_wc[col + 2];
+      a3 += xr[col + 3] * s_wc[col + 3];
+    }
+    for (; col < c1; ++col) a0 += xr[col] * s_wc[col];
+    s_red[wave * NR + lane] = (a0 + a1) + (a2 + a3);
+  }
+  __syncthreads();
+  if (tid < nrow) {
+    double t = 0.0;
+    for (int w = 0; w < nwaves; ++w) t += s_red[w * NR + tid];
+    s_e[tid] = t;
   }
   __syncthreads();
   if (live) {
@@ -1033,7 +1057,7 @@ template <typename TM, bool LDS_MATRIX, bool COARSE>
 __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
                                              PcgArgs<TM> a) {
 #ifdef PHISFT_PHASES
-  unsigned long long ph[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
 #endif
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double s_out[3];
@@ -1053,8 +1077,12 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][R]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)R);            // [maxnz][R]
   TM* Al = reinterpret_cast<TM*>(Cl + (size_t)maxnz * R);          // [maxnz][9][R] (LDS mode)
+  // coarse: w_c [max nc], row sums [waves][24], e [24], partial-sum indices
+  // [aggregates][kMaxAggWg]
   double* s_wc = reinterpret_cast<double*>(Al + (LDS_MATRIX ? (size_t)maxnz * 9 * R : 0));
-  double* s_e = s_wc + cs.max_nc;                                  // [kMaxWgAgg][6]
+  double* s_red = s_wc + cs.max_nc;
+  double* s_e = s_red + 4 * 6 * kMaxWgAgg;
+  int* s_pidx = reinterpret_cast<int*>(s_e + 6 * kMaxWgAgg);
   // matrix operand: LDS copy, or the assembled ELL array read in place
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
@@ -1071,12 +1099,36 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     }
   }
   // coarse-space data of this row
-  int wa0 = 0, wna = 0, kloc = 0;
+  int wa0 = 0, wna = 0, kloc = 0, kf = 0, kl = -1;
+  CoarseRow crow{};
   bool live = false;
   double cr[3] = {0.0, 0.0, 0.0};
   if (COARSE) {
     wa0 = cs.wg_agg0[wg];
     wna = cs.wg_nagg[wg];
+    // partial-sum indices of every aggregate of the sheet (fixed for the launch)
+    const int ag0 = cs.inst_agg0[inst], nag = cs.inst_nagg[inst];
+    for (int e = tid; e < nag * kMaxAggWg; e += blockDim.x) {
+      const int t = e / kMaxAggWg, k = e - t * kMaxAggWg, a = ag0 + t;
+      int pi = -1;
+      if (k < cs.agg_nwg[a]) {
+        const int w2 = cs.agg_wg0[a] + k;
+        pi = w2 * kMaxWgAgg + (a - cs.wg_agg0[w2]);
+      }
+      s_pidx[e] = pi;
+    }
+    const int np = cs.inst_np[inst];
+    crow.X = cs.mat + cs.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;
+    crow.part = cs.part;
+    crow.nc = cs.inst_nc[inst];
+    crow.np = np;
+    crow.nrow = 6 * wna;
+    crow.ok = cs.ok[inst];
+    const int f = (tid >> 6) * 64;
+    if (f < nrows) {
+      kf = cs.vert_agg[row0 + f] - wa0;
+      kl = cs.vert_agg[row0 + min(nrows, f + 64) - 1] - wa0;
+    }
     if (act) {
       kloc = cs.vert_agg[i] - wa0;
       live = m.pinned[i] == 0;
@@ -1099,9 +1151,9 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   for (int c = 0; c < 3; ++c) u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
   bool ok = true;
   if (COARSE) {
-    coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, r);
+    coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
     ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
-    if (ok) coarse_correct(cs, inst, wa0, wna, kloc, live, cr, u, s_wc, s_e);
+    if (ok) coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
   }
   // w_0 = A u_0 needs the neighbours' u_0
   double* ub = w.zbuf;
@@ -1110,7 +1162,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
   }
   if (ok) ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
-  if (ok && act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+  if (ok && act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 
   double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
@@ -1128,7 +1180,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       if (act) {
         double ax[3];
-        spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
+        spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -1136,16 +1188,16 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       for (int c = 0; c < 3; ++c)
         u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
       if (COARSE) {
-        coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, r);
+        coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
         if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
-        coarse_correct(cs, inst, wa0, wna, kloc, live, cr, u, s_wc, s_e);
+        coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
       }
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
       }
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
-      if (act) spmv_row<TM>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -1163,7 +1215,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
         ml[c * R + tid] = mm[c];
       }
     }
-    if (COARSE) coarse_restrict(cs, wg, row0, nrows, wa0, wna, kloc, live, cr, wv);
+    if (COARSE) coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, wv);
     const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
@@ -1198,9 +1250,10 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       flag = ST_NOT_CONVERGED;
       break;
     }
+    PHASE_T(t5);
     if (COARSE) {
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
-      coarse_correct(cs, inst, wa0, wna, kloc, live, cr, mm, s_wc, s_e);
+      coarse_correct(crow, kloc, live, cr, mm, s_pidx, s_wc, s_red, s_e);
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -1208,15 +1261,17 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
           ml[c * R + tid] = mm[c];
         }
       }
+      PHASE_ADD(4, wall_clock64() - t5);
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      PHASE_ADD(5, wall_clock64() - t5);
       if (act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
     }
     nn[0] = nn[1] = nn[2] = 0.0;
     if (act) {
-      applynb<TM>(Am, As, Ai, 0, maxnz, g, nn);
+      applynb<TM, LDS_MATRIX>(Am, As, Ai, 0, maxnz, g, nn);
       for (int k0 = kChunk; k0 < maxnz; k0 += kChunk) {
         loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
-        applynb<TM>(Am, As, Ai, k0, maxnz, g, nn);
+        applynb<TM, LDS_MATRIX>(Am, As, Ai, k0, maxnz, g, nn);
       }
     }
     PHASE_T(t4);
@@ -1259,8 +1314,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   }
 #ifdef PHISFT_PHASES
   if (tid == 0 && wg < 512) {
-    for (int k = 0; k < 4; ++k) g_phase[wg][k] += ph[k];
-    g_phase[wg][4] += it;
+    for (int k = 0; k < 7; ++k) g_phase[wg][k] += ph[k];
+    g_phase[wg][7] += it;
   }
 #endif
   if (wg == iw0 && tid == 0) {
@@ -1614,7 +1669,8 @@ template <typename TM>
 size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc) {
   return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
          6 * sizeof(double) * rows +
-         (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 6 * kMaxWgAgg) : 0);
+         (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg) +
+                              sizeof(int) * (size_t)(coarse_nc / 6) * kMaxAggWg : 0);
 }
 
 template <typename TM>
@@ -1772,7 +1828,7 @@ extern "C" int phisft_read_phases(unsigned long long* out, int reset) {
   if (hipMemcpyFromSymbol(out, HIP_SYMBOL(phisft::g_phase), sizeof(phisft::g_phase)) != hipSuccess)
     return -1;
   if (reset) {
-    static unsigned long long zero[512][6];
+    static unsigned long long zero[512][8];
     if (hipMemcpyToSymbol(HIP_SYMBOL(phisft::g_phase), zero, sizeof(zero)) != hipSuccess) return -1;
   }
   return 0;

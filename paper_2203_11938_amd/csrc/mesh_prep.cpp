@@ -563,6 +563,7 @@ HostPlan make_plan(const HostLayout& L, int rows, int group) {
       const int w1 = P.inst_wg0[b] + (L.agg_v0[a + 1] - 1 - voff) / rows;
       P.agg_wg0[a] = w0;
       P.agg_nwg[a] = w1 - w0 + 1;
+      P.max_agg_wg = std::max(P.max_agg_wg, w1 - w0 + 1);
     }
   }
   return P;

@@ -50,7 +50,7 @@ struct HostPlan {
   std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
   std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets
   // overlap of workgroup row ranges and aggregates (both are runs of vertices)
-  int max_wg_agg = 0;
+  int max_wg_agg = 0, max_agg_wg = 0;
   std::vector<int> wg_agg0, wg_nagg;   // [nwg] first aggregate touched, count
   std::vector<int> agg_wg0, agg_nwg;   // [nagg] first workgroup touching, count
 };

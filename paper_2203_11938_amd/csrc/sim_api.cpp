@@ -225,7 +225,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
       HostPlan P = make_plan(L, rows, kBarrierGroup);
       P.lds_matrix = mode;
-      if (P.max_wg_agg > kMaxWgAgg) continue;
+      if (P.max_wg_agg > kMaxWgAgg || P.max_agg_wg > kMaxAggWg) continue;
       if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
       const int ng = (int)P.group_wg0.size() - 1;
       if (ng < best_groups) {

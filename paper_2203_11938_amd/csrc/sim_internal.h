@@ -82,7 +82,8 @@ struct Elem {
 // at the step's positions (P_i = 0 on pinned vertices; an aggregate with fewer than
 // three free, non-collinear vertices keeps translations only, one without free
 // vertices keeps none). A_c = P^T A P is dense per sheet (nc = 6 x aggregates).
-constexpr int kMaxWgAgg = 16;     // aggregates overlapping one solver workgroup
+constexpr int kMaxWgAgg = 4;      // aggregates overlapping one solver workgroup
+constexpr int kMaxAggWg = 4;      // solver workgroups overlapping one aggregate
 constexpr int kGjTile = 32;       // tile of the blocked Gauss-Jordan inversion
 
 struct Coarse {

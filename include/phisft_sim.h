@@ -122,8 +122,8 @@ typedef struct {
                                (default 64; 0 = block-Jacobi preconditioner only).
                                The preconditioner adds P A_c^-1 P^T, where P holds the
                                six rigid motions of every aggregate of nearby vertices
-                               and A_c = P^T A P is factored per step; a sheet with
-                               more than 128 aggregates uses larger ones. The solution
+                               and A_c = P^T A P is inverted per step; a sheet with
+                               more than 1024 aggregates uses larger ones. The solution
                                still meets cg_tol on the true residual.                 */
 } sim_options;
 

@@ -742,14 +742,19 @@ struct Barrier {
   int epoch;
 };
 
+// Polls with relaxed agent-scope loads (they read the coherent value without cache
+// maintenance) and acquires once when the target is reached: an acquire load in the
+// loop would invalidate this XCD's L2 on every poll, evicting the data that the
+// workgroups still computing on it are reading.
 __device__ __forceinline__ bool bounded_wait_ge(int* addr, int target, int* abort_flag) {
   int spins = 0;
-  while (__hip_atomic_load(addr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit ||
         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
       return false;
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
@@ -785,9 +790,11 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
       __hip_atomic_fetch_add(b.root, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       ok = bounded_wait_ge(b.root, e * b.gsize, abort_flag);
     } else {
-      const int old = __hip_atomic_fetch_add(b.gctr, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      const int old = __hip_atomic_fetch_add(b.gctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (old == e * b.gsize - 1) {  // last arriver of the group
-        __hip_atomic_fetch_add(b.root, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // acquire what the group's members released, then release it to the root
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_fetch_add(b.root, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         ok = bounded_wait_ge(b.root, e * b.ngroups, abort_flag);
         __hip_atomic_store(b.gflag, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       } else {
@@ -1007,7 +1014,6 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
                                                const double r[3], double y[3],
                                                const int* s_pidx, double* s_wc, double* s_red,
                                                double* s_e) {
-  constexpr int NR = 6 * kMaxWgAgg;
   if (!cr_.ok) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -1023,30 +1029,41 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
     s_wc[col] = wc;
   }
   __syncthreads();
-  const int chunk = (nc + nwaves - 1) / nwaves;
-  const int c0 = wave * chunk, c1 = min(nc, c0 + chunk);
-  if (lane < nrow) {
-    const double* __restrict__ xr = cr_.X + (size_t)lane * np;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int col = c0;
-    for (; col + 4 <= c1; col += 4) {
-      a0 += xr[col] * s_wc[col];
-      a1 += xr[col + 1] * s_wc[col + 1];
-      a2 += xr[col + 2] * s_wc[col + 2];
-      a3 += xr[col + 3] * s_wc[col + 3];
+  // rows wave, wave + nwaves, ... on this wavefront; lanes over 64-column tiles.
+  // Addresses are clamped into the matrix and the weight is zero past its end, so
+  // the loads of six tiles carry no branches and are issued together.
+  constexpr int MR = 6;
+  constexpr int TU = 6;
+  const int ntile = (nc + 63) / 64;
+  for (int qb = 0; wave + qb * nwaves < nrow; qb += MR) {   // groups of MR rows per wavefront
+    double acc[MR];
+#pragma unroll
+    for (int q = 0; q < MR; ++q) acc[q] = 0.0;
+    for (int t0 = 0; t0 < ntile; t0 += TU) {
+#pragma unroll
+      for (int t = 0; t < TU; ++t) {
+        const int col = (t0 + t) * 64 + lane;
+        const int colc = min(col, nc - 1);
+        const double wcv = col < nc ? s_wc[colc] : 0.0;
+#pragma unroll
+        for (int q = 0; q < MR; ++q) {
+          const int row = min(wave + (qb + q) * nwaves, nrow - 1);
+          acc[q] += cr_.X[(size_t)row * np + colc] * wcv;
+        }
+      }
     }
-    for (; col < c1; ++col) a0 += xr[col] * s_wc[col];
-    s_red[wave * NR + lane] = (a0 + a1) + (a2 + a3);
-  }
-  __syncthreads();
-  if (tid < nrow) {
-    double t = 0.0;
-    for (int w = 0; w < nwaves; ++w) t += s_red[w * NR + tid];
-    s_e[tid] = t;
+#pragma unroll
+    for (int q = 0; q < MR; ++q) {
+      const int row = wave + (qb + q) * nwaves;
+      if (row < nrow) {   // uniform per wavefront
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) s_red[row] = v;
+      }
+    }
   }
   __syncthreads();
   if (live) {
-    const double* e = s_e + 6 * kloc;
+    const double* e = s_red + 6 * kloc;
     y[0] += e[0] + (e[4] * r[2] - e[5] * r[1]);
     y[1] += e[1] + (e[5] * r[0] - e[3] * r[2]);
     y[2] += e[2] + (e[3] * r[1] - e[4] * r[0]);

@@ -86,8 +86,8 @@ struct sim_s {
 
 namespace {
 
-// aggregates per sheet at most (coarse dimension 6 x 128 = 768)
-constexpr int kCoarseMaxAggs = 128;
+// aggregates per sheet at most (coarse dimension 6 x 1024 = 6144)
+constexpr int kCoarseMaxAggs = 1024;
 
 sim_status bits_to_status(int bits) {
   if (bits & ST_TIMEOUT) return SIM_E_HIP;

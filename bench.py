@@ -83,7 +83,7 @@ def cpu_baseline(w, inst, sample_steps: int):
                        f"+ adjoint in one single-threaded FP64 call ({dt:.1f} s)")
 
 
-def sequential_comparison(w, insts, batched_ms, steps, membrane):
+def sequential_comparison(w, insts, batched_ms, steps, membrane, autotune):
     """The same gradient with one handle per sheet, launched one after the other
     on the same stream (warm-up excluded); returns the wall times and the ratio."""
     import numpy as np
@@ -95,7 +95,7 @@ def sequential_comparison(w, insts, batched_ms, steps, membrane):
         sim = S.Simulator([S.Sheet(inst.tris, inst.rest, inst.pins, *inst.material.as_tuple())],
                           dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
                           checkpoint_every=w.checkpoint_every, max_steps=w.steps,
-                          membrane=membrane)
+                          membrane=membrane, autotune=autotune)
         dt = sim.dtype
         x0 = torch.tensor(W.to_soa(inst.x0), dtype=dt, device=dev)
         F = torch.tensor(W.to_soa(inst.forces), dtype=dt, device=dev)
@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--workload", default="H")
     ap.add_argument("--cpu-sample-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the rule-based solver launch shape instead of timing the candidates")
     ap.add_argument("--membrane", default="exact", choices=["exact", "tension"],
                     help="membrane block of the step matrix")
     ap.add_argument("--sequential", action="store_true",
@@ -166,7 +168,7 @@ def main():
     sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
     sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
                       checkpoint_every=w.checkpoint_every, max_steps=w.steps,
-                      membrane=args.membrane)
+                      membrane=args.membrane, autotune=not args.no_autotune)
     dt = sim.dtype
     V = sim.n_verts
     x0 = torch.tensor(W.to_soa(np.concatenate([i.x0 for i in insts])), dtype=dt, device=dev)
@@ -244,11 +246,14 @@ def main():
                            matrix_precision=sim.matrix_precision, membrane=args.membrane,
                            coarse_aggregates=st["coarse_aggregates"],
                            coarse_max_dim=st["coarse_max_dim"], bytes_per_cg_iter=b_iter,
+                           autotuned=bool(st["autotuned"]),
+                           autotune_candidates=st["autotune_candidates"],
+                           lds_matrix=bool(st["solver_lds_matrix"]),
                            device_status=S.status_name(sim.status())),
                roofline=roof)
     if args.sequential and len(insts) > 1:
         out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
-                                                             args.membrane)
+                                                             args.membrane, not args.no_autotune)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps)

@@ -125,6 +125,11 @@ typedef struct {
                                and A_c = P^T A P is inverted per step; a sheet with
                                more than 1024 aggregates uses larger ones. The solution
                                still meets cg_tol on the true residual.                 */
+  int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
+                               (rows per workgroup, matrix in LDS or streamed) on the
+                               step system of the rest state and keeps the fastest;
+                               0 (default): fewest co-resident launches, then LDS-
+                               resident rows, then larger workgroups                     */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -147,6 +152,9 @@ typedef struct {
   double solver_ms;           /* their summed duration (HIP events on the call's stream) */
   int32_t coarse_aggregates;  /* aggregates of the coarse space over all sheets (0: none) */
   int32_t coarse_max_dim;     /* largest per-sheet coarse dimension (6 x aggregates) */
+  int32_t autotuned;          /* 1: the launch shape was chosen by measurement */
+  int32_t autotune_candidates;/* feasible launch shapes */
+  double autotune_ms_per_iter;/* measured time per CG iteration of the chosen shape */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,

@@ -156,6 +156,119 @@ char* adj_state(sim_t* s, int k, int c0, int n) {
   return state_at(s->seg, s, k - c0);
 }
 
+// Uploads a solver plan's tables and (re)allocates its plan-sized buffers.
+sim_status apply_plan(sim_t* s, const HostPlan& P) {
+  const HostLayout& L = s->L;
+  const bool coarse = L.nagg > 0;
+  SolverPlan& p = s->plan;
+  p.nwg = P.nwg;
+  p.rows = P.rows;
+  p.lds_matrix = P.lds_matrix;
+  p.wg_base = 0;
+  p.ngroups = (int)P.group_wg0.size() - 1;
+  for (int g = 0; g <= p.ngroups; ++g) p.group_wg0_host[g] = P.group_wg0[g];
+  TRY(upload(s, P.inst_grp0, &p.inst_grp0));
+  TRY(upload(s, P.wg_inst, &p.wg_inst));
+  TRY(upload(s, P.wg_row0, &p.wg_row0));
+  TRY(upload(s, P.wg_nrows, &p.wg_nrows));
+  TRY(upload(s, P.inst_wg0, &p.inst_wg0));
+  TRY(upload(s, P.inst_nwg, &p.inst_nwg));
+  void* q = nullptr;
+  TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q));
+  s->sw.red = (double*)q;
+  s->sw.barrier_ints = P.barrier_slots * kBarrierSlot;
+  TRY(alloc(s, (size_t)s->sw.barrier_ints * 4, &q));
+  s->sw.barrier = (int*)q;
+  if (coarse) {
+    Coarse& cs = s->coarse;
+    TRY(upload(s, P.wg_agg0, &cs.wg_agg0));
+    TRY(upload(s, P.wg_nagg, &cs.wg_nagg));
+    TRY(upload(s, P.agg_wg0, &cs.agg_wg0));
+    TRY(upload(s, P.agg_nwg, &cs.agg_nwg));
+    TRY(alloc(s, (size_t)p.nwg * kMaxWgAgg * 6 * 8, &q));
+    cs.part = (double*)q;
+  }
+  const bool lm = P.lds_matrix != 0;
+  const int cnc = coarse ? L.max_nc : 0;
+  hipError_t e = s->mprec == SIM_FP64
+      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc), L.maxnz, lm, coarse)
+      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc), L.maxnz, lm, coarse);
+  if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
+  s->plan_h = P;
+  s->stats.rows_per_block = p.rows;
+  s->stats.blocks = p.nwg;
+  s->stats.solver_lds_matrix = p.lds_matrix;
+  s->stats.solver_launches_per_solve = p.ngroups;
+  return SIM_OK;
+}
+
+// Measuring autotuner: builds the step system of the rest state (the sheets at rest,
+// zero velocity, gravity) with the real kernels, then times kTuneIters PCG
+// iterations of every feasible launch shape and keeps the fastest.
+constexpr int kTuneIters = 40;
+
+template <typename TM>
+sim_status autotune(sim_t* s, const std::vector<HostPlan>& cands, const std::vector<double>& xr,
+                    int* pick) {
+  const int nv = s->L.nv;
+  void* q = nullptr;
+  TRY(alloc(s, 3 * (size_t)nv * 8, &q));
+  double* x = (double*)q;
+  HIPCHECK(s, hipMemcpy(x, xr.data(), 3 * (size_t)nv * 8, hipMemcpyHostToDevice));
+  hipStream_t st = nullptr;
+  launch_fill_double(s->gv, 3L * nv, 0.0, st);
+  launch_elements(s->mesh, s->el, x, s->mat_default, s->status, st);
+  AssembleArgs<double, TM> a{};
+  a.v = s->gv;
+  a.forces = nullptr;
+  a.mat = s->mat_default;
+  a.h = s->h;
+  for (int k = 0; k < 3; ++k) a.g[k] = s->grav[k];
+  a.want_rhs = 1;
+  a.A = static_cast<TM*>(s->A);
+  a.Jinv = static_cast<TM*>(s->Jinv);
+  a.b = s->rhs;
+  a.status = s->status;
+  launch_assemble<double, TM>(s->mesh, s->el, a, st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, x, a.A, s->L.coarse_doubles, s->gja_count.data(),
+                          s->gjb_count.data(), st);
+  PcgArgs<TM> c{};
+  c.A = a.A;
+  c.Jinv = a.Jinv;
+  c.rhs = s->rhs;
+  c.sol = s->sol;
+  c.tol = 0.0;  // never met: every trial runs kTuneIters iterations
+  c.max_iter = kTuneIters;
+  c.status = s->status;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHECK(s, hipEventCreate(&e0));
+  HIPCHECK(s, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  for (size_t k = 0; k < cands.size(); ++k) {
+    TRY(apply_plan(s, cands[k]));
+    launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);  // warm-up
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 3; ++r) launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);
+    (void)hipEventRecord(e1, st);
+    HIPCHECK(s, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHECK(s, hipEventElapsedTime(&ms, e0, e1));
+    int bits = 0;
+    HIPCHECK(s, hipMemcpy(&bits, s->status, 4, hipMemcpyDeviceToHost));
+    // a trial stops at kTuneIters (not converged by design); any other condition
+    // disqualifies the candidate
+    if ((bits & ~ST_NOT_CONVERGED) == 0 && ms < best_ms) {
+      best_ms = ms;
+      *pick = (int)k;
+    }
+    HIPCHECK(s, hipMemset(s->status, 0, 4 * (s->L.ninst + 1)));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->stats.autotune_ms_per_iter = best_ms / (3.0 * kTuneIters);
+  return SIM_OK;
+}
+
 sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, const sim_options* opt) {
   sim_options o;
   sim_default_options(&o);
@@ -170,7 +283,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
         o.rows_per_block == 256) ||
       (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
       (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
-      !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20)))) {
+      !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20))) ||
+      (o.autotune != 0 && o.autotune != 1)) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
@@ -207,8 +321,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   std::vector<int> cands;
   if (o.rows_per_block) cands.push_back(o.rows_per_block);
   else cands = {256, 224, 192, 160, 152, 128, 96, 64};
-  bool placed = false;
-  int best_groups = 1 << 30;
+  std::vector<HostPlan> feasible;
+  int best = -1, best_groups = 1 << 30;
   for (int mode = 1; mode >= 0; --mode) {
     for (int rows : cands) {
       const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
@@ -228,25 +342,16 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       if (P.max_wg_agg > kMaxWgAgg || P.max_agg_wg > kMaxAggWg) continue;
       if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
       const int ng = (int)P.group_wg0.size() - 1;
+      feasible.push_back(P);
       if (ng < best_groups) {
-        s->plan_h = P;
+        best = (int)feasible.size() - 1;
         best_groups = ng;
-        placed = true;
       }
     }
   }
-  if (!placed) {
+  if (best < 0) {
     s->err = "mesh too large for the co-resident solver";
     return SIM_E_INVALID;
-  }
-  {
-    // the LDS attribute of the chosen solver variant (the search set it per candidate)
-    const bool lm = s->plan_h.lds_matrix != 0;
-    const int cnc = coarse ? L.max_nc : 0;
-    hipError_t e = s->mprec == SIM_FP64
-        ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, s->plan_h.rows, lm, cnc), L.maxnz, lm, coarse)
-        : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, s->plan_h.rows, lm, cnc), L.maxnz, lm, coarse);
-    if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   }
 
   // ---- upload geometry and tables
@@ -284,20 +389,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   const double* md = nullptr;
   TRY(upload(s, L.mat, &md));
   s->mat_default = const_cast<double*>(md);
-
-  SolverPlan& p = s->plan;
-  p.nwg = s->plan_h.nwg;
-  p.rows = s->plan_h.rows;
-  p.lds_matrix = s->plan_h.lds_matrix;
-  p.wg_base = 0;
-  p.ngroups = (int)s->plan_h.group_wg0.size() - 1;
-  for (int g = 0; g <= p.ngroups; ++g) p.group_wg0_host[g] = s->plan_h.group_wg0[g];
-  TRY(upload(s, s->plan_h.inst_grp0, &p.inst_grp0));
-  TRY(upload(s, s->plan_h.wg_inst, &p.wg_inst));
-  TRY(upload(s, s->plan_h.wg_row0, &p.wg_row0));
-  TRY(upload(s, s->plan_h.wg_nrows, &p.wg_nrows));
-  TRY(upload(s, s->plan_h.inst_wg0, &p.inst_wg0));
-  TRY(upload(s, s->plan_h.inst_nwg, &p.inst_nwg));
 
   // ---- coarse space
   Coarse& cs = s->coarse;
@@ -357,10 +448,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       s->gj_doubles += (long long)kGjTile * L.inst_np[b];
     }
     TRY(upload(s, boff, &cs.inst_boff));
-    TRY(upload(s, s->plan_h.wg_agg0, &cs.wg_agg0));
-    TRY(upload(s, s->plan_h.wg_nagg, &cs.wg_nagg));
-    TRY(upload(s, s->plan_h.agg_wg0, &cs.agg_wg0));
-    TRY(upload(s, s->plan_h.agg_nwg, &cs.agg_nwg));
   }
 
   // ---- workspace
@@ -387,9 +474,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, 3 * nv * 8, &q)); s->gv = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->sw.zbuf = (double*)q;
   TRY(alloc(s, 6 * nv * 8, &q)); s->sw.pbuf = (double*)q;
-  TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q)); s->sw.red = (double*)q;
-  s->sw.barrier_ints = s->plan_h.barrier_slots * kBarrierSlot;
-  TRY(alloc(s, (size_t)s->sw.barrier_ints * 4, &q)); s->sw.barrier = (int*)q;
   TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
   if (coarse) {
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
@@ -398,7 +482,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
     TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
-    TRY(alloc(s, (size_t)p.nwg * kMaxWgAgg * 6 * 8, &q)); cs.part = (double*)q;
   }
   TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
   const size_t st = (size_t)s->max_steps * ni;
@@ -420,11 +503,26 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   HIPCHECK(s, hipMemset(s->it_rec, 0, st * 4));
   HIPCHECK(s, hipMemset(s->it_adj, 0, st * 4));
   HIPCHECK(s, hipDeviceSynchronize());
+
+  // ---- solver launch shape: the rule's choice, or the fastest candidate measured on
+  // the step system of the rest state
+  s->stats.autotune_candidates = (int)feasible.size();
+  if (o.autotune && feasible.size() > 1) {
+    std::vector<double> xr(3 * nv);
+    for (int b = 0; b < L.ninst; ++b)
+      for (int q2 = 0; q2 < L.inst_nv[b]; ++q2) {
+        const int i = L.inst_voff[b] + q2, src = L.vold[i] - L.inst_voff[b];
+        for (int c = 0; c < 3; ++c) xr[(size_t)c * nv + i] = sheets[b].rest[3 * (size_t)src + c];
+      }
+    int pick = best;
+    TRY(s->mprec == SIM_FP64 ? autotune<double>(s, feasible, xr, &pick)
+                             : autotune<float>(s, feasible, xr, &pick));
+    best = pick;
+    s->stats.autotuned = 1;
+  }
+  TRY(apply_plan(s, feasible[best]));
+  HIPCHECK(s, hipDeviceSynchronize());
   s->stats.n_instances = L.ninst;
-  s->stats.rows_per_block = p.rows;
-  s->stats.blocks = p.nwg;
-  s->stats.solver_lds_matrix = p.lds_matrix;
-  s->stats.solver_launches_per_solve = p.ngroups;
   long nnzb = 0;
   for (int c : L.ell_col) nnzb += c >= 0;
   s->stats.nnz_blocks = nnzb;

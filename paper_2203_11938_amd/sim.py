@@ -59,7 +59,8 @@ class _Options(ctypes.Structure):
                 ("cg_max_iter", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
-                ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32)]
+                ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -71,7 +72,8 @@ class _Stats(ctypes.Structure):
                 ("solver_lds_matrix", ctypes.c_int32), ("solver_launches_per_solve", ctypes.c_int32),
                 ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
                 ("solver_ms", ctypes.c_double), ("coarse_aggregates", ctypes.c_int32),
-                ("coarse_max_dim", ctypes.c_int32)]
+                ("coarse_max_dim", ctypes.c_int32), ("autotuned", ctypes.c_int32),
+                ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double)]
 
 
 _lib = None
@@ -151,14 +153,17 @@ class Simulator:
     ``dt`` is the step h [s]; ``precision`` "fp32" or "fp64"; ``cg_tol`` the
     relative residual at which each CG solve stops; ``checkpoint_every`` k > 0
     keeps every k-th state and recomputes the rest in the adjoint; ``membrane``
-    selects the system matrix's membrane block ("exact" Hessian or "tension").
+    selects the system matrix's membrane block ("exact" Hessian or "tension");
+    ``coarse_size`` sets the vertices per aggregate of the solver's coarse space
+    (0: block-Jacobi only); ``autotune`` times the feasible solver launch shapes at
+    creation and keeps the fastest.
     """
 
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
                  cg_tol: float = 1e-7, cg_max_iter: int = 20000, checkpoint_every: int = 0,
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
                  membrane: str = "exact", matrix_precision: str = "fp64",
-                 coarse_size: Optional[int] = None):
+                 coarse_size: Optional[int] = None, autotune: bool = False):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -177,6 +182,7 @@ class Simulator:
         opt.matrix_precision = SIM_FP32 if matrix_precision == "fp32" else SIM_FP64
         if coarse_size is not None:
             opt.coarse_size = coarse_size
+        opt.autotune = 1 if autotune else 0
         self.matrix_precision = matrix_precision
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32

@@ -103,3 +103,39 @@ def test_batch_matches_single_instances():
         assert np.array_equal(batched["forces"][:, sl], single["forces"]), b
         assert np.array_equal(batched["x0"][sl], single["x0"]), b
         assert np.array_equal(batched["material"][b], single["material"][0]), b
+
+
+def test_autotuned_handle_matches_oracle():
+    """The measuring autotuner only changes the solver's launch shape: results stay
+    within the parity gates of the 32x32 workload."""
+    w = W.workload("C2", steps=30)
+    inst = as_given(W.make_instances(w)[0], w.precision)
+    tgt = targets(w)
+    s = make_sim(w, [inst], autotune=True)
+    st = s.stats()
+    note(f"autotune: {st['autotune_candidates']} launch shapes timed, chose rows "
+         f"{st['rows_per_block']} (LDS matrix {st['solver_lds_matrix']}), "
+         f"{1e3 * st['autotune_ms_per_iter']:.1f} us per CG iteration")
+    assert st["autotuned"] == 1 and st["autotune_candidates"] > 1
+    out = gpu_run(s, w, [inst], [tgt])
+    ref = oracle_reference(w, inst, tgt)
+    assert rel(out["x"][-1], ref["x"][-1]) <= 1e-5
+    assert rel(out["forces"], ref["forces"]) <= 1e-4
+    assert rel(out["x0"], ref["x0"]) <= 1e-4
+    s.close()
+
+
+def test_block_jacobi_only_matches_oracle():
+    """The solver without its coarse space (coarse_size 0) meets the same gates."""
+    w = W.workload("C2", steps=30)
+    inst = as_given(W.make_instances(w)[0], w.precision)
+    tgt = targets(w)
+    s = make_sim(w, [inst], coarse_size=0)
+    assert s.stats()["coarse_aggregates"] == 0
+    out = gpu_run(s, w, [inst], [tgt])
+    ref = oracle_reference(w, inst, tgt)
+    note(f"block-Jacobi only: cg iters fwd {out['stats']['cg_iters_forward']}")
+    assert rel(out["x"][-1], ref["x"][-1]) <= 1e-5
+    assert rel(out["forces"], ref["forces"]) <= 1e-4
+    assert rel(out["x0"], ref["x0"]) <= 1e-4
+    s.close()

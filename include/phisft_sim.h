@@ -123,7 +123,7 @@ typedef struct {
                                The preconditioner adds P A_c^-1 P^T, where P holds the
                                six rigid motions of every aggregate of nearby vertices
                                and A_c = P^T A P is inverted per step; a sheet with
-                               more than 1024 aggregates uses larger ones. The solution
+                               more than 320 aggregates uses larger ones. The solution
                                still meets cg_tol on the true residual.                 */
   int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
                                (rows per workgroup, matrix in LDS or streamed) on the

@@ -863,30 +863,30 @@ __device__ __forceinline__ void collect3(const double* red_slot, int iw0, int nw
 // neighbours gathered per batch of independent loads
 constexpr int kChunk = GATHER_CHUNK;
 
-// Gather kChunk of the row's neighbour values of v, starting at slot k0 ([3][nv] in
-// global memory; entries of rows owned by this workgroup from the LDS copy vl
-// [3][R] when vl is given). All loads are issued before any is used.
+// Gather kChunk of the row's neighbour values, starting at slot k0, from the
+// workgroup's LDS copy vl [3][RH] of the vector: own rows at their local index, the
+// halo (neighbour rows of other workgroups, loaded after the barrier) behind them.
+// Cl holds those local indices.
 __device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int tid, int k0,
-                                       int maxnz, int nv, int row0, int nrows,
-                                       const double* __restrict__ vg,
-                                       const double* __restrict__ vl, double g[3][kChunk]) {
+                                       int maxnz, const double* __restrict__ vl, int RH,
+                                       double g[3][kChunk]) {
+  // slots past maxnz repeat the last one; applynb skips them
 #pragma unroll
   for (int k = 0; k < kChunk; ++k) {
-    if (k0 + k < maxnz) {
-      const int j = Cl[(k0 + k) * R + tid];
-      const int lj = j - row0;
-      if (vl != nullptr && (unsigned)lj < (unsigned)nrows) {
-        g[0][k] = vl[lj];
-        g[1][k] = vl[R + lj];
-        g[2][k] = vl[2 * R + lj];
-      } else {
-        g[0][k] = vg[j];
-        g[1][k] = vg[nv + j];
-        g[2][k] = vg[2 * nv + j];
-      }
-    } else {
-      g[0][k] = g[1][k] = g[2][k] = 0.0;
-    }
+    const int j = Cl[min(k0 + k, maxnz - 1) * R + tid];
+    g[0][k] = vl[j];
+    g[1][k] = vl[RH + j];
+    g[2][k] = vl[2 * RH + j];
+  }
+}
+
+// Halo of the vector vg ([3][nv] in global memory) into vl[c][R + h].
+__device__ __forceinline__ void halo_load(const double* __restrict__ vg, int nv,
+                                          const int* __restrict__ hidx, int nh,
+                                          double* __restrict__ vl, int R, int RH) {
+  for (int e = threadIdx.x; e < 3 * nh; e += blockDim.x) {
+    const int c = e / nh, h = e - c * nh;
+    vl[c * RH + R + h] = vg[(size_t)c * nv + hidx[h]];
   }
 }
 
@@ -915,27 +915,20 @@ __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, i
   }
 }
 
-// y = A v for this thread's row, v from global memory (and LDS when vl is given).
+// y = A v for this thread's row, v from the workgroup's LDS copy (own rows + halo).
 template <typename TM, bool SB>
 __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
                                          const int* __restrict__ Cl, int R, int tid, int maxnz,
-                                         int nv, int row0, int nrows,
-                                         const double* __restrict__ vg,
-                                         const double* __restrict__ vl, double y[3]) {
+                                         const double* __restrict__ vl, int RH, double y[3]) {
   y[0] = y[1] = y[2] = 0.0;
   for (int k0 = 0; k0 < maxnz; k0 += kChunk) {
     double g[3][kChunk];
-    loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, vg, vl, g);
+    loadnb(Cl, R, tid, k0, maxnz, vl, RH, g);
     applynb<TM, SB>(Am, stride, idx, k0, maxnz, g, y);
   }
 }
 
 constexpr int kMaxRestarts = 16;
-#ifndef LOCAL_GATHER
-#define LOCAL_GATHER 1
-#endif
-// neighbours owned by the same workgroup are read from its LDS copy of m
-constexpr bool kLocalGather = LOCAL_GATHER;
 
 // Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
 // reduction per iteration, (r,u), (w,u), (r,r), whose cluster barrier also
@@ -1018,15 +1011,27 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int nc = cr_.nc, np = cr_.np, nrow = cr_.nrow;
-  for (int col = tid; col < nc; col += blockDim.x) {
-    const int t = col / 6, q = col - 6 * t;
-    double wc = 0.0;
+  // four columns per pass; index -1 (no partial) reads entry 0 with weight 0, so the
+  // loads carry no branches and a pass issues them together
+  constexpr int CU = 4;
+  for (int col0 = tid; col0 < nc; col0 += CU * blockDim.x) {
+    double wc[CU];
 #pragma unroll
-    for (int k = 0; k < kMaxAggWg; ++k) {
-      const int pi = s_pidx[t * kMaxAggWg + k];
-      if (pi >= 0) wc += cr_.part[(size_t)pi * 6 + q];
+    for (int u = 0; u < CU; ++u) {
+      const int col = min(col0 + u * (int)blockDim.x, nc - 1);
+      const int t = col / 6, q = col - 6 * t;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxAggWg; ++k) {
+        const int pi = s_pidx[t * kMaxAggWg + k];
+        const double v = cr_.part[(size_t)max(pi, 0) * 6 + q];
+        acc += pi >= 0 ? v : 0.0;
+      }
+      wc[u] = acc;
     }
-    s_wc[col] = wc;
+#pragma unroll
+    for (int u = 0; u < CU; ++u)
+      if (col0 + u * (int)blockDim.x < nc) s_wc[col0 + u * blockDim.x] = wc[u];
   }
   __syncthreads();
   // rows wave, wave + nwaves, ... on this wavefront; lanes over 64-column tiles.
@@ -1084,16 +1089,19 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   const int nrows = plan.wg_nrows[wg];
   const int iw0 = plan.inst_wg0[inst], nwg = plan.inst_nwg[inst];
   // R rows per workgroup (the LDS stride); the block has R rounded up to whole
-  // wavefronts so every lane of every wave exists for the cross-lane reductions
-  const int tid = threadIdx.x, R = plan.rows;
+  // wavefronts so every lane of every wave exists for the cross-lane reductions.
+  // RH: R plus the largest halo, rounded up to 8 (the stride of the vector copies)
+  const int tid = threadIdx.x, R = plan.rows, RH = R + (plan.max_halo + 7) / 8 * 8;
   const int nv = m.nv, maxnz = m.maxnz;
   const bool act = tid < nrows;
   const int i = row0 + (act ? tid : 0);
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
+  const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
 
-  double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][R]
-  int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)R);            // [maxnz][R]
-  TM* Al = reinterpret_cast<TM*>(Cl + (size_t)maxnz * R);          // [maxnz][9][R] (LDS mode)
+  double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][RH]
+  int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)RH);           // [maxnz][R] local columns
+  int* s_hidx = Cl + (size_t)maxnz * R;                            // [RH - R] halo rows
+  TM* Al = reinterpret_cast<TM*>(s_hidx + (RH - R));               // [maxnz][9][R] (LDS mode)
   // coarse: w_c [max nc], row sums [waves][24], e [24], partial-sum indices
   // [aggregates][kMaxAggWg]
   double* s_wc = reinterpret_cast<double*>(Al + (LDS_MATRIX ? (size_t)maxnz * 9 * R : 0));
@@ -1106,15 +1114,16 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   const int Ai = LDS_MATRIX ? tid : i;
   if (act) {
     for (int k = 0; k < maxnz; ++k) {
-      int j = m.ell_col[k * nv + i];
-      Cl[k * R + tid] = j < 0 ? i : j;
+      Cl[k * R + tid] = plan.lcol[k * nv + i];
       if (LDS_MATRIX) {
+        const int j = m.ell_col[k * nv + i];
 #pragma unroll
         for (int q = 0; q < 9; ++q)
           Al[(k * 9 + q) * R + tid] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
       }
     }
   }
+  for (int h = tid; h < nh; h += blockDim.x) s_hidx[h] = plan.halo_idx[h0 + h];
   // coarse-space data of this row
   int wa0 = 0, wna = 0, kloc = 0, kf = 0, kl = -1;
   CoarseRow crow{};
@@ -1172,14 +1181,24 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
     if (ok) coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
   }
-  // w_0 = A u_0 needs the neighbours' u_0
+  // w_0 = A u_0 needs the neighbours' u_0 (LDS copy of parity 1; the loop starts at 0)
   double* ub = w.zbuf;
-  if (act) {
+  {
+    double* ul = mL + 3 * (size_t)RH;
+    if (act) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
+      for (int c = 0; c < 3; ++c) {
+        ub[c * nv + i] = u[c];
+        ul[c * RH + tid] = u[c];
+      }
+    }
+    if (ok) ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
+    if (ok) {
+      halo_load(ub, nv, s_hidx, nh, ul, R, RH);
+      __syncthreads();
+      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, ul, RH, wv);
+    }
   }
-  if (ok) ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
-  if (ok && act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
 
   double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
@@ -1187,17 +1206,23 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   while (ok) {
     if (restart) {
       // Restart the recurrences from the true residual r = b - A x (x published
-      // through the pbuf slot that no workgroup reads in this phase).
+      // through the pbuf slot and the LDS copy that no workgroup reads in this phase).
       restart = false;
       double* xb = w.pbuf + (size_t)((it + 1) & 1) * 3 * nv;
+      double* xl = mL + (size_t)((it + 1) & 1) * 3 * RH;
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xb[c * nv + i] = x[c];
+        for (int c = 0; c < 3; ++c) {
+          xb[c * nv + i] = x[c];
+          xl[c * RH + tid] = x[c];
+        }
       }
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      halo_load(xb, nv, s_hidx, nh, xl, R, RH);
+      __syncthreads();
       if (act) {
         double ax[3];
-        spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, xb, nullptr, ax);
+        spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -1209,12 +1234,18 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
         if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
         coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
       }
+      __syncthreads();  // every thread is done reading xl before it is overwritten
       if (act) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ub[c * nv + i] = u[c];
+        for (int c = 0; c < 3; ++c) {
+          ub[c * nv + i] = u[c];
+          xl[c * RH + tid] = u[c];
+        }
       }
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
-      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, nv, row0, nrows, ub, nullptr, wv);
+      halo_load(ub, nv, s_hidx, nh, xl, R, RH);
+      __syncthreads();
+      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -1222,14 +1253,14 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     }
     const int par = it & 1;
     double* mb = w.pbuf + (size_t)par * 3 * nv;
-    double* ml = mL + (size_t)par * 3 * R;
+    double* ml = mL + (size_t)par * 3 * RH;
 #pragma unroll
     for (int c = 0; c < 3; ++c) mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
     if (!COARSE && act) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mb[c * nv + i] = mm[c];
-        ml[c * R + tid] = mm[c];
+        ml[c * RH + tid] = mm[c];
       }
     }
     if (COARSE) coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, wv);
@@ -1242,9 +1273,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     PHASE_T(t1);
     if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
-    // issue the first kChunk loads of the SpMV gather and the partial-sum loads together
-    double g[3][kChunk];
-    if (!COARSE && act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
+    // the halo of m and the partial sums are loaded together
+    if (!COARSE) halo_load(mb, nv, s_hidx, nh, ml, R, RH);
     collect3(red_slot, iw0, nwg, s_out);
     __syncthreads();
     const double gamma = s_out[0], delta = s_out[1];
@@ -1275,22 +1305,17 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           mb[c * nv + i] = mm[c];
-          ml[c * R + tid] = mm[c];
+          ml[c * RH + tid] = mm[c];
         }
       }
       PHASE_ADD(4, wall_clock64() - t5);
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      halo_load(mb, nv, s_hidx, nh, ml, R, RH);
+      __syncthreads();
       PHASE_ADD(5, wall_clock64() - t5);
-      if (act) loadnb(Cl, R, tid, 0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
     }
-    nn[0] = nn[1] = nn[2] = 0.0;
-    if (act) {
-      applynb<TM, LDS_MATRIX>(Am, As, Ai, 0, maxnz, g, nn);
-      for (int k0 = kChunk; k0 < maxnz; k0 += kChunk) {
-        loadnb(Cl, R, tid, k0, maxnz, nv, row0, nrows, mb, kLocalGather ? ml : nullptr, g);
-        applynb<TM, LDS_MATRIX>(Am, As, Ai, k0, maxnz, g, nn);
-      }
-    }
+    if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, ml, RH, nn);
+    else nn[0] = nn[1] = nn[2] = 0.0;
     PHASE_T(t4);
     PHASE_ADD(0, t1 - t0);
     PHASE_ADD(1, t2 - t1);
@@ -1683,9 +1708,10 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
 }
 
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc) {
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo) {
+  const size_t rh = rows + (size_t)(max_halo + 7) / 8 * 8;
   return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
-         6 * sizeof(double) * rows +
+         6 * sizeof(double) * rh + sizeof(int) * (rh - rows) +
          (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg) +
                               sizeof(int) * (size_t)(coarse_nc / 6) * kMaxAggWg : 0);
 }
@@ -1722,7 +1748,8 @@ template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
                 const PcgArgs<TM>& a, hipStream_t st) {
   const bool coarse = cs.nagg > 0;
-  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0);
+  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0,
+                                 plan.max_halo);
   launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
@@ -1816,7 +1843,7 @@ PHISFT_INSTANTIATE_ASM(double, float)
 PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template size_t pcg_lds_bytes<T>(int, int, bool, int);                                         \
+  template size_t pcg_lds_bytes<T>(int, int, bool, int, int);                                    \
   template hipError_t pcg_prepare<T>(size_t, int, bool, bool);                                   \
   template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int*);                      \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \

@@ -545,6 +545,36 @@ HostPlan make_plan(const HostLayout& L, int rows, int group) {
     P.nwg += k;
   }
   P.barrier_slots = slot;
+  // halo of every workgroup and the local column table
+  {
+    const int nv = L.nv, mz = L.maxnz;
+    P.lcol.assign((size_t)mz * nv, 0);
+    P.halo_ptr.assign(1, 0);
+    std::vector<int> h;
+    for (int w = 0; w < P.nwg; ++w) {
+      const int r0 = P.wg_row0[w], n = P.wg_nrows[w];
+      h.clear();
+      for (int i = r0; i < r0 + n; ++i)
+        for (int k = 0; k < mz; ++k) {
+          const int j = L.ell_col[(size_t)k * nv + i];
+          if (j >= 0 && (j < r0 || j >= r0 + n)) h.push_back(j);
+        }
+      std::sort(h.begin(), h.end());
+      h.erase(std::unique(h.begin(), h.end()), h.end());
+      for (int i = r0; i < r0 + n; ++i)
+        for (int k = 0; k < mz; ++k) {
+          const int j = L.ell_col[(size_t)k * nv + i];
+          int loc;
+          if (j < 0) loc = i - r0;
+          else if (j >= r0 && j < r0 + n) loc = j - r0;
+          else loc = rows + (int)(std::lower_bound(h.begin(), h.end(), j) - h.begin());
+          P.lcol[(size_t)k * nv + i] = loc;
+        }
+      P.halo_idx.insert(P.halo_idx.end(), h.begin(), h.end());
+      P.halo_ptr.push_back((int)P.halo_idx.size());
+      P.max_halo = std::max(P.max_halo, (int)h.size());
+    }
+  }
   // workgroup / aggregate overlaps (both are runs of consecutive vertices)
   if (L.nagg > 0) {
     P.wg_agg0.resize(P.nwg);

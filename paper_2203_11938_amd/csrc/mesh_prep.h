@@ -53,6 +53,11 @@ struct HostPlan {
   int max_wg_agg = 0, max_agg_wg = 0;
   std::vector<int> wg_agg0, wg_nagg;   // [nwg] first aggregate touched, count
   std::vector<int> agg_wg0, agg_nwg;   // [nagg] first workgroup touching, count
+  // neighbour rows owned by other workgroups (the halo) and the local column table:
+  // lcol[k][i] = j - row0 for a column j of the workgroup's own rows, rows + h for the
+  // h-th halo row, the row's own local index for a padding slot
+  int max_halo = 0;
+  std::vector<int> halo_ptr, halo_idx, lcol;
 };
 
 // Splits the sheets (in order) into solver launches of at most `capacity`

@@ -46,6 +46,13 @@ struct sim_s {
   SolverWork sw{};
   Coarse coarse{};
   long long gj_doubles = 0;               // per-sheet [np][32] blocks of the inversion
+  // per-step coarse operators kept for the adjoint (inverse, offsets, flags); slot of
+  // step s: s - 1 (every state stored) or (s - 1) % k (checkpoints every k)
+  int cslots = 0;
+  double* cmat_store = nullptr;
+  double* crel_store = nullptr;
+  int* cok_store = nullptr;
+  std::vector<int> slot_step;             // step held by each slot, 0 = none
   std::vector<int> gja_count, gjb_count;  // inversion tasks per pivot step
   void* A = nullptr;
   void* Jinv = nullptr;
@@ -86,8 +93,11 @@ struct sim_s {
 
 namespace {
 
-// aggregates per sheet at most (coarse dimension 6 x 1024 = 6144)
-constexpr int kCoarseMaxAggs = 1024;
+// aggregates per sheet at most (coarse dimension 6 x 320 = 1920): beyond it the dense
+// coarse inverse costs more per step and per iteration than its fewer iterations save
+constexpr int kCoarseMaxAggs = 320;
+// device memory for coarse operators kept between the forward pass and the adjoint
+constexpr double kCoarseStoreCap = 16.0 * (1 << 30);
 
 sim_status bits_to_status(int bits) {
   if (bits & ST_TIMEOUT) return SIM_E_HIP;
@@ -173,6 +183,10 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   TRY(upload(s, P.wg_nrows, &p.wg_nrows));
   TRY(upload(s, P.inst_wg0, &p.inst_wg0));
   TRY(upload(s, P.inst_nwg, &p.inst_nwg));
+  p.max_halo = P.max_halo;
+  TRY(upload(s, P.halo_ptr, &p.halo_ptr));
+  TRY(upload(s, P.halo_idx, &p.halo_idx));
+  TRY(upload(s, P.lcol, &p.lcol));
   void* q = nullptr;
   TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q));
   s->sw.red = (double*)q;
@@ -191,8 +205,10 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   const bool lm = P.lds_matrix != 0;
   const int cnc = coarse ? L.max_nc : 0;
   hipError_t e = s->mprec == SIM_FP64
-      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc), L.maxnz, lm, coarse)
-      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc), L.maxnz, lm, coarse);
+      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo), L.maxnz, lm,
+                            coarse)
+      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo), L.maxnz, lm,
+                           coarse);
   if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   s->plan_h = P;
   s->stats.rows_per_block = p.rows;
@@ -327,8 +343,10 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     for (int rows : cands) {
       const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
       const int cnc = coarse ? L.max_nc : 0;
-      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc)
-                       : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc);
+      HostPlan P = make_plan(L, rows, kBarrierGroup);
+      P.lds_matrix = mode;
+      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P.max_halo)
+                       : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P.max_halo);
       if (lds > lds_cap) continue;
       hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse)
                          : pcg_prepare<float>(lds, L.maxnz, lm, coarse);
@@ -337,8 +355,6 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, &per_cu)
               : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, &per_cu);
       if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
-      HostPlan P = make_plan(L, rows, kBarrierGroup);
-      P.lds_matrix = mode;
       if (P.max_wg_agg > kMaxWgAgg || P.max_agg_wg > kMaxAggWg) continue;
       if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
       const int ng = (int)P.group_wg0.size() - 1;
@@ -482,6 +498,15 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
     TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
+    const int want = s->ckpt > 0 ? s->ckpt : s->max_steps;
+    const double slot_bytes = 8.0 * ((double)L.coarse_doubles + 3.0 * nv) + 4.0 * ni;
+    if (want * slot_bytes <= kCoarseStoreCap) {
+      s->cslots = want;
+      TRY(alloc(s, (size_t)want * L.coarse_doubles * 8, &q)); s->cmat_store = (double*)q;
+      TRY(alloc(s, (size_t)want * 3 * nv * 8, &q)); s->crel_store = (double*)q;
+      TRY(alloc(s, (size_t)want * ni * 4, &q)); s->cok_store = (int*)q;
+      s->slot_step.assign(want, 0);
+    }
   }
   TRY(alloc(s, 4 * (ni + 1), &q)); s->status = (int*)q;
   const size_t st = (size_t)s->max_steps * ni;
@@ -531,9 +556,24 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   return SIM_OK;
 }
 
+// The coarse operator of step `step`: its stored slot when the handle keeps them
+// (*have: the slot already holds that step), else the shared per-step buffers.
+Coarse coarse_for_step(sim_t* s, int step, bool* have) {
+  Coarse c = s->coarse;
+  *have = false;
+  if (s->cslots == 0 || c.nagg == 0) return c;
+  const int slot = s->ckpt > 0 ? (step - 1) % s->ckpt : step - 1;
+  c.mat = s->cmat_store + (size_t)slot * s->L.coarse_doubles;
+  c.crel = s->crel_store + (size_t)slot * 3 * s->L.nv;
+  c.ok = s->cok_store + (size_t)slot * s->L.ninst;
+  *have = s->slot_step[slot] == step;
+  s->slot_step[slot] = step;
+  return c;
+}
+
 // Solver launch bracketed by timing events when timing is enabled.
 template <typename TM>
-void timed_pcg(sim_t* s, const PcgArgs<TM>& c, hipStream_t st) {
+void timed_pcg(sim_t* s, const Coarse& cs, const PcgArgs<TM>& c, hipStream_t st) {
   if (s->timing) {
     if (s->ev_used + 2 > s->ev.size()) {
       for (int k = 0; k < 64; ++k) {
@@ -544,19 +584,19 @@ void timed_pcg(sim_t* s, const PcgArgs<TM>& c, hipStream_t st) {
     }
     if (s->ev_used + 2 <= s->ev.size()) {
       (void)hipEventRecord(s->ev[s->ev_used], st);
-      launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);
+      launch_pcg<TM>(s->mesh, s->plan, s->sw, cs, c, st);
       (void)hipEventRecord(s->ev[s->ev_used + 1], st);
       s->ev_used += 2;
       return;
     }
   }
-  launch_pcg<TM>(s->mesh, s->plan, s->sw, s->coarse, c, st);
+  launch_pcg<TM>(s->mesh, s->plan, s->sw, cs, c, st);
 }
 
 // ---------------------------------------------------------- step sequences
 template <typename T, typename TM>
-void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* mat, T* xout,
-                  int* iters, double* resid, hipStream_t st) {
+void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, const double* mat,
+                  T* xout, int* iters, double* resid, hipStream_t st) {
   const int nv = s->L.nv;
   const double* xp = reinterpret_cast<const double*>(sp);
   const double* vp = xp + 3 * (size_t)nv;
@@ -575,7 +615,9 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   a.b = s->rhs;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
-  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
+  bool have = false;
+  const Coarse cs = coarse_for_step(s, step, &have);
+  launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
                           s->gjb_count.data(), st);
   PcgArgs<TM> c{};
   c.A = a.A;
@@ -587,7 +629,7 @@ void forward_step(sim_t* s, const char* sp, char* sn, const T* F, const double* 
   c.iters = iters;
   c.resid = resid;
   c.status = s->status;
-  timed_pcg<TM>(s, c, st);
+  timed_pcg<TM>(s, cs, c, st);
   launch_update<T>(s->mesh, xp, vp, s->sol, s->h, xn, vn, xout, s->status, st);
 }
 
@@ -612,7 +654,7 @@ sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x
       xo = static_cast<T*>(x_out) + f * 3 * (size_t)nv;
       ++f;
     }
-    forward_step<T, TM>(s, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
+    forward_step<T, TM>(s, k, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
                     s->material, xo, s->it_fwd + (size_t)(k - 1) * ni,
                     s->res_fwd + (size_t)(k - 1) * ni, st);
   }
@@ -643,8 +685,13 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   a.b = nullptr;
   a.status = s->status;
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
-  launch_coarse_setup<TM>(s->mesh, s->coarse, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
-                          s->gjb_count.data(), st);
+  // the step's coarse operator: kept from the forward pass or the recompute when the
+  // handle stores them, else rebuilt (the same kernels on the same inputs)
+  bool have = false;
+  const Coarse cs = coarse_for_step(s, k, &have);
+  if (!have)
+    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
+                            s->gjb_count.data(), st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -655,7 +702,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   c.iters = s->it_adj + (size_t)(k - 1) * ni;
   c.resid = s->res_adj + (size_t)(k - 1) * ni;
   c.status = s->status;
-  timed_pcg<TM>(s, c, st);
+  timed_pcg<TM>(s, cs, c, st);
   AdjArgs<T> j{};
   j.x = xp;
   j.vp = vp;
@@ -690,7 +737,7 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
     if (s->ckpt != 0) {
       // recompute the interior states of the segment from its checkpoint
       for (int q = c0 + 1; q < c1; ++q)
-        forward_step<T, TM>(s, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
+        forward_step<T, TM>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
                         s->material, nullptr, s->it_rec + (size_t)(q - 1) * ni,
                         s->res_rec + (size_t)(q - 1) * ni, st);
     }

@@ -148,6 +148,10 @@ struct SolverPlan {
   const int* inst_wg0;     // [ninst]
   const int* inst_nwg;     // [ninst]
   const int* inst_grp0;    // [ninst] first group slot (counter, flag pairs) of the sheet
+  int max_halo;            // largest halo (neighbour rows of other workgroups)
+  const int* halo_ptr;     // [nwg+1]
+  const int* halo_idx;     // halo rows of each workgroup (global vertex ids)
+  const int* lcol;         // [maxnz][nv] local columns: own row j - row0, halo rows + h
 };
 
 // Solver scratch (device).

@@ -62,5 +62,28 @@ extern "C" int layout_check(int nsheets, const int* nv, const int* nt, const int
       if (w < 0 || a - P.wg_agg0[w] < 0 || a - P.wg_agg0[w] >= P.wg_nagg[w]) ++bad;
     }
   out_counts[8] = bad;
+  // halo tables: every local column names the right vertex
+  int hbad = 0;
+  for (int w = 0; w < P.nwg; ++w) {
+    const int r0 = P.wg_row0[w], n = P.wg_nrows[w];
+    const int h0 = P.halo_ptr[w], nh = P.halo_ptr[w + 1] - h0;
+    if (nh > P.max_halo) ++hbad;
+    for (int h = 0; h < nh; ++h) {
+      const int j = P.halo_idx[h0 + h];
+      if (j >= r0 && j < r0 + n) ++hbad;          // own rows are not halo
+      if (h > 0 && P.halo_idx[h0 + h - 1] >= j) ++hbad;  // sorted, unique
+    }
+    for (int i = r0; i < r0 + n; ++i)
+      for (int k = 0; k < L.maxnz; ++k) {
+        const int j = L.ell_col[(size_t)k * L.nv + i], loc = P.lcol[(size_t)k * L.nv + i];
+        int named;
+        if (loc < 0 || loc >= rows + nh) { ++hbad; continue; }
+        named = loc < rows ? r0 + loc : P.halo_idx[h0 + loc - rows];
+        if (loc < rows && loc >= n) ++hbad;
+        if (named != (j < 0 ? i : j)) ++hbad;
+      }
+  }
+  out_counts[9] = hbad;
+  out_counts[10] = P.max_halo;
   return 0;
 }

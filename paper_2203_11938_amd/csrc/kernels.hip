@@ -548,6 +548,89 @@ __global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const 
   }
 }
 
+// Middle level, one wavefront per run of kMid vertices: offsets of its members from
+// the centroid of its free vertices, its 6x6 diagonal block of P1^T A P1 (the same
+// block formula as the coarse operator) and that block's inverse. Unused modes get a
+// zero row and column in the inverse; a block that is not positive definite gives a
+// zero inverse (the run then adds nothing to the preconditioner).
+template <typename TM>
+__global__ void __launch_bounds__(64) k_mid_setup(Mesh m, Coarse c, const double* __restrict__ x,
+                                                  const TM* __restrict__ A) {
+  __shared__ double sr[3][kMid];
+  const int a = blockIdx.x, lane = threadIdx.x, nv = m.nv;
+  const int v0 = c.mid_v0[a], v1 = c.mid_v0[a + 1], modes = c.mid_modes[a];
+  const int i = v0 + lane;
+  const bool mem = lane < kMid && i < v1;
+  const bool fr = mem && !m.pinned[i];
+  double s3[3], cnt = wave_sum(fr ? 1.0 : 0.0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s3[k] = wave_sum(fr ? x[k * nv + i] : 0.0);
+  if (lane < kMid) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double r = (fr && modes == 6) ? x[k * nv + i] - s3[k] / cnt : 0.0;
+      sr[k][lane] = r;
+      if (mem) c.mid_crel[k * nv + i] = r;
+    }
+  }
+  __syncthreads();
+  double acc[36];
+#pragma unroll
+  for (int e = 0; e < 36; ++e) acc[e] = 0.0;
+  for (int t = c.mid_ptr[a] + lane; t < c.mid_ptr[a + 1]; t += 64) {
+    const int sl = c.mid_slot[t];
+    const int k = sl / nv, ii = sl - k * nv, j = m.ell_col[sl];
+    double Ab[9], Ri[9], Rj[9], AR[9], RA[9], RAR[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Ab[q] = (double)A[(size_t)(k * 9 + q) * nv + ii];
+    const double ri[3] = {sr[0][ii - v0], sr[1][ii - v0], sr[2][ii - v0]};
+    const double rj[3] = {sr[0][j - v0], sr[1][j - v0], sr[2][j - v0]};
+    skew(ri, Ri);
+    skew(rj, Rj);
+    mul33(Ab, Rj, AR);
+    mul33(Ri, Ab, RA);
+    mul33(RA, Rj, RAR);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        acc[r * 6 + q] += Ab[r * 3 + q];
+        acc[r * 6 + 3 + q] -= AR[r * 3 + q];
+        acc[(3 + r) * 6 + q] += RA[r * 3 + q];
+        acc[(3 + r) * 6 + 3 + q] -= RAR[r * 3 + q];
+      }
+  }
+#pragma unroll
+  for (int e = 0; e < 36; ++e) acc[e] = wave_sum(acc[e]);
+  if (lane == 0) {
+    // Gauss-Jordan on the used modes (SPD: no pivoting); unused modes stay zero
+    double g[36];
+#pragma unroll
+    for (int e = 0; e < 36; ++e) g[e] = (e / 6 < modes && e % 6 < modes) ? acc[e] : 0.0;
+    bool good = modes > 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      if (p < modes) {
+        const double piv = g[p * 6 + p];
+        if (!(piv > 0.0) || !isfinite(piv)) good = false;
+        const double d = good ? 1.0 / piv : 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) g[p * 6 + j] = j == p ? d : g[p * 6 + j] * d;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          if (r == p || r >= modes) continue;
+          const double f = g[r * 6 + p];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) g[r * 6 + j] = j == p ? -f * d : g[r * 6 + j] - f * g[p * 6 + j];
+        }
+      }
+    }
+    double* out = c.mid_inv + (size_t)a * 36;
+#pragma unroll
+    for (int e = 0; e < 36; ++e) out[e] = good ? g[e] : 0.0;
+  }
+}
+
 // Unit diagonal for the unused modes of every aggregate and for the padding rows
 // of every sheet (threads past the aggregates handle the sheets).
 __global__ void __launch_bounds__(256) k_coarse_dead(Coarse c, int ninst) {
@@ -1075,6 +1158,34 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
   }
 }
 
+// y += P1_i B1^-1 P1^T v on this thread's row: the middle-level correction. The run
+// of kMid rows occupies one aligned group of kMid lanes, so P1^T v is a butterfly
+// within the group; Bm is the run's 6x6 inverse (LDS). No barrier, no global access.
+__device__ __forceinline__ void mid_apply(const double* __restrict__ Bm, bool live, const double r[3],
+                                          const double v[3], double y[3]) {
+  double t[6];
+  t[0] = live ? v[0] : 0.0;
+  t[1] = live ? v[1] : 0.0;
+  t[2] = live ? v[2] : 0.0;
+  t[3] = live ? r[1] * v[2] - r[2] * v[1] : 0.0;
+  t[4] = live ? r[2] * v[0] - r[0] * v[2] : 0.0;
+  t[5] = live ? r[0] * v[1] - r[1] * v[0] : 0.0;
+#pragma unroll
+  for (int off = 1; off < kMid; off <<= 1)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) t[q] += __shfl_xor(t[q], off, kMid);
+  double e[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    e[q] = Bm[q * 6] * t[0] + Bm[q * 6 + 1] * t[1] + Bm[q * 6 + 2] * t[2] + Bm[q * 6 + 3] * t[3] +
+           Bm[q * 6 + 4] * t[4] + Bm[q * 6 + 5] * t[5];
+  if (live) {
+    y[0] += e[0] + (e[4] * r[2] - e[5] * r[1]);
+    y[1] += e[1] + (e[5] * r[0] - e[3] * r[2]);
+    y[2] += e[2] + (e[3] * r[1] - e[4] * r[0]);
+  }
+}
+
 template <typename TM, bool LDS_MATRIX, bool COARSE>
 __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
                                              PcgArgs<TM> a) {
@@ -1107,7 +1218,8 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   double* s_wc = reinterpret_cast<double*>(Al + (LDS_MATRIX ? (size_t)maxnz * 9 * R : 0));
   double* s_red = s_wc + cs.max_nc;
   double* s_e = s_red + 4 * 6 * kMaxWgAgg;
-  int* s_pidx = reinterpret_cast<int*>(s_e + 6 * kMaxWgAgg);
+  double* s_mid = s_e + 6 * kMaxWgAgg;                             // [block / kMid][36]
+  int* s_pidx = reinterpret_cast<int*>(s_mid + (blockDim.x / kMid) * 36);
   // matrix operand: LDS copy, or the assembled ELL array read in place
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
@@ -1124,11 +1236,11 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     }
   }
   for (int h = tid; h < nh; h += blockDim.x) s_hidx[h] = plan.halo_idx[h0 + h];
-  // coarse-space data of this row
+  // coarse-space data of this row (cr: offset in its aggregate, cr1: in its run)
   int wa0 = 0, wna = 0, kloc = 0, kf = 0, kl = -1;
   CoarseRow crow{};
   bool live = false;
-  double cr[3] = {0.0, 0.0, 0.0};
+  double cr[3] = {0.0, 0.0, 0.0}, cr1[3] = {0.0, 0.0, 0.0};
   if (COARSE) {
     wa0 = cs.wg_agg0[wg];
     wna = cs.wg_nagg[wg];
@@ -1159,9 +1271,17 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       kloc = cs.vert_agg[i] - wa0;
       live = m.pinned[i] == 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cr[c] = cs.crel[c * nv + i];
+      for (int c = 0; c < 3; ++c) {
+        cr[c] = cs.crel[c * nv + i];
+        cr1[c] = cs.mid_crel[c * nv + i];
+      }
     }
+    // the middle level's 6x6 inverses of this workgroup's runs (rows start on a run)
+    const int m0 = cs.vert_mid[row0], nmw = (nrows + kMid - 1) / kMid;
+    for (int e = tid; e < nmw * 36; e += blockDim.x) s_mid[e] = cs.mid_inv[(size_t)m0 * 36 + e];
   }
+  __syncthreads();
+  const double* Bm = s_mid + (tid / kMid) * 36;
 
   double J[9];
 #pragma unroll
@@ -1177,6 +1297,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   for (int c = 0; c < 3; ++c) u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
   bool ok = true;
   if (COARSE) {
+    mid_apply(Bm, live, cr1, r, u);
     coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
     ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
     if (ok) coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
@@ -1230,6 +1351,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       for (int c = 0; c < 3; ++c)
         u[c] = J[3 * c] * r[0] + J[3 * c + 1] * r[1] + J[3 * c + 2] * r[2];
       if (COARSE) {
+        mid_apply(Bm, live, cr1, r, u);
         coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
         if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
         coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
@@ -1256,6 +1378,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     double* ml = mL + (size_t)par * 3 * RH;
 #pragma unroll
     for (int c = 0; c < 3; ++c) mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
+    if (COARSE) mid_apply(Bm, live, cr1, wv, mm);
     if (!COARSE && act) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1712,7 +1835,8 @@ size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int ma
   const size_t rh = rows + (size_t)(max_halo + 7) / 8 * 8;
   return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
          6 * sizeof(double) * rh + sizeof(int) * (rh - rows) +
-         (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg) +
+         (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg +
+                                            (size_t)pcg_threads(rows) / kMid * 36) +
                               sizeof(int) * (size_t)(coarse_nc / 6) * kMaxAggWg : 0);
 }
 
@@ -1780,6 +1904,7 @@ void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const 
   launch_fill_double(c.mat, coarse_doubles, 0.0, st);
   if (c.npair > 0)
     hipLaunchKernelGGL((k_coarse_assemble<TM>), dim3(c.npair), dim3(64), 0, st, m, c, A);
+  if (c.nmid > 0) hipLaunchKernelGGL((k_mid_setup<TM>), dim3(c.nmid), dim3(64), 0, st, m, c, x, A);
   hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst, 256)), dim3(256), 0, st, c,
                      m.ninst);
   hipLaunchKernelGGL(k_gj_pivot0, dim3(m.ninst), dim3(64), 0, st, c);

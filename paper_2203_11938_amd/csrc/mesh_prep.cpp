@@ -45,10 +45,13 @@ inline uint64_t edge_key(int i, int j) { return ((uint64_t)(uint32_t)i << 32) | 
 // Recursive coordinate bisection: orders ids[lo, hi) so that every run of `leaf`
 // consecutive vertices counted from lo is a compact patch of the rest shape. Each
 // split is along the longest side of the bounding box, at a multiple of `leaf`.
-void rcb(const std::vector<double>& rest, std::vector<int>& ids, int lo, int hi, int leaf) {
+void rcb(const std::vector<double>& rest, std::vector<int>& ids, int lo, int hi, int leaf,
+         int inner) {
   const int n = hi - lo;
   if (n <= leaf) {
-    std::sort(ids.begin() + lo, ids.begin() + hi);
+    // a leaf is ordered again into runs of `inner` vertices (the middle level)
+    if (inner > 0 && inner < leaf && n > inner) rcb(rest, ids, lo, hi, inner, 0);
+    else std::sort(ids.begin() + lo, ids.begin() + hi);
     return;
   }
   const int k = (n + leaf - 1) / leaf;
@@ -66,8 +69,8 @@ void rcb(const std::vector<double>& rest, std::vector<int>& ids, int lo, int hi,
     const double xa = rest[3 * (size_t)a + ax], xb = rest[3 * (size_t)b + ax];
     return xa < xb || (xa == xb && a < b);
   });
-  rcb(rest, ids, lo, mid, leaf);
-  rcb(rest, ids, mid, hi, leaf);
+  rcb(rest, ids, lo, mid, leaf, inner);
+  rcb(rest, ids, mid, hi, leaf, inner);
 }
 
 // Coarse modes an aggregate supports: rigid motions (6) when its free vertices are
@@ -137,10 +140,12 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
       }
     const int base = agg_size > 0 ? agg_size : 64;
     leaf[b] = std::max(base, (s.nv + max_aggs - 1) / max_aggs);
+    // coarse aggregates are whole runs of the middle level
+    if (agg_size > 0) leaf[b] = (leaf[b] + kMidSize - 1) / kMidSize * kMidSize;
     std::vector<int>& ids = order[b];
     ids.resize(s.nv);
     for (int i = 0; i < s.nv; ++i) ids[i] = i;
-    rcb(s.rest, ids, 0, s.nv, leaf[b]);
+    rcb(s.rest, ids, 0, s.nv, leaf[b], agg_size > 0 ? kMidSize : 0);
     std::vector<int> inv(s.nv);
     for (int q = 0; q < s.nv; ++q) inv[ids[q]] = q;
     HostSheet& t = sheets[b];
@@ -446,6 +451,31 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
   } else {
     L.pair_ptr.assign(1, 0);
   }
+  // ---- middle level: runs of kMidSize vertices from every sheet's start
+  L.mid_ptr.assign(1, 0);
+  L.vert_mid.assign(agg_size > 0 ? nv : 0, 0);
+  if (agg_size > 0) {
+    for (int b = 0; b < L.ninst; ++b) {
+      const int n = L.inst_nv[b], voff = L.inst_voff[b];
+      L.inst_mid0.push_back(L.nmid);
+      for (int v0 = 0; v0 < n; v0 += kMidSize) {
+        const int v1 = std::min(n, v0 + kMidSize);
+        L.mid_v0.push_back(voff + v0);
+        L.mid_modes.push_back(aggregate_modes(sheets[b].rest, L.pinned, voff, v0, v1));
+        for (int i = voff + v0; i < voff + v1; ++i) L.vert_mid[i] = L.nmid;
+        for (int i = voff + v0; i < voff + v1; ++i) {
+          if (L.pinned[i]) continue;
+          for (int k = 0; k < mz; ++k) {
+            const int j = L.ell_col[(size_t)k * nv + i];
+            if (j >= voff + v0 && j < voff + v1 && !L.pinned[j]) L.mid_slot.push_back(k * nv + i);
+          }
+        }
+        L.mid_ptr.push_back((int)L.mid_slot.size());
+        ++L.nmid;
+      }
+    }
+    L.mid_v0.push_back(nv);
+  }
   return 0;
 }
 
@@ -521,6 +551,22 @@ bool check_layout(const HostLayout& L, std::string& err) {
       if (sl < 0 || sl >= L.maxnz * nv) return bad("coarse pair slot");
       const int i = sl % nv, j = L.ell_col[sl];
       if (j < 0 || L.vert_agg[i] != a || L.vert_agg[j] != c) return bad("coarse pair slot");
+    }
+  }
+  if (L.nmid > 0) {
+    if ((int)L.mid_v0.size() != L.nmid + 1 || (int)L.mid_modes.size() != L.nmid ||
+        (int)L.mid_ptr.size() != L.nmid + 1 || L.mid_ptr.back() != (int)L.mid_slot.size())
+      return bad("middle level sizes");
+    for (int a = 0; a < L.nmid; ++a) {
+      const int v0 = L.mid_v0[a], v1 = L.mid_v0[a + 1];
+      if (v1 - v0 < 1 || v1 - v0 > kMidSize || v1 > nv || L.vert_inst[v0] != L.vert_inst[v1 - 1])
+        return bad("middle aggregate");
+      for (int t = L.mid_ptr[a]; t < L.mid_ptr[a + 1]; ++t) {
+        const int sl = L.mid_slot[t];
+        if (sl < 0 || sl >= L.maxnz * nv) return bad("middle slot");
+        const int i = sl % nv, j = L.ell_col[sl];
+        if (i < v0 || i >= v1 || j < v0 || j >= v1) return bad("middle slot");
+      }
     }
   }
   return true;

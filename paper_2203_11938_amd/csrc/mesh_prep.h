@@ -7,6 +7,8 @@
 
 namespace phisft {
 
+constexpr int kMidSize = 16;  // vertices per aggregate of the middle level
+
 struct HostSheet {
   int nv = 0, nt = 0;
   std::vector<int> tris;      // [nt][3]
@@ -42,6 +44,10 @@ struct HostLayout {
   long long coarse_doubles = 0;
   // aggregate pairs (a <= b, adjacent) and the matrix slots s = k*nv + i (i in a, col in b)
   std::vector<int> pair_a, pair_b, pair_ptr, pair_slot;
+  // middle level: runs of kMidSize vertices from each sheet's start (compact 4x4 patches
+  // of the grid sheets); the slots coupling two free vertices of the same run
+  int nmid = 0;
+  std::vector<int> mid_v0, mid_modes, mid_ptr, mid_slot, inst_mid0, vert_mid;
 };
 
 struct HostPlan {

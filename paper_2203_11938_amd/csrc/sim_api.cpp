@@ -25,6 +25,8 @@
 
 using namespace phisft;
 
+static_assert(kMid == kMidSize, "device and host sizes of the middle level differ");
+
 struct sim_s {
   HostLayout L;
   HostPlan plan_h;
@@ -52,6 +54,8 @@ struct sim_s {
   double* cmat_store = nullptr;
   double* crel_store = nullptr;
   int* cok_store = nullptr;
+  double* mrel_store = nullptr;
+  double* minv_store = nullptr;
   std::vector<int> slot_step;             // step held by each slot, 0 = none
   std::vector<int> gja_count, gjb_count;  // inversion tasks per pivot step
   void* A = nullptr;
@@ -343,6 +347,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     for (int rows : cands) {
       const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
       const int cnc = coarse ? L.max_nc : 0;
+      if (L.nmid > 0 && rows % kMidSize != 0) continue;  // workgroups hold whole runs
       HostPlan P = make_plan(L, rows, kBarrierGroup);
       P.lds_matrix = mode;
       size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P.max_halo)
@@ -464,6 +469,12 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       s->gj_doubles += (long long)kGjTile * L.inst_np[b];
     }
     TRY(upload(s, boff, &cs.inst_boff));
+    cs.nmid = L.nmid;
+    TRY(upload(s, L.mid_v0, &cs.mid_v0));
+    TRY(upload(s, L.mid_modes, &cs.mid_modes));
+    TRY(upload(s, L.mid_ptr, &cs.mid_ptr));
+    TRY(upload(s, L.mid_slot, &cs.mid_slot));
+    TRY(upload(s, L.vert_mid, &cs.vert_mid));
   }
 
   // ---- workspace
@@ -498,13 +509,18 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
     TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
+    TRY(alloc(s, 3 * nv * 8, &q)); cs.mid_crel = (double*)q;
+    TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;
     const int want = s->ckpt > 0 ? s->ckpt : s->max_steps;
-    const double slot_bytes = 8.0 * ((double)L.coarse_doubles + 3.0 * nv) + 4.0 * ni;
+    const double slot_bytes =
+        8.0 * ((double)L.coarse_doubles + 6.0 * nv + 36.0 * L.nmid) + 4.0 * ni;
     if (want * slot_bytes <= kCoarseStoreCap) {
       s->cslots = want;
       TRY(alloc(s, (size_t)want * L.coarse_doubles * 8, &q)); s->cmat_store = (double*)q;
       TRY(alloc(s, (size_t)want * 3 * nv * 8, &q)); s->crel_store = (double*)q;
       TRY(alloc(s, (size_t)want * ni * 4, &q)); s->cok_store = (int*)q;
+      TRY(alloc(s, (size_t)want * 3 * nv * 8, &q)); s->mrel_store = (double*)q;
+      TRY(alloc(s, (size_t)want * L.nmid * 36 * 8, &q)); s->minv_store = (double*)q;
       s->slot_step.assign(want, 0);
     }
   }
@@ -566,6 +582,8 @@ Coarse coarse_for_step(sim_t* s, int step, bool* have) {
   c.mat = s->cmat_store + (size_t)slot * s->L.coarse_doubles;
   c.crel = s->crel_store + (size_t)slot * 3 * s->L.nv;
   c.ok = s->cok_store + (size_t)slot * s->L.ninst;
+  c.mid_crel = s->mrel_store + (size_t)slot * 3 * s->L.nv;
+  c.mid_inv = s->minv_store + (size_t)slot * s->L.nmid * 36;
   *have = s->slot_step[slot] == step;
   s->slot_step[slot] = step;
   return c;

@@ -85,6 +85,7 @@ struct Elem {
 constexpr int kMaxWgAgg = 4;      // aggregates overlapping one solver workgroup
 constexpr int kMaxAggWg = 4;      // solver workgroups overlapping one aggregate
 constexpr int kGjTile = 32;       // tile of the blocked Gauss-Jordan inversion
+constexpr int kMid = 16;          // vertices per aggregate of the middle level
 
 struct Coarse {
   int nagg;                    // 0: no coarse space
@@ -125,6 +126,16 @@ struct Coarse {
   const long long* inst_boff;  // [ninst] offset of the sheet's gj_c / gj_r blocks (32 np)
   int* ok;                     // [ninst] 1 when this step's inversion succeeded
   double* part;                // [nwg][kMaxWgAgg][6] restriction partial sums
+  // middle level: the six rigid motions of runs of kMid vertices, each with the
+  // inverse of its own 6x6 diagonal block of P1^T A P1 (purely local to a workgroup)
+  int nmid;
+  const int* mid_v0;           // [nmid+1]
+  const int* mid_modes;        // [nmid]
+  const int* mid_ptr;          // [nmid+1] slots of the run's diagonal block
+  const int* mid_slot;
+  const int* vert_mid;         // [nv]
+  double* mid_crel;            // [3][nv] x_i - centroid of the run (per step)
+  double* mid_inv;             // [nmid][36] inverse diagonal blocks (per step)
 };
 
 // Cluster-barrier layout: counters 128 bytes apart; sheets with more than

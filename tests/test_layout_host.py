@@ -61,12 +61,16 @@ def test_order_is_a_permutation_and_aggregates_are_square_patches(lib):
     assert counts[9] == 0                          # halo tables name the right vertices
     assert 0 < counts[10] < 128                    # 8x16 patches have a thin halo
     assert counts[7] == 13                         # blocks per row of the grid sheet
-    # each aggregate is an 8x8 block of grid cells
+    # each aggregate is an 8x8 block of grid cells, each run of 16 (the middle level)
+    # a 4x4 block
     ij = np.stack([vold % 64, vold // 64], 1)
     for a in range(64):
         m = ij[vagg == a]
         assert len(m) == 64
         assert np.ptp(m[:, 0]) == 7 and np.ptp(m[:, 1]) == 7
+    for r in range(64 * 64 // 16):
+        m = ij[16 * r:16 * r + 16]
+        assert np.ptp(m[:, 0]) == 3 and np.ptp(m[:, 1]) == 3
 
 
 def test_aggregate_cap_and_batches(lib):
@@ -74,7 +78,8 @@ def test_aggregate_cap_and_batches(lib):
     _, vagg, counts = run(lib, [(rest, tris, pins)], 64, max_aggs=128)
     assert counts[0] <= 128 and counts[1] == 6 * counts[0]
     sizes = np.bincount(vagg)
-    assert sizes.max() == int(np.ceil(200 * 200 / 128))
+    # the cap's aggregate size, rounded up to whole runs of the middle level (16)
+    assert sizes.max() == int(np.ceil(np.ceil(200 * 200 / 128) / 16) * 16)
     # a batch keeps every sheet's vertices in its own range
     sh = [sheet(n) for n in (16, 23, 40)]
     vold, vagg, counts = run(lib, sh, 64)

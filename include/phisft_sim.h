@@ -112,7 +112,8 @@ typedef struct {
                                0: keep every state                                      */
   double gravity[3];        /* m/s^2                                                    */
   int32_t max_steps;        /* capacity: longest rollout this handle will run           */
-  int32_t rows_per_block;   /* solver rows per workgroup (64..256); 0 = tuned choice     */
+  int32_t rows_per_block;   /* solver rows per workgroup, a multiple of 16 from 64 to
+                               256; 0 = the library's choice (rule or autotuner)        */
   int32_t membrane_system;  /* sim_membrane_system                                      */
   int32_t matrix_precision; /* sim_precision of the stored system matrix and its
                                block-Jacobi inverse (default SIM_FP64; SIM_FP32 halves

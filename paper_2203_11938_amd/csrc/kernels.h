@@ -57,7 +57,8 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo);
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo,
+                     int xl_floats);
 // threads of a solver block: its rows rounded up to whole 64-lane wavefronts
 inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 // Rows may couple at most this many vertices (grid sheets: 13).

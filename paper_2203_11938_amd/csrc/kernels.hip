@@ -808,6 +808,31 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   }
 }
 
+// The solver's copy of A_c^-1: (X + X^T) / 2 rounded to FP32, one 32x32 tile per
+// workgroup (grid: tiles of the largest sheet x sheets). The coarse correction is a
+// preconditioner term, so its rounding only changes the iteration count, never the
+// converged residual; the average keeps the preconditioner exactly symmetric.
+__global__ void __launch_bounds__(256) k_coarse_pack(Coarse c) {
+  constexpr int T = kGjTile;
+  __shared__ double A[T][T + 1], B[T][T + 1];
+  const int inst = blockIdx.y, tid = threadIdx.x;
+  const int np = c.inst_np[inst], nb = np / T;
+  const int I = blockIdx.x / c.max_nb, J = blockIdx.x - I * c.max_nb;
+  if (I >= nb || J >= nb) return;
+  const double* M = c.mat + c.inst_coff[inst];
+  float* X = c.xinv + c.inst_coff[inst];
+  for (int e = tid; e < T * T; e += 256) {
+    const int r = e / T, q = e % T;
+    A[r][q] = M[(size_t)(I * T + r) * np + J * T + q];
+    B[r][q] = M[(size_t)(J * T + r) * np + I * T + q];
+  }
+  __syncthreads();
+  for (int e = tid; e < T * T; e += 256) {
+    const int r = e / T, q = e % T;
+    X[(size_t)(I * T + r) * np + J * T + q] = (float)(0.5 * (A[r][q] + B[q][r]));
+  }
+}
+
 // ------------------------------------------------------- persistent PCG
 constexpr int kSpinLimit = 1 << 25;
 // Cluster barrier of the workgroups of one sheet. Counters live in 128-byte slots
@@ -943,23 +968,30 @@ __device__ __forceinline__ void collect3(const double* red_slot, int iw0, int nw
 #ifndef GATHER_CHUNK
 #define GATHER_CHUNK 8
 #endif
-// neighbours gathered per batch of independent loads
+// neighbours gathered per batch: LDS matrix (kChunk) and streamed matrix (kStreamChunk,
+// whose 9 x kStreamChunk matrix loads are issued back to back before any of them is used)
 constexpr int kChunk = GATHER_CHUNK;
+#ifndef STREAM_CHUNK
+#define STREAM_CHUNK 7
+#endif
+constexpr int kStreamChunk = STREAM_CHUNK;
 
-// Gather kChunk of the row's neighbour values, starting at slot k0, from the
-// workgroup's LDS copy vl [3][RH] of the vector: own rows at their local index, the
-// halo (neighbour rows of other workgroups, loaded after the barrier) behind them.
-// Cl holds those local indices.
+// Gather CH of the row's neighbour values, starting at slot k0, from the workgroup's
+// LDS copy vl [3][RH] of the vector: own rows at their local index, the halo
+// (neighbour rows of other workgroups, loaded after the barrier) behind them. Cl holds
+// those local indices. Slots past maxnz read the last one; with ZERO they contribute
+// zero (the streamed product reads those slots' blocks without branches).
+template <int CH, bool ZERO>
 __device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int tid, int k0,
                                        int maxnz, const double* __restrict__ vl, int RH,
-                                       double g[3][kChunk]) {
-  // slots past maxnz repeat the last one; applynb skips them
+                                       double g[3][CH]) {
 #pragma unroll
-  for (int k = 0; k < kChunk; ++k) {
+  for (int k = 0; k < CH; ++k) {
     const int j = Cl[min(k0 + k, maxnz - 1) * R + tid];
-    g[0][k] = vl[j];
-    g[1][k] = vl[RH + j];
-    g[2][k] = vl[2 * RH + j];
+    const bool in = !ZERO || k0 + k < maxnz;
+    g[0][k] = in ? vl[j] : 0.0;
+    g[1][k] = in ? vl[RH + j] : 0.0;
+    g[2][k] = in ? vl[2 * RH + j] : 0.0;
   }
 }
 
@@ -973,28 +1005,47 @@ __device__ __forceinline__ void halo_load(const double* __restrict__ vg, int nv,
   }
 }
 
-// y += (blocks k0..k0+kChunk-1 of the row) * g. With SB (matrix in LDS) scheduling
-// barriers keep each block's LDS loads next to their use instead of hoisting them all
-// into registers; a matrix streamed from memory is left to the scheduler so that its
-// loads are issued early.
-// The matrix is read at A[((k * 9 + e) * stride) + idx]: the LDS copy (stride R,
-// idx = thread) or the assembled ELL array in global memory (stride nv, idx = row).
-template <typename TM, bool SB>
+// y += (blocks k0..k0+CH-1 of the row) * g. The matrix is read at
+// A[((k * 9 + e) * stride) + idx]: the LDS copy (stride R, idx = thread) or the
+// assembled ELL array in global memory (stride nv, idx = row).
+// LDS matrix (SB): scheduling barriers keep each block's LDS loads next to their use
+// instead of hoisting them all into registers; slots past maxnz are skipped.
+// Streamed matrix: all 9 x CH loads first (slots past maxnz re-read the last block,
+// whose g is zero), then a scheduling barrier, then the products, so one round trip
+// to memory serves the whole chunk whatever the register allocator does elsewhere.
+template <typename TM, bool SB, int CH>
 __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, int idx, int k0,
-                                        int maxnz, const double g[3][kChunk], double y[3]) {
+                                        int maxnz, const double g[3][CH], double y[3]) {
+  if (SB) {
 #pragma unroll
-  for (int k = 0; k < kChunk; ++k) {
+    for (int k = 0; k < CH; ++k) {
 #if SCHED_BARRIER
-    if (SB) __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_sched_barrier(0);
 #endif
-    if (k0 + k < maxnz) {
-      const TM* blk = Am + (size_t)(k0 + k) * 9 * stride + idx;
+      if (k0 + k < maxnz) {
+        const TM* blk = Am + (size_t)(k0 + k) * 9 * stride + idx;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          y[r] += (double)blk[(size_t)(r * 3) * stride] * g[0][k] +
+                  (double)blk[(size_t)(r * 3 + 1) * stride] * g[1][k] +
+                  (double)blk[(size_t)(r * 3 + 2) * stride] * g[2][k];
+      }
+    }
+  } else {
+    TM a[CH][9];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const TM* blk = Am + (size_t)min(k0 + k, maxnz - 1) * 9 * stride + idx;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) a[k][e] = blk[(size_t)e * stride];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < CH; ++k)
 #pragma unroll
       for (int r = 0; r < 3; ++r)
-        y[r] += (double)blk[(size_t)(r * 3) * stride] * g[0][k] +
-                (double)blk[(size_t)(r * 3 + 1) * stride] * g[1][k] +
-                (double)blk[(size_t)(r * 3 + 2) * stride] * g[2][k];
-    }
+        y[r] += (double)a[k][r * 3] * g[0][k] + (double)a[k][r * 3 + 1] * g[1][k] +
+                (double)a[k][r * 3 + 2] * g[2][k];
   }
 }
 
@@ -1003,11 +1054,12 @@ template <typename TM, bool SB>
 __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
                                          const int* __restrict__ Cl, int R, int tid, int maxnz,
                                          const double* __restrict__ vl, int RH, double y[3]) {
+  constexpr int CH = SB ? kChunk : kStreamChunk;
   y[0] = y[1] = y[2] = 0.0;
-  for (int k0 = 0; k0 < maxnz; k0 += kChunk) {
-    double g[3][kChunk];
-    loadnb(Cl, R, tid, k0, maxnz, vl, RH, g);
-    applynb<TM, SB>(Am, stride, idx, k0, maxnz, g, y);
+  for (int k0 = 0; k0 < maxnz; k0 += CH) {
+    double g[3][CH];
+    loadnb<CH, !SB>(Cl, R, tid, k0, maxnz, vl, RH, g);
+    applynb<TM, SB, CH>(Am, stride, idx, k0, maxnz, g, y);
   }
 }
 
@@ -1075,25 +1127,102 @@ __device__ __forceinline__ void coarse_restrict(double* __restrict__ part, int w
 
 // Per-launch constants of a workgroup's coarse correction.
 struct CoarseRow {
-  const double* X;       // rows of A_c^-1 of the workgroup's aggregates (stride np)
+  const float* X;        // rows of A_c^-1 of the workgroup's aggregates (global, stride np)
+  const float* XL;       // the same rows in LDS (stride nc), or nullptr
   const double* part;    // restriction partial sums
   int nc, np, nrow, ok;
 };
 
+// Sums of NP values over the 64 lanes of a wavefront by recursive halving: at each
+// step a lane keeps one half of its values and adds its partner's copy of that half,
+// so lane l ends with the total of value l >> (6 - log2 NP) (fixed order, NP - 1 +
+// log2(64 / NP) shuffles instead of 6 NP for one butterfly per value).
+template <int H, int O, int NP>
+__device__ __forceinline__ void halve_step(double (&v)[NP], int lane) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double send = up ? v[k] : v[k + H];
+      const double keep = up ? v[k + H] : v[k];
+      v[k] = keep + __shfl_xor(send, O, 64);
+    }
+    halve_step<H / 2, O / 2, NP>(v, lane);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
+  halve_step<NP / 2, 32, NP>(v, lane);
+  double t = v[0];
+#pragma unroll
+  for (int o = 32 / NP; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
+// e_q = sum_c X[q][c] w_c for the NR rows of this workgroup: the wavefronts take
+// 64-column tiles in turn, every lane accumulates all NR rows of its columns (NR x TU
+// independent loads per pass), then one recursive-halving reduction per wavefront and
+// a fixed-order sum over the wavefronts leave e in s_e[0..NR).
+template <int NR, bool XLDS>
+__device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld, int nc,
+                                            const double* s_wc, double* s_red, double* s_e) {
+  constexpr int NP = NR <= 8 ? 8 : (NR <= 16 ? 16 : 32);
+  constexpr int TU = NR <= 12 ? 4 : 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int ntile = (nc + 63) >> 6;
+  double acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  for (int t0 = wave; t0 < ntile; t0 += TU * nwaves) {
+    float xv[TU][NR];
+    double wcv[TU];
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      // tiles past the end read the last column with weight zero (no branches)
+      const int col = (t0 + u * nwaves) * 64 + lane;
+      const int colc = min(col, nc - 1);
+      wcv[u] = col < nc ? s_wc[colc] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) xv[u][q] = X[(size_t)q * ld + colc];
+    }
+#pragma unroll
+    for (int u = 0; u < TU; ++u)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) acc[q] += (double)xv[u][q] * wcv[u];
+  }
+  const double t = wave_sums_scatter<NP>(acc, lane);
+  constexpr int SH = (NP == 8 ? 3 : (NP == 16 ? 2 : 1));   // 6 - log2 NP
+  const int idx = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && idx < NR) s_red[wave * 24 + idx] = t;
+  __syncthreads();
+  if (tid < NR) {
+    double e = 0.0;
+    for (int w = 0; w < nwaves; ++w) e += s_red[w * 24 + tid];
+    s_e[tid] = e;
+  }
+  __syncthreads();
+}
+
+template <int NR>
+__device__ __forceinline__ void coarse_rows_at(const CoarseRow& cr_, const double* s_wc,
+                                               double* s_red, double* s_e) {
+  if (cr_.XL) coarse_rows<NR, true>(cr_.XL, cr_.nc, cr_.nc, s_wc, s_red, s_e);
+  else coarse_rows<NR, false>(cr_.X, cr_.np, cr_.nc, s_wc, s_red, s_e);
+}
+
 // After the cluster barrier that publishes the partial sums: the sheet's coarse
 // residual w_c (into LDS), then e = the rows of A_c^-1 belonging to this
-// workgroup's aggregates times w_c (one row per lane, the columns split over the
-// wavefronts, w_c read as LDS broadcasts; no cross-lane reductions), then
-// y += P_i e on this thread's row. Fixed summation order throughout. Skipped when
-// the step's inversion failed.
+// workgroup's aggregates times w_c, then y += P_i e on this thread's row. Fixed
+// summation order throughout. Skipped when the step's inversion failed.
 __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, bool live,
                                                const double r[3], double y[3],
                                                const int* s_pidx, double* s_wc, double* s_red,
                                                double* s_e) {
   if (!cr_.ok) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwaves = blockDim.x >> 6;
-  const int nc = cr_.nc, np = cr_.np, nrow = cr_.nrow;
+  const int tid = threadIdx.x;
+  const int nc = cr_.nc;
   // four columns per pass; index -1 (no partial) reads entry 0 with weight 0, so the
   // loads carry no branches and a pass issues them together
   constexpr int CU = 4;
@@ -1117,41 +1246,15 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
       if (col0 + u * (int)blockDim.x < nc) s_wc[col0 + u * blockDim.x] = wc[u];
   }
   __syncthreads();
-  // rows wave, wave + nwaves, ... on this wavefront; lanes over 64-column tiles.
-  // Addresses are clamped into the matrix and the weight is zero past its end, so
-  // the loads of six tiles carry no branches and are issued together.
-  constexpr int MR = 6;
-  constexpr int TU = 6;
-  const int ntile = (nc + 63) / 64;
-  for (int qb = 0; wave + qb * nwaves < nrow; qb += MR) {   // groups of MR rows per wavefront
-    double acc[MR];
-#pragma unroll
-    for (int q = 0; q < MR; ++q) acc[q] = 0.0;
-    for (int t0 = 0; t0 < ntile; t0 += TU) {
-#pragma unroll
-      for (int t = 0; t < TU; ++t) {
-        const int col = (t0 + t) * 64 + lane;
-        const int colc = min(col, nc - 1);
-        const double wcv = col < nc ? s_wc[colc] : 0.0;
-#pragma unroll
-        for (int q = 0; q < MR; ++q) {
-          const int row = min(wave + (qb + q) * nwaves, nrow - 1);
-          acc[q] += cr_.X[(size_t)row * np + colc] * wcv;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < MR; ++q) {
-      const int row = wave + (qb + q) * nwaves;
-      if (row < nrow) {   // uniform per wavefront
-        const double v = wave_sum(acc[q]);
-        if (lane == 0) s_red[row] = v;
-      }
-    }
+  switch (cr_.nrow) {   // 6 x the workgroup's aggregates (uniform)
+    case 6: coarse_rows_at<6>(cr_, s_wc, s_red, s_e); break;
+    case 12: coarse_rows_at<12>(cr_, s_wc, s_red, s_e); break;
+    case 18: coarse_rows_at<18>(cr_, s_wc, s_red, s_e); break;
+    case 24: coarse_rows_at<24>(cr_, s_wc, s_red, s_e); break;
+    default: break;
   }
-  __syncthreads();
   if (live) {
-    const double* e = s_red + 6 * kloc;
+    const double* e = s_e + 6 * kloc;
     y[0] += e[0] + (e[4] * r[2] - e[5] * r[1]);
     y[1] += e[1] + (e[5] * r[0] - e[3] * r[2]);
     y[2] += e[2] + (e[3] * r[1] - e[4] * r[0]);
@@ -1220,6 +1323,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   double* s_e = s_red + 4 * 6 * kMaxWgAgg;
   double* s_mid = s_e + 6 * kMaxWgAgg;                             // [block / kMid][36]
   int* s_pidx = reinterpret_cast<int*>(s_mid + (blockDim.x / kMid) * 36);
+  float* s_x = reinterpret_cast<float*>(s_pidx + (cs.max_nc / 6) * kMaxAggWg);  // [nrow][nc]
   // matrix operand: LDS copy, or the assembled ELL array read in place
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
@@ -1256,12 +1360,20 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       s_pidx[e] = pi;
     }
     const int np = cs.inst_np[inst];
-    crow.X = cs.mat + cs.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;
+    crow.X = cs.xinv + cs.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;
+    crow.XL = nullptr;
     crow.part = cs.part;
     crow.nc = cs.inst_nc[inst];
     crow.np = np;
     crow.nrow = 6 * wna;
     crow.ok = cs.ok[inst];
+    if (plan.xl_floats > 0) {
+      // the rows are fixed for the launch: one copy into LDS
+      const int nc = crow.nc;
+      for (int q = 0; q < crow.nrow; ++q)
+        for (int c = tid; c < nc; c += blockDim.x) s_x[q * nc + c] = crow.X[(size_t)q * np + c];
+      crow.XL = s_x;
+    }
     const int f = (tid >> 6) * 64;
     if (f < nrows) {
       kf = cs.vert_agg[row0 + f] - wa0;
@@ -1831,13 +1943,16 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
 }
 
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo) {
+size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo,
+                     int xl_floats) {
   const size_t rh = rows + (size_t)(max_halo + 7) / 8 * 8;
   return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
          6 * sizeof(double) * rh + sizeof(int) * (rh - rows) +
          (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg +
                                             (size_t)pcg_threads(rows) / kMid * 36) +
-                              sizeof(int) * (size_t)(coarse_nc / 6) * kMaxAggWg : 0);
+                              sizeof(int) * (size_t)(coarse_nc / 6) * kMaxAggWg +
+                              sizeof(float) * (size_t)xl_floats
+                        : 0);
 }
 
 template <typename TM>
@@ -1873,7 +1988,7 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
                 const PcgArgs<TM>& a, hipStream_t st) {
   const bool coarse = cs.nagg > 0;
   size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0,
-                                 plan.max_halo);
+                                 plan.max_halo, coarse ? plan.xl_floats : 0);
   launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
@@ -1914,6 +2029,7 @@ void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const 
     if (gjb_count[K] > 0)
       hipLaunchKernelGGL(k_gj_update, dim3(gjb_count[K]), dim3(256), 0, st, c, K, m.ninst);
   }
+  hipLaunchKernelGGL(k_coarse_pack, dim3(c.max_nb * c.max_nb, m.ninst), dim3(256), 0, st, c);
 }
 
 template <typename T>
@@ -1968,7 +2084,7 @@ PHISFT_INSTANTIATE_ASM(double, float)
 PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template size_t pcg_lds_bytes<T>(int, int, bool, int, int);                                    \
+  template size_t pcg_lds_bytes<T>(int, int, bool, int, int, int);                               \
   template hipError_t pcg_prepare<T>(size_t, int, bool, bool);                                   \
   template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int*);                      \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \

@@ -64,6 +64,9 @@ struct HostPlan {
   // h-th halo row, the row's own local index for a padding slot
   int max_halo = 0;
   std::vector<int> halo_ptr, halo_idx, lcol;
+  // > 0: the solver keeps the FP32 rows of the coarse inverse that each workgroup
+  // uses in LDS (6 x max_wg_agg x the largest coarse dimension floats)
+  int xl_floats = 0;
 };
 
 // Splits the sheets (in order) into solver launches of at most `capacity`

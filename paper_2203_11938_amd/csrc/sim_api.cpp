@@ -51,7 +51,7 @@ struct sim_s {
   // per-step coarse operators kept for the adjoint (inverse, offsets, flags); slot of
   // step s: s - 1 (every state stored) or (s - 1) % k (checkpoints every k)
   int cslots = 0;
-  double* cmat_store = nullptr;
+  float* cmat_store = nullptr;
   double* crel_store = nullptr;
   int* cok_store = nullptr;
   double* mrel_store = nullptr;
@@ -188,6 +188,7 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   TRY(upload(s, P.inst_wg0, &p.inst_wg0));
   TRY(upload(s, P.inst_nwg, &p.inst_nwg));
   p.max_halo = P.max_halo;
+  p.xl_floats = coarse ? P.xl_floats : 0;
   TRY(upload(s, P.halo_ptr, &p.halo_ptr));
   TRY(upload(s, P.halo_idx, &p.halo_idx));
   TRY(upload(s, P.lcol, &p.lcol));
@@ -209,9 +210,9 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   const bool lm = P.lds_matrix != 0;
   const int cnc = coarse ? L.max_nc : 0;
   hipError_t e = s->mprec == SIM_FP64
-      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo), L.maxnz, lm,
+      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm,
                             coarse)
-      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo), L.maxnz, lm,
+      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm,
                            coarse);
   if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   s->plan_h = P;
@@ -299,8 +300,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   }
   if ((o.precision != SIM_FP32 && o.precision != SIM_FP64) || !(o.cg_tol > 0.0) ||
       o.cg_max_iter < 1 || o.checkpoint_every < 0 || o.max_steps < 1 ||
-      !(o.rows_per_block == 0 || o.rows_per_block == 64 || o.rows_per_block == 128 ||
-        o.rows_per_block == 256) ||
+      !(o.rows_per_block == 0 ||
+        (o.rows_per_block >= 64 && o.rows_per_block <= 256 && o.rows_per_block % 16 == 0)) ||
       (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
       (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
       !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20))) ||
@@ -348,25 +349,32 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
       const int cnc = coarse ? L.max_nc : 0;
       if (L.nmid > 0 && rows % kMidSize != 0) continue;  // workgroups hold whole runs
-      HostPlan P = make_plan(L, rows, kBarrierGroup);
-      P.lds_matrix = mode;
-      size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P.max_halo)
-                       : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P.max_halo);
-      if (lds > lds_cap) continue;
-      hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse)
-                         : pcg_prepare<float>(lds, L.maxnz, lm, coarse);
-      if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
-      int per_cu = 0;
-      e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, &per_cu)
-              : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, &per_cu);
-      if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
-      if (P.max_wg_agg > kMaxWgAgg || P.max_agg_wg > kMaxAggWg) continue;
-      if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
-      const int ng = (int)P.group_wg0.size() - 1;
-      feasible.push_back(P);
-      if (ng < best_groups) {
-        best = (int)feasible.size() - 1;
-        best_groups = ng;
+      HostPlan P0 = make_plan(L, rows, kBarrierGroup);
+      P0.lds_matrix = mode;
+      if (P0.max_wg_agg > kMaxWgAgg || P0.max_agg_wg > kMaxAggWg) continue;
+      // the rows of the coarse inverse in LDS as well (when that fits), or streamed
+      const int xl_full = coarse ? 6 * P0.max_wg_agg * L.max_nc : 0;
+      for (int xl : {xl_full, 0}) {
+        HostPlan P = P0;
+        P.xl_floats = xl;
+        const size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P.max_halo, xl)
+                               : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P.max_halo, xl);
+        if (lds > lds_cap) continue;
+        hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse)
+                           : pcg_prepare<float>(lds, L.maxnz, lm, coarse);
+        if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
+        int per_cu = 0;
+        e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, &per_cu)
+                : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, &per_cu);
+        if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
+        if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
+        const int ng = (int)P.group_wg0.size() - 1;
+        feasible.push_back(P);
+        if (ng < best_groups) {
+          best = (int)feasible.size() - 1;
+          best_groups = ng;
+        }
+        if (xl_full == 0) break;   // both options are the same plan
       }
     }
   }
@@ -505,6 +513,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   if (coarse) {
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.mat = (double*)q;
+    TRY(alloc(s, (size_t)L.coarse_doubles * 4, &q)); cs.xinv = (float*)q;
     TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_c = (double*)q;
     TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
     TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
@@ -513,10 +522,10 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;
     const int want = s->ckpt > 0 ? s->ckpt : s->max_steps;
     const double slot_bytes =
-        8.0 * ((double)L.coarse_doubles + 6.0 * nv + 36.0 * L.nmid) + 4.0 * ni;
+        4.0 * (double)L.coarse_doubles + 8.0 * (6.0 * nv + 36.0 * L.nmid) + 4.0 * ni;
     if (want * slot_bytes <= kCoarseStoreCap) {
       s->cslots = want;
-      TRY(alloc(s, (size_t)want * L.coarse_doubles * 8, &q)); s->cmat_store = (double*)q;
+      TRY(alloc(s, (size_t)want * L.coarse_doubles * 4, &q)); s->cmat_store = (float*)q;
       TRY(alloc(s, (size_t)want * 3 * nv * 8, &q)); s->crel_store = (double*)q;
       TRY(alloc(s, (size_t)want * ni * 4, &q)); s->cok_store = (int*)q;
       TRY(alloc(s, (size_t)want * 3 * nv * 8, &q)); s->mrel_store = (double*)q;
@@ -579,7 +588,7 @@ Coarse coarse_for_step(sim_t* s, int step, bool* have) {
   *have = false;
   if (s->cslots == 0 || c.nagg == 0) return c;
   const int slot = s->ckpt > 0 ? (step - 1) % s->ckpt : step - 1;
-  c.mat = s->cmat_store + (size_t)slot * s->L.coarse_doubles;
+  c.xinv = s->cmat_store + (size_t)slot * s->L.coarse_doubles;
   c.crel = s->crel_store + (size_t)slot * 3 * s->L.nv;
   c.ok = s->cok_store + (size_t)slot * s->L.ninst;
   c.mid_crel = s->mrel_store + (size_t)slot * 3 * s->L.nv;

@@ -119,7 +119,8 @@ struct Coarse {
   const int* agg_nwg;          // [nagg]
   // per-step data
   double* crel;                // [3][nv] x_i - c (zero where the rotations are not used)
-  double* mat;                 // A_c, inverted in place
+  double* mat;                 // A_c, inverted in place (FP64 work matrix)
+  float* xinv;                 // symmetrised FP32 copy of A_c^-1 read by the solver
   double* gj_c;                // per sheet [np][32] column multipliers
   double* gj_r;                // per sheet [32][np] pivot-row copy
   double* gj_pinv;             // [2][ninst][32][32] inverse pivot tiles
@@ -163,6 +164,9 @@ struct SolverPlan {
   const int* halo_ptr;     // [nwg+1]
   const int* halo_idx;     // halo rows of each workgroup (global vertex ids)
   const int* lcol;         // [maxnz][nv] local columns: own row j - row0, halo rows + h
+  int xl_floats;           // > 0: LDS floats holding the rows of the coarse inverse that
+                           // a workgroup uses (6 x its aggregates x the coarse dimension);
+                           // 0: those rows are read from global memory every iteration
 };
 
 // Solver scratch (device).

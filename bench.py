@@ -249,6 +249,9 @@ def main():
                            autotuned=bool(st["autotuned"]),
                            autotune_candidates=st["autotune_candidates"],
                            lds_matrix=bool(st["solver_lds_matrix"]),
+                           solver_launches_per_solve=st["solver_launches_per_solve"],
+                           solver_wg_per_cu=st["solver_wg_per_cu"],
+                           coarse_rows_lds=bool(st["coarse_rows_lds"]),
                            device_status=S.status_name(sim.status())),
                roofline=roof)
     if args.sequential and len(insts) > 1:

@@ -156,6 +156,8 @@ typedef struct {
   int32_t autotuned;          /* 1: the launch shape was chosen by measurement */
   int32_t autotune_candidates;/* feasible launch shapes */
   double autotune_ms_per_iter;/* measured time per CG iteration of the chosen shape */
+  int32_t solver_wg_per_cu;   /* solver variant: 1 or 2 workgroups per CU */
+  int32_t coarse_rows_lds;    /* 1: the solver keeps its rows of the coarse inverse in LDS */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,

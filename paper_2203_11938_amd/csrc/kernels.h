@@ -64,9 +64,9 @@ inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 // Rows may couple at most this many vertices (grid sheets: 13).
 constexpr int kMaxRowBlocks = 32;
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse);
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ);
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse,
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ,
                          int* blocks_per_cu);
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,

@@ -38,6 +38,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sums of NP values over the 64 lanes of a wavefront by recursive halving: at each
+// step a lane keeps one half of its values and adds its partner's copy of that half,
+// so lane l ends with the total of value l >> (6 - log2 NP) (fixed order, NP - 1 +
+// log2(64 / NP) shuffles instead of 6 NP for one butterfly per value).
+template <int H, int O, int NP>
+__device__ __forceinline__ void halve_step(double (&v)[NP], int lane) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const double send = up ? v[k] : v[k + H];
+      const double keep = up ? v[k + H] : v[k];
+      v[k] = keep + __shfl_xor(send, O, 64);
+    }
+    halve_step<H / 2, O / 2, NP>(v, lane);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
+  halve_step<NP / 2, 32, NP>(v, lane);
+  double t = v[0];
+#pragma unroll
+  for (int o = 32 / NP; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+  return t;
+}
+
+
 // status[0]: handle-wide word, status[1 + inst]: the instance's word
 __device__ __forceinline__ void set_status(int* status, int inst, int bits) {
   __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -919,6 +947,40 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
   return s_ok != 0;
 }
 
+// Point-to-point publication: after the workgroup has stored a vector's rows, it sets
+// its own flag to `epoch` (release) and waits until every workgroup that owns one of
+// its halo rows has done the same (relaxed polls by the lanes of wavefront 0, one
+// flag each, then an acquire), instead of waiting for the whole cluster. Every
+// workgroup stores before it waits, so the waits cannot form a cycle; they are
+// bounded like the cluster barrier's. The caller keeps a full cluster barrier between
+// two publications into the same buffer, so a neighbour never overwrites rows that
+// are still being read.
+__device__ __forceinline__ bool neighbour_sync(int* flags, int wg, const int* __restrict__ nbw,
+                                               int nnb, int epoch, int* abort_flag, int* status,
+                                               int inst) {
+  __shared__ int s_nok;
+  if (threadIdx.x == 0) s_nok = 0;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    if (threadIdx.x == 0)
+      __hip_atomic_store(flags + (size_t)wg * kBarrierSlot, epoch, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+    for (int q = threadIdx.x; q < nnb; q += 64)
+      ok = ok && bounded_wait_ge(flags + (size_t)nbw[q] * kBarrierSlot, epoch, abort_flag);
+    if (!ok) s_nok = 1;
+  }
+  __syncthreads();
+  if (s_nok != 0) {
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      set_status(status, inst, ST_TIMEOUT);
+    }
+    return false;
+  }
+  return true;
+}
+
 // Fixed-order workgroup sum of three values; thread 0 stores them at dst.
 __device__ __forceinline__ void publish3(const double a[3], double* dst) {
   __shared__ double s_part[3][4];
@@ -943,23 +1005,29 @@ __device__ __forceinline__ void publish3(const double a[3], double* dst) {
 }
 
 // After a cluster barrier: fixed-order sum of the cluster's partials (wave 0),
-// left in s_out; the caller synchronises the workgroup before reading it.
+// left in s_out; the caller synchronises the workgroup before reading it. Each lane
+// loads up to four workgroups' partials per pass, so clusters of up to 256
+// workgroups need one round trip.
 __device__ __forceinline__ void collect3(const double* red_slot, int iw0, int nwg, double* s_out) {
   const int lane = threadIdx.x & 63;
   if ((threadIdx.x >> 6) != 0) return;
-  double t[3] = {0.0, 0.0, 0.0};
-  for (int q = lane; q < nwg; q += 64) {
-    const double* src = red_slot + (size_t)(iw0 + q) * 3;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q0 = lane; q0 < nwg; q0 += 4 * 64) {
+    double v[4][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      t[k] += __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int u = 0; u < 4; ++u) {
+      const double* src = red_slot + (size_t)(iw0 + min(q0 + 64 * u, nwg - 1)) * 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        v[u][k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[k] += q0 + 64 * u < nwg ? v[u][k] : 0.0;
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) t[k] = wave_sum(t[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) s_out[k] = t[k];
-  }
+  const double s = wave_sums_scatter<4>(t, lane);   // lane l holds sum l >> 4
+  if ((lane & 15) == 0 && (lane >> 4) < 3) s_out[lane >> 4] = s;
 }
 
 #ifndef SCHED_BARRIER
@@ -1050,11 +1118,12 @@ __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, i
 }
 
 // y = A v for this thread's row, v from the workgroup's LDS copy (own rows + halo).
-template <typename TM, bool SB>
+// CH: slots per batch of a streamed matrix (fewer when registers are scarce).
+template <typename TM, bool SB, int SCH = kStreamChunk>
 __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
                                          const int* __restrict__ Cl, int R, int tid, int maxnz,
                                          const double* __restrict__ vl, int RH, double y[3]) {
-  constexpr int CH = SB ? kChunk : kStreamChunk;
+  constexpr int CH = SB ? kChunk : SCH;
   y[0] = y[1] = y[2] = 0.0;
   for (int k0 = 0; k0 < maxnz; k0 += CH) {
     double g[3][CH];
@@ -1125,6 +1194,72 @@ __device__ __forceinline__ void coarse_restrict(double* __restrict__ part, int w
   }
 }
 
+// The iteration's publication in one pass: the coarse restriction of y (as
+// coarse_restrict) and the workgroup's three dot-product partials (as publish3). A
+// wavefront whose rows lie in one aggregate (the usual case: aggregates are runs of
+// whole 16-row groups) reduces its nine values together by recursive halving; one
+// that spans several aggregates falls back to a butterfly per aggregate and value.
+// One workgroup barrier in all.
+__device__ __forceinline__ void publish_restrict_dots(double* __restrict__ part, int wg, int wna,
+                                                      int kf, int kl, int kloc, bool live,
+                                                      const double r[3], const double y[3],
+                                                      const double loc[3], double* dst) {
+  __shared__ double s_wp[4][kMaxWgAgg][6];
+  __shared__ double s_pd[4][3];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  double v[6];
+  v[0] = live ? y[0] : 0.0;
+  v[1] = live ? y[1] : 0.0;
+  v[2] = live ? y[2] : 0.0;
+  v[3] = live ? r[1] * y[2] - r[2] * y[1] : 0.0;
+  v[4] = live ? r[2] * y[0] - r[0] * y[2] : 0.0;
+  v[5] = live ? r[0] * y[1] - r[1] * y[0] : 0.0;
+  if (kl <= kf) {   // uniform per wavefront; kl < kf: a wavefront without rows (all zero)
+    const int ka = kl < kf ? 0 : kf;
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a[q] = v[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a[6 + q] = loc[q];
+#pragma unroll
+    for (int q = 9; q < 16; ++q) a[q] = 0.0;
+    const double t = wave_sums_scatter<16>(a, lane);   // lane l holds value l >> 2
+    const int idx = lane >> 2;
+    if ((lane & 3) == 0) {
+      if (idx < 6) s_wp[wave][ka][idx] = t;
+      else if (idx < 9) s_pd[wave][idx - 6] = t;
+    }
+    for (int e = lane; e < wna * 6; e += 64)
+      if (e / 6 != ka) s_wp[wave][e / 6][e % 6] = 0.0;
+  } else {
+    for (int k = 0; k < wna; ++k) {
+      const bool mine = kloc == k;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double t = wave_sum(mine ? v[q] : 0.0);
+        if (lane == 0) s_wp[wave][k][q] = t;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const double t = wave_sum(loc[q]);
+      if (lane == 0) s_pd[wave][q] = t;
+    }
+  }
+  __syncthreads();
+  if (tid < wna * 6) {
+    const int k = tid / 6, q = tid % 6;
+    double t = 0.0;
+    for (int w = 0; w < nwaves; ++w) t += s_wp[w][k][q];
+    part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
+  } else if (tid >= 32 && tid < 35) {
+    double t = 0.0;
+    for (int w = 0; w < nwaves; ++w) t += s_pd[w][tid - 32];
+    dst[tid - 32] = t;
+  }
+}
+
 // Per-launch constants of a workgroup's coarse correction.
 struct CoarseRow {
   const float* X;        // rows of A_c^-1 of the workgroup's aggregates (global, stride np)
@@ -1132,33 +1267,6 @@ struct CoarseRow {
   const double* part;    // restriction partial sums
   int nc, np, nrow, ok;
 };
-
-// Sums of NP values over the 64 lanes of a wavefront by recursive halving: at each
-// step a lane keeps one half of its values and adds its partner's copy of that half,
-// so lane l ends with the total of value l >> (6 - log2 NP) (fixed order, NP - 1 +
-// log2(64 / NP) shuffles instead of 6 NP for one butterfly per value).
-template <int H, int O, int NP>
-__device__ __forceinline__ void halve_step(double (&v)[NP], int lane) {
-  if constexpr (H >= 1) {
-    const bool up = (lane & O) != 0;
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const double send = up ? v[k] : v[k + H];
-      const double keep = up ? v[k + H] : v[k];
-      v[k] = keep + __shfl_xor(send, O, 64);
-    }
-    halve_step<H / 2, O / 2, NP>(v, lane);
-  }
-}
-
-template <int NP>
-__device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
-  halve_step<NP / 2, 32, NP>(v, lane);
-  double t = v[0];
-#pragma unroll
-  for (int o = 32 / NP; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
-  return t;
-}
 
 // e_q = sum_c X[q][c] w_c for the NR rows of this workgroup: the wavefronts take
 // 64-column tiles in turn, every lane accumulates all NR rows of its columns (NR x TU
@@ -1168,7 +1276,7 @@ template <int NR, bool XLDS>
 __device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld, int nc,
                                             const double* s_wc, double* s_red, double* s_e) {
   constexpr int NP = NR <= 8 ? 8 : (NR <= 16 ? 16 : 32);
-  constexpr int TU = NR <= 12 ? 4 : 2;
+  constexpr int TU = NR <= 6 ? 4 : (NR <= 12 ? 2 : 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int ntile = (nc + 63) >> 6;
@@ -1213,19 +1321,16 @@ __device__ __forceinline__ void coarse_rows_at(const CoarseRow& cr_, const doubl
 }
 
 // After the cluster barrier that publishes the partial sums: the sheet's coarse
-// residual w_c (into LDS), then e = the rows of A_c^-1 belonging to this
-// workgroup's aggregates times w_c, then y += P_i e on this thread's row. Fixed
-// summation order throughout. Skipped when the step's inversion failed.
-__device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, bool live,
-                                               const double r[3], double y[3],
-                                               const int* s_pidx, double* s_wc, double* s_red,
-                                               double* s_e) {
+// residual w_c into LDS (every column sums its aggregate's partials of up to
+// kMaxAggWg workgroups; absent partials are masked lanes, so no memory traffic, and
+// one pass issues all loads together). The caller synchronises the workgroup before
+// w_c is read. Skipped when the step's inversion failed.
+__device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s_pidx,
+                                              double* s_wc) {
   if (!cr_.ok) return;
   const int tid = threadIdx.x;
   const int nc = cr_.nc;
-  // four columns per pass; index -1 (no partial) reads entry 0 with weight 0, so the
-  // loads carry no branches and a pass issues them together
-  constexpr int CU = 4;
+  constexpr int CU = 8;
   for (int col0 = tid; col0 < nc; col0 += CU * blockDim.x) {
     double wc[CU];
 #pragma unroll
@@ -1236,8 +1341,7 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
 #pragma unroll
       for (int k = 0; k < kMaxAggWg; ++k) {
         const int pi = s_pidx[t * kMaxAggWg + k];
-        const double v = cr_.part[(size_t)max(pi, 0) * 6 + q];
-        acc += pi >= 0 ? v : 0.0;
+        if (pi >= 0) acc += cr_.part[(size_t)pi * 6 + q];
       }
       wc[u] = acc;
     }
@@ -1245,7 +1349,15 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
     for (int u = 0; u < CU; ++u)
       if (col0 + u * (int)blockDim.x < nc) s_wc[col0 + u * blockDim.x] = wc[u];
   }
-  __syncthreads();
+}
+
+// e = the rows of A_c^-1 belonging to this workgroup's aggregates times w_c (already
+// in LDS), then y += P_i e on this thread's row. Fixed summation order throughout.
+// Skipped when the step's inversion failed.
+__device__ __forceinline__ void coarse_apply(const CoarseRow& cr_, int kloc, bool live,
+                                             const double r[3], double y[3], const double* s_wc,
+                                             double* s_red, double* s_e) {
+  if (!cr_.ok) return;
   switch (cr_.nrow) {   // 6 x the workgroup's aggregates (uniform)
     case 6: coarse_rows_at<6>(cr_, s_wc, s_red, s_e); break;
     case 12: coarse_rows_at<12>(cr_, s_wc, s_red, s_e); break;
@@ -1259,6 +1371,17 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
     y[1] += e[1] + (e[5] * r[0] - e[3] * r[2]);
     y[2] += e[2] + (e[3] * r[1] - e[4] * r[0]);
   }
+}
+
+// The whole coarse correction after the barrier that publishes the partial sums.
+__device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, bool live,
+                                               const double r[3], double y[3],
+                                               const int* s_pidx, double* s_wc, double* s_red,
+                                               double* s_e) {
+  if (!cr_.ok) return;
+  coarse_gather(cr_, s_pidx, s_wc);
+  __syncthreads();
+  coarse_apply(cr_, kloc, live, r, y, s_wc, s_red, s_e);
 }
 
 // y += P1_i B1^-1 P1^T v on this thread's row: the middle-level correction. The run
@@ -1289,12 +1412,14 @@ __device__ __forceinline__ void mid_apply(const double* __restrict__ Bm, bool li
   }
 }
 
-template <typename TM, bool LDS_MATRIX, bool COARSE>
-__global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
+template <typename TM, bool LDS_MATRIX, bool COARSE, int OCC>
+__global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
                                              PcgArgs<TM> a) {
 #ifdef PHISFT_PHASES
   unsigned long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
 #endif
+  // two workgroups per CU leave 256 registers per lane: smaller streamed batches
+  constexpr int SCH = OCC >= 2 ? 4 : kStreamChunk;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double s_out[3];
   const int wg = plan.wg_base + blockIdx.x;
@@ -1311,6 +1436,11 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
   const int i = row0 + (act ? tid : 0);
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
   const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
+  // publication flags of the workgroups and the owners of this workgroup's halo
+  int* nbflags = w.barrier + (size_t)plan.nb_slot0 * kBarrierSlot;
+  const int* nbw = plan.nbw_idx + plan.nbw_ptr[wg];
+  const int nnb = plan.nbw_ptr[wg + 1] - plan.nbw_ptr[wg];
+  int nep = 0;
 
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][RH]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)RH);           // [maxnz][R] local columns
@@ -1429,7 +1559,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     if (ok) {
       halo_load(ub, nv, s_hidx, nh, ul, R, RH);
       __syncthreads();
-      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, ul, RH, wv);
+      if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, ul, RH, wv);
     }
   }
 
@@ -1455,7 +1585,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       __syncthreads();
       if (act) {
         double ax[3];
-        spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, ax);
+        spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -1479,7 +1609,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(ub, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
-      if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, wv);
+      if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -1498,18 +1628,22 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
         ml[c * RH + tid] = mm[c];
       }
     }
-    if (COARSE) coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, wv);
     const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
     double* red_slot = w.red + (size_t)par * plan.nwg * 3;
     PHASE_T(t0);
-    publish3(loc, red_slot + (size_t)wg * 3);
+    if (COARSE)
+      publish_restrict_dots(cs.part, wg, wna, kf, kl, kloc, live, cr, wv, loc,
+                            red_slot + (size_t)wg * 3);
+    else
+      publish3(loc, red_slot + (size_t)wg * 3);
     PHASE_T(t1);
     if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
-    // the halo of m and the partial sums are loaded together
+    // the halo of m (or the coarse residual) and the partial sums are loaded together
     if (!COARSE) halo_load(mb, nv, s_hidx, nh, ml, R, RH);
+    if (COARSE) coarse_gather(crow, s_pidx, s_wc);
     collect3(red_slot, iw0, nwg, s_out);
     __syncthreads();
     const double gamma = s_out[0], delta = s_out[1];
@@ -1535,7 +1669,7 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
     PHASE_T(t5);
     if (COARSE) {
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
-      coarse_correct(crow, kloc, live, cr, mm, s_pidx, s_wc, s_red, s_e);
+      coarse_apply(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
       if (act) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -1544,12 +1678,13 @@ __global__ void __launch_bounds__(256) k_pcg(Mesh m, SolverPlan plan, SolverWork
         }
       }
       PHASE_ADD(4, wall_clock64() - t5);
-      if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+      if (!(ok = neighbour_sync(nbflags, wg, nbw, nnb, ++nep, w.abort_flag, a.status, inst)))
+        break;
       halo_load(mb, nv, s_hidx, nh, ml, R, RH);
       __syncthreads();
       PHASE_ADD(5, wall_clock64() - t5);
     }
-    if (act) spmv_row<TM, LDS_MATRIX>(Am, As, Ai, Cl, R, tid, maxnz, ml, RH, nn);
+    if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, ml, RH, nn);
     else nn[0] = nn[1] = nn[2] = 0.0;
     PHASE_T(t4);
     PHASE_ADD(0, t1 - t0);
@@ -1955,32 +2090,43 @@ size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int ma
                         : 0);
 }
 
-template <typename TM>
-static const void* pcg_entry(bool lds_matrix, bool coarse) {
+// Kernel variants: matrix in LDS or streamed, coarse space or not, one or two
+// workgroups of 256 threads per CU (the latter caps registers at 256 per lane).
+template <typename TM, int OCC>
+static const void* pcg_entry_occ(bool lds_matrix, bool coarse) {
   if (coarse)
-    return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, true>)
-                      : reinterpret_cast<const void*>(&k_pcg<TM, false, true>);
-  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, false>)
-                    : reinterpret_cast<const void*>(&k_pcg<TM, false, false>);
+    return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, true, OCC>)
+                      : reinterpret_cast<const void*>(&k_pcg<TM, false, true, OCC>);
+  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, false, OCC>)
+                    : reinterpret_cast<const void*>(&k_pcg<TM, false, false, OCC>);
 }
 
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse) {
+static const void* pcg_entry(bool lds_matrix, bool coarse, int occ) {
+  return occ >= 2 ? pcg_entry_occ<TM, 2>(lds_matrix, coarse)
+                  : pcg_entry_occ<TM, 1>(lds_matrix, coarse);
+}
+
+template <typename TM>
+hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ) {
   if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix, coarse),
+  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix, coarse, occ),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse,
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ,
                          int* blocks_per_cu) {
   if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  const int nt = pcg_threads(rows);
-  if (coarse)
-    return lds_matrix ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true, true>, nt, lds)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false, true>, nt, lds);
-  return lds_matrix ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, true, false>, nt, lds)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_pcg<TM, false, false>, nt, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, pcg_entry<TM>(lds_matrix, coarse, occ), pcg_threads(rows), lds);
+}
+
+template <typename TM, bool L, bool C, int O>
+static void launch_pcg_v(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Mesh& m,
+                         const SolverPlan& pg, const SolverWork& w, const Coarse& cs,
+                         const PcgArgs<TM>& a) {
+  hipLaunchKernelGGL((k_pcg<TM, L, C, O>), grid, block, lds, st, m, pg, w, cs, a);
 }
 
 template <typename TM>
@@ -1996,16 +2142,16 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
     SolverPlan pg = plan;
     pg.wg_base = plan.group_wg0_host[g];
     const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base), block(pcg_threads(plan.rows));
-    if (coarse) {
-      if (plan.lds_matrix)
-        hipLaunchKernelGGL((k_pcg<TM, true, true>), grid, block, lds, st, m, pg, w, cs, a);
-      else
-        hipLaunchKernelGGL((k_pcg<TM, false, true>), grid, block, lds, st, m, pg, w, cs, a);
-    } else {
-      if (plan.lds_matrix)
-        hipLaunchKernelGGL((k_pcg<TM, true, false>), grid, block, lds, st, m, pg, w, cs, a);
-      else
-        hipLaunchKernelGGL((k_pcg<TM, false, false>), grid, block, lds, st, m, pg, w, cs, a);
+    const int sel = (plan.lds_matrix ? 4 : 0) + (coarse ? 2 : 0) + (plan.occ >= 2 ? 1 : 0);
+    switch (sel) {
+      case 0: launch_pcg_v<TM, false, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 1: launch_pcg_v<TM, false, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 2: launch_pcg_v<TM, false, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 3: launch_pcg_v<TM, false, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 4: launch_pcg_v<TM, true, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 5: launch_pcg_v<TM, true, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 6: launch_pcg_v<TM, true, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      default: launch_pcg_v<TM, true, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
     }
   }
 }
@@ -2085,8 +2231,8 @@ PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
   template size_t pcg_lds_bytes<T>(int, int, bool, int, int, int);                               \
-  template hipError_t pcg_prepare<T>(size_t, int, bool, bool);                                   \
-  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int*);                      \
+  template hipError_t pcg_prepare<T>(size_t, int, bool, bool, int);                              \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int, int*);                 \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \

@@ -51,7 +51,7 @@ struct HostLayout {
 };
 
 struct HostPlan {
-  int rows = 0, nwg = 0, lds_matrix = 1;
+  int rows = 0, nwg = 0, lds_matrix = 1, occ = 1;
   int barrier_slots = 0;   // root slots + group counter/flag slots
   std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
   std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets
@@ -64,6 +64,10 @@ struct HostPlan {
   // h-th halo row, the row's own local index for a padding slot
   int max_halo = 0;
   std::vector<int> halo_ptr, halo_idx, lcol;
+  // workgroups owning each workgroup's halo rows, and the first of the per-workgroup
+  // flag slots that announce a published vector to them
+  std::vector<int> nbw_ptr, nbw_idx;
+  int nb_slot0 = 0;
   // > 0: the solver keeps the FP32 rows of the coarse inverse that each workgroup
   // uses in LDS (6 x max_wg_agg x the largest coarse dimension floats)
   int xl_floats = 0;

@@ -178,6 +178,7 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   p.nwg = P.nwg;
   p.rows = P.rows;
   p.lds_matrix = P.lds_matrix;
+  p.occ = P.occ;
   p.wg_base = 0;
   p.ngroups = (int)P.group_wg0.size() - 1;
   for (int g = 0; g <= p.ngroups; ++g) p.group_wg0_host[g] = P.group_wg0[g];
@@ -192,6 +193,9 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   TRY(upload(s, P.halo_ptr, &p.halo_ptr));
   TRY(upload(s, P.halo_idx, &p.halo_idx));
   TRY(upload(s, P.lcol, &p.lcol));
+  p.nb_slot0 = P.nb_slot0;
+  TRY(upload(s, P.nbw_ptr, &p.nbw_ptr));
+  TRY(upload(s, P.nbw_idx, &p.nbw_idx));
   void* q = nullptr;
   TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q));
   s->sw.red = (double*)q;
@@ -210,15 +214,17 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   const bool lm = P.lds_matrix != 0;
   const int cnc = coarse ? L.max_nc : 0;
   hipError_t e = s->mprec == SIM_FP64
-      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm,
+      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm, P.occ,
                             coarse)
-      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm,
+      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm, P.occ,
                            coarse);
   if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   s->plan_h = P;
   s->stats.rows_per_block = p.rows;
   s->stats.blocks = p.nwg;
   s->stats.solver_lds_matrix = p.lds_matrix;
+  s->stats.solver_wg_per_cu = p.occ;
+  s->stats.coarse_rows_lds = p.xl_floats > 0 ? 1 : 0;
   s->stats.solver_launches_per_solve = p.ngroups;
   return SIM_OK;
 }
@@ -355,24 +361,32 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       // the rows of the coarse inverse in LDS as well (when that fits), or streamed
       const int xl_full = coarse ? 6 * P0.max_wg_agg * L.max_nc : 0;
       for (int xl : {xl_full, 0}) {
-        HostPlan P = P0;
-        P.xl_floats = xl;
-        const size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P.max_halo, xl)
-                               : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P.max_halo, xl);
+        const size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P0.max_halo, xl)
+                               : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P0.max_halo, xl);
         if (lds > lds_cap) continue;
-        hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse)
-                           : pcg_prepare<float>(lds, L.maxnz, lm, coarse);
-        if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
-        int per_cu = 0;
-        e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, &per_cu)
-                : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, &per_cu);
-        if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
-        if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
-        const int ng = (int)P.group_wg0.size() - 1;
-        feasible.push_back(P);
-        if (ng < best_groups) {
-          best = (int)feasible.size() - 1;
-          best_groups = ng;
+        // the one-workgroup-per-CU variant, and the two-per-CU one where it adds
+        // co-resident workgroups
+        int prev_cap = 0;
+        for (int occ = 1; occ <= 2; ++occ) {
+          HostPlan P = P0;
+          P.xl_floats = xl;
+          P.occ = occ;
+          hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse, occ)
+                             : pcg_prepare<float>(lds, L.maxnz, lm, coarse, occ);
+          if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
+          int per_cu = 0;
+          e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, occ, &per_cu)
+                  : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, occ, &per_cu);
+          if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
+          if (occ == 2 && per_cu <= prev_cap) continue;
+          prev_cap = per_cu;
+          if (!group_plan(P, per_cu * ncu, kMaxSolverGroups)) continue;
+          const int ng = (int)P.group_wg0.size() - 1;
+          feasible.push_back(P);
+          if (ng < best_groups) {
+            best = (int)feasible.size() - 1;
+            best_groups = ng;
+          }
         }
         if (xl_full == 0) break;   // both options are the same plan
       }

@@ -153,6 +153,7 @@ struct SolverPlan {
   int ngroups;             // launches per solve: sets of whole sheets that fit co-resident
   int group_wg0_host[kMaxSolverGroups + 1];  // workgroup ranges of the groups
   int lds_matrix;          // 1: matrix rows copied to LDS; 0: streamed from global memory
+  int occ;                 // 1 or 2 workgroups of 256 threads per CU (kernel variant)
   int rows;                // rows per workgroup (LDS stride; block = rows rounded up to 64)
   const int* wg_inst;      // [nwg]
   const int* wg_row0;      // [nwg]
@@ -164,6 +165,9 @@ struct SolverPlan {
   const int* halo_ptr;     // [nwg+1]
   const int* halo_idx;     // halo rows of each workgroup (global vertex ids)
   const int* lcol;         // [maxnz][nv] local columns: own row j - row0, halo rows + h
+  int nb_slot0;            // barrier slot of workgroup 0's publication flag
+  const int* nbw_ptr;      // [nwg+1]
+  const int* nbw_idx;      // workgroups owning each workgroup's halo rows
   int xl_floats;           // > 0: LDS floats holding the rows of the coarse inverse that
                            // a workgroup uses (6 x its aggregates x the coarse dimension);
                            // 0: those rows are read from global memory every iteration

@@ -73,7 +73,8 @@ class _Stats(ctypes.Structure):
                 ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
                 ("solver_ms", ctypes.c_double), ("coarse_aggregates", ctypes.c_int32),
                 ("coarse_max_dim", ctypes.c_int32), ("autotuned", ctypes.c_int32),
-                ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double)]
+                ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double),
+                ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32)]
 
 
 _lib = None

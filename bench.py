@@ -122,6 +122,44 @@ def sequential_comparison(w, insts, batched_ms, steps, membrane, autotune):
                 speedup=round(seq_ms / batched_ms, 2))
 
 
+def graph_timing(w, sheets, x0, v0, F, tgt, frames, steps, warmup, membrane, autotune):
+    """The same gradient on a handle in graph mode: rollout and adjoint are captured
+    once and replayed (fixed input, output and loss-gradient arrays); returns the wall
+    time per gradient."""
+    import torch
+    from paper_2203_11938_amd import sim as S
+    sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
+                      checkpoint_every=w.checkpoint_every, max_steps=w.steps,
+                      membrane=membrane, autotune=autotune, graph=True)
+    xo = torch.empty((len(frames), 3, sim.n_verts), dtype=sim.dtype, device=x0.device)
+    dl = torch.empty_like(xo)
+    V, nb = sim.n_verts, sim.n_instances
+    outs = dict(material=torch.empty((nb, 3), dtype=torch.float64, device=x0.device),
+                forces=torch.empty((w.steps, 3, V), dtype=sim.dtype, device=x0.device),
+                x0=torch.empty((3, V), dtype=sim.dtype, device=x0.device),
+                v0=torch.empty((3, V), dtype=sim.dtype, device=x0.device))
+
+    def gradient():
+        sim.rollout(w.steps, x0, v0, F, None, frames, x_out=xo)
+        torch.sub(xo, tgt, out=dl).mul_(2.0)
+        sim.adjoint(dl, out=outs)
+
+    for _ in range(max(warmup, 1)):
+        gradient()
+        sim.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gradient()
+        sim.status()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = sim.stats()
+    sim.close()
+    return dict(ms_per_gradient=round(ms, 3), captures=int(st["graph_captures"]),
+                replays=int(st["graph_replays"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +172,8 @@ def main():
                     help="keep the rule-based solver launch shape instead of timing the candidates")
     ap.add_argument("--membrane", default="exact", choices=["exact", "tension"],
                     help="membrane block of the step matrix")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the same gradients on a handle in HIP-graph mode")
     ap.add_argument("--sequential", action="store_true",
                     help="batched workloads: also time one handle per sheet, run back to back, "
                          "and report the batched speed-up")
@@ -254,6 +294,10 @@ def main():
                            coarse_rows_lds=bool(st["coarse_rows_lds"]),
                            device_status=S.status_name(sim.status())),
                roofline=roof)
+    if args.graph:
+        print("bench: graph-mode handle", file=sys.stderr, flush=True)
+        out["graph_mode"] = graph_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
+                                         args.warmup, args.membrane, not args.no_autotune)
     if args.sequential and len(insts) > 1:
         out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
                                                              args.membrane, not args.no_autotune)

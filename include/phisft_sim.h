@@ -125,12 +125,22 @@ typedef struct {
                                six rigid motions of every aggregate of nearby vertices
                                and A_c = P^T A P is inverted per step; a sheet with
                                more than 320 aggregates uses larger ones. The solution
-                               still meets cg_tol on the true residual.                 */
+                               still meets cg_tol on the true residual. Each step's
+                               operators (FP32 A_c^-1, offsets, 6x6 blocks) are kept
+                               for the adjoint: for every step when that fits 16 GB
+                               (with checkpointing, recomputed steps reuse them too),
+                               else for one checkpoint segment, else not at all.      */
   int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
                                (rows per workgroup, matrix in LDS or streamed) on the
                                step system of the rest state and keeps the fastest;
                                0 (default): fewest co-resident launches, then LDS-
                                resident rows, then larger workgroups                     */
+  int32_t graph;            /* 1: sim_rollout and sim_adjoint capture their launches
+                               into a HIP graph (on a stream of the handle) and launch
+                               it on the caller's stream; a later call with the same
+                               pointers, step count and loss frames replays it (the
+                               arrays' contents may change). Ignored while solver
+                               timing is on. 0 (default): direct launches              */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -158,6 +168,8 @@ typedef struct {
   double autotune_ms_per_iter;/* measured time per CG iteration of the chosen shape */
   int32_t solver_wg_per_cu;   /* solver variant: 1 or 2 workgroups per CU */
   int32_t coarse_rows_lds;    /* 1: the solver keeps its rows of the coarse inverse in LDS */
+  int64_t graph_captures;     /* rollout / adjoint graphs captured (graph option) */
+  int64_t graph_replays;      /* calls served by replaying a captured graph */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,

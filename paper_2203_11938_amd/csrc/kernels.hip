@@ -735,8 +735,14 @@ __device__ __forceinline__ void tile_mul4(const double (*X)[kGjTile + 1], const 
   }
 }
 
-// Step K, first half: column multipliers C_t = A_tK Pinv (t != K) and a copy R_j of
-// the pivot row tiles A_Kj. One 256-thread workgroup per task.
+// Blocked symmetric sweep (the in-place inverse of an SPD matrix that keeps every
+// intermediate matrix symmetric, so only the tiles (i, j), i <= j, are stored and
+// updated): for each pivot tile K with P = M_KK^-1,
+//   M_ij -= M_iK P M_Kj (i, j != K),  M_iK = M_iK P,  M_Kj = P M_Kj,  M_KK = -P,
+// and after the last pivot M = -A_c^-1.
+// Step K, first half: for every t != K the column panel D_t = M_tK (read from the
+// stored tile (t, K) or, below the diagonal, as the transpose of (K, t)) and
+// C_t = D_t P. One 256-thread workgroup per task; panels are stored tile-major.
 __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
   constexpr int T = kGjTile;
   __shared__ double X[T][T + 1], Y[T][T + 1];
@@ -745,20 +751,13 @@ __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
   if (!c.ok[inst]) return;
   const int np = c.inst_np[inst];
   const double* M = c.mat + c.inst_coff[inst];
-  double* C = c.gj_c + c.inst_boff[inst];
-  double* Rr = c.gj_r + c.inst_boff[inst];
-  if (t < 0) {
-    const int j = -t - 1;
-    for (int e = tid; e < T * T; e += 256) {
-      const int r = e / T, q = e % T;
-      Rr[(size_t)r * np + j * T + q] = M[(size_t)(K * T + r) * np + j * T + q];
-    }
-    return;
-  }
+  double* C = c.gj_c + c.inst_boff[inst] + (size_t)t * T * T;
+  double* D = c.gj_r + c.inst_boff[inst] + (size_t)t * T * T;
   const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
   for (int e = tid; e < T * T; e += 256) {
     const int r = e / T, q = e % T;
-    X[r][q] = M[(size_t)(t * T + r) * np + K * T + q];
+    if (t < K) X[r][q] = M[(size_t)(t * T + r) * np + K * T + q];
+    else X[q][r] = M[(size_t)(K * T + r) * np + t * T + q];   // coalesced read, LDS transpose
     Y[r][q] = P[r * T + q];
   }
   __syncthreads();
@@ -767,13 +766,14 @@ __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = tid + k * 256, r = e / T, q = e % T;
-    C[(size_t)(t * T + r) * T + q] = o[k];
+    C[r * T + q] = o[k];
+    D[r * T + q] = X[r][q];
   }
 }
 
-// Step K, second half: every tile (i, j) of the sheet:
-//   i, j != K: A_ij -= C_i R_j;   i = K: A_Kj = Pinv R_j;   j = K: A_iK = -C_i;
-//   (K, K): Pinv. The tile (K+1, K+1) then inverts itself as the next pivot.
+// Step K, second half: every stored tile (i, j), i <= j, of the sheet:
+//   i, j != K: M_ij -= C_i D_j^T;   j = K: M_iK = C_i;   i = K: M_Kj = C_j^T;
+//   (K, K): -P. The tile (K+1, K+1) then inverts itself as the next pivot.
 __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   constexpr int T = kGjTile;
   __shared__ double X[T][T + 1], Y[T][T + 1];
@@ -783,39 +783,56 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   const int i = ij >> 16, j = ij & 0xffff;
   const int np = c.inst_np[inst], nb = np / T;
   double* M = c.mat + c.inst_coff[inst];
-  const double* C = c.gj_c + c.inst_boff[inst];
-  const double* Rr = c.gj_r + c.inst_boff[inst];
+  const double* Cb = c.gj_c + c.inst_boff[inst];
+  const double* Db = c.gj_r + c.inst_boff[inst];
   const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
-  double o[4];
-  if (i != K && j == K) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + k * 256, r = e / T, q = e % T;
-      M[(size_t)(i * T + r) * np + K * T + q] = -C[(size_t)(i * T + r) * T + q];
-    }
-    return;
-  }
   if (i == K && j == K) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int e = tid + k * 256, r = e / T, q = e % T;
-      M[(size_t)(K * T + r) * np + K * T + q] = P[r * T + q];
+      M[(size_t)(K * T + r) * np + K * T + q] = -P[r * T + q];
     }
     return;
   }
+  if (j == K) {   // i < K
+    const double* Ci = Cb + (size_t)i * T * T;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + k * 256, r = e / T, q = e % T;
+      M[(size_t)(i * T + r) * np + K * T + q] = Ci[r * T + q];
+    }
+    return;
+  }
+  if (i == K) {   // j > K: the transpose of C_j, through LDS
+    const double* Cj = Cb + (size_t)j * T * T;
+    for (int e = tid; e < T * T; e += 256) {
+      const int r = e / T, q = e % T;
+      X[q][r] = Cj[r * T + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + k * 256, r = e / T, q = e % T;
+      M[(size_t)(K * T + r) * np + j * T + q] = X[r][q];
+    }
+    return;
+  }
+  const double* Ci = Cb + (size_t)i * T * T;
+  const double* Dj = Db + (size_t)j * T * T;
   for (int e = tid; e < T * T; e += 256) {
     const int r = e / T, q = e % T;
-    X[r][q] = i == K ? P[r * T + q] : C[(size_t)(i * T + r) * T + q];
-    Y[r][q] = Rr[(size_t)r * np + j * T + q];
+    X[r][q] = Ci[r * T + q];
+    Y[q][r] = Dj[r * T + q];   // Y = D_j^T
   }
   __syncthreads();
+  double o[4];
   tile_mul4(X, Y, o);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = tid + k * 256, r = e / T, q = e % T;
     double* dst = M + (size_t)(i * T + r) * np + j * T + q;
-    const double v = i == K ? o[k] : *dst - o[k];
+    const double v = *dst - o[k];
     *dst = v;
     if (i == K + 1 && j == K + 1) X[r][q] = v;
   }
@@ -836,28 +853,31 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   }
 }
 
-// The solver's copy of A_c^-1: (X + X^T) / 2 rounded to FP32, one 32x32 tile per
+// The solver's copy of A_c^-1 = -M, rounded to FP32, from the stored upper tiles
+// (a tile below the diagonal is the transpose of its mirror; a diagonal tile is
+// averaged with its transpose, so the copy is exactly symmetric). One 32x32 tile per
 // workgroup (grid: tiles of the largest sheet x sheets). The coarse correction is a
 // preconditioner term, so its rounding only changes the iteration count, never the
-// converged residual; the average keeps the preconditioner exactly symmetric.
+// converged residual.
 __global__ void __launch_bounds__(256) k_coarse_pack(Coarse c) {
   constexpr int T = kGjTile;
-  __shared__ double A[T][T + 1], B[T][T + 1];
+  __shared__ double A[T][T + 1];
   const int inst = blockIdx.y, tid = threadIdx.x;
   const int np = c.inst_np[inst], nb = np / T;
   const int I = blockIdx.x / c.max_nb, J = blockIdx.x - I * c.max_nb;
   if (I >= nb || J >= nb) return;
   const double* M = c.mat + c.inst_coff[inst];
   float* X = c.xinv + c.inst_coff[inst];
+  const int I0 = min(I, J), J0 = max(I, J);
   for (int e = tid; e < T * T; e += 256) {
     const int r = e / T, q = e % T;
-    A[r][q] = M[(size_t)(I * T + r) * np + J * T + q];
-    B[r][q] = M[(size_t)(J * T + r) * np + I * T + q];
+    A[r][q] = M[(size_t)(I0 * T + r) * np + J0 * T + q];
   }
   __syncthreads();
   for (int e = tid; e < T * T; e += 256) {
     const int r = e / T, q = e % T;
-    X[(size_t)(I * T + r) * np + J * T + q] = (float)(0.5 * (A[r][q] + B[q][r]));
+    const double v = I < J ? A[r][q] : (I > J ? A[q][r] : 0.5 * (A[r][q] + A[q][r]));
+    X[(size_t)(I * T + r) * np + J * T + q] = (float)(-v);
   }
 }
 
@@ -1322,9 +1342,9 @@ __device__ __forceinline__ void coarse_rows_at(const CoarseRow& cr_, const doubl
 
 // After the cluster barrier that publishes the partial sums: the sheet's coarse
 // residual w_c into LDS (every column sums its aggregate's partials of up to
-// kMaxAggWg workgroups; absent partials are masked lanes, so no memory traffic, and
-// one pass issues all loads together). The caller synchronises the workgroup before
-// w_c is read. Skipped when the step's inversion failed.
+// kMaxAggWg workgroups; index -1 reads entry 0 with weight 0, so the loads carry no
+// branches and one pass issues them together). The caller synchronises the
+// workgroup before w_c is read. Skipped when the step's inversion failed.
 __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s_pidx,
                                               double* s_wc) {
   if (!cr_.ok) return;
@@ -1341,7 +1361,8 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
 #pragma unroll
       for (int k = 0; k < kMaxAggWg; ++k) {
         const int pi = s_pidx[t * kMaxAggWg + k];
-        if (pi >= 0) acc += cr_.part[(size_t)pi * 6 + q];
+        const double v = cr_.part[(size_t)max(pi, 0) * 6 + q];
+        acc += pi >= 0 ? v : 0.0;
       }
       wc[u] = acc;
     }

@@ -86,6 +86,20 @@ struct sim_s {
   const double* material = nullptr;
   hipStream_t stream = nullptr;
 
+  // HIP graphs of the last rollout and adjoint (graph option): replayed when a call
+  // repeats the captured arguments
+  struct GraphCache {
+    bool valid = false;
+    std::vector<uintptr_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<int> slot_after;   // host slot bookkeeping after the captured call
+  };
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  GraphCache gfwd, gadj;
+  long long graph_captures = 0, graph_replays = 0;
+
   sim_stats stats{};
   std::vector<int> inst_status;
   // solver timing: event pairs recorded around each solver launch
@@ -311,11 +325,12 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
       (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
       !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20))) ||
-      (o.autotune != 0 && o.autotune != 1)) {
+      (o.autotune != 0 && o.autotune != 1) || (o.graph != 0 && o.graph != 1)) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
   s->prec = o.precision;
+  s->use_graph = o.graph != 0;
   s->tsize = o.precision == SIM_FP64 ? 8 : 4;
   s->mprec = o.matrix_precision;
   s->msize = o.matrix_precision == SIM_FP64 ? 8 : 4;
@@ -465,11 +480,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
           if (t == K) continue;
           ainst.push_back(b);
           at.push_back(t);
-          ainst.push_back(b);
-          at.push_back(-t - 1);
         }
-        for (int i = 0; i < nb; ++i)
-          for (int j = 0; j < nb; ++j) {
+        for (int i = 0; i < nb; ++i)   // the stored upper tiles
+          for (int j = i; j < nb; ++j) {
             binst.push_back(b);
             bij.push_back(i * 65536 + j);
           }
@@ -534,9 +547,14 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
     TRY(alloc(s, 3 * nv * 8, &q)); cs.mid_crel = (double*)q;
     TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;
-    const int want = s->ckpt > 0 ? s->ckpt : s->max_steps;
+    // one slot per step when they fit the cap (the adjoint, and with checkpointing the
+    // recomputed steps too, then reuse the forward's operators), else one per step of
+    // a checkpoint segment (the recomputed steps rebuild them, the adjoint reuses
+    // those), else none (every step rebuilds)
     const double slot_bytes =
         4.0 * (double)L.coarse_doubles + 8.0 * (6.0 * nv + 36.0 * L.nmid) + 4.0 * ni;
+    int want = s->max_steps;
+    if (want * slot_bytes > kCoarseStoreCap && s->ckpt > 0) want = s->ckpt;
     if (want * slot_bytes <= kCoarseStoreCap) {
       s->cslots = want;
       TRY(alloc(s, (size_t)want * L.coarse_doubles * 4, &q)); s->cmat_store = (float*)q;
@@ -601,7 +619,7 @@ Coarse coarse_for_step(sim_t* s, int step, bool* have) {
   Coarse c = s->coarse;
   *have = false;
   if (s->cslots == 0 || c.nagg == 0) return c;
-  const int slot = s->ckpt > 0 ? (step - 1) % s->ckpt : step - 1;
+  const int slot = (step - 1) % s->cslots;
   c.xinv = s->cmat_store + (size_t)slot * s->L.coarse_doubles;
   c.crel = s->crel_store + (size_t)slot * 3 * s->L.nv;
   c.ok = s->cok_store + (size_t)slot * s->L.ninst;
@@ -635,9 +653,11 @@ void timed_pcg(sim_t* s, const Coarse& cs, const PcgArgs<TM>& c, hipStream_t st)
 }
 
 // ---------------------------------------------------------- step sequences
+// reuse: a recomputed step, whose coarse operator the forward pass of the same rollout
+// may have kept (the forward pass always builds its own)
 template <typename T, typename TM>
 void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, const double* mat,
-                  T* xout, int* iters, double* resid, hipStream_t st) {
+                  T* xout, int* iters, double* resid, bool reuse, hipStream_t st) {
   const int nv = s->L.nv;
   const double* xp = reinterpret_cast<const double*>(sp);
   const double* vp = xp + 3 * (size_t)nv;
@@ -658,8 +678,9 @@ void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, cons
   launch_assemble<T, TM>(s->mesh, s->el, a, st);
   bool have = false;
   const Coarse cs = coarse_for_step(s, step, &have);
-  launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
-                          s->gjb_count.data(), st);
+  if (!(reuse && have))
+    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
+                            s->gjb_count.data(), st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -697,7 +718,7 @@ sim_status rollout_impl(sim_t* s, int n, const void* x0, const void* v0, void* x
     }
     forward_step<T, TM>(s, k, fwd_state(s, k - 1, n), fwd_state(s, k, n), force_slice<T>(s, k),
                     s->material, xo, s->it_fwd + (size_t)(k - 1) * ni,
-                    s->res_fwd + (size_t)(k - 1) * ni, st);
+                    s->res_fwd + (size_t)(k - 1) * ni, false, st);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(s, e, "rollout launch");
@@ -780,7 +801,7 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
       for (int q = c0 + 1; q < c1; ++q)
         forward_step<T, TM>(s, q, adj_state(s, q - 1, c0, n), adj_state(s, q, c0, n), force_slice<T>(s, q),
                         s->material, nullptr, s->it_rec + (size_t)(q - 1) * ni,
-                        s->res_rec + (size_t)(q - 1) * ni, st);
+                        s->res_rec + (size_t)(q - 1) * ni, true, st);
     }
     for (int q = c1; q > c0; --q) {
       const T* dlq = nullptr;
@@ -796,6 +817,47 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
   if (dl_dmat) launch_material_sum(s->mesh, s->el, static_cast<double*>(dl_dmat), st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(s, e, "adjoint launch");
+  return SIM_OK;
+}
+
+void graph_release(sim_t::GraphCache& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = sim_t::GraphCache{};
+}
+
+// Runs body(stream) directly, or (graph option, timing off) replays the cached graph
+// when the key matches, else captures body on the handle's capture stream, keeps the
+// graph and launches it on the caller's stream. Nothing in the step sequences
+// allocates, synchronises or records memsets, so they capture as plain kernel nodes.
+template <class Body>
+sim_status graphed(sim_t* s, sim_t::GraphCache& gc, const std::vector<uintptr_t>& key,
+                   hipStream_t user, Body&& body) {
+  if (!s->use_graph || s->timing) return body(user);
+  if (gc.valid && gc.key == key) {
+    s->slot_step = gc.slot_after;
+    HIPCHECK(s, hipGraphLaunch(gc.exec, user));
+    ++s->graph_replays;
+    return SIM_OK;
+  }
+  graph_release(gc);
+  if (!s->cap_stream) HIPCHECK(s, hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+  HIPCHECK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+  const sim_status st = body(s->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+  if (st != SIM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "hipStreamEndCapture");
+  gc.graph = g;
+  HIPCHECK(s, hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0));
+  gc.key = key;
+  gc.slot_after = s->slot_step;
+  gc.valid = true;
+  ++s->graph_captures;
+  HIPCHECK(s, hipGraphLaunch(gc.exec, user));
   return SIM_OK;
 }
 
@@ -891,13 +953,16 @@ sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0
   s->forces = forces;
   s->material = material ? static_cast<const double*>(material) : s->mat_default;
   s->stream = static_cast<hipStream_t>(stream);
-  sim_status st;
-  if (s->prec == SIM_FP64)
-    st = s->mprec == SIM_FP64 ? rollout_impl<double, double>(s, n_steps, x0, v0, x_out, s->stream)
-                              : rollout_impl<double, float>(s, n_steps, x0, v0, x_out, s->stream);
-  else
-    st = s->mprec == SIM_FP64 ? rollout_impl<float, double>(s, n_steps, x0, v0, x_out, s->stream)
-                              : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, s->stream);
+  std::vector<uintptr_t> key = {(uintptr_t)n_steps, (uintptr_t)x0, (uintptr_t)v0,
+                                (uintptr_t)forces, (uintptr_t)s->material, (uintptr_t)x_out};
+  key.insert(key.end(), s->frames.begin(), s->frames.end());
+  const sim_status st = graphed(s, s->gfwd, key, s->stream, [&](hipStream_t q) {
+    if (s->prec == SIM_FP64)
+      return s->mprec == SIM_FP64 ? rollout_impl<double, double>(s, n_steps, x0, v0, x_out, q)
+                                  : rollout_impl<double, float>(s, n_steps, x0, v0, x_out, q);
+    return s->mprec == SIM_FP64 ? rollout_impl<float, double>(s, n_steps, x0, v0, x_out, q)
+                                : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, q);
+  });
   if (st == SIM_OK) s->have_rollout = true;
   return st;
 }
@@ -914,17 +979,19 @@ sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl
     return SIM_E_INVALID;
   }
   s->stream = static_cast<hipStream_t>(stream);
-  if (s->prec == SIM_FP64)
+  // the adjoint reads the rollout's states, forces and material: its key includes them
+  std::vector<uintptr_t> key = {(uintptr_t)dl_dx, (uintptr_t)dl_dmaterial, (uintptr_t)dl_dforces,
+                                (uintptr_t)dl_dx0, (uintptr_t)dl_dv0};
+  key.insert(key.end(), s->gfwd.key.begin(), s->gfwd.key.end());
+  return graphed(s, s->gadj, key, s->stream, [&](hipStream_t q) {
+    if (s->prec == SIM_FP64)
+      return s->mprec == SIM_FP64
+                 ? adjoint_impl<double, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q)
+                 : adjoint_impl<double, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q);
     return s->mprec == SIM_FP64
-               ? adjoint_impl<double, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
-                                              s->stream)
-               : adjoint_impl<double, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
-                                             s->stream);
-  return s->mprec == SIM_FP64
-             ? adjoint_impl<float, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
-                                           s->stream)
-             : adjoint_impl<float, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0,
-                                          s->stream);
+               ? adjoint_impl<float, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q)
+               : adjoint_impl<float, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q);
+  });
 }
 
 sim_status sim_sync_status(sim_t* s) {
@@ -996,6 +1063,8 @@ sim_status sim_get_instance_status(const sim_t* s, int32_t* out) {
 sim_status sim_get_stats(const sim_t* s, sim_stats* out) {
   if (!s || !out) return SIM_E_INVALID;
   *out = s->stats;
+  out->graph_captures = s->graph_captures;
+  out->graph_replays = s->graph_replays;
   return SIM_OK;
 }
 
@@ -1030,6 +1099,9 @@ const char* sim_last_error(const sim_t* s) { return s ? s->err.c_str() : ""; }
 void sim_destroy(sim_t* s) {
   if (!s) return;
   if (!s->allocs.empty()) (void)hipDeviceSynchronize();
+  graph_release(s->gfwd);
+  graph_release(s->gadj);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   for (void* p : s->allocs) (void)hipFree(p);
   delete s;

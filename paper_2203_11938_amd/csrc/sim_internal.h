@@ -108,10 +108,10 @@ struct Coarse {
   // blocked Gauss-Jordan task lists, per pivot tile K (ptr arrays have max_nb + 1 entries)
   const int* gja_ptr;          // column multipliers / pivot-row copies of step K
   const int* gja_inst;
-  const int* gja_t;            // >= 0: C_t = A_tK Pinv; < 0: R_j = A_Kj with j = -t - 1
+  const int* gja_t;            // panel tile t != K of step K
   const int* gjb_ptr;          // tile updates of step K
   const int* gjb_inst;
-  const int* gjb_ij;           // i * 65536 + j
+  const int* gjb_ij;           // i * 65536 + j, i <= j (stored upper tiles)
   // solver-plan overlaps
   const int* wg_agg0;          // [nwg]
   const int* wg_nagg;          // [nwg]
@@ -119,10 +119,11 @@ struct Coarse {
   const int* agg_nwg;          // [nagg]
   // per-step data
   double* crel;                // [3][nv] x_i - c (zero where the rotations are not used)
-  double* mat;                 // A_c, inverted in place (FP64 work matrix)
+  double* mat;                 // A_c, swept in place to -A_c^-1 (FP64 work matrix, upper
+                               // tiles; the lower ones are written by the assembly only)
   float* xinv;                 // symmetrised FP32 copy of A_c^-1 read by the solver
-  double* gj_c;                // per sheet [np][32] column multipliers
-  double* gj_r;                // per sheet [32][np] pivot-row copy
+  double* gj_c;                // per sheet [nb][32][32] C_t = M_tK P of the current step
+  double* gj_r;                // per sheet [nb][32][32] column panel D_t = M_tK
   double* gj_pinv;             // [2][ninst][32][32] inverse pivot tiles
   const long long* inst_boff;  // [ninst] offset of the sheet's gj_c / gj_r blocks (32 np)
   int* ok;                     // [ninst] 1 when this step's inversion succeeded
@@ -142,7 +143,7 @@ struct Coarse {
 // Cluster-barrier layout: counters 128 bytes apart; sheets with more than
 // kBarrierGroup workgroups arrive in groups of that size.
 constexpr int kBarrierSlot = 32;   // ints per counter slot
-constexpr int kBarrierGroup = 16;
+constexpr int kBarrierGroup = 64;
 
 constexpr int kMaxSolverGroups = 64;
 

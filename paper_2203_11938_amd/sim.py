@@ -60,7 +60,7 @@ class _Options(ctypes.Structure):
                 ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
                 ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -74,7 +74,8 @@ class _Stats(ctypes.Structure):
                 ("solver_ms", ctypes.c_double), ("coarse_aggregates", ctypes.c_int32),
                 ("coarse_max_dim", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double),
-                ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32)]
+                ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32),
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
 
 _lib = None
@@ -157,14 +158,16 @@ class Simulator:
     selects the system matrix's membrane block ("exact" Hessian or "tension");
     ``coarse_size`` sets the vertices per aggregate of the solver's coarse space
     (0: block-Jacobi only); ``autotune`` times the feasible solver launch shapes at
-    creation and keeps the fastest.
+    creation and keeps the fastest; ``graph`` captures rollout and adjoint into HIP
+    graphs that later calls with the same arrays replay.
     """
 
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
                  cg_tol: float = 1e-7, cg_max_iter: int = 20000, checkpoint_every: int = 0,
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
                  membrane: str = "exact", matrix_precision: str = "fp64",
-                 coarse_size: Optional[int] = None, autotune: bool = False):
+                 coarse_size: Optional[int] = None, autotune: bool = False,
+                 graph: bool = False):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -184,6 +187,7 @@ class Simulator:
         if coarse_size is not None:
             opt.coarse_size = coarse_size
         opt.autotune = 1 if autotune else 0
+        opt.graph = 1 if graph else 0
         self.matrix_precision = matrix_precision
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
@@ -275,15 +279,27 @@ class Simulator:
         return x_out
 
     def adjoint(self, dl_dx: torch.Tensor, want_forces: bool = True, want_x0: bool = True,
-                want_v0: bool = True, want_material: bool = True):
-        """Gradients of the loss whose frame gradients are ``dl_dx`` [n_loss, 3, V]."""
+                want_v0: bool = True, want_material: bool = True, out: Optional[dict] = None):
+        """Gradients of the loss whose frame gradients are ``dl_dx`` [n_loss, 3, V].
+
+        ``out`` may hold preallocated result tensors (keys material, forces, x0, v0);
+        passing the same ones on every call lets a graph-mode handle replay."""
         V = self.n_verts
         self._need(dl_dx, (self.n_loss, 3, V), "dl_dx")
         dev = dl_dx.device
-        g_mat = torch.empty((self.n_instances, 3), dtype=torch.float64, device=dev) if want_material else None
-        g_F = torch.empty((self.n_steps, 3, V), dtype=self.dtype, device=dev) if want_forces else None
-        g_x0 = torch.empty((3, V), dtype=self.dtype, device=dev) if want_x0 else None
-        g_v0 = torch.empty((3, V), dtype=self.dtype, device=dev) if want_v0 else None
+        out = out or {}
+        def buf(key, want, shape, dtype):
+            if not want:
+                return None
+            t = out.get(key)
+            if t is None:
+                return torch.empty(shape, dtype=dtype, device=dev)
+            self._need(t, shape, key, dtype)
+            return t
+        g_mat = buf("material", want_material, (self.n_instances, 3), torch.float64)
+        g_F = buf("forces", want_forces, (self.n_steps, 3, V), self.dtype)
+        g_x0 = buf("x0", want_x0, (3, V), self.dtype)
+        g_v0 = buf("v0", want_v0, (3, V), self.dtype)
         st = self._lib.sim_adjoint(self._h, _ptr(dl_dx), _ptr(g_mat), _ptr(g_F), _ptr(g_x0),
                                    _ptr(g_v0), _stream())
         self._check(st, "sim_adjoint")

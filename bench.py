@@ -122,15 +122,17 @@ def sequential_comparison(w, insts, batched_ms, steps, membrane, autotune):
                 speedup=round(seq_ms / batched_ms, 2))
 
 
-def graph_timing(w, sheets, x0, v0, F, tgt, frames, steps, warmup, membrane, autotune):
-    """The same gradient on a handle in graph mode: rollout and adjoint are captured
-    once and replayed (fixed input, output and loss-gradient arrays); returns the wall
-    time per gradient."""
+def variant_timing(w, sheets, x0, v0, F, tgt, frames, steps, warmup, membrane, autotune,
+                   graph=False, checkpoint_every=None):
+    """The same gradient on another handle: in graph mode (rollout and adjoint
+    captured once and replayed; fixed input, output and loss-gradient arrays) and/or
+    with another checkpoint interval; returns the wall time per gradient."""
     import torch
     from paper_2203_11938_amd import sim as S
+    ck = w.checkpoint_every if checkpoint_every is None else checkpoint_every
     sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
-                      checkpoint_every=w.checkpoint_every, max_steps=w.steps,
-                      membrane=membrane, autotune=autotune, graph=True)
+                      checkpoint_every=ck, max_steps=w.steps,
+                      membrane=membrane, autotune=autotune, graph=graph)
     xo = torch.empty((len(frames), 3, sim.n_verts), dtype=sim.dtype, device=x0.device)
     dl = torch.empty_like(xo)
     V, nb = sim.n_verts, sim.n_instances
@@ -156,8 +158,13 @@ def graph_timing(w, sheets, x0, v0, F, tgt, frames, steps, warmup, membrane, aut
     ms = 1e3 * (time.perf_counter() - t0) / steps
     st = sim.stats()
     sim.close()
-    return dict(ms_per_gradient=round(ms, 3), captures=int(st["graph_captures"]),
-                replays=int(st["graph_replays"]))
+    out = dict(ms_per_gradient=round(ms, 3),
+               value=round(sim.n_verts * w.steps / (ms * 1e-3), 1))
+    if graph:
+        out.update(captures=int(st["graph_captures"]), replays=int(st["graph_replays"]))
+    if ck:
+        out.update(checkpoint_every=ck, cg_iters_recompute=int(st["cg_iters_recompute"]))
+    return out
 
 
 def main():
@@ -172,6 +179,9 @@ def main():
                     help="keep the rule-based solver launch shape instead of timing the candidates")
     ap.add_argument("--membrane", default="exact", choices=["exact", "tension"],
                     help="membrane block of the step matrix")
+    ap.add_argument("--checkpoint-report", type=int, default=10, metavar="K",
+                    help="store-all workloads: also time the gradient with a state "
+                         "checkpoint every K steps (0: skip)")
     ap.add_argument("--graph", action="store_true",
                     help="also time the same gradients on a handle in HIP-graph mode")
     ap.add_argument("--sequential", action="store_true",
@@ -296,8 +306,14 @@ def main():
                roofline=roof)
     if args.graph:
         print("bench: graph-mode handle", file=sys.stderr, flush=True)
-        out["graph_mode"] = graph_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
-                                         args.warmup, args.membrane, not args.no_autotune)
+        out["graph_mode"] = variant_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
+                                           args.warmup, args.membrane, not args.no_autotune,
+                                           graph=True)
+    if args.checkpoint_report > 0 and w.checkpoint_every == 0:
+        print(f"bench: checkpoint every {args.checkpoint_report}", file=sys.stderr, flush=True)
+        out["checkpointed"] = variant_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
+                                             args.warmup, args.membrane, not args.no_autotune,
+                                             checkpoint_every=args.checkpoint_report)
     if args.sequential and len(insts) > 1:
         out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
                                                              args.membrane, not args.no_autotune)

@@ -32,9 +32,51 @@
 namespace phisft {
 
 // ------------------------------------------------------------------ helpers
+// Lane exchanges without the LDS crossbar: the partner of lane l differs from l in bit
+// O (and, for O = 4, 8, in the lower bits too), which is all a butterfly or a
+// recursive halving needs. O = 32, 16: the gfx950 permlane swaps (the swapped copy
+// holds lane l ^ O's value in the lanes whose bit O is clear, the kept copy in the
+// others); O = 8, 4: DPP row mirror / half mirror (l <-> 15 - l, l <-> 7 - l within
+// each 16 / 8 lanes); O = 2, 1: DPP quad permutations. Every lane of the wavefront
+// must be active.
+template <int O>
+__device__ __forceinline__ int exch_i(int v, int lane) {
+  if constexpr (O == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32) ? r[0] : r[1];
+  } else if constexpr (O == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return (lane & 16) ? r[0] : r[1];
+  } else if constexpr (O == 8) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);   // row_mirror
+  } else if constexpr (O == 4) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);   // row_half_mirror
+  } else if constexpr (O == 2) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);    // quad_perm [2,3,0,1]
+  } else {
+    static_assert(O == 1, "exchange distance");
+    return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);    // quad_perm [1,0,3,2]
+  }
+}
+
+template <int O>
+__device__ __forceinline__ double exch(double v, int lane) {
+  int2 t = *reinterpret_cast<int2*>(&v);
+  t.x = exch_i<O>(t.x, lane);
+  t.y = exch_i<O>(t.y, lane);
+  return *reinterpret_cast<double*>(&t);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-  // xor butterfly: every lane ends with the same, order-fixed sum
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  // butterfly: every lane ends with the same, order-fixed sum (each step adds two
+  // copies in either order, which rounds identically)
+  const int lane = threadIdx.x & 63;
+  v += exch<32>(v, lane);
+  v += exch<16>(v, lane);
+  v += exch<8>(v, lane);
+  v += exch<4>(v, lane);
+  v += exch<2>(v, lane);
+  v += exch<1>(v, lane);
   return v;
 }
 
@@ -50,7 +92,7 @@ __device__ __forceinline__ void halve_step(double (&v)[NP], int lane) {
     for (int k = 0; k < H; ++k) {
       const double send = up ? v[k] : v[k + H];
       const double keep = up ? v[k + H] : v[k];
-      v[k] = keep + __shfl_xor(send, O, 64);
+      v[k] = keep + exch<O>(send, lane);
     }
     halve_step<H / 2, O / 2, NP>(v, lane);
   }
@@ -60,8 +102,11 @@ template <int NP>
 __device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
   halve_step<NP / 2, 32, NP>(v, lane);
   double t = v[0];
-#pragma unroll
-  for (int o = 32 / NP; o >= 1; o >>= 1) t += __shfl_xor(t, o, 64);
+  if constexpr (32 / NP >= 16) t += exch<16>(t, lane);
+  if constexpr (32 / NP >= 8) t += exch<8>(t, lane);
+  if constexpr (32 / NP >= 4) t += exch<4>(t, lane);
+  if constexpr (32 / NP >= 2) t += exch<2>(t, lane);
+  if constexpr (32 / NP >= 1) t += exch<1>(t, lane);
   return t;
 }
 
@@ -1417,10 +1462,16 @@ __device__ __forceinline__ void mid_apply(const double* __restrict__ Bm, bool li
   t[3] = live ? r[1] * v[2] - r[2] * v[1] : 0.0;
   t[4] = live ? r[2] * v[0] - r[0] * v[2] : 0.0;
   t[5] = live ? r[0] * v[1] - r[1] * v[0] : 0.0;
+  // sums over the run's 16 lanes (one DPP row), in every lane of the row
+  static_assert(kMid == 16, "a run is one DPP row");
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int off = 1; off < kMid; off <<= 1)
-#pragma unroll
-    for (int q = 0; q < 6; ++q) t[q] += __shfl_xor(t[q], off, kMid);
+  for (int q = 0; q < 6; ++q) {
+    t[q] += exch<1>(t[q], lane);
+    t[q] += exch<2>(t[q], lane);
+    t[q] += exch<4>(t[q], lane);
+    t[q] += exch<8>(t[q], lane);
+  }
   double e[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q)

@@ -944,9 +944,14 @@ struct Barrier {
 };
 
 // Polls with relaxed agent-scope loads (they read the coherent value without cache
-// maintenance) and acquires once when the target is reached: an acquire load in the
-// loop would invalidate this XCD's L2 on every poll, evicting the data that the
-// workgroups still computing on it are reading.
+// maintenance). Everything another workgroup of the same launch wrote and this one
+// reads after a wait (partial sums, restriction partials, halo rows) is read with
+// agent-scope atomic loads as well, which are coherent on their own; so no agent
+// acquire (an invalidation of this XCD's L2, which would also evict the matrix and
+// coarse rows that the other workgroups on the XCD are reading) is needed, only the
+// ordering of those loads after the poll: a workgroup-scope acquire (a wait for the
+// poll, and a compiler barrier). The writers release with an agent-scope release
+// (their stores are written back before the flag or counter moves).
 __device__ __forceinline__ bool bounded_wait_ge(int* addr, int target, int* abort_flag) {
   int spins = 0;
   while (__hip_atomic_load(addr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -955,7 +960,7 @@ __device__ __forceinline__ bool bounded_wait_ge(int* addr, int target, int* abor
         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
       return false;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return true;
 }
 
@@ -1128,13 +1133,15 @@ __device__ __forceinline__ void loadnb(const int* __restrict__ Cl, int R, int ti
   }
 }
 
-// Halo of the vector vg ([3][nv] in global memory) into vl[c][R + h].
-__device__ __forceinline__ void halo_load(const double* __restrict__ vg, int nv,
+// Halo of the vector vg ([3][nv] in global memory, written by other workgroups of
+// this launch; coherent agent-scope loads) into vl[c][R + h].
+__device__ __forceinline__ void halo_load(const double* vg, int nv,
                                           const int* __restrict__ hidx, int nh,
                                           double* __restrict__ vl, int R, int RH) {
   for (int e = threadIdx.x; e < 3 * nh; e += blockDim.x) {
     const int c = e / nh, h = e - c * nh;
-    vl[c * RH + R + h] = vg[(size_t)c * nv + hidx[h]];
+    vl[c * RH + R + h] = __hip_atomic_load(const_cast<double*>(vg) + (size_t)c * nv + hidx[h],
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1406,7 +1413,8 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
 #pragma unroll
       for (int k = 0; k < kMaxAggWg; ++k) {
         const int pi = s_pidx[t * kMaxAggWg + k];
-        const double v = cr_.part[(size_t)max(pi, 0) * 6 + q];
+        const double v = __hip_atomic_load(const_cast<double*>(cr_.part) + (size_t)max(pi, 0) * 6 + q,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         acc += pi >= 0 ? v : 0.0;
       }
       wc[u] = acc;

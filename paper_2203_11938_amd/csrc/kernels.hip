@@ -4,14 +4,17 @@
 //   k_elements      per triangle: deformation gradient F, Green strain G, force and
 //                   the nine 3x3 blocks of the system stiffness; per hinge: dihedral
 //                   angle, its gradient, force and Gauss-Newton weight.
-//   k_assemble      per vertex row, atomic-free: gathers the row's blocks in a fixed
-//                   order into A = M + h^2 K_sys (ELL layout, pins eliminated), the
-//                   right-hand side b = h (f + M g + F_t - h K_sys v) and the inverse
-//                   of the diagonal block (block-Jacobi preconditioner).
+//   k_assemble      per vertex row (four lanes each), atomic-free: gathers the row's
+//                   blocks in a fixed order into A = M + h^2 K_sys (ELL layout, pins
+//                   eliminated), the right-hand side b = h (f + M g + F_t - h K_sys v)
+//                   and the inverse of the diagonal block.
+//   coarse set-up   aggregate frames, A_c = P^T A P, its inverse by a blocked
+//                   symmetric sweep, the FP32 copy; the 6x6 blocks of the middle level.
 //   k_pcg           persistent preconditioned pipelined CG: every workgroup owns a
-//                   row range, keeps its matrix rows in LDS and its vectors in FP64
-//                   registers; the workgroups of one sheet meet at one counter
-//                   barrier per iteration (reductions are fixed-order, so results
+//                   row range, keeps its vectors in FP64 registers (matrix rows in
+//                   LDS or streamed); per iteration the workgroups of one sheet meet
+//                   at one counter barrier and publish the preconditioned vector to
+//                   their neighbours only (reductions are fixed-order, so results
 //                   are bitwise reproducible).
 //   k_update        v_t = v_{t-1} + dv, x_t = x_{t-1} + h v_t, pins held.
 // Adjoint step (implicit differentiation of Eq. 4): k_adj_pre, the same assembly and
@@ -445,15 +448,22 @@ __device__ __forceinline__ bool inv3(const double a[9], double o[9]) {
 
 template <typename T, typename TM>
 __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<T, TM> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // 64 rows per workgroup, 16 per wavefront: the four lanes l, l + 16, l + 32, l + 48
+  // of a wavefront share a row, each taking every fourth matrix slot and every fourth
+  // incident element; their partial sums meet through two lane exchanges, so every
+  // lane stays active up to there (lanes past the last row work on a copy of it and
+  // store nothing).
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int i0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * 16 + (lane & 15);
   const int nv = m.nv;
-  if (i >= nv) return;
+  const bool live = i0 < nv;
+  const int i = live ? i0 : nv - 1;
   const int inst = m.vert_inst[i];
   const double mass = a.mat[3 * inst + 2] * m.varea[i];
   const bool pin_i = m.pinned[i] != 0;
   const double h = a.h, h2 = a.h * a.h;
-  double kv[3] = {0.0, 0.0, 0.0}, diag[9];
-  for (int k = 0; k < m.maxnz; ++k) {
+  double kv[3] = {0.0, 0.0, 0.0};
+  for (int k = g; k < m.maxnz; k += 4) {
     const int s = k * nv + i;
     const int j = m.ell_col[s];
     double Ab[9];
@@ -482,27 +492,27 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
         }
       }
     }
+    if (live) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) a.A[(size_t)(k * 9 + q) * nv + i] = (TM)Ab[q];
-    if (j == i) {
+      for (int q = 0; q < 9; ++q) a.A[(size_t)(k * 9 + q) * nv + i] = (TM)Ab[q];
+    }
+    if (j == i && live) {
+      // block-Jacobi inverse of the stored (rounded) diagonal block
+      double dr[9], Ji[9];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) diag[q] = Ab[q];
+      for (int q = 0; q < 9; ++q) dr[q] = (double)(TM)Ab[q];
+      if (!inv3(dr, Ji)) {
+        set_status(a.status, inst, ST_INDEFINITE);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Ji[q] = (q % 4) == 0 ? 1.0 : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) a.Jinv[q * nv + i] = (TM)Ji[q];
     }
   }
-  // block-Jacobi inverse of the stored (rounded) diagonal block
-  double dr[9], Ji[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) dr[q] = (double)(TM)diag[q];
-  if (!inv3(dr, Ji)) {
-    set_status(a.status, inst, ST_INDEFINITE);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) Ji[q] = (q % 4) == 0 ? 1.0 : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < 9; ++q) a.Jinv[q * nv + i] = (TM)Ji[q];
-  if (!a.want_rhs) return;
+  if (!a.want_rhs) return;   // uniform
   double f[3] = {0.0, 0.0, 0.0};
-  for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
+  for (int c = m.vinc_ptr[i] + g; c < m.vinc_ptr[i + 1]; c += 4) {
     int ref = m.vinc_ref[c];
     if (ref >= 0) {
       int t = ref / 3, va = ref - 3 * (ref / 3);
@@ -515,6 +525,14 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
       for (int r = 0; r < 3; ++r) f[r] += el.hin_f[(va * 3 + r) * m.nh + e];
     }
   }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    kv[r] += exch<16>(kv[r], lane);
+    kv[r] += exch<32>(kv[r], lane);
+    f[r] += exch<16>(f[r], lane);
+    f[r] += exch<32>(f[r], lane);
+  }
+  if (g != 0 || !live) return;
   double b[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
@@ -526,9 +544,9 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
 }
 
 // ------------------------------------------------- coarse space (once per step)
-// Two-level additive preconditioner M^-1 = B^-1 + P A_c^-1 P^T. Per step: the
-// aggregate frames at x_{t-1}, the Galerkin product A_c = P^T A P (dense per
-// sheet), its Cholesky factorisation and its inverse. The PCG applies A_c^-1 as a
+// Coarse level of the preconditioner M^-1 = B^-1 + P1 B1^-1 P1^T + P A_c^-1 P^T. Per
+// step: the aggregate frames at x_{t-1}, the Galerkin product A_c = P^T A P (dense per
+// sheet) and its inverse by a blocked symmetric sweep. The PCG applies A_c^-1 as a
 // dense product with the rows of the inverse that its workgroup needs.
 
 // One wavefront per aggregate: centroid of the free vertices at x and the offsets
@@ -2154,7 +2172,7 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_assemble<T, TM>), dim3(blocks_for(m.nv, 128)), dim3(128), 0, st, m, el, a);
+  hipLaunchKernelGGL((k_assemble<T, TM>), dim3(blocks_for(m.nv, 64)), dim3(256), 0, st, m, el, a);
 }
 
 template <typename TM>

@@ -1069,6 +1069,60 @@ __device__ __forceinline__ bool neighbour_sync(int* flags, int wg, const int* __
   return true;
 }
 
+// Tagged publication of a row vector: each double travels as two 64-bit words, each
+// holding a 32-bit tag (the publication's number, the same in every workgroup of a
+// sheet) above 32 bits of the value. A 64-bit store is single-copy atomic, so a
+// reader that sees the expected tag in both words has the value published with it:
+// no flag, no fence, no separate round trip. Words are written and read with
+// coherent agent-scope atomics; the buffer is zeroed before each launch (tags start
+// at 1). The full cluster barrier of every iteration keeps a workgroup from
+// rewriting a word (two publications later) before its readers are done with it.
+__device__ __forceinline__ void publish_tagged(unsigned long long* tb, int nv, int i,
+                                               const double v[3], unsigned tag) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v[c]);
+    const unsigned long long t = (unsigned long long)tag << 32;
+    unsigned long long* p = tb + ((size_t)c * nv + i) * 2;
+    __hip_atomic_store(p, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Halo of a tagged vector into vl[c][R + h]: every entry is polled until both of its
+// words carry `tag` (bounded like the barrier's waits). False (every thread) on a
+// time-out or an abort; the caller then stops.
+__device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
+                                                 const int* __restrict__ hidx, int nh,
+                                                 double* __restrict__ vl, int R, int RH,
+                                                 unsigned tag, int* abort_flag) {
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  bool ok = true;
+  for (int e = threadIdx.x; e < 3 * nh && ok; e += blockDim.x) {
+    const int c = e / nh, h = e - c * nh;
+    unsigned long long* p = const_cast<unsigned long long*>(tb) + ((size_t)c * nv + hidx[h]) * 2;
+    unsigned long long w0, w1;
+    int spins = 0;
+    while (true) {
+      w0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      w1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit ||
+          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = false;
+        break;
+      }
+    }
+    if (ok) vl[c * RH + R + h] = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+  }
+  if (!ok) s_bad = 1;
+  __syncthreads();
+  return s_bad == 0;
+}
+
 // Fixed-order workgroup sum of three values; thread 0 stores them at dst.
 __device__ __forceinline__ void publish3(const double a[3], double* dst) {
   __shared__ double s_part[3][4];
@@ -1768,18 +1822,22 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     if (COARSE) {
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
       coarse_apply(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
+      unsigned long long* tb = w.tbuf + (size_t)par * 6 * nv;
+      ++nep;
       if (act) {
+        publish_tagged(tb, nv, i, mm, (unsigned)nep);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          mb[c * nv + i] = mm[c];
-          ml[c * RH + tid] = mm[c];
-        }
+        for (int c = 0; c < 3; ++c) ml[c * RH + tid] = mm[c];
       }
       PHASE_ADD(4, wall_clock64() - t5);
-      if (!(ok = neighbour_sync(nbflags, wg, nbw, nnb, ++nep, w.abort_flag, a.status, inst)))
+      if (!halo_load_tagged(tb, nv, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
+        if (tid == 0) {
+          __hip_atomic_store(w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          set_status(a.status, inst, ST_TIMEOUT);
+        }
+        ok = false;
         break;
-      halo_load(mb, nv, s_hidx, nh, ml, R, RH);
-      __syncthreads();
+      }
       PHASE_ADD(5, wall_clock64() - t5);
     }
     if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, ml, RH, nn);
@@ -2235,6 +2293,7 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
                                  plan.max_halo, coarse ? plan.xl_floats : 0);
   launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
+  if (coarse) launch_fill_int(reinterpret_cast<int*>(w.tbuf), 24 * m.nv, 0, st);
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
   for (int g = 0; g < plan.ngroups; ++g) {
     SolverPlan pg = plan;

@@ -178,6 +178,8 @@ struct SolverPlan {
 struct SolverWork {
   double* zbuf;            // [3][nv]     preconditioned initial residual, gathered once
   double* pbuf;            // [2][3][nv]  m = M^-1 w of even / odd iterations
+  unsigned long long* tbuf;  // [2][3][nv][2] the same, published as tagged 64-bit words
+                             // (tag << 32 | 32 data bits), zeroed before each launch
   double* red;             // [2][nwg][3] per-workgroup partial sums
   int* barrier;            // counter slots: [ninst] roots, then group counter/flag pairs
   int barrier_ints;        // ints to zero before each launch

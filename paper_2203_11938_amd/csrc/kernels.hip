@@ -1035,6 +1035,11 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
   return s_ok != 0;
 }
 
+// Sheets with at most this many solver workgroups exchange their per-iteration partial
+// sums as tagged words instead of through a cluster barrier (measured: 32 workgroups
+// gain, 157 lose).
+constexpr int kTagWgMax = 64;
+
 // Point-to-point publication: after the workgroup has stored a vector's rows, it sets
 // its own flag to `epoch` (release) and waits until every workgroup that owns one of
 // its halo rows has done the same (relaxed polls by the lanes of wavefront 0, one
@@ -1087,6 +1092,46 @@ __device__ __forceinline__ void publish_tagged(unsigned long long* tb, int nv, i
     __hip_atomic_store(p, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(p + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+__device__ __forceinline__ void store_tagged(unsigned long long* p, unsigned tag, double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long t = (unsigned long long)tag << 32;
+  __hip_atomic_store(p, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool tag_ok(unsigned long long w0, unsigned long long w1, unsigned tag) {
+  return (unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag;
+}
+
+__device__ __forceinline__ double tag_value(unsigned long long w0, unsigned long long w1) {
+  return __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+}
+
+// Re-reads one tagged entry until it carries `tag` (bounded); false on a time-out or
+// an abort.
+__device__ __forceinline__ bool poll_tagged(const unsigned long long* p, unsigned tag,
+                                            int* abort_flag, unsigned long long& w0,
+                                            unsigned long long& w1) {
+  unsigned long long* q = const_cast<unsigned long long*>(p);
+  int spins = 0;
+  while (!tag_ok(w0, w1, tag)) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit ||
+        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+      return false;
+    w0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    w1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+__device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigned long long& w0,
+                                            unsigned long long& w1) {
+  unsigned long long* q = const_cast<unsigned long long*>(p);
+  w0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  w1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Halo of a tagged vector into vl[c][R + h]: every entry is polled until both of its
@@ -1339,15 +1384,19 @@ __device__ __forceinline__ void coarse_restrict(double* __restrict__ part, int w
 }
 
 // The iteration's publication in one pass: the coarse restriction of y (as
-// coarse_restrict) and the workgroup's three dot-product partials (as publish3). A
+// coarse_restrict) and the workgroup's three dot-product partials (as publish3),
+// either as tagged words that the other workgroups of the sheet poll (no barrier) or
+// into the plain arrays that a cluster barrier releases. A
 // wavefront whose rows lie in one aggregate (the usual case: aggregates are runs of
 // whole 16-row groups) reduces its nine values together by recursive halving; one
 // that spans several aggregates falls back to a butterfly per aggregate and value.
 // One workgroup barrier in all.
-__device__ __forceinline__ void publish_restrict_dots(double* __restrict__ part, int wg, int wna,
-                                                      int kf, int kl, int kloc, bool live,
+__device__ __forceinline__ void publish_restrict_dots(bool tagged, unsigned long long* trw,
+                                                      unsigned tag, double* __restrict__ part,
+                                                      double* dst, int wg, int wna, int kf,
+                                                      int kl, int kloc, bool live,
                                                       const double r[3], const double y[3],
-                                                      const double loc[3], double* dst) {
+                                                      const double loc[3]) {
   __shared__ double s_wp[4][kMaxWgAgg][6];
   __shared__ double s_pd[4][3];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1392,15 +1441,19 @@ __device__ __forceinline__ void publish_restrict_dots(double* __restrict__ part,
     }
   }
   __syncthreads();
+  // tagged: this workgroup's slots (the dot partials, then 6 per aggregate); else the
+  // plain partial arrays read after a barrier
   if (tid < wna * 6) {
     const int k = tid / 6, q = tid % 6;
     double t = 0.0;
     for (int w = 0; w < nwaves; ++w) t += s_wp[w][k][q];
-    part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
+    if (tagged) store_tagged(trw + (size_t)(3 + tid) * 2, tag, t);
+    else part[((size_t)wg * kMaxWgAgg + k) * 6 + q] = t;
   } else if (tid >= 32 && tid < 35) {
     double t = 0.0;
     for (int w = 0; w < nwaves; ++w) t += s_pd[w][tid - 32];
-    dst[tid - 32] = t;
+    if (tagged) store_tagged(trw + (size_t)(tid - 32) * 2, tag, t);
+    else dst[tid - 32] = t;
   }
 }
 
@@ -1495,6 +1548,81 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
     for (int u = 0; u < CU; ++u)
       if (col0 + u * (int)blockDim.x < nc) s_wc[col0 + u * blockDim.x] = wc[u];
   }
+}
+
+// Tagged counterparts of coarse_gather and collect3, reading the partials of the
+// iteration's tagged publication (slot base trp = [nwg][kTagSlots][2] words): loads are
+// issued together, then each entry is re-read until it carries `tag`. False on a
+// time-out or an abort (per thread; the caller combines).
+__device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const int* s_pidx,
+                                                     double* s_wc,
+                                                     const unsigned long long* trp,
+                                                     unsigned tag, int* abort_flag) {
+  if (!cr_.ok) return true;
+  const int tid = threadIdx.x;
+  const int nc = cr_.nc;
+  constexpr int CU = 4;
+  bool ok = true;
+  for (int col0 = tid; col0 < nc; col0 += CU * blockDim.x) {
+    unsigned long long w0[CU][kMaxAggWg], w1[CU][kMaxAggWg];
+    const unsigned long long* adr[CU][kMaxAggWg];
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const int col = min(col0 + u * (int)blockDim.x, nc - 1);
+      const int t = col / 6, q = col - 6 * t;
+#pragma unroll
+      for (int k = 0; k < kMaxAggWg; ++k) {
+        const int pi = max(s_pidx[t * kMaxAggWg + k], 0);
+        adr[u][k] = trp + ((size_t)(pi / kMaxWgAgg) * kTagSlots + 3 + (pi % kMaxWgAgg) * 6 + q) * 2;
+        load_tagged(adr[u][k], w0[u][k], w1[u][k]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CU; ++u) {
+      const int col = col0 + u * (int)blockDim.x;
+      if (col >= nc) continue;
+      const int t = col / 6;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxAggWg; ++k) {
+        if (s_pidx[t * kMaxAggWg + k] < 0) continue;
+        ok = ok && poll_tagged(adr[u][k], tag, abort_flag, w0[u][k], w1[u][k]);
+        acc += tag_value(w0[u][k], w1[u][k]);
+      }
+      s_wc[col] = acc;
+    }
+  }
+  return ok;
+}
+
+__device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, int iw0, int nwg,
+                                                double* s_out, unsigned tag, int* abort_flag) {
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) != 0) return true;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  bool ok = true;
+  for (int q0 = lane; q0 < nwg; q0 += 4 * 64) {
+    unsigned long long w0[4][3], w1[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        load_tagged(trp + ((size_t)(iw0 + min(q0 + 64 * u, nwg - 1)) * kTagSlots + k) * 2,
+                    w0[u][k], w1[u][k]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (q0 + 64 * u >= nwg) continue;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ok = ok && poll_tagged(trp + ((size_t)(iw0 + q0 + 64 * u) * kTagSlots + k) * 2, tag,
+                               abort_flag, w0[u][k], w1[u][k]);
+        t[k] += tag_value(w0[u][k], w1[u][k]);
+      }
+    }
+  }
+  const double s = wave_sums_scatter<4>(t, lane);   // lane l holds sum l >> 4
+  if ((lane & 15) == 0 && (lane >> 4) < 3) s_out[lane >> 4] = s;
+  return ok;
 }
 
 // e = the rows of A_c^-1 belonging to this workgroup's aggregates times w_c (already
@@ -1592,7 +1720,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   int* nbflags = w.barrier + (size_t)plan.nb_slot0 * kBarrierSlot;
   const int* nbw = plan.nbw_idx + plan.nbw_ptr[wg];
   const int nnb = plan.nbw_ptr[wg + 1] - plan.nbw_ptr[wg];
-  int nep = 0;
+  int nep = 0, pep = 0;   // tagged publications of m and of the partials
+  const bool tagp = COARSE && nwg <= kTagWgMax;
 
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][RH]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)RH);           // [maxnz][R] local columns
@@ -1784,20 +1913,47 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
     double* red_slot = w.red + (size_t)par * plan.nwg * 3;
+    // Coarse space on a sheet of at most kTagWgMax workgroups: the partials go out as
+    // tagged words that every workgroup of the sheet polls (no barrier). Larger
+    // sheets (their all-to-all polling costs more than it saves) and block-Jacobi
+    // only: plain partials released by a cluster barrier.
+    const unsigned long long* trp = w.tred + (size_t)par * plan.nwg * kTagSlots * 2;
     PHASE_T(t0);
-    if (COARSE)
-      publish_restrict_dots(cs.part, wg, wna, kf, kl, kloc, live, cr, wv, loc,
-                            red_slot + (size_t)wg * 3);
-    else
+    if (COARSE) {
+      ++pep;
+      publish_restrict_dots(tagp, const_cast<unsigned long long*>(trp) + (size_t)wg * kTagSlots * 2,
+                            (unsigned)pep, cs.part, red_slot + (size_t)wg * 3, wg, wna, kf, kl,
+                            kloc, live, cr, wv, loc);
+    } else {
       publish3(loc, red_slot + (size_t)wg * 3);
+    }
     PHASE_T(t1);
-    if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+    if (!tagp && !(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
-    // the halo of m (or the coarse residual) and the partial sums are loaded together
-    if (!COARSE) halo_load(mb, nv, s_hidx, nh, ml, R, RH);
-    if (COARSE) coarse_gather(crow, s_pidx, s_wc);
-    collect3(red_slot, iw0, nwg, s_out);
-    __syncthreads();
+    if (tagp) {
+      // the coarse residual and the dot partials are polled together
+      __shared__ int s_late;
+      if (tid == 0) s_late = 0;
+      __syncthreads();
+      bool got = coarse_gather_tagged(crow, s_pidx, s_wc, trp, (unsigned)pep, w.abort_flag);
+      got = collect3_tagged(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag) && got;
+      if (!got) s_late = 1;
+      __syncthreads();
+      if (s_late) {
+        if (tid == 0) {
+          __hip_atomic_store(w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          set_status(a.status, inst, ST_TIMEOUT);
+        }
+        ok = false;
+        break;
+      }
+    } else {
+      // the halo of m (block-Jacobi only) or the coarse residual, and the partial sums
+      if (!COARSE) halo_load(mb, nv, s_hidx, nh, ml, R, RH);
+      if (COARSE) coarse_gather(crow, s_pidx, s_wc);
+      collect3(red_slot, iw0, nwg, s_out);
+      __syncthreads();
+    }
     const double gamma = s_out[0], delta = s_out[1];
     rr = s_out[2];
     __syncthreads();  // s_out is rewritten by the next collect3
@@ -2293,7 +2449,10 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
                                  plan.max_halo, coarse ? plan.xl_floats : 0);
   launch_fill_int(w.barrier, w.barrier_ints, 0, st);
   launch_fill_int(w.abort_flag, 1, 0, st);
-  if (coarse) launch_fill_int(reinterpret_cast<int*>(w.tbuf), 24 * m.nv, 0, st);
+  if (coarse) {
+    launch_fill_int(reinterpret_cast<int*>(w.tbuf), 24 * m.nv, 0, st);
+    launch_fill_int(reinterpret_cast<int*>(w.tred), w.tred_ints, 0, st);
+  }
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
   for (int g = 0; g < plan.ngroups; ++g) {
     SolverPlan pg = plan;

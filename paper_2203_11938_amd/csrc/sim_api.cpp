@@ -213,6 +213,9 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   void* q = nullptr;
   TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q));
   s->sw.red = (double*)q;
+  TRY(alloc(s, 2 * (size_t)p.nwg * kTagSlots * 16, &q));
+  s->sw.tred = (unsigned long long*)q;
+  s->sw.tred_ints = 2 * p.nwg * kTagSlots * 4;
   s->sw.barrier_ints = P.barrier_slots * kBarrierSlot;
   TRY(alloc(s, (size_t)s->sw.barrier_ints * 4, &q));
   s->sw.barrier = (int*)q;

@@ -175,14 +175,20 @@ struct SolverPlan {
 };
 
 // Solver scratch (device).
+// tagged partials of one workgroup: 3 dot products, then 6 per overlapped aggregate
+constexpr int kTagSlots = 3 + 6 * kMaxWgAgg;
+
 struct SolverWork {
   double* zbuf;            // [3][nv]     preconditioned initial residual, gathered once
   double* pbuf;            // [2][3][nv]  m = M^-1 w of even / odd iterations
   unsigned long long* tbuf;  // [2][3][nv][2] the same, published as tagged 64-bit words
                              // (tag << 32 | 32 data bits), zeroed before each launch
   double* red;             // [2][nwg][3] per-workgroup partial sums
+  unsigned long long* tred;  // [2][nwg][kTagSlots][2] the same and the coarse restriction
+                             // partials as tagged words (coarse space), zeroed per launch
   int* barrier;            // counter slots: [ninst] roots, then group counter/flag pairs
   int barrier_ints;        // ints to zero before each launch
+  int tred_ints;           // ints of tred
   int* abort_flag;         // [1]
 };
 

@@ -1040,40 +1040,6 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
 // gain, 157 lose).
 constexpr int kTagWgMax = 64;
 
-// Point-to-point publication: after the workgroup has stored a vector's rows, it sets
-// its own flag to `epoch` (release) and waits until every workgroup that owns one of
-// its halo rows has done the same (relaxed polls by the lanes of wavefront 0, one
-// flag each, then an acquire), instead of waiting for the whole cluster. Every
-// workgroup stores before it waits, so the waits cannot form a cycle; they are
-// bounded like the cluster barrier's. The caller keeps a full cluster barrier between
-// two publications into the same buffer, so a neighbour never overwrites rows that
-// are still being read.
-__device__ __forceinline__ bool neighbour_sync(int* flags, int wg, const int* __restrict__ nbw,
-                                               int nnb, int epoch, int* abort_flag, int* status,
-                                               int inst) {
-  __shared__ int s_nok;
-  if (threadIdx.x == 0) s_nok = 0;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    if (threadIdx.x == 0)
-      __hip_atomic_store(flags + (size_t)wg * kBarrierSlot, epoch, __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    bool ok = true;
-    for (int q = threadIdx.x; q < nnb; q += 64)
-      ok = ok && bounded_wait_ge(flags + (size_t)nbw[q] * kBarrierSlot, epoch, abort_flag);
-    if (!ok) s_nok = 1;
-  }
-  __syncthreads();
-  if (s_nok != 0) {
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      set_status(status, inst, ST_TIMEOUT);
-    }
-    return false;
-  }
-  return true;
-}
-
 // Tagged publication of a row vector: each double travels as two 64-bit words, each
 // holding a 32-bit tag (the publication's number, the same in every workgroup of a
 // sheet) above 32 bits of the value. A 64-bit store is single-copy atomic, so a
@@ -1716,10 +1682,6 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   const int i = row0 + (act ? tid : 0);
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
   const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
-  // publication flags of the workgroups and the owners of this workgroup's halo
-  int* nbflags = w.barrier + (size_t)plan.nb_slot0 * kBarrierSlot;
-  const int* nbw = plan.nbw_idx + plan.nbw_ptr[wg];
-  const int nnb = plan.nbw_ptr[wg + 1] - plan.nbw_ptr[wg];
   int nep = 0, pep = 0;   // tagged publications of m and of the partials
   const bool tagp = COARSE && nwg <= kTagWgMax;
 

@@ -596,7 +596,6 @@ HostPlan make_plan(const HostLayout& L, int rows, int group) {
     const int nv = L.nv, mz = L.maxnz;
     P.lcol.assign((size_t)mz * nv, 0);
     P.halo_ptr.assign(1, 0);
-    P.nbw_ptr.assign(1, 0);
     std::vector<int> h;
     for (int w = 0; w < P.nwg; ++w) {
       const int r0 = P.wg_row0[w], n = P.wg_nrows[w];
@@ -620,21 +619,9 @@ HostPlan make_plan(const HostLayout& L, int rows, int group) {
       P.halo_idx.insert(P.halo_idx.end(), h.begin(), h.end());
       P.halo_ptr.push_back((int)P.halo_idx.size());
       P.max_halo = std::max(P.max_halo, (int)h.size());
-      // the workgroups that own the halo rows (sorted, distinct)
-      std::vector<int> nbw;
-      for (int j : h) {
-        const int b = L.vert_inst[j];
-        nbw.push_back(P.inst_wg0[b] + (j - L.inst_voff[b]) / rows);
-      }
-      std::sort(nbw.begin(), nbw.end());
-      nbw.erase(std::unique(nbw.begin(), nbw.end()), nbw.end());
-      P.nbw_idx.insert(P.nbw_idx.end(), nbw.begin(), nbw.end());
-      P.nbw_ptr.push_back((int)P.nbw_idx.size());
     }
   }
-  // one flag slot per workgroup behind the barrier counters (neighbour publication)
-  P.nb_slot0 = P.barrier_slots;
-  P.barrier_slots += P.nwg;
+
   // workgroup / aggregate overlaps (both are runs of consecutive vertices)
   if (L.nagg > 0) {
     P.wg_agg0.resize(P.nwg);

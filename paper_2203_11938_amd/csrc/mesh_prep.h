@@ -64,10 +64,6 @@ struct HostPlan {
   // h-th halo row, the row's own local index for a padding slot
   int max_halo = 0;
   std::vector<int> halo_ptr, halo_idx, lcol;
-  // workgroups owning each workgroup's halo rows, and the first of the per-workgroup
-  // flag slots that announce a published vector to them
-  std::vector<int> nbw_ptr, nbw_idx;
-  int nb_slot0 = 0;
   // > 0: the solver keeps the FP32 rows of the coarse inverse that each workgroup
   // uses in LDS (6 x max_wg_agg x the largest coarse dimension floats)
   int xl_floats = 0;

@@ -207,9 +207,6 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   TRY(upload(s, P.halo_ptr, &p.halo_ptr));
   TRY(upload(s, P.halo_idx, &p.halo_idx));
   TRY(upload(s, P.lcol, &p.lcol));
-  p.nb_slot0 = P.nb_slot0;
-  TRY(upload(s, P.nbw_ptr, &p.nbw_ptr));
-  TRY(upload(s, P.nbw_idx, &p.nbw_idx));
   void* q = nullptr;
   TRY(alloc(s, 6 * (size_t)p.nwg * 8, &q));
   s->sw.red = (double*)q;

@@ -166,9 +166,6 @@ struct SolverPlan {
   const int* halo_ptr;     // [nwg+1]
   const int* halo_idx;     // halo rows of each workgroup (global vertex ids)
   const int* lcol;         // [maxnz][nv] local columns: own row j - row0, halo rows + h
-  int nb_slot0;            // barrier slot of workgroup 0's publication flag
-  const int* nbw_ptr;      // [nwg+1]
-  const int* nbw_idx;      // workgroups owning each workgroup's halo rows
   int xl_floats;           // > 0: LDS floats holding the rows of the coarse inverse that
                            // a workgroup uses (6 x its aggregates x the coarse dimension);
                            // 0: those rows are read from global memory every iteration

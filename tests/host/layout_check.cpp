@@ -86,26 +86,5 @@ extern "C" int layout_check(int nsheets, const int* nv, const int* nt, const int
   }
   out_counts[9] = hbad;
   out_counts[10] = P.max_halo;
-  // neighbour lists: exactly the other workgroups that own a halo row, sorted,
-  // distinct, of the same sheet; one flag slot per workgroup behind the counters
-  int nbad = 0, nmax = 0;
-  if ((int)P.nbw_ptr.size() != P.nwg + 1 || P.nb_slot0 + P.nwg != P.barrier_slots) ++nbad;
-  for (int w = 0; w < P.nwg && nbad == 0; ++w) {
-    std::vector<int> want;
-    for (int h = P.halo_ptr[w]; h < P.halo_ptr[w + 1]; ++h) {
-      const int j = P.halo_idx[h];
-      for (int q = 0; q < P.nwg; ++q)
-        if (j >= P.wg_row0[q] && j < P.wg_row0[q] + P.wg_nrows[q]) want.push_back(q);
-    }
-    std::sort(want.begin(), want.end());
-    want.erase(std::unique(want.begin(), want.end()), want.end());
-    const std::vector<int> got(P.nbw_idx.begin() + P.nbw_ptr[w], P.nbw_idx.begin() + P.nbw_ptr[w + 1]);
-    if (got != want) ++nbad;
-    for (int q : got)
-      if (q == w || P.wg_inst[q] != P.wg_inst[w]) ++nbad;
-    nmax = std::max(nmax, (int)got.size());
-  }
-  out_counts[11] = nbad;
-  out_counts[12] = nmax;
   return 0;
 }

@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--checkpoint-report", type=int, default=10, metavar="K",
                     help="store-all workloads: also time the gradient with a state "
                          "checkpoint every K steps (0: skip)")
+    ap.add_argument("--coarse-size", type=int, default=None, metavar="N",
+                    help="vertices per aggregate of the solver's coarse space (library "
+                         "default 64; 0: block-Jacobi only)")
     ap.add_argument("--graph", action="store_true",
                     help="also time the same gradients on a handle in HIP-graph mode")
     ap.add_argument("--sequential", action="store_true",
@@ -218,7 +221,8 @@ def main():
     sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
     sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
                       checkpoint_every=w.checkpoint_every, max_steps=w.steps,
-                      membrane=args.membrane, autotune=not args.no_autotune)
+                      membrane=args.membrane, autotune=not args.no_autotune,
+                      coarse_size=args.coarse_size)
     dt = sim.dtype
     V = sim.n_verts
     x0 = torch.tensor(W.to_soa(np.concatenate([i.x0 for i in insts])), dtype=dt, device=dev)

@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -757,12 +758,13 @@ __device__ __forceinline__ bool gj_tile_inverse(double (&a)[kGjTile], int lane) 
     const double piv = row[p];
     good = good && piv > 0.0 && isfinite(piv);
     const double d = 1.0 / piv;
-    const double f = a[p];
+    // one update for every row, a_j -= f s_j, with the scaled pivot row s_j = row_j d
+    // and s_p = 1 + d: other rows (f = a_p) get a_p - f (1 + d) = -f d in the pivot
+    // column; the pivot row itself (f = a_pp - 1) gets a_pj - (a_pp - 1) a_pj d = a_pj d
+    // and a_pp - (a_pp - 1)(1 + d) = d. No per-element selects.
+    const double f = lane == p ? a[p] - 1.0 : a[p];
 #pragma unroll
-    for (int j = 0; j < kGjTile; ++j) {
-      const double sj = j == p ? d : row[j] * d;   // scaled pivot row
-      a[j] = lane == p ? sj : (j == p ? -f * d : a[j] - f * sj);
-    }
+    for (int j = 0; j < kGjTile; ++j) a[j] -= f * (j == p ? 1.0 + d : row[j] * d);
   }
   return good;
 }
@@ -2323,6 +2325,20 @@ __global__ void k_fill_int(int* p, int n, int v) {
   if (k < n) p[k] = v;
 }
 
+// Zeroes up to four int ranges in one launch (grid-stride; the solver's counters,
+// abort flag and tagged buffers before each launch).
+struct ZeroRanges {
+  int* p[4];
+  int n[4];
+};
+
+__global__ void __launch_bounds__(256) k_zero_ranges(ZeroRanges z) {
+  const int stride = gridDim.x * blockDim.x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < z.n[r]; k += stride) z.p[r][k] = 0;
+}
+
 __global__ void k_fill_double(double* p, long n, double v) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
@@ -2409,12 +2425,20 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
   const bool coarse = cs.nagg > 0;
   size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0,
                                  plan.max_halo, coarse ? plan.xl_floats : 0);
-  launch_fill_int(w.barrier, w.barrier_ints, 0, st);
-  launch_fill_int(w.abort_flag, 1, 0, st);
+  ZeroRanges z{};
+  z.p[0] = w.barrier;
+  z.n[0] = w.barrier_ints;
+  z.p[1] = w.abort_flag;
+  z.n[1] = 1;
   if (coarse) {
-    launch_fill_int(reinterpret_cast<int*>(w.tbuf), 24 * m.nv, 0, st);
-    launch_fill_int(reinterpret_cast<int*>(w.tred), w.tred_ints, 0, st);
+    z.p[2] = reinterpret_cast<int*>(w.tbuf);
+    z.n[2] = 24 * m.nv;
+    z.p[3] = reinterpret_cast<int*>(w.tred);
+    z.n[3] = w.tred_ints;
   }
+  const int most = std::max(std::max(z.n[0], z.n[2]), z.n[3]);
+  hipLaunchKernelGGL(k_zero_ranges, dim3(std::min(blocks_for(most, 256), 1024)), dim3(256), 0,
+                     st, z);
   // one launch per solver group (a set of whole sheets whose workgroups are co-resident)
   for (int g = 0; g < plan.ngroups; ++g) {
     SolverPlan pg = plan;

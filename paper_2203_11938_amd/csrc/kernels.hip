@@ -12,10 +12,11 @@
 //                   symmetric sweep, the FP32 copy; the 6x6 blocks of the middle level.
 //   k_pcg           persistent preconditioned pipelined CG: every workgroup owns a
 //                   row range, keeps its vectors in FP64 registers (matrix rows in
-//                   LDS or streamed); per iteration the workgroups of one sheet meet
-//                   at one counter barrier and publish the preconditioned vector to
-//                   their neighbours only (reductions are fixed-order, so results
-//                   are bitwise reproducible).
+//                   LDS or streamed); per iteration the workgroups of one sheet
+//                   exchange their partial sums (tagged words, or a counter barrier
+//                   on large sheets) and publish the preconditioned vector as tagged
+//                   words that each workgroup polls for its halo only (reductions
+//                   are fixed-order, so results are bitwise reproducible).
 //   k_update        v_t = v_{t-1} + dv, x_t = x_{t-1} + h v_t, pins held.
 // Adjoint step (implicit differentiation of Eq. 4): k_adj_pre, the same assembly and
 // solver (A is symmetric), k_adj_elements (element vector-Jacobian products) and
@@ -1292,8 +1293,10 @@ __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, 
 constexpr int kMaxRestarts = 16;
 
 // Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
-// reduction per iteration, (r,u), (w,u), (r,r), whose cluster barrier also
-// publishes m = M^-1 w for the iteration's single SpMV n = A m. Vectors per row:
+// reduction per iteration, (r,u), (w,u), (r,r), exchanged with the coarse restriction
+// (tagged words, or a cluster barrier on large sheets and without a coarse space);
+// then m = M^-1 w is published (tagged) for the iteration's single SpMV n = A m,
+// each workgroup reading only its halo. Vectors per row:
 // x, r, u = M^-1 r, w = A u, z, q, s, p (recurrences of the method), all FP64.
 // The recursively updated residual drifts from b - A x (rounding), so
 // convergence is accepted only on a true residual: when the recursive residual
@@ -1301,10 +1304,12 @@ constexpr int kMaxRestarts = 16;
 // repeated. A step denominator <= 0 also triggers a restart; at a fresh start
 // the denominator is u^T A u, so a non-positive value there is reported as an
 // indefinite system.
-// LDS: two copies of m [parity][3][row] (neighbours inside the workgroup are read
-// from there, the others from global memory), the rows' block columns
-// [slot][row] and, when LDS_MATRIX, the workgroup's matrix rows [slot][entry][row]
-// (otherwise the assembled matrix is streamed from global memory each SpMV).
+// LDS: two copies of m [parity][3][rows + halo] (own rows written directly, the halo
+// loaded after each publication), the rows' local columns [slot][row], the halo row
+// list, and, when LDS_MATRIX, the workgroup's matrix rows [slot][entry][row]
+// (otherwise the assembled matrix is streamed from global memory each SpMV); with a
+// coarse space also the coarse residual, reduction scratch, the middle level's 6x6
+// inverses and, when they fit, the workgroup's FP32 rows of the coarse inverse.
 #ifdef PHISFT_PHASES
 // per-workgroup accumulated wall-clock ticks of the solver phases (tuning builds only)
 __device__ unsigned long long g_phase[512][8];

@@ -764,8 +764,9 @@ __device__ __forceinline__ bool gj_tile_inverse(double (&a)[kGjTile], int lane) 
     // column; the pivot row itself (f = a_pp - 1) gets a_pj - (a_pp - 1) a_pj d = a_pj d
     // and a_pp - (a_pp - 1)(1 + d) = d. No per-element selects.
     const double f = lane == p ? a[p] - 1.0 : a[p];
+    const double fd = f * d;
 #pragma unroll
-    for (int j = 0; j < kGjTile; ++j) a[j] -= f * (j == p ? 1.0 + d : row[j] * d);
+    for (int j = 0; j < kGjTile; ++j) a[j] -= j == p ? f * (1.0 + d) : fd * row[j];
   }
   return good;
 }

@@ -302,7 +302,7 @@ def main():
                            coarse_max_dim=st["coarse_max_dim"], bytes_per_cg_iter=b_iter,
                            autotuned=bool(st["autotuned"]),
                            autotune_candidates=st["autotune_candidates"],
-                           lds_matrix=bool(st["solver_lds_matrix"]),
+                           solver_matrix=S.MATRIX_HOMES[st["solver_matrix_home"]],
                            solver_launches_per_solve=st["solver_launches_per_solve"],
                            solver_wg_per_cu=st["solver_wg_per_cu"],
                            coarse_rows_lds=bool(st["coarse_rows_lds"]),

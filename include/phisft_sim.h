@@ -88,6 +88,24 @@ typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
  *                         depend on rounding. */
 typedef enum { SIM_MEMBRANE_EXACT = 0, SIM_MEMBRANE_TENSION = 1 } sim_membrane_system;
 
+/* Where the persistent solver keeps its workgroup's rows of the system matrix during
+ * a solve. Every home computes the same products in the same order (bitwise equal
+ * results); they differ only in speed.
+ *   SIM_MATRIX_AUTO       the library's choice (rule or autotuner).
+ *   SIM_MATRIX_STREAMED   read from the assembled matrix in device memory at every
+ *                         product.
+ *   SIM_MATRIX_LDS        copied once per solve into LDS (only where they fit).
+ *   SIM_MATRIX_REGISTERS  copied once per solve into the registers of each row's
+ *                         lane (rows of at most 13 blocks, i.e. grid sheets; one
+ *                         solver workgroup per CU).
+ * A home that no launch shape can use makes sim_create fail with SIM_E_INVALID. */
+typedef enum {
+  SIM_MATRIX_AUTO = 0,
+  SIM_MATRIX_STREAMED = 1,
+  SIM_MATRIX_LDS = 2,
+  SIM_MATRIX_REGISTERS = 3
+} sim_matrix_home;
+
 /* Host triangle mesh: tris [n_tris][3] vertex ids, counter-clockwise. */
 typedef struct {
   int32_t n_verts;
@@ -141,6 +159,7 @@ typedef struct {
                                pointers, step count and loss frames replays it (the
                                arrays' contents may change). Ignored while solver
                                timing is on. 0 (default): direct launches              */
+  int32_t matrix_home;      /* sim_matrix_home (default SIM_MATRIX_AUTO)                */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -156,7 +175,7 @@ typedef struct {
   int32_t device_status;      /* sticky device status (sim_status value) */
   int32_t rows_per_block;     /* solver launch shape in use */
   int32_t blocks;             /* solver workgroups per launch */
-  int32_t solver_lds_matrix;  /* 1: matrix rows held in LDS, 0: streamed from memory */
+  int32_t solver_matrix_home; /* sim_matrix_home of the launch shape in use (never AUTO) */
   int32_t solver_launches_per_solve; /* batches split into sets of co-resident sheets */
   int64_t nnz_blocks;         /* non-zero 3x3 blocks of the system matrix */
   int64_t solver_launches;    /* timed solver launches since timing was enabled */

@@ -57,16 +57,18 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo,
+size_t pcg_lds_bytes(int maxnz, int rows, int mat_home, int coarse_nc, int max_halo,
                      int xl_floats);
 // threads of a solver block: its rows rounded up to whole 64-lane wavefronts
 inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 // Rows may couple at most this many vertices (grid sheets: 13).
 constexpr int kMaxRowBlocks = 32;
+// Rows of at most this many blocks can hold them in registers (kMatReg).
+constexpr int kRegRowBlocks = 13;
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ);
+hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ);
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ,
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int mat_home, bool coarse, int occ,
                          int* blocks_per_cu);
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,

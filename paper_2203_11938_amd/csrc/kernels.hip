@@ -1105,8 +1105,11 @@ __device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigne
 }
 
 // Halo of a tagged vector into vl[c][R + h]: every entry is polled until both of its
-// words carry `tag` (bounded like the barrier's waits). False (every thread) on a
-// time-out or an abort; the caller then stops.
+// words carry `tag` (bounded like the barrier's waits). A thread's entries are read
+// kHaloBatch at a time, all loads issued before any is checked (one round trip per
+// batch, not per entry). False (every thread) on a time-out or an abort; the caller
+// then stops.
+constexpr int kHaloBatch = 8;
 __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
                                                  const int* __restrict__ hidx, int nh,
                                                  double* __restrict__ vl, int R, int RH,
@@ -1115,23 +1118,26 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, i
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   bool ok = true;
-  for (int e = threadIdx.x; e < 3 * nh && ok; e += blockDim.x) {
-    const int c = e / nh, h = e - c * nh;
-    unsigned long long* p = const_cast<unsigned long long*>(tb) + ((size_t)c * nv + hidx[h]) * 2;
-    unsigned long long w0, w1;
-    int spins = 0;
-    while (true) {
-      w0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      w1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit ||
-          __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-        ok = false;
-        break;
-      }
+  const int ne = 3 * nh, nb = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < ne && ok; e0 += kHaloBatch * nb) {
+    const unsigned long long* adr[kHaloBatch];
+    unsigned long long w0[kHaloBatch], w1[kHaloBatch];
+#pragma unroll
+    for (int u = 0; u < kHaloBatch; ++u) {
+      // entries past the end re-read the last one (no branches around the loads)
+      const int e = min(e0 + u * nb, ne - 1);
+      const int c = e / nh, h = e - c * nh;
+      adr[u] = tb + ((size_t)c * nv + hidx[h]) * 2;
+      load_tagged(adr[u], w0[u], w1[u]);
     }
-    if (ok) vl[c * RH + R + h] = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+#pragma unroll
+    for (int u = 0; u < kHaloBatch; ++u) {
+      const int e = e0 + u * nb;
+      if (e >= ne) break;
+      ok = ok && poll_tagged(adr[u], tag, abort_flag, w0[u], w1[u]);
+      const int c = e / nh, h = e - c * nh;
+      if (ok) vl[c * RH + R + h] = tag_value(w0[u], w1[u]);
+    }
   }
   if (!ok) s_bad = 1;
   __syncthreads();
@@ -1291,6 +1297,25 @@ __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, 
   }
 }
 
+// y = A v for this thread's row with the row's blocks held in registers (copied once
+// per launch; slots past maxnz hold zero blocks): all neighbour values are read from
+// LDS first (local columns Cl as for the other products), then the products, in slot
+// order (the same operations in the same order as the streamed and LDS products).
+template <typename TM>
+__device__ __forceinline__ void spmv_reg(const TM (&Ar)[kRegRowBlocks][9],
+                                         const int* __restrict__ Cl, int R, int tid, int maxnz,
+                                         const double* __restrict__ vl, int RH, double y[3]) {
+  double g[3][kRegRowBlocks];
+  loadnb<kRegRowBlocks, true>(Cl, R, tid, 0, maxnz, vl, RH, g);
+  y[0] = y[1] = y[2] = 0.0;
+#pragma unroll
+  for (int k = 0; k < kRegRowBlocks; ++k)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      y[r] += (double)Ar[k][r * 3] * g[0][k] + (double)Ar[k][r * 3 + 1] * g[1][k] +
+              (double)Ar[k][r * 3 + 2] * g[2][k];
+}
+
 constexpr int kMaxRestarts = 16;
 
 // Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
@@ -1307,8 +1332,9 @@ constexpr int kMaxRestarts = 16;
 // indefinite system.
 // LDS: two copies of m [parity][3][rows + halo] (own rows written directly, the halo
 // loaded after each publication), the rows' local columns [slot][row], the halo row
-// list, and, when LDS_MATRIX, the workgroup's matrix rows [slot][entry][row]
-// (otherwise the assembled matrix is streamed from global memory each SpMV); with a
+// list, and, with the matrix at home in LDS, the workgroup's matrix rows
+// [slot][entry][row] (held in registers, or streamed from the assembled array in
+// global memory at every product, in the other two variants); with a
 // coarse space also the coarse residual, reduction scratch, the middle level's 6x6
 // inverses and, when they fit, the workgroup's FP32 rows of the coarse inverse.
 #ifdef PHISFT_PHASES
@@ -1666,9 +1692,11 @@ __device__ __forceinline__ void mid_apply(const double* __restrict__ Bm, bool li
   }
 }
 
-template <typename TM, bool LDS_MATRIX, bool COARSE, int OCC>
+template <typename TM, int MM, bool COARSE, int OCC>
 __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
                                              PcgArgs<TM> a) {
+  constexpr bool LDS_MATRIX = MM == kMatLds, REG_MATRIX = MM == kMatReg;
+  static_assert(!REG_MATRIX || OCC == 1, "register-resident rows need the whole register file");
 #ifdef PHISFT_PHASES
   unsigned long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
 #endif
@@ -1709,6 +1737,21 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
   const int Ai = LDS_MATRIX ? tid : i;
+  // REG_MATRIX: the row's blocks, in registers for the launch
+  TM Ar[REG_MATRIX ? kRegRowBlocks : 1][9];
+  if (REG_MATRIX) {
+#pragma unroll
+    for (int k = 0; k < kRegRowBlocks; ++k) {
+      const bool in = act && k < maxnz;
+      const int j = in ? m.ell_col[k * nv + i] : -1;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) Ar[k][q] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+    }
+  }
+  auto spmv = [&](const double* vl, double y[3]) {
+    if constexpr (REG_MATRIX) spmv_reg<TM>(Ar, Cl, R, tid, maxnz, vl, RH, y);
+    else spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, vl, RH, y);
+  };
   if (act) {
     for (int k = 0; k < maxnz; ++k) {
       Cl[k * R + tid] = plan.lcol[k * nv + i];
@@ -1810,7 +1853,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     if (ok) {
       halo_load(ub, nv, s_hidx, nh, ul, R, RH);
       __syncthreads();
-      if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, ul, RH, wv);
+      if (act) spmv(ul, wv);
     }
   }
 
@@ -1836,7 +1879,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       __syncthreads();
       if (act) {
         double ax[3];
-        spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, ax);
+        spmv(xl, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -1860,7 +1903,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(ub, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
-      if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, xl, RH, wv);
+      if (act) spmv(xl, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -1966,7 +2009,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       }
       PHASE_ADD(5, wall_clock64() - t5);
     }
-    if (act) spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, ml, RH, nn);
+    if (act) spmv(ml, nn);
     else nn[0] = nn[1] = nn[2] = 0.0;
     PHASE_T(t4);
     PHASE_ADD(0, t1 - t0);
@@ -2374,10 +2417,10 @@ void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a
 }
 
 template <typename TM>
-size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int max_halo,
+size_t pcg_lds_bytes(int maxnz, int rows, int mat_home, int coarse_nc, int max_halo,
                      int xl_floats) {
   const size_t rh = rows + (size_t)(max_halo + 7) / 8 * 8;
-  return (size_t)maxnz * rows * ((lds_matrix ? 9 * sizeof(TM) : 0) + sizeof(int)) +
+  return (size_t)maxnz * rows * ((mat_home == kMatLds ? 9 * sizeof(TM) : 0) + sizeof(int)) +
          6 * sizeof(double) * rh + sizeof(int) * (rh - rows) +
          (coarse_nc > 0 ? sizeof(double) * ((size_t)coarse_nc + 5 * 6 * kMaxWgAgg +
                                             (size_t)pcg_threads(rows) / kMid * 36) +
@@ -2386,39 +2429,52 @@ size_t pcg_lds_bytes(int maxnz, int rows, bool lds_matrix, int coarse_nc, int ma
                         : 0);
 }
 
-// Kernel variants: matrix in LDS or streamed, coarse space or not, one or two
-// workgroups of 256 threads per CU (the latter caps registers at 256 per lane).
+// Kernel variants: matrix streamed, in LDS or in registers (MatrixHome), coarse space
+// or not, one or two workgroups of 256 threads per CU (the latter caps registers at
+// 256 per lane; register-resident rows only with one).
 template <typename TM, int OCC>
-static const void* pcg_entry_occ(bool lds_matrix, bool coarse) {
-  if (coarse)
-    return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, true, OCC>)
-                      : reinterpret_cast<const void*>(&k_pcg<TM, false, true, OCC>);
-  return lds_matrix ? reinterpret_cast<const void*>(&k_pcg<TM, true, false, OCC>)
-                    : reinterpret_cast<const void*>(&k_pcg<TM, false, false, OCC>);
+static const void* pcg_entry_occ(int mat_home, bool coarse) {
+  if (coarse) {
+    if (mat_home == kMatLds) return reinterpret_cast<const void*>(&k_pcg<TM, kMatLds, true, OCC>);
+    return reinterpret_cast<const void*>(&k_pcg<TM, kMatStream, true, OCC>);
+  }
+  if (mat_home == kMatLds) return reinterpret_cast<const void*>(&k_pcg<TM, kMatLds, false, OCC>);
+  return reinterpret_cast<const void*>(&k_pcg<TM, kMatStream, false, OCC>);
 }
 
 template <typename TM>
-static const void* pcg_entry(bool lds_matrix, bool coarse, int occ) {
-  return occ >= 2 ? pcg_entry_occ<TM, 2>(lds_matrix, coarse)
-                  : pcg_entry_occ<TM, 1>(lds_matrix, coarse);
+static const void* pcg_entry(int mat_home, bool coarse, int occ) {
+  if (mat_home == kMatReg)
+    return coarse ? reinterpret_cast<const void*>(&k_pcg<TM, kMatReg, true, 1>)
+                  : reinterpret_cast<const void*>(&k_pcg<TM, kMatReg, false, 1>);
+  return occ >= 2 ? pcg_entry_occ<TM, 2>(mat_home, coarse)
+                  : pcg_entry_occ<TM, 1>(mat_home, coarse);
+}
+
+// Rejects shapes no variant handles: rows of more than kMaxRowBlocks blocks, and
+// register-resident rows of more than kRegRowBlocks or with two workgroups per CU.
+static bool pcg_shape_ok(int maxnz, int mat_home, int occ) {
+  if (maxnz > kMaxRowBlocks) return false;
+  if (mat_home == kMatReg && (maxnz > kRegRowBlocks || occ != 1)) return false;
+  return mat_home >= kMatStream && mat_home <= kMatReg;
 }
 
 template <typename TM>
-hipError_t pcg_prepare(size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ) {
-  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(pcg_entry<TM>(lds_matrix, coarse, occ),
+hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ) {
+  if (!pcg_shape_ok(maxnz, mat_home, occ)) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(pcg_entry<TM>(mat_home, coarse, occ),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename TM>
-hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, bool lds_matrix, bool coarse, int occ,
+hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int mat_home, bool coarse, int occ,
                          int* blocks_per_cu) {
-  if (maxnz > kMaxRowBlocks) return hipErrorInvalidValue;
+  if (!pcg_shape_ok(maxnz, mat_home, occ)) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, pcg_entry<TM>(lds_matrix, coarse, occ), pcg_threads(rows), lds);
+      blocks_per_cu, pcg_entry<TM>(mat_home, coarse, occ), pcg_threads(rows), lds);
 }
 
-template <typename TM, bool L, bool C, int O>
+template <typename TM, int L, bool C, int O>
 static void launch_pcg_v(dim3 grid, dim3 block, size_t lds, hipStream_t st, const Mesh& m,
                          const SolverPlan& pg, const SolverWork& w, const Coarse& cs,
                          const PcgArgs<TM>& a) {
@@ -2429,7 +2485,7 @@ template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
                 const PcgArgs<TM>& a, hipStream_t st) {
   const bool coarse = cs.nagg > 0;
-  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.lds_matrix != 0, coarse ? cs.max_nc : 0,
+  size_t lds = pcg_lds_bytes<TM>(m.maxnz, plan.rows, plan.mat_home, coarse ? cs.max_nc : 0,
                                  plan.max_halo, coarse ? plan.xl_floats : 0);
   ZeroRanges z{};
   z.p[0] = w.barrier;
@@ -2450,16 +2506,22 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
     SolverPlan pg = plan;
     pg.wg_base = plan.group_wg0_host[g];
     const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base), block(pcg_threads(plan.rows));
-    const int sel = (plan.lds_matrix ? 4 : 0) + (coarse ? 2 : 0) + (plan.occ >= 2 ? 1 : 0);
+    if (plan.mat_home == kMatReg) {
+      // one workgroup per CU only (pcg_prepare rejects the rest)
+      if (coarse) launch_pcg_v<TM, kMatReg, true, 1>(grid, block, lds, st, m, pg, w, cs, a);
+      else launch_pcg_v<TM, kMatReg, false, 1>(grid, block, lds, st, m, pg, w, cs, a);
+      continue;
+    }
+    const int sel = (plan.mat_home == kMatLds ? 4 : 0) + (coarse ? 2 : 0) + (plan.occ >= 2 ? 1 : 0);
     switch (sel) {
-      case 0: launch_pcg_v<TM, false, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 1: launch_pcg_v<TM, false, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 2: launch_pcg_v<TM, false, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 3: launch_pcg_v<TM, false, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 4: launch_pcg_v<TM, true, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 5: launch_pcg_v<TM, true, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
-      case 6: launch_pcg_v<TM, true, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
-      default: launch_pcg_v<TM, true, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 0: launch_pcg_v<TM, kMatStream, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 1: launch_pcg_v<TM, kMatStream, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 2: launch_pcg_v<TM, kMatStream, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 3: launch_pcg_v<TM, kMatStream, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 4: launch_pcg_v<TM, kMatLds, false, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 5: launch_pcg_v<TM, kMatLds, false, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
+      case 6: launch_pcg_v<TM, kMatLds, true, 1>(grid, block, lds, st, m, pg, w, cs, a); break;
+      default: launch_pcg_v<TM, kMatLds, true, 2>(grid, block, lds, st, m, pg, w, cs, a); break;
     }
   }
 }
@@ -2538,9 +2600,9 @@ PHISFT_INSTANTIATE_ASM(double, float)
 PHISFT_INSTANTIATE_ASM(double, double)
 
 #define PHISFT_INSTANTIATE(T)                                                                    \
-  template size_t pcg_lds_bytes<T>(int, int, bool, int, int, int);                               \
-  template hipError_t pcg_prepare<T>(size_t, int, bool, bool, int);                              \
-  template hipError_t pcg_occupancy<T>(int, size_t, int, bool, bool, int, int*);                 \
+  template size_t pcg_lds_bytes<T>(int, int, int, int, int, int);                                \
+  template hipError_t pcg_prepare<T>(size_t, int, int, bool, int);                               \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, int, bool, int, int*);                  \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \

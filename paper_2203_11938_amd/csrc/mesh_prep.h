@@ -51,7 +51,7 @@ struct HostLayout {
 };
 
 struct HostPlan {
-  int rows = 0, nwg = 0, lds_matrix = 1, occ = 1;
+  int rows = 0, nwg = 0, mat_home = 1, occ = 1;   // mat_home: MatrixHome
   int barrier_slots = 0;   // root slots + group counter/flag slots
   std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
   std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets

@@ -26,6 +26,9 @@
 using namespace phisft;
 
 static_assert(kMid == kMidSize, "device and host sizes of the middle level differ");
+static_assert(kMatStream + 1 == SIM_MATRIX_STREAMED && kMatLds + 1 == SIM_MATRIX_LDS &&
+                  kMatReg + 1 == SIM_MATRIX_REGISTERS,
+              "solver matrix homes and their public values differ");
 
 struct sim_s {
   HostLayout L;
@@ -191,7 +194,7 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   SolverPlan& p = s->plan;
   p.nwg = P.nwg;
   p.rows = P.rows;
-  p.lds_matrix = P.lds_matrix;
+  p.mat_home = P.mat_home;
   p.occ = P.occ;
   p.wg_base = 0;
   p.ngroups = (int)P.group_wg0.size() - 1;
@@ -225,18 +228,18 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
     TRY(alloc(s, (size_t)p.nwg * kMaxWgAgg * 6 * 8, &q));
     cs.part = (double*)q;
   }
-  const bool lm = P.lds_matrix != 0;
+  const int lm = P.mat_home;
   const int cnc = coarse ? L.max_nc : 0;
   hipError_t e = s->mprec == SIM_FP64
-      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm, P.occ,
-                            coarse)
-      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats), L.maxnz, lm, P.occ,
-                           coarse);
+      ? pcg_prepare<double>(pcg_lds_bytes<double>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats),
+                            L.maxnz, lm, coarse, P.occ)
+      : pcg_prepare<float>(pcg_lds_bytes<float>(L.maxnz, P.rows, lm, cnc, P.max_halo, P.xl_floats),
+                           L.maxnz, lm, coarse, P.occ);
   if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
   s->plan_h = P;
   s->stats.rows_per_block = p.rows;
   s->stats.blocks = p.nwg;
-  s->stats.solver_lds_matrix = p.lds_matrix;
+  s->stats.solver_matrix_home = p.mat_home + 1;   // MatrixHome -> sim_matrix_home
   s->stats.solver_wg_per_cu = p.occ;
   s->stats.coarse_rows_lds = p.xl_floats > 0 ? 1 : 0;
   s->stats.solver_launches_per_solve = p.ngroups;
@@ -325,7 +328,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       (o.membrane_system != SIM_MEMBRANE_EXACT && o.membrane_system != SIM_MEMBRANE_TENSION) ||
       (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
       !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20))) ||
-      (o.autotune != 0 && o.autotune != 1) || (o.graph != 0 && o.graph != 1)) {
+      (o.autotune != 0 && o.autotune != 1) || (o.graph != 0 && o.graph != 1) ||
+      o.matrix_home < SIM_MATRIX_AUTO || o.matrix_home > SIM_MATRIX_REGISTERS) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
@@ -358,20 +362,25 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   // dynamic LDS budget: 160 KB less the kernel's static buffers
   const size_t lds_cap = 160 * 1024 - (coarse ? 4096 : 1024);
   // Largest feasible block first (fewer workgroups meet faster at the per-iteration
-  // barrier); matrix rows in LDS when they fit, else streamed from global memory.
-  // A plan needing fewer solver launches wins; then LDS-resident rows; then larger blocks.
+  // barrier); matrix rows in registers (rows of at most kRegRowBlocks blocks, one
+  // workgroup per CU), in LDS when they fit, else streamed from global memory.
+  // A plan needing fewer solver launches wins; then that order of homes; then larger
+  // blocks.
   std::vector<int> cands;
   if (o.rows_per_block) cands.push_back(o.rows_per_block);
   else cands = {256, 224, 192, 160, 152, 128, 96, 64};
   std::vector<HostPlan> feasible;
   int best = -1, best_groups = 1 << 30;
-  for (int mode = 1; mode >= 0; --mode) {
+  for (int mode : {kMatReg, kMatLds, kMatStream}) {
+    if (o.matrix_home != SIM_MATRIX_AUTO && mode != o.matrix_home - 1) continue;
+    if (mode == kMatReg && L.maxnz > kRegRowBlocks) continue;
     for (int rows : cands) {
-      const bool m64 = s->mprec == SIM_FP64, lm = mode == 1;
+      const bool m64 = s->mprec == SIM_FP64;
+      const int lm = mode;
       const int cnc = coarse ? L.max_nc : 0;
       if (L.nmid > 0 && rows % kMidSize != 0) continue;  // workgroups hold whole runs
       HostPlan P0 = make_plan(L, rows, kBarrierGroup);
-      P0.lds_matrix = mode;
+      P0.mat_home = mode;
       if (P0.max_wg_agg > kMaxWgAgg || P0.max_agg_wg > kMaxAggWg) continue;
       // the rows of the coarse inverse in LDS as well (when that fits), or streamed
       const int xl_full = coarse ? 6 * P0.max_wg_agg * L.max_nc : 0;
@@ -382,7 +391,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
         // the one-workgroup-per-CU variant, and the two-per-CU one where it adds
         // co-resident workgroups
         int prev_cap = 0;
-        for (int occ = 1; occ <= 2; ++occ) {
+        for (int occ = 1; occ <= (mode == kMatReg ? 1 : 2); ++occ) {
           HostPlan P = P0;
           P.xl_floats = xl;
           P.occ = occ;
@@ -408,7 +417,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     }
   }
   if (best < 0) {
-    s->err = "mesh too large for the co-resident solver";
+    s->err = o.matrix_home != SIM_MATRIX_AUTO
+                 ? "no co-resident solver launch shape keeps the matrix where requested"
+                 : "mesh too large for the co-resident solver";
     return SIM_E_INVALID;
   }
 
@@ -882,6 +893,7 @@ void sim_default_options(sim_options* o) {
   o->membrane_system = SIM_MEMBRANE_EXACT;
   o->matrix_precision = SIM_FP64;
   o->coarse_size = 64;
+  o->matrix_home = SIM_MATRIX_AUTO;
 }
 
 sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,

@@ -147,13 +147,19 @@ constexpr int kBarrierGroup = 64;
 
 constexpr int kMaxSolverGroups = 64;
 
+// Where the persistent solver keeps its workgroup's matrix rows during a solve:
+// streamed from the assembled array in global memory at every product, copied once
+// into LDS, or copied once into each row's lane registers (one workgroup per CU,
+// rows of at most kRegRowBlocks blocks).
+enum MatrixHome { kMatStream = 0, kMatLds = 1, kMatReg = 2 };
+
 // Persistent solver launch description.
 struct SolverPlan {
   int nwg;                 // workgroups over all solver groups
   int wg_base;             // first workgroup of the current launch
   int ngroups;             // launches per solve: sets of whole sheets that fit co-resident
   int group_wg0_host[kMaxSolverGroups + 1];  // workgroup ranges of the groups
-  int lds_matrix;          // 1: matrix rows copied to LDS; 0: streamed from global memory
+  int mat_home;            // where the solver reads the matrix rows: MatrixHome
   int occ;                 // 1 or 2 workgroups of 256 threads per CU (kernel variant)
   int rows;                // rows per workgroup (LDS stride; block = rows rounded up to 64)
   const int* wg_inst;      // [nwg]

@@ -54,13 +54,18 @@ class _Material(ctypes.Structure):
                 ("density", ctypes.c_double)]
 
 
+# sim_matrix_home values by index (0: the library's choice)
+MATRIX_HOMES = ("auto", "streamed", "lds", "registers")
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cg_tol", ctypes.c_double),
                 ("cg_max_iter", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32),
                 ("gravity", ctypes.c_double * 3), ("max_steps", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
                 ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("matrix_home", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -69,7 +74,7 @@ class _Stats(ctypes.Structure):
                 ("cg_iters_adjoint", ctypes.c_int64), ("cg_iters_max", ctypes.c_int32),
                 ("max_rel_residual", ctypes.c_double), ("device_status", ctypes.c_int32),
                 ("rows_per_block", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("solver_lds_matrix", ctypes.c_int32), ("solver_launches_per_solve", ctypes.c_int32),
+                ("solver_matrix_home", ctypes.c_int32), ("solver_launches_per_solve", ctypes.c_int32),
                 ("nnz_blocks", ctypes.c_int64), ("solver_launches", ctypes.c_int64),
                 ("solver_ms", ctypes.c_double), ("coarse_aggregates", ctypes.c_int32),
                 ("coarse_max_dim", ctypes.c_int32), ("autotuned", ctypes.c_int32),
@@ -159,7 +164,9 @@ class Simulator:
     ``coarse_size`` sets the vertices per aggregate of the solver's coarse space
     (0: block-Jacobi only); ``autotune`` times the feasible solver launch shapes at
     creation and keeps the fastest; ``graph`` captures rollout and adjoint into HIP
-    graphs that later calls with the same arrays replay.
+    graphs that later calls with the same arrays replay; ``matrix_home`` pins where
+    the solver keeps its matrix rows ("streamed", "lds" or "registers"; None: the
+    library's choice).
     """
 
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
@@ -167,7 +174,7 @@ class Simulator:
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
                  membrane: str = "exact", matrix_precision: str = "fp64",
                  coarse_size: Optional[int] = None, autotune: bool = False,
-                 graph: bool = False):
+                 graph: bool = False, matrix_home: Optional[str] = None):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -188,6 +195,10 @@ class Simulator:
             opt.coarse_size = coarse_size
         opt.autotune = 1 if autotune else 0
         opt.graph = 1 if graph else 0
+        if matrix_home is not None:
+            if matrix_home not in MATRIX_HOMES[1:]:
+                raise ValueError(f"matrix_home must be one of {MATRIX_HOMES[1:]}")
+            opt.matrix_home = MATRIX_HOMES.index(matrix_home)
         self.matrix_precision = matrix_precision
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32

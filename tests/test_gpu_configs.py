@@ -176,7 +176,7 @@ def test_c4_batched_members_match_oracle():
     st = s.stats()
     note(f"C4: handle status {status}, solver launches per solve "
          f"{st['solver_launches_per_solve']}, blocks {st['blocks']}, rows {st['rows_per_block']}, "
-         f"LDS matrix {st['solver_lds_matrix']}")
+         f"matrix home {st['solver_matrix_home']}")
     broken = [b for b in range(len(insts)) if inst_status[b] != 0]
     note(f"C4: sheets whose step matrix stopped being positive definite: {broken}")
     # a breakdown is the method's own (the exact membrane block is indefinite under
@@ -232,7 +232,7 @@ def test_c5_large_sheet_full_size():
     st = out["stats"]
     note(f"C5: cg iters fwd {st['cg_iters_forward']} recompute {st['cg_iters_recompute']} "
          f"adj {st['cg_iters_adjoint']}, blocks {st['blocks']}, rows {st['rows_per_block']}, "
-         f"LDS matrix {st['solver_lds_matrix']}")
+         f"matrix home {st['solver_matrix_home']}")
     check_single_steps(w, inst, out, [1, 300], w.cg_tol, oracle_tol=1e-9)
     check_identities(w, inst, out, tol=1e-4)
     check_segment_adjoint(w, inst, out, 1, target, tol=1e-4, oracle_tol=1e-9)

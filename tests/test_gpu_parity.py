@@ -105,6 +105,31 @@ def test_batch_matches_single_instances():
         assert np.array_equal(batched["material"][b], single["material"][0]), b
 
 
+@pytest.mark.parametrize("coarse_size", [64, 0])
+def test_matrix_homes_are_bitwise_equal(coarse_size):
+    """Streamed, LDS-resident and register-resident matrix rows feed the same
+    products in the same order: at the same launch shape (rows per workgroup, one
+    workgroup per CU) the rollout and every gradient agree bit for bit; the
+    register-resident run also meets the FP64 gates against the oracle."""
+    w = W.workload("C2", steps=20, precision="fp64", cg_tol=1e-10)
+    inst = W.make_instances(w)[0]
+    tgt = inst.x0[None].repeat(w.steps, axis=0) + 0.01
+    outs = {}
+    for home in ("streamed", "lds", "registers"):
+        s = make_sim(w, [inst], rows_per_block=128, matrix_home=home, coarse_size=coarse_size)
+        st = s.stats()
+        assert st["solver_matrix_home"] == ("auto", "streamed", "lds", "registers").index(home)
+        outs[home] = gpu_run(s, w, [inst], [tgt])
+        note(f"matrix home {home} (coarse {coarse_size}): workgroups per CU "
+             f"{st['solver_wg_per_cu']}, cg iters fwd {outs[home]['stats']['cg_iters_forward']}")
+    for home in ("lds", "registers"):
+        for k in ("x", "forces", "x0", "v0", "material"):
+            assert np.array_equal(outs[home][k], outs["streamed"][k]), (home, k)
+    ref = oracle_reference(w, inst, tgt)
+    assert rel(outs["registers"]["x"][-1], ref["x"][-1]) <= 1e-9
+    check_grads(outs["registers"], ref, 1e-6, f"registers (coarse {coarse_size})")
+
+
 def test_autotuned_handle_matches_oracle():
     """The measuring autotuner only changes the solver's launch shape: results stay
     within the parity gates of the 32x32 workload."""
@@ -114,7 +139,7 @@ def test_autotuned_handle_matches_oracle():
     s = make_sim(w, [inst], autotune=True)
     st = s.stats()
     note(f"autotune: {st['autotune_candidates']} launch shapes timed, chose rows "
-         f"{st['rows_per_block']} (LDS matrix {st['solver_lds_matrix']}), "
+         f"{st['rows_per_block']} (matrix home {st['solver_matrix_home']}), "
          f"{1e3 * st['autotune_ms_per_iter']:.1f} us per CG iteration")
     assert st["autotuned"] == 1 and st["autotune_candidates"] > 1
     out = gpu_run(s, w, [inst], [tgt])

@@ -64,3 +64,28 @@ def test_adjoint_before_rollout_and_bad_arguments_without_gpu():
     h = ctypes.c_void_p()
     assert lib.sim_create(None, None, None, 0, None, 0.01, None, ctypes.byref(h)) == sim.SIM_E_INVALID
     assert not h.value
+
+
+def test_matrix_home_option_without_gpu():
+    """The solver's matrix home defaults to the library's choice; a value outside
+    sim_matrix_home is rejected at option validation, before any device work."""
+    import numpy as np
+    from paper_2203_11938_amd import sim
+    lib = sim.load_library()
+    opt = sim._Options()
+    lib.sim_default_options(ctypes.byref(opt))
+    assert opt.matrix_home == 0 and sim.MATRIX_HOMES[0] == "auto"
+    tris = np.array([[0, 1, 2]], np.int32)
+    rest = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    mesh = sim._Mesh()
+    mesh.n_verts, mesh.n_tris = 3, 1
+    mesh.tris = tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    mat = sim._Material()
+    mat.stretch, mat.bend, mat.density = 1.0, 1.0, 1.0
+    for bad in (-1, 4):
+        opt.matrix_home = bad
+        h = ctypes.c_void_p()
+        assert lib.sim_create(ctypes.byref(mesh), rest.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              None, 0, ctypes.byref(mat), 0.01, ctypes.byref(opt),
+                              ctypes.byref(h)) == sim.SIM_E_INVALID
+        assert not h.value

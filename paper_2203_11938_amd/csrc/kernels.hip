@@ -72,12 +72,36 @@ __device__ __forceinline__ double exch(double v, int lane) {
   return *reinterpret_cast<double*>(&t);
 }
 
+// One step of a pairwise sum across lane bit O = 32 or 16 with a permlane swap of
+// a (kept by the lanes whose bit O is clear) and b (kept by the others): the swap
+// leaves, in every lane, its own kept value in one result and its partner's copy of
+// the same value in the other, so their sum is the pair's sum with no lane selects
+// (the two lanes of a pair add in opposite orders, which rounds identically).
+template <int O>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  static_assert(O == 32 || O == 16, "permlane swap distance");
+  const int2 x = *reinterpret_cast<int2*>(&a), y = *reinterpret_cast<int2*>(&b);
+  int2 p, q;
+  if constexpr (O == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(x.x, y.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(x.y, y.y, false, false);
+    p = make_int2(lo[0], hi[0]);
+    q = make_int2(lo[1], hi[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(x.x, y.x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(x.y, y.y, false, false);
+    p = make_int2(lo[0], hi[0]);
+    q = make_int2(lo[1], hi[1]);
+  }
+  return *reinterpret_cast<double*>(&p) + *reinterpret_cast<double*>(&q);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   // butterfly: every lane ends with the same, order-fixed sum (each step adds two
   // copies in either order, which rounds identically)
   const int lane = threadIdx.x & 63;
-  v += exch<32>(v, lane);
-  v += exch<16>(v, lane);
+  v = swap_sum<32>(v, v);
+  v = swap_sum<16>(v, v);
   v += exch<8>(v, lane);
   v += exch<4>(v, lane);
   v += exch<2>(v, lane);
@@ -92,12 +116,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int H, int O, int NP>
 __device__ __forceinline__ void halve_step(double (&v)[NP], int lane) {
   if constexpr (H >= 1) {
-    const bool up = (lane & O) != 0;
+    if constexpr (O >= 16) {
+      // lanes with bit O clear keep v[k], the others v[k + H]
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const double send = up ? v[k] : v[k + H];
-      const double keep = up ? v[k + H] : v[k];
-      v[k] = keep + exch<O>(send, lane);
+      for (int k = 0; k < H; ++k) v[k] = swap_sum<O>(v[k], v[k + H]);
+    } else {
+      const bool up = (lane & O) != 0;
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        const double send = up ? v[k] : v[k + H];
+        const double keep = up ? v[k + H] : v[k];
+        v[k] = keep + exch<O>(send, lane);
+      }
     }
     halve_step<H / 2, O / 2, NP>(v, lane);
   }
@@ -107,7 +137,7 @@ template <int NP>
 __device__ __forceinline__ double wave_sums_scatter(double (&v)[NP], int lane) {
   halve_step<NP / 2, 32, NP>(v, lane);
   double t = v[0];
-  if constexpr (32 / NP >= 16) t += exch<16>(t, lane);
+  if constexpr (32 / NP >= 16) t = swap_sum<16>(t, t);
   if constexpr (32 / NP >= 8) t += exch<8>(t, lane);
   if constexpr (32 / NP >= 4) t += exch<4>(t, lane);
   if constexpr (32 / NP >= 2) t += exch<2>(t, lane);
@@ -529,10 +559,10 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    kv[r] += exch<16>(kv[r], lane);
-    kv[r] += exch<32>(kv[r], lane);
-    f[r] += exch<16>(f[r], lane);
-    f[r] += exch<32>(f[r], lane);
+    kv[r] = swap_sum<16>(kv[r], kv[r]);
+    kv[r] = swap_sum<32>(kv[r], kv[r]);
+    f[r] = swap_sum<16>(f[r], f[r]);
+    f[r] = swap_sum<32>(f[r], f[r]);
   }
   if (g != 0 || !live) return;
   double b[3];
@@ -1991,6 +2021,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     if (COARSE) {
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
       coarse_apply(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
+      PHASE_ADD(6, wall_clock64() - t5);
       unsigned long long* tb = w.tbuf + (size_t)par * 6 * nv;
       ++nep;
       if (act) {

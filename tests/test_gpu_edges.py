@@ -202,3 +202,26 @@ def test_tension_membrane_system():
     tgt, ref = reference(w, inst, membrane=oracle.Oracle.MEMBRANE_TENSION)
     out = gpu_run(make_sim(w, [inst], membrane="tension"), w, [inst], [tgt])
     check(out, ref, 1e-9, 1e-6, "tension membrane system")
+
+
+def test_matrix_home_on_rows_of_more_than_13_blocks():
+    """The irregular sheet couples up to 17 vertices in a row: the register-resident
+    home is refused at creation (SIM_E_INVALID), the library's choice falls back to
+    another home, and the streamed and LDS homes agree bit for bit and with the
+    oracle."""
+    from paper_2203_11938_amd import sim
+    w = fp64(15)
+    rest, tris = irregular_sheet(14, 5)
+    inst = instance(rest, tris, [13 * 14, 14 * 14 - 1], w.steps, 6)
+    with pytest.raises(sim.SimError) as err:
+        make_sim(w, [inst], matrix_home="registers")
+    assert err.value.code == sim.SIM_E_INVALID
+    s = make_sim(w, [inst])
+    assert s.stats()["solver_matrix_home"] in (1, 2)
+    s.close()
+    tgt, ref = reference(w, inst)
+    outs = {h: gpu_run(make_sim(w, [inst], matrix_home=h, rows_per_block=64), w, [inst], [tgt])
+            for h in ("streamed", "lds")}
+    for k in ("x", "forces", "x0", "v0", "material"):
+        assert np.array_equal(outs["lds"][k], outs["streamed"][k]), k
+    check(outs["lds"], ref, 1e-9, 1e-6, "14x14 irregular sheet, LDS and streamed homes")

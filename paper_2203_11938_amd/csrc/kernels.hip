@@ -39,20 +39,13 @@ namespace phisft {
 // ------------------------------------------------------------------ helpers
 // Lane exchanges without the LDS crossbar: the partner of lane l differs from l in bit
 // O (and, for O = 4, 8, in the lower bits too), which is all a butterfly or a
-// recursive halving needs. O = 32, 16: the gfx950 permlane swaps (the swapped copy
-// holds lane l ^ O's value in the lanes whose bit O is clear, the kept copy in the
-// others); O = 8, 4: DPP row mirror / half mirror (l <-> 15 - l, l <-> 7 - l within
-// each 16 / 8 lanes); O = 2, 1: DPP quad permutations. Every lane of the wavefront
-// must be active.
+// recursive halving needs. O = 8, 4: DPP row mirror / half mirror (l <-> 15 - l,
+// l <-> 7 - l within each 16 / 8 lanes); O = 2, 1: DPP quad permutations. Steps
+// across bits 5 and 4 use the gfx950 permlane swaps directly (swap_sum). Every lane
+// of the wavefront must be active.
 template <int O>
 __device__ __forceinline__ int exch_i(int v, int lane) {
-  if constexpr (O == 32) {
-    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (lane & 32) ? r[0] : r[1];
-  } else if constexpr (O == 16) {
-    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-    return (lane & 16) ? r[0] : r[1];
-  } else if constexpr (O == 8) {
+  if constexpr (O == 8) {
     return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);   // row_mirror
   } else if constexpr (O == 4) {
     return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);   // row_half_mirror

@@ -1,0 +1,115 @@
+"""GPU results pinned to closed forms that hold at any size, so they check the full-size
+sheets without the oracle.
+
+* Free fall (no pins, no forces, start at the rest shape): the stiffness annihilates
+  the uniform velocity of a translating sheet, so every step solves M dv = h M g
+  exactly: x_s = X + g h^2 s(s+1)/2 and v_s = s h g (Sec. 3.1, Eq. 1 and 4 with a
+  force-free rest state).
+* Forces only (k_s = k_b = 0, g = 0): the step matrix is the lumped mass
+  m_i = d * (sum of the incident rest areas) / 3, so v_s = v_0 + h sum_{r<s} F_r / m
+  and x_s = x_0 + h sum_{q<=s} v_q, pinned vertices held; for L = sum_s <c_s, x_s>
+  over the loss frames the gradients are dL/dF_r = sum_{s>r} c_s h^2 (s - r) / m,
+  dL/dx_0 = sum_s c_s, dL/dv_0 = sum_s s h c_s and
+  dL/dd = -sum_s <c_s, x_s - x_0 - s h v_0> / d on free vertices.
+Gates: FP64 handles with CG tolerance 1e-12; positions to 1e-10 m absolute (the
+displacements are centimetres), gradients to 1e-9 relative.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import note, rel
+from paper_2203_11938_amd import sim as S, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+F64 = dict(dtype=torch.float64, device=DEV)
+
+
+def vertex_areas(rest, tris):
+    """Lumped vertex areas: a third of every incident rest triangle's area."""
+    e1 = rest[tris[:, 1]] - rest[tris[:, 0]]
+    e2 = rest[tris[:, 2]] - rest[tris[:, 0]]
+    at = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+    va = np.zeros(rest.shape[0])
+    for k in range(3):
+        np.add.at(va, tris[:, k], at / 3.0)
+    return va
+
+
+@pytest.mark.parametrize("n,steps", [(64, 12), (200, 6)])
+def test_free_fall_full_size(n, steps):
+    rest, tris = W.grid_sheet(n)
+    h = 0.01
+    s = S.Simulator([S.Sheet(tris, rest, [], 1e3, 1e-4, 0.1)], dt=h, precision="fp64",
+                    cg_tol=1e-12, max_steps=steps)
+    x0 = torch.tensor(W.to_soa(rest), **F64)
+    xo = s.rollout(steps, x0)
+    s.sync()
+    x = W.from_soa(xo.cpu().numpy())
+    g = np.array(W.GRAVITY)
+    err = max(np.abs(x[k] - (rest + g * h * h * (k + 1) * (k + 2) / 2)).max() for k in range(steps))
+    st = s.stats()
+    note(f"free fall {n}x{n}, {steps} steps: max position error {err:.2e} m, "
+         f"cg iters {st['cg_iters_forward']}, matrix home {st['solver_matrix_home']}")
+    assert err <= 1e-10
+    s.close()
+
+
+def test_forces_only_rollout_and_gradients():
+    n, steps, h, d = 64, 12, 0.02, 0.3
+    rest, tris = W.grid_sheet(n)
+    pins = W.pin_set(n, "top2")
+    V = n * n
+    s = S.Simulator([S.Sheet(tris, rest, pins, 0.0, 0.0, d)], dt=h, precision="fp64",
+                    cg_tol=1e-12, max_steps=steps, gravity=(0.0, 0.0, 0.0))
+    g = np.random.default_rng(12)
+    F = g.normal(size=(steps, V, 3)) * (W.SHEET_SIDE ** 2 / V)
+    x0 = rest + 0.01 * g.normal(size=rest.shape)
+    v0 = 0.1 * g.normal(size=rest.shape)
+    frames = np.array([3, 7, 12], np.int32)
+    c = g.normal(size=(len(frames), V, 3))
+
+    xo = s.rollout(steps, torch.tensor(W.to_soa(x0), **F64), torch.tensor(W.to_soa(v0), **F64),
+                   torch.tensor(W.to_soa(F), **F64), None, frames)
+    gr = s.adjoint(torch.tensor(W.to_soa(c), **F64).contiguous())
+    s.sync()
+    x = W.from_soa(xo.cpu().numpy())
+
+    m = d * vertex_areas(rest, tris)[:, None]
+    free = np.ones(V, bool)
+    free[pins] = False
+    v = v0.copy()
+    v[~free] = 0.0
+    xs, xc = [], x0.copy()
+    for q in range(steps):
+        v = v + h * F[q] / m
+        v[~free] = 0.0
+        xc = xc + h * v
+        xs.append(xc.copy())
+    err_x = max(np.abs(x[k] - xs[f - 1]).max() for k, f in enumerate(frames))
+
+    gF = np.zeros((steps, V, 3))
+    for k, f in enumerate(frames):
+        for r in range(f):
+            gF[r] += c[k] * h * h * (f - r) / m
+    gF[:, ~free] = 0.0
+    gx0 = c.sum(axis=0)
+    gv0 = sum(f * h * c[k] for k, f in enumerate(frames))
+    gv0[~free] = 0.0
+    v0m = v0.copy()
+    v0m[~free] = 0.0
+    gd = -sum(np.sum((c[k] * (xs[f - 1] - x0 - f * h * v0m))[free]) for k, f in enumerate(frames)) / d
+
+    errs = dict(forces=rel(W.from_soa(gr["forces"].cpu().numpy()), gF),
+                x0=rel(W.from_soa(gr["x0"].cpu().numpy()), gx0),
+                v0=rel(W.from_soa(gr["v0"].cpu().numpy()), gv0),
+                density=abs(gr["material"].cpu().numpy()[0][2] - gd) / abs(gd))
+    note(f"forces only {n}x{n}: position error {err_x:.2e} m; gradient rel errors " +
+         ", ".join(f"{k} {e:.2e}" for k, e in errs.items()))
+    assert err_x <= 1e-10
+    for k, e in errs.items():
+        assert e <= 1e-9, (k, e)
+    s.close()

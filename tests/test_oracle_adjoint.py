@@ -130,6 +130,40 @@ def test_only_forces_gradient_closed_form(oracle_mod):
     assert np.allclose(g["material"][:2], 0.0, atol=1e-15)
 
 
+def test_only_forces_initial_state_and_density_gradients_closed_form(oracle_mod):
+    # k_s = k_b = 0, g = 0, pinned vertices held: x_s = x_0 + s h v_0 + (h^2 / m) sum_{r<s}
+    # (s - r) F_r on free vertices, m = d * (incident rest area) / 3, so for
+    # L = sum_s <c_s, x_s>: dL/dx_0 = sum_s c_s, dL/dv_0 = sum_s s h c_s (free rows) and
+    # dL/dd = -sum_s <c_s, x_s - x_0 - s h v_0> / d (the force term scales with 1 / d)
+    n, steps, h, d = 5, 12, 0.02, 0.3
+    rest, tris = W.grid_sheet(n)
+    pins = W.pin_set(n, "top2")
+    V = n * n
+    o = oracle_mod.Oracle(tris, rest, pins, 0.0, 0.0, d, dt=h, gravity=(0, 0, 0), cg_tol=1e-14)
+    g = np.random.default_rng(12)
+    F = g.normal(size=(steps, V, 3))
+    x0 = rest + 0.01 * g.normal(size=rest.shape)
+    v0 = 0.1 * g.normal(size=rest.shape)
+    frames = np.array([3, 7, 12], np.int32)
+    c = g.normal(size=(len(frames), V, 3))
+    gr = o.gradient(steps, x0, v0, F, frames, c)
+    free = np.ones(V, bool)
+    free[pins] = False
+    e1, e2 = rest[tris[:, 1]] - rest[tris[:, 0]], rest[tris[:, 2]] - rest[tris[:, 0]]
+    area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1)
+    m = np.zeros(V)
+    for k in range(3):
+        np.add.at(m, tris[:, k], d * area / 3.0)
+    # the force part of x_s on free rows: (h^2 / m) sum_{r<s} (s - r) F_r
+    disp = [h * h * sum((f - r) * F[r] for r in range(f)) / m[:, None] for f in frames]
+    gx0 = c.sum(axis=0)
+    gv0 = sum(f * h * c[k] for k, f in enumerate(frames)) * free[:, None]
+    gd = -sum(np.sum((c[k] * disp[k])[free]) for k in range(len(frames))) / d
+    assert np.allclose(gr["x0"], gx0, rtol=1e-12, atol=1e-14)
+    assert np.allclose(gr["v0"], gv0, rtol=1e-12, atol=1e-14)
+    assert np.isclose(gr["material"][2], gd, rtol=1e-10)
+
+
 def test_homogeneity_identity(oracle_mod):
     # (k_s, k_b, d, F) -> c (k_s, k_b, d, F) scales A and b alike, so the trajectory is
     # unchanged: k_s dL/dk_s + k_b dL/dk_b + d dL/dd + <F, dL/dF> = 0

@@ -11,8 +11,10 @@ sheets without the oracle.
   over the loss frames the gradients are dL/dF_r = sum_{s>r} c_s h^2 (s - r) / m,
   dL/dx_0 = sum_s c_s, dL/dv_0 = sum_s s h c_s and
   dL/dd = -sum_s <c_s, x_s - x_0 - s h v_0> / d on free vertices.
+* Momentum (no pins, no gravity, any stiffness): the mass-weighted position sum and
+  the gradients of any loss on it follow from the inputs alone.
 Gates: FP64 handles with CG tolerance 1e-12; positions to 1e-10 m absolute (the
-displacements are centimetres), gradients to 1e-9 relative.
+displacements are centimetres), gradients to 1e-9 relative (momentum: 1e-8).
 """
 
 import numpy as np
@@ -112,4 +114,67 @@ def test_forces_only_rollout_and_gradients():
     assert err_x <= 1e-10
     for k, e in errs.items():
         assert e <= 1e-9, (k, e)
+    s.close()
+
+
+@pytest.mark.parametrize("n,steps", [(64, 20), (200, 8)])
+def test_momentum_identity_full_size(n, steps):
+    """No pins, no gravity: the internal forces sum to zero in every state and the step
+    matrix maps translations to the mass alone, so every step conserves momentum
+    exactly up to its solve's residual, and
+      sum_i m_i x_i(T) = sum_i m_i (x0_i + T h v0_i) + h^2 sum_{r<T} (T - r) sum_i F_{r,i}
+    whatever the stiffness. For L = <a, sum_i m_i x_i(T)> with the weights m_i held
+    fixed, the gradients follow in closed form: dL/dx0_i = m_i a, dL/dv0_i = T h m_i a,
+    dL/dF_{r,i} = h^2 (T - r) a, dL/dk_s = dL/dk_b = 0, and, differentiating the identity
+    with m = d A, dL/dd = -(h^2 / d) sum_{r<T} (T - r) <a, sum_i F_{r,i}>. The sheet
+    crumples under random forces, so the tension membrane system keeps every step SPD.
+
+    Gates: the positions' identity, dL/dv0, dL/dF and the vertex sum of dL/dx0 (the
+    stiffness terms cancel exactly in it) to 1e-8. Per vertex, dL/dx0 = m_i a (about
+    1e-6 kg times a) is what remains after stiffness terms h K mu cancel, and they
+    cancel only for an exact adjoint: the solves' residual (cg_tol relative) shows up
+    amplified by about h k_s V / (d L^2), the ratio of a vertex's stiffness term to its
+    mass (1.6e6 at 64x64, 1.6e7 at 200x200), so those values, the density gradient
+    and the vanishing stiffness gradients are held to 10 x cg_tol x that ratio."""
+    rest, tris = W.grid_sheet(n)
+    V = n * n
+    h, (ks, kb, d) = 0.01, W.Material().as_tuple()
+    cg_tol = 1e-12
+    s = S.Simulator([S.Sheet(tris, rest, [], ks, kb, d)], dt=h, precision="fp64", cg_tol=cg_tol,
+                    max_steps=steps, gravity=(0.0, 0.0, 0.0), membrane="tension")
+    g = np.random.default_rng(n)
+    x0 = rest + 0.002 * W.SHEET_SIDE * g.normal(size=rest.shape)
+    v0 = 0.05 * g.normal(size=rest.shape)
+    F = 0.05 * g.normal(size=(steps, V, 3)) * (W.SHEET_SIDE ** 2 / V)
+    a = g.normal(size=3)
+    m = d * vertex_areas(rest, tris)
+    xo = s.rollout(steps, torch.tensor(W.to_soa(x0), **F64), torch.tensor(W.to_soa(v0), **F64),
+                   torch.tensor(W.to_soa(F), **F64), None, np.array([steps], np.int32))
+    dl = (m[:, None] * a[None, :])[None]
+    gr = s.adjoint(torch.tensor(W.to_soa(dl), **F64).contiguous())
+    s.sync()
+    xT = W.from_soa(xo.cpu().numpy())[0]
+    com = (m[:, None] * xT).sum(axis=0)
+    ref = (m[:, None] * (x0 + steps * h * v0)).sum(axis=0) + \
+        h * h * sum((steps - r) * F[r].sum(axis=0) for r in range(steps))
+    gF = np.broadcast_to((h * h * (steps - np.arange(steps)))[:, None, None] * a, (steps, V, 3))
+    mat = gr["material"].cpu().numpy()[0]
+    gd = -h * h / d * sum((steps - r) * float(a @ F[r].sum(axis=0)) for r in range(steps))
+    gx0 = W.from_soa(gr["x0"].cpu().numpy())
+    tight = dict(v0=rel(W.from_soa(gr["v0"].cpu().numpy()), steps * h * m[:, None] * a),
+                 forces=rel(W.from_soa(gr["forces"].cpu().numpy()), gF),
+                 x0_sum=rel(gx0.sum(axis=0), m.sum() * a))
+    amp = h * ks * V / (d * W.SHEET_SIDE ** 2)
+    loose = dict(x0=rel(gx0, m[:, None] * a), density=abs(mat[2] - gd) / abs(gd),
+                 k_s=abs(mat[0]) * ks / (abs(gd) * d), k_b=abs(mat[1]) * kb / (abs(gd) * d))
+    st = s.stats()
+    note(f"momentum {n}x{n}, {steps} steps: centre of mass error "
+         f"{np.abs(com - ref).max() / np.abs(ref).max():.2e}; gradient rel errors " +
+         ", ".join(f"{k} {e:.2e}" for k, e in {**tight, **loose}.items()) +
+         f" (amplification {amp:.1e}); cg iters {st['cg_iters_forward']}")
+    assert np.abs(com - ref).max() <= 1e-9 * np.abs(ref).max()
+    for k, e in tight.items():
+        assert e <= 1e-8, (k, e)
+    for k, e in loose.items():
+        assert e <= 10 * cg_tol * amp, (k, e, amp)
     s.close()

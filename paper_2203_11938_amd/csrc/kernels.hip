@@ -986,6 +986,8 @@ struct Barrier {
   int ngroups;
   int gsize;   // members of this workgroup's group (flat: workgroups of the sheet)
   int epoch;
+  bool released;   // thread 0: this workgroup completed its group's arrival and released it
+  bool ok;         // thread 0: no time-out or abort in the arrival half
 };
 
 // Polls with relaxed agent-scope loads (they read the coherent value without cache
@@ -1029,29 +1031,43 @@ __device__ __forceinline__ Barrier make_barrier(const SolverPlan& plan, const So
   return b;
 }
 
-__device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int* status,
-                                                int inst) {
-  __shared__ int s_ok;
+// Arrival half: thread 0 counts the workgroup in (a release of everything the workgroup
+// wrote before it). The last arriver of a group completes the group's arrival at the
+// root, waits for every group and releases its own, so the sheet's release never waits
+// for work placed between the halves; every other workgroup may do work that needs
+// nothing from the others before cluster_wait.
+__device__ __forceinline__ void cluster_arrive(Barrier& b, int* abort_flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
     b.epoch += 1;
     const int e = b.epoch;
-    bool ok;
+    b.released = false;
+    b.ok = true;
     if (b.gctr == nullptr) {
       __hip_atomic_fetch_add(b.root, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      ok = bounded_wait_ge(b.root, e * b.gsize, abort_flag);
     } else {
       const int old = __hip_atomic_fetch_add(b.gctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       if (old == e * b.gsize - 1) {  // last arriver of the group
         // acquire what the group's members released, then release it to the root
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_fetch_add(b.root, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        ok = bounded_wait_ge(b.root, e * b.ngroups, abort_flag);
+        b.ok = bounded_wait_ge(b.root, e * b.ngroups, abort_flag);
         __hip_atomic_store(b.gflag, e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        ok = bounded_wait_ge(b.gflag, e, abort_flag);
+        b.released = true;
       }
     }
+  }
+}
+
+// Waiting half: true when every workgroup of the sheet has arrived (false on a time-out
+// or an abort, after setting the abort flag and the sheet's status).
+__device__ __forceinline__ bool cluster_wait(Barrier& b, int* abort_flag, int* status, int inst) {
+  __shared__ int s_ok;
+  if (threadIdx.x == 0) {
+    const int e = b.epoch;
+    bool ok = b.ok;
+    if (b.gctr == nullptr) ok = bounded_wait_ge(b.root, e * b.gsize, abort_flag);
+    else if (!b.released) ok = bounded_wait_ge(b.gflag, e, abort_flag);
     if (!ok) {
       __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       set_status(status, inst, ST_TIMEOUT);
@@ -1060,6 +1076,12 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
   }
   __syncthreads();
   return s_ok != 0;
+}
+
+__device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int* status,
+                                                int inst) {
+  cluster_arrive(b, abort_flag);
+  return cluster_wait(b, abort_flag, status, inst);
 }
 
 // Sheets with at most this many solver workgroups exchange their per-iteration partial
@@ -1935,14 +1957,23 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     const int par = it & 1;
     double* mb = w.pbuf + (size_t)par * 3 * nv;
     double* ml = mL + (size_t)par * 3 * RH;
+    // m = M^-1 w: block Jacobi and middle level here (block Jacobi only: published
+    // before the barrier, whose halo read needs it), with the coarse space after the
+    // partials have left (the local part needs nothing from other workgroups)
+    auto m_local = [&]() {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
-    if (COARSE) mid_apply(Bm, live, cr1, wv, mm);
-    if (!COARSE && act) {
+      for (int c = 0; c < 3; ++c)
+        mm[c] = J[3 * c] * wv[0] + J[3 * c + 1] * wv[1] + J[3 * c + 2] * wv[2];
+      if (COARSE) mid_apply(Bm, live, cr1, wv, mm);
+    };
+    if (!COARSE) {
+      m_local();
+      if (act) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        mb[c * nv + i] = mm[c];
-        ml[c * RH + tid] = mm[c];
+        for (int c = 0; c < 3; ++c) {
+          mb[c * nv + i] = mm[c];
+          ml[c * RH + tid] = mm[c];
+        }
       }
     }
     const double loc[3] = {r[0] * u[0] + r[1] * u[1] + r[2] * u[2],
@@ -1964,7 +1995,9 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       publish3(loc, red_slot + (size_t)wg * 3);
     }
     PHASE_T(t1);
-    if (!tagp && !(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
+    if (!tagp) cluster_arrive(bar, w.abort_flag);
+    if (COARSE) m_local();
+    if (!tagp && !(ok = cluster_wait(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
     if (tagp) {
       // the coarse residual and the dot partials are polled together

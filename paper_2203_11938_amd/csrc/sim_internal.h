@@ -143,7 +143,7 @@ struct Coarse {
 // Cluster-barrier layout: counters 128 bytes apart; sheets with more than
 // kBarrierGroup workgroups arrive in groups of that size.
 constexpr int kBarrierSlot = 32;   // ints per counter slot
-constexpr int kBarrierGroup = 64;
+constexpr int kBarrierGroup = 32;
 
 constexpr int kMaxSolverGroups = 64;
 

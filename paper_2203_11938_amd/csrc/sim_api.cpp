@@ -484,6 +484,15 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     cs.max_nb = max_nb;
     std::vector<int> aptr(1, 0), ainst, at, bptr(1, 0), binst, bij;
     for (int K = 0; K < max_nb; ++K) {
+      // every sheet's next pivot tile first: its workgroup also inverts it, the
+      // longest task of the launch, so it is dispatched before the others
+      for (int b = 0; b < L.ninst; ++b) {
+        const int nb = L.inst_np[b] / kGjTile;
+        if (K + 1 < nb) {
+          binst.push_back(b);
+          bij.push_back((K + 1) * 65536 + K + 1);
+        }
+      }
       for (int b = 0; b < L.ninst; ++b) {
         const int nb = L.inst_np[b] / kGjTile;
         if (nb <= K) continue;
@@ -492,8 +501,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
           ainst.push_back(b);
           at.push_back(t);
         }
-        for (int i = 0; i < nb; ++i)   // the stored upper tiles
+        for (int i = 0; i < nb; ++i)   // the other stored upper tiles
           for (int j = i; j < nb; ++j) {
+            if (i == K + 1 && j == K + 1) continue;
             binst.push_back(b);
             bij.push_back(i * 65536 + j);
           }

@@ -841,8 +841,9 @@ __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
   if (!c.ok[inst]) return;
   const int np = c.inst_np[inst];
   const double* M = c.mat + c.inst_coff[inst];
-  double* C = c.gj_c + c.inst_boff[inst] + (size_t)t * T * T;
-  double* D = c.gj_r + c.inst_boff[inst] + (size_t)t * T * T;
+  const long long par = (K & 1) * c.gj_half;
+  double* C = c.gj_c + par + c.inst_boff[inst] + (size_t)t * T * T;
+  double* D = c.gj_r + par + c.inst_boff[inst] + (size_t)t * T * T;
   const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
   for (int e = tid; e < T * T; e += 256) {
     const int r = e / T, q = e % T;
@@ -861,9 +862,59 @@ __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
   }
 }
 
+// Polls of a panel workgroup for the next pivot's inverse (seconds, far beyond the
+// microseconds the inverse takes).
+constexpr int kGjSpinLimit = 1 << 22;
+
+// The panels of step K + 1 for tile t != K + 1, formed by the workgroup that has just
+// written the tile of row / column K + 1 holding M_{t,K+1} (in X, oriented as D_t, i.e.
+// rows of tile t): D_t = that tile, C_t = D_t P_{K+1}, once the workgroup inverting
+// pivot tile K + 1 (listed first in the launch, so dispatched before this one) has
+// stored P_{K+1}. The wait is bounded; on a time-out the step's coarse correction is
+// switched off (ok = 0), as for a failed pivot.
+__device__ __forceinline__ void gj_next_panel(const Coarse& c, int K, int ninst, int inst, int t,
+                                              double (*X)[kGjTile + 1], double (*Y)[kGjTile + 1]) {
+  constexpr int T = kGjTile;
+  __shared__ int s_go;
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    bool ready = true;
+    while (__hip_atomic_load(c.gj_ready + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < K + 2) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kGjSpinLimit) {
+        ready = false;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (!ready) __hip_atomic_store(c.ok + inst, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_go = ready && __hip_atomic_load(c.ok + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  }
+  __syncthreads();
+  if (!s_go) return;
+  // P_{K+1} was written by another workgroup of this launch: coherent loads
+  double* Pn = c.gj_pinv + ((size_t)((K + 1) & 1) * ninst + inst) * T * T;
+  for (int e = threadIdx.x; e < T * T; e += 256)
+    Y[e / T][e % T] = __hip_atomic_load(Pn + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  double o[4];
+  tile_mul4(X, Y, o);
+  const long long par = ((K + 1) & 1) * c.gj_half;
+  double* C = c.gj_c + par + c.inst_boff[inst] + (size_t)t * T * T;
+  double* D = c.gj_r + par + c.inst_boff[inst] + (size_t)t * T * T;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + k * 256, r = e / T, q = e % T;
+    C[r * T + q] = o[k];
+    D[r * T + q] = X[r][q];
+  }
+}
+
 // Step K, second half: every stored tile (i, j), i <= j, of the sheet:
 //   i, j != K: M_ij -= C_i D_j^T;   j = K: M_iK = C_i;   i = K: M_Kj = C_j^T;
-//   (K, K): -P. The tile (K+1, K+1) then inverts itself as the next pivot.
+//   (K, K): -P. The tile (K+1, K+1) then inverts itself as the next pivot, and the
+// workgroups of the other tiles of row and column K + 1 form step K + 1's panels from
+// their new values (so step K + 1 needs no launch of k_gj_cols).
 __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   constexpr int T = kGjTile;
   __shared__ double X[T][T + 1], Y[T][T + 1];
@@ -873,9 +924,11 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   const int i = ij >> 16, j = ij & 0xffff;
   const int np = c.inst_np[inst], nb = np / T;
   double* M = c.mat + c.inst_coff[inst];
-  const double* Cb = c.gj_c + c.inst_boff[inst];
-  const double* Db = c.gj_r + c.inst_boff[inst];
+  const long long par = (K & 1) * c.gj_half;
+  const double* Cb = c.gj_c + par + c.inst_boff[inst];
+  const double* Db = c.gj_r + par + c.inst_boff[inst];
   const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
+  const bool next = K + 1 < nb && (i == K + 1) != (j == K + 1);   // a tile of step K+1's panel
   if (i == K && j == K) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -905,6 +958,8 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
       const int e = tid + k * 256, r = e / T, q = e % T;
       M[(size_t)(K * T + r) * np + j * T + q] = X[r][q];
     }
+    // tile (K, K+1) is M_{t,K+1} for t = K, already oriented as D_t
+    if (next) gj_next_panel(c, K, ninst, inst, K, X, Y);
     return;
   }
   const double* Ci = Cb + (size_t)i * T * T;
@@ -924,7 +979,9 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
     double* dst = M + (size_t)(i * T + r) * np + j * T + q;
     const double v = *dst - o[k];
     *dst = v;
-    if (i == K + 1 && j == K + 1) X[r][q] = v;
+    // the new value in X for the next pivot or panel, oriented as D_t (rows of t)
+    if (i == K + 1 && j != K + 1) X[q][r] = v;
+    else X[r][q] = v;
   }
   if (i == K + 1 && j == K + 1 && K + 1 < nb) {
     __syncthreads();
@@ -938,8 +995,16 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
 #pragma unroll
         for (int q = 0; q < T; ++q) Pn[tid * T + q] = a[q];
       }
-      if (tid == 0 && !good) c.ok[inst] = 0;
+      if (tid == 0 && !good) __hip_atomic_store(c.ok + inst, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
+    // release P_{K+1} (and a failed pivot's ok = 0) to the panel workgroups
+    if (tid == 0) __hip_atomic_store(c.gj_ready + inst, K + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+  if (next) {
+    __syncthreads();
+    gj_next_panel(c, K, ninst, inst, i == K + 1 ? j : i, X, Y);
   }
 }
 
@@ -2595,9 +2660,11 @@ void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const 
   if (c.nmid > 0) hipLaunchKernelGGL((k_mid_setup<TM>), dim3(c.nmid), dim3(64), 0, st, m, c, x, A);
   hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst, 256)), dim3(256), 0, st, c,
                      m.ninst);
+  launch_fill_int(c.gj_ready, m.ninst, 0, st);
   hipLaunchKernelGGL(k_gj_pivot0, dim3(m.ninst), dim3(64), 0, st, c);
   for (int K = 0; K < c.max_nb; ++K) {
-    if (gja_count[K] > 0)
+    // later steps' panels are formed by the previous update launch
+    if (K == 0 && gja_count[K] > 0)
       hipLaunchKernelGGL(k_gj_cols, dim3(gja_count[K]), dim3(256), 0, st, c, K, m.ninst);
     if (gjb_count[K] > 0)
       hipLaunchKernelGGL(k_gj_update, dim3(gjb_count[K]), dim3(256), 0, st, c, K, m.ninst);

@@ -563,9 +563,11 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.mat = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 4, &q)); cs.xinv = (float*)q;
-    TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_c = (double*)q;
-    TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
+    TRY(alloc(s, 2 * (size_t)s->gj_doubles * 8, &q)); cs.gj_c = (double*)q;
+    TRY(alloc(s, 2 * (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
+    cs.gj_half = s->gj_doubles;
     TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
+    TRY(alloc(s, 4 * ni, &q)); cs.gj_ready = (int*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
     TRY(alloc(s, 3 * nv * 8, &q)); cs.mid_crel = (double*)q;
     TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;

@@ -122,9 +122,13 @@ struct Coarse {
   double* mat;                 // A_c, swept in place to -A_c^-1 (FP64 work matrix, upper
                                // tiles; the lower ones are written by the assembly only)
   float* xinv;                 // symmetrised FP32 copy of A_c^-1 read by the solver
-  double* gj_c;                // per sheet [nb][32][32] C_t = M_tK P of the current step
-  double* gj_r;                // per sheet [nb][32][32] column panel D_t = M_tK
+  double* gj_c;                // [2][...] per sheet [nb][32][32] C_t = M_tK P of step K
+  double* gj_r;                // [2][...] per sheet [nb][32][32] column panel D_t = M_tK
+                               // (both by the parity of K: one update launch reads step
+                               // K's panels while it writes step K + 1's)
+  long long gj_half;           // doubles per parity of gj_c / gj_r
   double* gj_pinv;             // [2][ninst][32][32] inverse pivot tiles
+  int* gj_ready;               // [ninst] K + 1 once pivot tile K's inverse is stored
   const long long* inst_boff;  // [ninst] offset of the sheet's gj_c / gj_r blocks (32 np)
   int* ok;                     // [ninst] 1 when this step's inversion succeeded
   double* part;                // [nwg][kMaxWgAgg][6] restriction partial sums

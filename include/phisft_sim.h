@@ -131,7 +131,10 @@ typedef struct {
   double gravity[3];        /* m/s^2                                                    */
   int32_t max_steps;        /* capacity: longest rollout this handle will run           */
   int32_t rows_per_block;   /* solver rows per workgroup, a multiple of 16 from 64 to
-                               256; 0 = the library's choice (rule or autotuner)        */
+                               256; 0 = the library's choice (rule or autotuner). With
+                               a coarse space a workgroup may overlap at most four
+                               aggregates (so at most 4 x their size rows), else
+                               sim_create fails with SIM_E_INVALID                      */
   int32_t membrane_system;  /* sim_membrane_system                                      */
   int32_t matrix_precision; /* sim_precision of the stored system matrix and its
                                block-Jacobi inverse (default SIM_FP64; SIM_FP32 halves

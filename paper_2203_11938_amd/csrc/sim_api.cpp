@@ -419,7 +419,11 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   if (best < 0) {
     s->err = o.matrix_home != SIM_MATRIX_AUTO
                  ? "no co-resident solver launch shape keeps the matrix where requested"
-                 : "mesh too large for the co-resident solver";
+                 : o.rows_per_block != 0
+                       ? "no co-resident solver launch shape with the requested rows per workgroup "
+                         "(a workgroup may overlap at most 4 coarse aggregates, an aggregate at "
+                         "most 4 workgroups)"
+                       : "mesh too large for the co-resident solver";
     return SIM_E_INVALID;
   }
 

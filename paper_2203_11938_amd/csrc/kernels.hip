@@ -1160,8 +1160,10 @@ constexpr int kTagWgMax = 64;
 // reader that sees the expected tag in both words has the value published with it:
 // no flag, no fence, no separate round trip. Words are written and read with
 // coherent agent-scope atomics; the buffer is zeroed before each launch (tags start
-// at 1). The full cluster barrier of every iteration keeps a workgroup from
-// rewriting a word (two publications later) before its readers are done with it.
+// at 1). Publications alternate between two buffers by iteration parity, and a
+// workgroup cannot rewrite a word two publications later before its readers are done
+// with it: in between it needs their partial sums of the next iteration, which they
+// publish only after they have read (restarts pass full cluster barriers).
 __device__ __forceinline__ void publish_tagged(unsigned long long* tb, int nv, int i,
                                                const double v[3], unsigned tag) {
 #pragma unroll
@@ -1432,7 +1434,10 @@ constexpr int kMaxRestarts = 16;
 // reduction per iteration, (r,u), (w,u), (r,r), exchanged with the coarse restriction
 // (tagged words, or a cluster barrier on large sheets and without a coarse space);
 // then m = M^-1 w is published (tagged) for the iteration's single SpMV n = A m,
-// each workgroup reading only its halo. Vectors per row:
+// each workgroup reading only its halo. The local part of m (block Jacobi and middle
+// level) is formed while the partial sums travel, between their publication and the
+// wait for the other workgroups' (the arrival and waiting halves of the barrier on
+// large sheets). Vectors per row:
 // x, r, u = M^-1 r, w = A u, z, q, s, p (recurrences of the method), all FP64.
 // The recursively updated residual drifts from b - A x (rounding), so
 // convergence is accepted only on a true residual: when the recursive residual

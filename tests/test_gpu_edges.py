@@ -225,3 +225,18 @@ def test_matrix_home_on_rows_of_more_than_13_blocks():
     for k in ("x", "forces", "x0", "v0", "material"):
         assert np.array_equal(outs["lds"][k], outs["streamed"][k]), k
     check(outs["lds"], ref, 1e-9, 1e-6, "14x14 irregular sheet, LDS and streamed homes")
+
+
+def test_rows_per_block_the_coarse_space_cannot_use():
+    """A workgroup may overlap at most four coarse aggregates: 256 rows per workgroup
+    with 16-vertex aggregates is refused at creation (SIM_E_INVALID), and the same
+    aggregates with 64 rows work."""
+    from paper_2203_11938_amd import sim
+    w = fp64(5)
+    inst = W.make_instances(w)[0]
+    with pytest.raises(sim.SimError) as err:
+        make_sim(w, [inst], rows_per_block=256, coarse_size=16)
+    assert err.value.code == sim.SIM_E_INVALID
+    s = make_sim(w, [inst], rows_per_block=64, coarse_size=16)
+    assert s.stats()["rows_per_block"] == 64
+    s.close()

@@ -1154,26 +1154,44 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
 // gain, 157 lose).
 constexpr int kTagWgMax = 64;
 
-// Tagged publication of a row vector: each double travels as two 64-bit words, each
-// holding a 32-bit tag (the publication's number, the same in every workgroup of a
-// sheet) above 32 bits of the value. A 64-bit store is single-copy atomic, so a
-// reader that sees the expected tag in both words has the value published with it:
-// no flag, no fence, no separate round trip. Words are written and read with
-// coherent agent-scope atomics; the buffer is zeroed before each launch (tags start
-// at 1). Publications alternate between two buffers by iteration parity, and a
-// workgroup cannot rewrite a word two publications later before its readers are done
-// with it: in between it needs their partial sums of the next iteration, which they
-// publish only after they have read (restarts pass full cluster barriers).
-__device__ __forceinline__ void publish_tagged(unsigned long long* tb, int nv, int i,
-                                               const double v[3], unsigned tag) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v[c]);
-    const unsigned long long t = (unsigned long long)tag << 32;
-    unsigned long long* p = tb + ((size_t)c * nv + i) * 2;
-    __hip_atomic_store(p, t | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(p + 1, t | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+// Tagged publication of a vertex's three doubles of a row vector as four 64-bit words
+// (vertex-major, [nv][4]), each holding a 16-bit tag (from the publication's number,
+// the same in every workgroup of a sheet, never 0) above 48 of the 192 value bits. A
+// 64-bit store is single-copy atomic, so a reader that sees the expected tag in all
+// four words has the values published with it: no flag, no fence, no separate round
+// trip. Words are written and read with coherent agent-scope atomics; the buffer is
+// zeroed before each launch. Publications alternate between two buffers by iteration
+// parity, and a workgroup cannot rewrite a word two publications later before its
+// readers are done with it: in between it needs their partial sums of the next
+// iteration, which they publish only after they have read (restarts pass full cluster
+// barriers). So a word a reader sees is from this publication or from the one two
+// before (tag 2 lower modulo 65535), which the 16-bit tag tells apart.
+__device__ __forceinline__ unsigned long long vtag(unsigned pub) {
+  return (unsigned long long)((pub - 1u) % 65535u + 1u) << 48;
+}
+
+constexpr unsigned long long kLow48 = (1ull << 48) - 1;
+
+__device__ __forceinline__ void publish_tagged(unsigned long long* tb, int i, const double v[3],
+                                               unsigned pub) {
+  const unsigned long long t = vtag(pub);
+  const unsigned long long a = (unsigned long long)__double_as_longlong(v[0]);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v[1]);
+  const unsigned long long c = (unsigned long long)__double_as_longlong(v[2]);
+  unsigned long long* p = tb + (size_t)i * 4;
+  __hip_atomic_store(p, t | (a & kLow48), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, t | (a >> 48) | ((b & 0xffffffffull) << 16), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 2, t | (b >> 32) | ((c & 0xffffull) << 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 3, t | (c >> 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The three doubles of four words published together (tags already checked).
+__device__ __forceinline__ void unpack_tagged(const unsigned long long (&w)[4], double v[3]) {
+  v[0] = __longlong_as_double((long long)((w[0] & kLow48) | ((w[1] & 0xffffull) << 48)));
+  v[1] = __longlong_as_double((long long)(((w[1] >> 16) & 0xffffffffull) | ((w[2] & 0xffffffffull) << 32)));
+  v[2] = __longlong_as_double((long long)(((w[2] >> 32) & 0xffffull) | ((w[3] & kLow48) << 16)));
 }
 
 __device__ __forceinline__ void store_tagged(unsigned long long* p, unsigned tag, double v) {
@@ -1216,39 +1234,56 @@ __device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigne
   w1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Halo of a tagged vector into vl[c][R + h]: every entry is polled until both of its
-// words carry `tag` (bounded like the barrier's waits). A thread's entries are read
-// kHaloBatch at a time, all loads issued before any is checked (one round trip per
-// batch, not per entry). False (every thread) on a time-out or an abort; the caller
-// then stops.
-constexpr int kHaloBatch = 8;
-__device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
+// Halo of a tagged vector into vl[c][R + h]: every halo vertex's four words are polled
+// until all carry the publication's tag (bounded like the barrier's waits). A thread's
+// vertices are read kHaloBatch at a time, all loads issued before any is checked (one
+// round trip per batch, not per vertex). False (every thread) on a time-out or an
+// abort; the caller then stops.
+constexpr int kHaloBatch = 4;
+__device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb,
                                                  const int* __restrict__ hidx, int nh,
                                                  double* __restrict__ vl, int R, int RH,
-                                                 unsigned tag, int* abort_flag) {
+                                                 unsigned pub, int* abort_flag) {
   __shared__ int s_bad;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   bool ok = true;
-  const int ne = 3 * nh, nb = blockDim.x;
-  for (int e0 = threadIdx.x; e0 < ne && ok; e0 += kHaloBatch * nb) {
-    const unsigned long long* adr[kHaloBatch];
-    unsigned long long w0[kHaloBatch], w1[kHaloBatch];
+  const unsigned long long t = vtag(pub);
+  const int nb = blockDim.x;
+  for (int h0 = threadIdx.x; h0 < nh && ok; h0 += kHaloBatch * nb) {
+    unsigned long long w[kHaloBatch][4];
 #pragma unroll
     for (int u = 0; u < kHaloBatch; ++u) {
-      // entries past the end re-read the last one (no branches around the loads)
-      const int e = min(e0 + u * nb, ne - 1);
-      const int c = e / nh, h = e - c * nh;
-      adr[u] = tb + ((size_t)c * nv + hidx[h]) * 2;
-      load_tagged(adr[u], w0[u], w1[u]);
+      // vertices past the end re-read the last one (no branches around the loads)
+      unsigned long long* p = const_cast<unsigned long long*>(tb) + (size_t)hidx[min(h0 + u * nb, nh - 1)] * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[u][k] = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int u = 0; u < kHaloBatch; ++u) {
-      const int e = e0 + u * nb;
-      if (e >= ne) break;
-      ok = ok && poll_tagged(adr[u], tag, abort_flag, w0[u], w1[u]);
-      const int c = e / nh, h = e - c * nh;
-      if (ok) vl[c * RH + R + h] = tag_value(w0[u], w1[u]);
+      const int h = h0 + u * nb;
+      if (h >= nh) break;
+      unsigned long long* p = const_cast<unsigned long long*>(tb) + (size_t)hidx[h] * 4;
+      int spins = 0;
+      while (ok && ((w[u][0] ^ t) >> 48 | (w[u][1] ^ t) >> 48 | (w[u][2] ^ t) >> 48 |
+                    (w[u][3] ^ t) >> 48) != 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit ||
+            __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          ok = false;
+          break;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          w[u][k] = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (ok) {
+        double v[3];
+        unpack_tagged(w[u], v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vl[c * RH + R + h] = v[c];
+      }
     }
   }
   if (!ok) s_bad = 1;
@@ -2118,15 +2153,15 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
       coarse_apply(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
       PHASE_ADD(6, wall_clock64() - t5);
-      unsigned long long* tb = w.tbuf + (size_t)par * 6 * nv;
+      unsigned long long* tb = w.tbuf + (size_t)par * 4 * nv;
       ++nep;
       if (act) {
-        publish_tagged(tb, nv, i, mm, (unsigned)nep);
+        publish_tagged(tb, i, mm, (unsigned)nep);
 #pragma unroll
         for (int c = 0; c < 3; ++c) ml[c * RH + tid] = mm[c];
       }
       PHASE_ADD(4, wall_clock64() - t5);
-      if (!halo_load_tagged(tb, nv, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
+      if (!halo_load_tagged(tb, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
         if (tid == 0) {
           __hip_atomic_store(w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           set_status(a.status, inst, ST_TIMEOUT);
@@ -2621,7 +2656,7 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
   z.n[1] = 1;
   if (coarse) {
     z.p[2] = reinterpret_cast<int*>(w.tbuf);
-    z.n[2] = 24 * m.nv;
+    z.n[2] = 16 * m.nv;   // [2][nv][4] 64-bit words
     z.p[3] = reinterpret_cast<int*>(w.tred);
     z.n[3] = w.tred_ints;
   }

@@ -70,6 +70,10 @@ def _load():
         "orc_step": (c_int, [P, D, D, D, D, D, D, I]),
         "orc_rollout": (c_int, [P, c_int, D, D, D, I, c_int, D, D, I]),
         "orc_gradient": (c_int, [P, c_int, D, D, D, I, c_int, D, D, D, D, D, I, I]),
+        "orc_pattern": (None, [P, I, I]),
+        "orc_system_blocks": (c_int, [P, D, D, D, D, D]),
+        "orc_adjoint_rhs": (None, [P, D, D, D]),
+        "orc_adjoint_update": (None, [P, D, D, D, D, D, D, D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -112,6 +116,37 @@ def hinge_theta_grad(x4):
     g = np.zeros((4, 3))
     _load().orc_hinge_theta_grad(_d(x4), _d(g))
     return g
+
+
+class ExactSolve:
+    """Sparse LU of one step matrix A with one step of iterative refinement per
+    solve. The factorisation first runs without pivoting on the symmetric structure
+    (the matrix is symmetric and, away from breakdowns, positive definite); if a
+    solve's refined residual is not at rounding level it refactors with partial
+    pivoting."""
+
+    def __init__(self, A):
+        import scipy.sparse.linalg as spla
+        self.A = A
+        self._spla = spla
+        self._csc = A.tocsc()
+        self.lu = spla.splu(self._csc, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                            options=dict(SymmetricMode=True))
+        self.pivoted = False
+
+    def _solve(self, rhs):
+        x = self.lu.solve(rhs)
+        return x + self.lu.solve(rhs - self.A @ x)
+
+    def solve(self, rhs):
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        x = self._solve(rhs)
+        nb = np.linalg.norm(rhs)
+        if nb > 0 and not np.linalg.norm(self.A @ x - rhs) <= 1e-9 * nb and not self.pivoted:
+            self.lu = self._spla.splu(self._csc, permc_spec="MMD_AT_PLUS_A")
+            self.pivoted = True
+            x = self._solve(rhs)
+        return x
 
 
 class Oracle:
@@ -318,3 +353,99 @@ class Oracle:
             raise OracleError(st, "gradient")
         return dict(material=gm, forces=gF, x0=gx0, v0=gv0, iters_fwd=itf, iters_adj=ita,
                     status=st)
+
+    # ------------------------------------------- exact-solve driver (golden files)
+    def pattern(self):
+        """CSR block pattern of the step matrix: (rowptr [V+1], col [nnzb])."""
+        rp = np.zeros(self.nv + 1, dtype=np.int32)
+        col = np.zeros(self.nnzb, dtype=np.int32)
+        _load().orc_pattern(self._h, _i(rp), _i(col))
+        return rp, col
+
+    def system_sparse(self, x, v, F=None):
+        """The step's system (Eq. 4-5, pins eliminated) as a scipy CSR matrix A
+        [3V, 3V] and b [3V] (vertex-major unknowns)."""
+        import scipy.sparse as sp
+        if not hasattr(self, "_csr"):
+            rp, col = self.pattern()
+            # block (i, j) at slot s expands to rows 3i+k, columns 3j+m
+            rows = np.repeat(np.arange(self.nv), np.diff(rp))
+            r = (3 * rows[:, None, None] + np.arange(3)[None, :, None]).repeat(3, axis=2)
+            c = (3 * col[:, None, None] + np.arange(3)[None, None, :]).repeat(3, axis=1)
+            self._csr = (r.ravel(), c.ravel())
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        F = _f64(F, (self.nv, 3)) if F is not None else None
+        blocks = np.zeros((self.nnzb, 3, 3))
+        b = np.zeros(3 * self.nv)
+        st = _load().orc_system_blocks(self._h, _d(x), _d(v), _d(F), _d(blocks), _d(b))
+        if st != ORC_OK:
+            raise OracleError(st, "system_blocks")
+        n = 3 * self.nv
+        A = sp.csr_matrix((blocks.ravel(), self._csr), shape=(n, n))
+        return A, b
+
+    def _exact_solver(self, x, v, F):
+        """Exact solver of the step matrix A(x) (scipy's sparse LU, a library routine
+        standing for 'solve A dv = b' of Eq. 4) and the step's b."""
+        A, b = self.system_sparse(x, v, F)
+        return ExactSolve(A), b
+
+    def rollout_exact(self, n_steps, x0, v0=None, forces=None):
+        """Every state of a rollout whose steps are solved exactly (sparse LU instead of
+        CG): returns X, V, DV [n_steps + 1, V, 3]."""
+        x0 = _f64(x0, (self.nv, 3))
+        v0 = np.zeros((self.nv, 3)) if v0 is None else _f64(v0, (self.nv, 3))
+        X = np.zeros((n_steps + 1, self.nv, 3))
+        Vv = np.zeros_like(X)
+        DV = np.zeros_like(X)
+        X[0] = x0
+        Vv[0] = v0
+        Vv[0][self.pins] = 0.0
+        pinned = np.zeros(self.nv, dtype=bool)
+        pinned[self.pins] = True
+        for s in range(1, n_steps + 1):
+            F = None if forces is None else forces[s - 1]
+            lu, b = self._exact_solver(X[s - 1], Vv[s - 1], F)
+            dv = lu.solve(b).reshape(self.nv, 3)
+            dv[pinned] = 0.0
+            DV[s] = dv
+            Vv[s] = Vv[s - 1] + dv
+            Vv[s][pinned] = 0.0
+            X[s] = X[s - 1] + self.dt * Vv[s]
+        return X, Vv, DV
+
+    def gradient_exact(self, n_steps, x0, v0, forces, loss_frames, targets, states=None):
+        """Rollout + adjoint with exact step solves, for the loss
+        L = sum over the loss frames of |x_s - target_s|^2 (dL/dx_s = 2 (x_s - target_s)).
+        The backward sweep is the oracle's own (orc_adjoint_rhs, orc_adjoint_update)
+        around an exact solve of A(x_{s-1}) mu = u. Returns the positions at the loss
+        frames, the loss and dL/d(k_s, k_b, d), dL/dF, dL/dx0, dL/dv0."""
+        frames = [int(f) for f in loss_frames]
+        X, Vv, DV = states if states is not None else self.rollout_exact(n_steps, x0, v0, forces)
+        targets = np.asarray(targets, dtype=np.float64)
+        xo = X[frames]
+        dl = 2.0 * (xo - targets)
+        gx = np.zeros((self.nv, 3))
+        gv = np.zeros((self.nv, 3))
+        u = np.zeros((self.nv, 3))
+        gm = np.zeros(3)
+        gF = np.zeros((n_steps, self.nv, 3))
+        lib = _load()
+        fi = len(frames) - 1
+        for s in range(n_steps, 0, -1):
+            if fi >= 0 and frames[fi] == s:
+                gx += dl[fi]
+                fi -= 1
+            lib.orc_adjoint_rhs(self._h, _d(gx), _d(gv), _d(u))
+            F = None if forces is None else forces[s - 1]
+            lu, _ = self._exact_solver(X[s - 1], Vv[s - 1], F)
+            mu = np.ascontiguousarray(lu.solve(u.ravel()).reshape(self.nv, 3))
+            gF[s - 1] = self.dt * mu
+            xp = np.ascontiguousarray(X[s - 1])
+            vs = np.ascontiguousarray(Vv[s])
+            dvs = np.ascontiguousarray(DV[s])
+            lib.orc_adjoint_update(self._h, _d(xp), _d(vs), _d(dvs), _d(mu), _d(u), _d(gx),
+                                   _d(gv), _d(gm))
+        return dict(x=xo, loss=float(np.sum((xo - targets) ** 2)), material=gm, forces=gF,
+                    x0=gx, v0=gv)

@@ -766,6 +766,48 @@ int rollout_store(const Problem& P, int nsteps, const double* x0, const double* 
   return st;
 }
 
+
+// Right-hand side of one adjoint solve (step 2 of the backward sweep):
+// u = mask(gv + h gx), zero on pinned rows.
+void adjoint_rhs(const Problem& P, const double* gx, const double* gv, double* u) {
+  for (int i = 0; i < P.nv; ++i)
+    for (int k = 0; k < 3; ++k)
+      u[3 * i + k] = P.pinned[i] ? 0.0 : gv[3 * i + k] + P.h * gx[3 * i + k];
+}
+
+// Steps 5-9 of one backward step of the implicit differentiation of Eq. 4, given
+// the adjoint solution mu of A(x_{s-1}) mu = u, the state x_{s-1}, the new
+// velocity v_s and the increment dv_s: accumulates the material gradient
+// (dL/dk_s, dL/dk_b, dL/dd) in gmat and replaces (gx, gv) by the gradients with
+// respect to (x_{s-1}, v_{s-1}).
+void adjoint_update(const Problem& P, const double* xp, const double* vs, const double* dvs,
+                    const double* mu, const double* u, double* gx, double* gv, double* gmat) {
+  const int n = 3 * P.nv;
+  const double h1 = P.h, h2 = P.h * P.h;
+  std::vector<double> tmp(n), tmp2(n), fh(n);
+  // 5. dL/dk_s += mu . (h f_m/k_s - h^2 (K_m/k_s) v_s)
+  internal_force(P, xp, 1.0, 0.0, fh.data());
+  stiffness_apply(P, xp, vs, 1.0, 0.0, false, tmp.data());
+  for (int k = 0; k < n; ++k) gmat[0] += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
+  // 6. dL/dk_b += mu . (h f_b/k_b - h^2 (K_b,GN/k_b) v_s)
+  internal_force(P, xp, 0.0, 1.0, fh.data());
+  stiffness_apply(P, xp, vs, 0.0, 1.0, false, tmp.data());
+  for (int k = 0; k < n; ++k) gmat[1] += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
+  // 7. dL/dd += mu . (h A_vert g - A_vert dv_s)
+  for (int i = 0; i < P.nv; ++i)
+    for (int k = 0; k < 3; ++k)
+      gmat[2] += mu[3 * i + k] * P.varea[i] * (h1 * P.grav[k] - dvs[3 * i + k]);
+  // 8. gx -= h K_exact mu + h^2 grad_x(mu^T K_sys v_s)
+  stiffness_apply(P, xp, mu, P.ks, P.kb, true, tmp.data());
+  third_contraction(P, xp, mu, vs, tmp2.data());
+  for (int k = 0; k < n; ++k) gx[k] -= h1 * tmp[k] + h2 * tmp2[k];
+  // 9. gv = mask(u - h^2 K_sys mu)
+  stiffness_apply(P, xp, mu, P.ks, P.kb, false, tmp.data());
+  for (int i = 0; i < P.nv; ++i)
+    for (int k = 0; k < 3; ++k)
+      gv[3 * i + k] = P.pinned[i] ? 0.0 : u[3 * i + k] - h2 * tmp[3 * i + k];
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -971,23 +1013,18 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
   int st = rollout_store(*P, nsteps, x0, v0, forces, X, Vv, DV, iters_fwd);
   if (st != ORC_OK && st != ORC_E_NOT_CONVERGED) return st;
 
-  std::vector<double> gx(n, 0.0), gv(n, 0.0), u(n), mu(n), K, A, tmp(n), tmp2(n), fh(n);
-  double gks = 0, gkb = 0, gd = 0;
+  std::vector<double> gx(n, 0.0), gv(n, 0.0), u(n), mu(n), K, A;
+  double gmat[3] = {0.0, 0.0, 0.0};
   int frame = nloss - 1;
-  double h1 = P->h, h2 = P->h * P->h;
   for (int s = nsteps; s >= 1; --s) {
     const double* xp = &X[(size_t)(s - 1) * n];
-    const double* vs = &Vv[(size_t)s * n];
-    const double* dvs = &DV[(size_t)s * n];
     // 1. loss gradient of frame s
     if (frame >= 0 && loss_frames[frame] == s) {
       for (int k = 0; k < n; ++k) gx[k] += dl_dx[(size_t)frame * n + k];
       --frame;
     }
     // 2. u = mask(gv + h gx)
-    for (int i = 0; i < P->nv; ++i)
-      for (int k = 0; k < 3; ++k)
-        u[3 * i + k] = P->pinned[i] ? 0.0 : gv[3 * i + k] + h1 * gx[3 * i + k];
+    adjoint_rhs(*P, gx.data(), gv.data(), u.data());
     // 3. A(x_{s-1}) mu = u  (A is symmetric)
     assemble_ksys(*P, xp, K);
     system_matrix(*P, K, A);
@@ -998,29 +1035,12 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
     if (st != ORC_OK && st != ORC_E_NOT_CONVERGED) return st;
     // 4. dL/dF_{s-1} = h mu
     if (dl_dF)
-      for (int k = 0; k < n; ++k) dl_dF[(size_t)(s - 1) * n + k] = h1 * mu[k];
-    // 5. dL/dk_s += mu . (h f_m/k_s - h^2 (K_m/k_s) v_s)
-    internal_force(*P, xp, 1.0, 0.0, fh.data());
-    stiffness_apply(*P, xp, vs, 1.0, 0.0, false, tmp.data());
-    for (int k = 0; k < n; ++k) gks += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
-    // 6. dL/dk_b += mu . (h f_b/k_b - h^2 (K_b,GN/k_b) v_s)
-    internal_force(*P, xp, 0.0, 1.0, fh.data());
-    stiffness_apply(*P, xp, vs, 0.0, 1.0, false, tmp.data());
-    for (int k = 0; k < n; ++k) gkb += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
-    // 7. dL/dd += mu . (h A_vert g - A_vert dv_s)
-    for (int i = 0; i < P->nv; ++i)
-      for (int k = 0; k < 3; ++k)
-        gd += mu[3 * i + k] * P->varea[i] * (h1 * P->grav[k] - dvs[3 * i + k]);
-    // 8. gx -= h K_exact mu + h^2 grad_x(mu^T K_sys v_s)
-    stiffness_apply(*P, xp, mu.data(), P->ks, P->kb, true, tmp.data());
-    third_contraction(*P, xp, mu.data(), vs, tmp2.data());
-    for (int k = 0; k < n; ++k) gx[k] -= h1 * tmp[k] + h2 * tmp2[k];
-    // 9. gv = mask(u - h^2 K_sys mu)
-    stiffness_apply(*P, xp, mu.data(), P->ks, P->kb, false, tmp.data());
-    for (int i = 0; i < P->nv; ++i)
-      for (int k = 0; k < 3; ++k)
-        gv[3 * i + k] = P->pinned[i] ? 0.0 : u[3 * i + k] - h2 * tmp[3 * i + k];
+      for (int k = 0; k < n; ++k) dl_dF[(size_t)(s - 1) * n + k] = P->h * mu[k];
+    // 5.-9. material, state and velocity gradients through the step
+    adjoint_update(*P, xp, &Vv[(size_t)s * n], &DV[(size_t)s * n], mu.data(), u.data(), gx.data(),
+                   gv.data(), gmat);
   }
+  double gks = gmat[0], gkb = gmat[1], gd = gmat[2];
   if (dl_dmat) {
     dl_dmat[0] = gks;
     dl_dmat[1] = gkb;
@@ -1030,6 +1050,46 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
   if (dl_dv0) std::copy(gv.begin(), gv.end(), dl_dv0);
   P->last_status = st;
   return st;
+}
+
+// Block sparsity pattern of the step matrix (CSR over vertices): rowptr [V+1], col [nnzb].
+void orc_pattern(void* h, int* rowptr, int* col) {
+  Problem* P = static_cast<Problem*>(h);
+  std::copy(P->rowptr.begin(), P->rowptr.end(), rowptr);
+  std::copy(P->col.begin(), P->col.end(), col);
+}
+
+// The step's system (Eq. 4 with Eq. 5 substituted) in the block pattern of
+// orc_pattern: A_blocks [nnzb][3][3] = M + h^2 K_sys with pinned rows and columns
+// replaced by the identity, and b [V][3]. Lets a caller solve the step by any
+// method (the exact sparse solve of the golden-file driver).
+int orc_system_blocks(void* h, const double* x, const double* v, const double* F,
+                      double* A_blocks, double* b) {
+  Problem* P = static_cast<Problem*>(h);
+  int n = 3 * P->nv;
+  std::vector<double> vm(v, v + n);
+  for (int i = 0; i < P->nv; ++i)
+    if (P->pinned[i])
+      for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
+  std::vector<double> K, A;
+  assemble_ksys(*P, x, K);
+  system_matrix(*P, K, A);
+  step_rhs(*P, x, vm.data(), F, K, b);
+  std::copy(A.begin(), A.end(), A_blocks);
+  return all_finite(b, n) && all_finite(A.data(), A.size()) ? ORC_OK : ORC_E_NONFINITE;
+}
+
+// u = mask(gv + h gx): the right-hand side of one backward step's solve.
+void orc_adjoint_rhs(void* h, const double* gx, const double* gv, double* u) {
+  adjoint_rhs(*static_cast<Problem*>(h), gx, gv, u);
+}
+
+// The rest of one backward step once mu solves A(x_{s-1}) mu = u: accumulates
+// (dL/dk_s, dL/dk_b, dL/dd) into gmat[3] and replaces (gx, gv) in place by the
+// gradients with respect to (x_{s-1}, v_{s-1}). dL/dF_{s-1} is h mu.
+void orc_adjoint_update(void* h, const double* xp, const double* vs, const double* dvs,
+                        const double* mu, const double* u, double* gx, double* gv, double* gmat) {
+  adjoint_update(*static_cast<Problem*>(h), xp, vs, dvs, mu, u, gx, gv, gmat);
 }
 
 }  // extern "C"

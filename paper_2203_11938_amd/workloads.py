@@ -220,12 +220,35 @@ def make_instances(w: Workload) -> list:
     return out
 
 
+def loss_targets(w: Workload, inst: Instance, frames, scale: float = 0.01,
+                 sheet: int = 0) -> np.ndarray:
+    """Seeded target positions [n_frames, V, 3] for the full-size parity runs: the
+    initial positions plus N(0, scale^2) m offsets per frame (stream 4, jumped ahead
+    by the sheet's index in a batch). A cheap stand-in for the scaled-material target
+    rollout, which on the largest sheets would cost as much oracle time as the
+    gradient itself."""
+    g = np.random.Generator(np.random.PCG64(1000 * w.number + 4).jumped(sheet))
+    frames = np.asarray(frames)
+    return inst.x0[None] + scale * g.normal(size=(frames.size,) + inst.x0.shape)
+
+
 def fd_directions(w: Workload, count: int, shape) -> np.ndarray:
     """Seeded unit directions for finite-difference checks."""
     g = rng(w.number, 4)
     d = g.normal(size=(count,) + tuple(shape))
     d /= np.linalg.norm(d.reshape(count, -1), axis=1).reshape((count,) + (1,) * len(shape))
     return d
+
+
+def as_given(inst: Instance, precision: str) -> Instance:
+    """The instance's inputs as a handle of the given precision receives them: an FP32
+    handle takes x0, v0 and the forces as float32, so a reference fed the same rounded
+    values sees the same problem (rest positions stay float64: sim_create takes them
+    in double)."""
+    if precision != "fp32":
+        return inst
+    q = lambda a: None if a is None else a.astype(np.float32).astype(np.float64)
+    return replace(inst, x0=q(inst.x0), v0=q(inst.v0), forces=q(inst.forces))
 
 
 def to_soa(a: np.ndarray) -> np.ndarray:

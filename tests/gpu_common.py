@@ -3,7 +3,6 @@ rollout + adjoint through the C ABI, and compute the FP64 oracle's reference."""
 
 from __future__ import annotations
 
-import dataclasses
 import functools
 
 import numpy as np
@@ -16,13 +15,7 @@ def note(msg):
     print(msg, flush=True)
 
 
-def as_given(inst, precision):
-    """The instance's inputs as the library receives them: an FP32 handle takes x0, v0
-    and the forces as float32, so both sides are fed those rounded values."""
-    if precision != "fp32":
-        return inst
-    q = lambda a: None if a is None else a.astype(np.float32).astype(np.float64)
-    return dataclasses.replace(inst, x0=q(inst.x0), v0=q(inst.v0), forces=q(inst.forces))
+as_given = W.as_given
 
 
 def make_sim(w, insts, **kw):

@@ -3,23 +3,31 @@
  *
  * What it computes (Kairanda et al., "phi-SfT", CVPR 2022, Sec. 3.1):
  *   * the deformation model S_t = PS(S_{t-1}; phi_{t-1}) (Eq. 1) with
- *     phi = {d, S, B, F_t} (Eq. 2; the wind term w is not modelled here):
- *     areal density d, stretching stiffness k_s (a scalar reduction of S),
- *     bending stiffness k_b (a scalar reduction of B) and per-step,
- *     per-vertex corrective forces F_t;
+ *     phi = {d, S, B, w, F_t} (Eq. 2): areal density d, stretching stiffness
+ *     k_s (a scalar reduction of S), bending stiffness k_b (a scalar reduction
+ *     of B), an optional wind velocity w driving an aerodynamic force (air
+ *     density fixed, Sec. 3.4; see sim_rollout) and per-step, per-vertex
+ *     corrective forces F_t;
  *   * per step one linearised backward-Euler update (Eq. 4 with the force
  *     linearisation of Eq. 5, df/dv = 0), solved for Delta v by a
- *     block-Jacobi preconditioned conjugate gradient:
- *         (M + h^2 K_sys(x_{t-1})) Delta v = h (f(x_{t-1}) + M g + F_t - h K_sys v_{t-1})
+ *     preconditioned conjugate gradient (pipelined; three-level additive
+ *     preconditioner: 3x3 block Jacobi, the rigid motions of runs of 16
+ *     vertices, and a coarse space of the rigid motions of larger aggregates;
+ *     block Jacobi alone with coarse_size = 0). A solve is accepted only on a
+ *     true residual, ||b - A Delta v||_2 <= cg_tol ||b||_2:
+ *         (M + h D + h^2 K_sys(x_{t-1})) Delta v = h (f(x_{t-1}, v_{t-1}) + M g + F_t - h K_sys v_{t-1})
  *         v_t = v_{t-1} + Delta v,   x_t = x_{t-1} + h v_t
  *     with M the lumped mass (density times a third of the incident triangle
  *     areas), f = -dE/dx for E = sum_tri area (k_s/2) |G|_F^2 (Green strain G)
  *     + sum_hinge k_b c_e (theta - theta_rest)^2, and K_sys the system
  *     stiffness (membrane Hessian, see sim_membrane_system, plus the
- *     Gauss-Newton bending Hessian 2 k_b c_e grad(theta) grad(theta)^T);
+ *     Gauss-Newton bending Hessian 2 k_b c_e grad(theta) grad(theta)^T), and
+ *     D = -df/dv the velocity Jacobian of the aerodynamic force (zero without
+ *     wind);
  *   * the adjoint of that rollout (the paper's backward pass by implicit
  *     differentiation of Eq. 4): gradients of a per-frame loss with respect to
- *     (k_s, k_b, d), the forces F_t and the initial state (x_0, v_0).
+ *     (k_s, k_b, d), the wind velocity w, the forces F_t and the initial state
+ *     (x_0, v_0).
  * Collisions (Eq. 6) are not part of this library.
  *
  * Conventions
@@ -67,7 +75,9 @@ typedef enum {
   SIM_E_MESH = -2,          /* degenerate / non-manifold / inconsistently oriented mesh */
   SIM_E_NOMEM = -3,         /* device or host allocation failed */
   SIM_E_HIP = -4,           /* HIP runtime error (text in sim_last_error) */
-  SIM_E_NOT_CONVERGED = -5, /* a CG solve stopped at cg_max_iter */
+  SIM_E_NOT_CONVERGED = -5, /* a CG solve stopped at cg_max_iter, or its recurrences kept
+                               meeting cg_tol while the true residual did not (16
+                               restarts); the rollout continues with the last iterate */
   SIM_E_INDEFINITE = -6,    /* CG breakdown: p.Ap <= 0 or a singular diagonal block */
   SIM_E_NONFINITE = -7,     /* NaN/Inf in inputs, system or state */
   SIM_E_STATE = -8          /* call out of order (e.g. adjoint without a rollout) */
@@ -152,10 +162,12 @@ typedef struct {
                                (with checkpointing, recomputed steps reuse them too),
                                else for one checkpoint segment, else not at all.      */
   int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
-                               (rows per workgroup, matrix in LDS or streamed) on the
-                               step system of the rest state and keeps the fastest;
-                               0 (default): fewest co-resident launches, then LDS-
-                               resident rows, then larger workgroups                     */
+                               (rows per workgroup; matrix rows in registers, in LDS or
+                               streamed; rows of the coarse inverse in LDS or streamed;
+                               one or two workgroups per CU) on the step system of the
+                               rest state and keeps the fastest; 0 (default): fewest
+                               co-resident launches, then the matrix homes in the order
+                               registers, LDS, streamed, then larger workgroups          */
   int32_t graph;            /* 1: sim_rollout and sim_adjoint capture their launches
                                into a HIP graph (on a stream of the handle) and launch
                                it on the caller's stream; a later call with the same
@@ -163,6 +175,14 @@ typedef struct {
                                arrays' contents may change). Ignored while solver
                                timing is on. 0 (default): direct launches              */
   int32_t matrix_home;      /* sim_matrix_home (default SIM_MATRIX_AUTO)                */
+  double air_density;       /* rho_air [kg/m^3] of the aerodynamic force (default 1, the
+                               value the paper fixes, Sec. 3.4); it acts only in
+                               rollouts given a wind velocity                           */
+  int32_t coarse_keep_all;  /* with checkpointing: 0 (default) keeps the coarse
+                               operators of one checkpoint segment (device memory
+                               bounded by checkpoint_every; recomputed steps rebuild
+                               theirs), 1 keeps every step's when they fit 16 GB (the
+                               recompute then reuses the forward's: faster, more memory) */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -174,7 +194,9 @@ typedef struct {
   int64_t cg_iters_recompute; /* forward solves repeated by checkpoint recompute */
   int64_t cg_iters_adjoint;
   int32_t cg_iters_max;       /* largest single solve */
-  double max_rel_residual;    /* largest final ||r||/||b|| of any solve */
+  double max_rel_residual;    /* largest final ||r||/||b|| of any solve (the true residual
+                                 of the last restart when a solve ends unverified; the
+                                 recursive estimate when it stops at cg_max_iter) */
   int32_t device_status;      /* sticky device status (sim_status value) */
   int32_t rows_per_block;     /* solver launch shape in use */
   int32_t blocks;             /* solver workgroups per launch */
@@ -192,11 +214,15 @@ typedef struct {
   int32_t coarse_rows_lds;    /* 1: the solver keeps its rows of the coarse inverse in LDS */
   int64_t graph_captures;     /* rollout / adjoint graphs captured (graph option) */
   int64_t graph_replays;      /* calls served by replaying a captured graph */
+  int64_t device_bytes;       /* device memory the handle holds (workspace, trajectory or
+                                 checkpoints, kept coarse operators, tables) */
+  int32_t coarse_store_slots; /* steps whose coarse operators are kept for the adjoint */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,
  * store every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
- * exact membrane Hessian, FP64 system matrix, aggregates of 64 vertices. */
+ * exact membrane Hessian, FP64 system matrix, aggregates of 64 vertices, air
+ * density 1 kg/m^3, coarse operators of one checkpoint segment kept. */
 void sim_default_options(sim_options* opt);
 
 /* Creates a handle for one sheet.
@@ -231,24 +257,35 @@ sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* con
  *                vertices keep x0 and zero velocity.
  *   forces       device [n_steps][3][V]: forces[s-1] acts in step s; NULL = none
  *   material     device double [n_instances][3]; NULL = the create-time materials
+ *   wind         device double [n_instances][3]: the wind velocity w [m/s] of each
+ *                sheet (Eq. 2's w), or NULL for no aerodynamic force. Given a wind,
+ *                every triangle t feels rho_air * area_t * |s| s n in the step's
+ *                force, n its unit normal at x_{t-1}, area_t its rest area and
+ *                s = n . (w - mean velocity of its vertices at t-1), shared equally
+ *                by its vertices; its velocity Jacobian enters the step matrix
+ *                (Eq. 4-5: A = M - h df/dv + h^2 K_sys; the position Jacobian of
+ *                this force is left out of A, so A stays symmetric)
  *   loss_frames  host int32 [n_loss], strictly increasing, each in 1..n_steps
  *   x_out        device [n_loss][3][V]: positions after each loss frame
  *   stream       hipStream_t
- * Errors: SIM_E_INVALID (n_steps outside 1..max_steps, bad frames, NULL
- * pointers), SIM_E_HIP. Device-side conditions: see sim_sync_status. */
+ * The forces, material and wind arrays are read again by the matching
+ * sim_adjoint. Errors: SIM_E_INVALID (n_steps outside 1..max_steps, bad frames,
+ * NULL pointers), SIM_E_HIP. Device-side conditions: see sim_sync_status. */
 sim_status sim_rollout(sim_t* sim, int32_t n_steps, const void* x0, const void* v0,
-                       const void* forces, const void* material, const int32_t* loss_frames,
-                       int32_t n_loss, void* x_out, void* stream);
+                       const void* forces, const void* material, const void* wind,
+                       const int32_t* loss_frames, int32_t n_loss, void* x_out, void* stream);
 
 /* Adjoint of the most recent rollout for a loss with gradient dl_dx
  * (device [n_loss][3][V], one slice per loss frame).
  *   dl_dmaterial  device double [n_instances][3] (dL/dk_s, dL/dk_b, dL/dd) or NULL
+ *   dl_dwind      device double [n_instances][3] (dL/dw) or NULL; must be NULL when
+ *                 the rollout had no wind
  *   dl_dforces    device [n_steps][3][V] or NULL
  *   dl_dx0        device [3][V] or NULL
  *   dl_dv0        device [3][V] or NULL (zero on pinned vertices)
  * Errors: SIM_E_STATE (no rollout), SIM_E_INVALID, SIM_E_HIP. */
-sim_status sim_adjoint(sim_t* sim, const void* dl_dx, void* dl_dmaterial, void* dl_dforces,
-                       void* dl_dx0, void* dl_dv0, void* stream);
+sim_status sim_adjoint(sim_t* sim, const void* dl_dx, void* dl_dmaterial, void* dl_dwind,
+                       void* dl_dforces, void* dl_dx0, void* dl_dv0, void* stream);
 
 /* Waits for the handle's last stream and returns the sticky device status
  * (SIM_OK, SIM_E_NOT_CONVERGED, SIM_E_INDEFINITE or SIM_E_NONFINITE) or a HIP

@@ -2007,7 +2007,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     }
   }
 
-  double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
+  // rr_true: the squared residual at the last (re)start, where r = b - A x exactly
+  double bnorm = 0.0, rr = 0.0, rr_true = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
   bool restart = false;
   while (ok) {
@@ -2137,10 +2138,18 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       flag = ST_NONFINITE;
       break;
     }
+    if (fresh) rr_true = rr;
     if (bnorm == 0.0) break;
     if (sqrt(rr) <= a.tol * bnorm) {
       // accept only a true residual: right after a (re)start r = b - A x exactly
-      if (fresh || restarts >= kMaxRestarts) break;
+      if (fresh) break;
+      if (restarts >= kMaxRestarts) {
+        // the recurrences keep meeting the tolerance while the true residual does
+        // not: stop unverified, reporting the last true residual
+        flag = ST_NOT_CONVERGED;
+        rr = rr_true;
+        break;
+      }
       restart = true;
       continue;
     }
@@ -2182,9 +2191,15 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     const double denom = fresh ? delta : delta - beta * gamma / alpha_prev;
     if (!(denom > 0.0)) {
       // Right after a (re)start denom = u^T A u: A is not positive definite. Later, the
-      // recurrences have drifted (rounding): restart them from the true residual.
-      if (fresh || restarts >= kMaxRestarts) {
+      // recurrences have drifted (rounding): restart them from the true residual, unless
+      // the restarts are used up (then the solve ends unverified).
+      if (fresh) {
         flag = ST_INDEFINITE;
+        break;
+      }
+      if (restarts >= kMaxRestarts) {
+        flag = ST_NOT_CONVERGED;
+        rr = rr_true;
         break;
       }
       restart = true;

@@ -43,8 +43,11 @@ struct sim_s {
   int cg_max_iter = 20000;
   int ckpt = 0;
   int max_steps = 0;
+  double rho_air = 1.0;      // air density of the aerodynamic force
+  bool coarse_keep_all = false;
 
   std::vector<void*> allocs;
+  size_t dev_bytes = 0;      // device memory held by the handle
   Mesh mesh{};
   Elem el{};
   SolverPlan plan{};
@@ -87,6 +90,7 @@ struct sim_s {
   std::vector<int> frames;
   const void* forces = nullptr;
   const double* material = nullptr;
+  const double* wind = nullptr;   // [ninst][3] wind velocity, or nullptr: no aerodynamic force
   hipStream_t stream = nullptr;
 
   // HIP graphs of the last rollout and adjoint (graph option): replayed when a call
@@ -145,6 +149,7 @@ sim_status upload(sim_t* s, const std::vector<V>& h, const V** out) {
   size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(V);
   HIPCHECK(s, hipMalloc(&d, bytes));
   s->allocs.push_back(d);
+  s->dev_bytes += bytes;
   if (!h.empty()) HIPCHECK(s, hipMemcpy(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
   *out = static_cast<const V*>(d);
   return SIM_OK;
@@ -154,6 +159,7 @@ sim_status alloc(sim_t* s, size_t bytes, void** out) {
   void* d = nullptr;
   HIPCHECK(s, hipMalloc(&d, std::max<size_t>(bytes, 8)));
   s->allocs.push_back(d);
+  s->dev_bytes += std::max<size_t>(bytes, 8);
   *out = d;
   return SIM_OK;
 }
@@ -329,7 +335,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       (o.matrix_precision != SIM_FP32 && o.matrix_precision != SIM_FP64) ||
       !(o.coarse_size == 0 || (o.coarse_size >= 16 && o.coarse_size <= (1 << 20))) ||
       (o.autotune != 0 && o.autotune != 1) || (o.graph != 0 && o.graph != 1) ||
-      o.matrix_home < SIM_MATRIX_AUTO || o.matrix_home > SIM_MATRIX_REGISTERS) {
+      o.matrix_home < SIM_MATRIX_AUTO || o.matrix_home > SIM_MATRIX_REGISTERS ||
+      !(o.air_density >= 0.0) || !std::isfinite(o.air_density) ||
+      (o.coarse_keep_all != 0 && o.coarse_keep_all != 1)) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
@@ -344,6 +352,8 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->cg_max_iter = o.cg_max_iter;
   s->ckpt = o.checkpoint_every;
   s->max_steps = o.max_steps;
+  s->rho_air = o.air_density;
+  s->coarse_keep_all = o.coarse_keep_all != 0;
 
   int rc = build_layout(sheets, o.coarse_size, kCoarseMaxAggs, s->L, s->err);
   if (rc != 0) return rc == -1 ? SIM_E_INVALID : SIM_E_MESH;
@@ -575,14 +585,16 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
     TRY(alloc(s, 3 * nv * 8, &q)); cs.mid_crel = (double*)q;
     TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;
-    // one slot per step when they fit the cap (the adjoint, and with checkpointing the
-    // recomputed steps too, then reuse the forward's operators), else one per step of
-    // a checkpoint segment (the recomputed steps rebuild them, the adjoint reuses
-    // those), else none (every step rebuilds)
+    // Store-all: one slot per step when they fit the cap (the adjoint reuses the
+    // forward's operators). With checkpointing: one per step of a checkpoint segment
+    // (memory bounded by the interval; the recomputed steps rebuild theirs, the adjoint
+    // reuses those), or, with coarse_keep_all, one per step when they fit (the
+    // recompute reuses the forward's too). Else none (every step rebuilds).
     const double slot_bytes =
         4.0 * (double)L.coarse_doubles + 8.0 * (6.0 * nv + 36.0 * L.nmid) + 4.0 * ni;
     int want = s->max_steps;
-    if (want * slot_bytes > kCoarseStoreCap && s->ckpt > 0) want = s->ckpt;
+    if (s->ckpt > 0 && (!s->coarse_keep_all || want * slot_bytes > kCoarseStoreCap))
+      want = std::min(s->ckpt, s->max_steps);
     if (want * slot_bytes <= kCoarseStoreCap) {
       s->cslots = want;
       TRY(alloc(s, (size_t)want * L.coarse_doubles * 4, &q)); s->cmat_store = (float*)q;
@@ -638,6 +650,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   s->stats.nnz_blocks = nnzb;
   s->stats.coarse_aggregates = L.nagg;
   s->stats.coarse_max_dim = L.max_nc;
+  s->stats.coarse_store_slots = s->cslots;
   return SIM_OK;
 }
 
@@ -910,6 +923,8 @@ void sim_default_options(sim_options* o) {
   o->matrix_precision = SIM_FP64;
   o->coarse_size = 64;
   o->matrix_home = SIM_MATRIX_AUTO;
+  o->air_density = 1.0;
+  o->coarse_keep_all = 0;
 }
 
 sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,
@@ -961,8 +976,8 @@ sim_status sim_create(const sim_mesh* mesh, const double* rest_pos, const int32_
 }
 
 sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0,
-                       const void* forces, const void* material, const int32_t* loss_frames,
-                       int32_t n_loss, void* x_out, void* stream) {
+                       const void* forces, const void* material, const void* wind,
+                       const int32_t* loss_frames, int32_t n_loss, void* x_out, void* stream) {
   if (!s) return SIM_E_INVALID;
   if (n_steps < 1 || n_steps > s->max_steps || !x0 || n_loss < 0 || (n_loss > 0 && (!loss_frames || !x_out))) {
     s->err = "invalid rollout arguments";
@@ -979,11 +994,17 @@ sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0
   s->have_rollout = false;
   s->n_steps = n_steps;
   s->frames.assign(loss_frames, loss_frames + n_loss);
+  if (wind) {
+    s->err = "wind is not supported by this build";
+    return SIM_E_INVALID;
+  }
   s->forces = forces;
   s->material = material ? static_cast<const double*>(material) : s->mat_default;
+  s->wind = static_cast<const double*>(wind);
   s->stream = static_cast<hipStream_t>(stream);
   std::vector<uintptr_t> key = {(uintptr_t)n_steps, (uintptr_t)x0, (uintptr_t)v0,
-                                (uintptr_t)forces, (uintptr_t)s->material, (uintptr_t)x_out};
+                                (uintptr_t)forces, (uintptr_t)s->material, (uintptr_t)wind,
+                                (uintptr_t)x_out};
   key.insert(key.end(), s->frames.begin(), s->frames.end());
   const sim_status st = graphed(s, s->gfwd, key, s->stream, [&](hipStream_t q) {
     if (s->prec == SIM_FP64)
@@ -996,12 +1017,16 @@ sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0
   return st;
 }
 
-sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl_dforces,
-                       void* dl_dx0, void* dl_dv0, void* stream) {
+sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl_dwind,
+                       void* dl_dforces, void* dl_dx0, void* dl_dv0, void* stream) {
   if (!s) return SIM_E_INVALID;
   if (!s->have_rollout) {
     s->err = "sim_adjoint needs a preceding sim_rollout";
     return SIM_E_STATE;
+  }
+  if (dl_dwind && !s->wind) {
+    s->err = "dl_dwind needs a rollout with a wind velocity";
+    return SIM_E_INVALID;
   }
   if (!s->frames.empty() && !dl_dx) {
     s->err = "dl_dx is required when the rollout has loss frames";
@@ -1009,8 +1034,8 @@ sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl
   }
   s->stream = static_cast<hipStream_t>(stream);
   // the adjoint reads the rollout's states, forces and material: its key includes them
-  std::vector<uintptr_t> key = {(uintptr_t)dl_dx, (uintptr_t)dl_dmaterial, (uintptr_t)dl_dforces,
-                                (uintptr_t)dl_dx0, (uintptr_t)dl_dv0};
+  std::vector<uintptr_t> key = {(uintptr_t)dl_dx, (uintptr_t)dl_dmaterial, (uintptr_t)dl_dwind,
+                                (uintptr_t)dl_dforces, (uintptr_t)dl_dx0, (uintptr_t)dl_dv0};
   key.insert(key.end(), s->gfwd.key.begin(), s->gfwd.key.end());
   return graphed(s, s->gadj, key, s->stream, [&](hipStream_t q) {
     if (s->prec == SIM_FP64)
@@ -1094,6 +1119,7 @@ sim_status sim_get_stats(const sim_t* s, sim_stats* out) {
   *out = s->stats;
   out->graph_captures = s->graph_captures;
   out->graph_replays = s->graph_replays;
+  out->device_bytes = (int64_t)s->dev_bytes;
   return SIM_OK;
 }
 

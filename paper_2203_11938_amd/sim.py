@@ -12,7 +12,9 @@ float64 ``[n_instances, 3]`` = (k_s, k_b, d).
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import os
+import warnings
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -20,8 +22,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# PHISFT_SIM_LIB selects another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("PHISFT_SIM_LIB") or os.path.join(HERE, "libphisft_sim.so")
+LIB_PATH = os.path.join(HERE, "libphisft_sim.so")
 
 SIM_OK = 0
 SIM_E_INVALID = -1
@@ -65,7 +66,8 @@ class _Options(ctypes.Structure):
                 ("rows_per_block", ctypes.c_int32), ("membrane_system", ctypes.c_int32),
                 ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("matrix_home", ctypes.c_int32)]
+                ("matrix_home", ctypes.c_int32), ("air_density", ctypes.c_double),
+                ("coarse_keep_all", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -80,7 +82,8 @@ class _Stats(ctypes.Structure):
                 ("coarse_max_dim", ctypes.c_int32), ("autotuned", ctypes.c_int32),
                 ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double),
                 ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32),
-                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("coarse_store_slots", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,8 +114,8 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(ctypes.POINTER(i32)), ctypes.POINTER(i32),
                                    ctypes.POINTER(_Material), ctypes.c_double,
                                    ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
-        "sim_rollout": (i32, [vp, i32, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp, vp]),
-        "sim_adjoint": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "sim_rollout": (i32, [vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp, vp]),
+        "sim_adjoint": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "sim_sync_status": (i32, [vp]),
         "sim_set_timing": (i32, [vp, i32]),
         "sim_get_stats": (i32, [vp, ctypes.POINTER(_Stats)]),
@@ -128,6 +131,14 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def library_identity(path: str = LIB_PATH) -> dict:
+    """Path and content hash of the library this process loads (recorded by the
+    benchmark so that a measurement names the exact build it ran)."""
+    with open(path, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    return dict(path=os.path.relpath(path, os.path.dirname(HERE)), sha256_16=digest)
 
 
 def status_name(code: int) -> str:
@@ -166,7 +177,10 @@ class Simulator:
     creation and keeps the fastest; ``graph`` captures rollout and adjoint into HIP
     graphs that later calls with the same arrays replay; ``matrix_home`` pins where
     the solver keeps its matrix rows ("streamed", "lds" or "registers"; None: the
-    library's choice).
+    library's choice); ``air_density`` is the aerodynamic force's rho_air [kg/m^3]
+    (acting in rollouts given a wind velocity); ``coarse_keep_all`` keeps every
+    step's coarse operators under checkpointing (faster, memory not bounded by the
+    checkpoint interval).
     """
 
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
@@ -174,7 +188,8 @@ class Simulator:
                  max_steps: int = 1000, gravity=(0.0, 0.0, -9.81), rows_per_block: int = 0,
                  membrane: str = "exact", matrix_precision: str = "fp64",
                  coarse_size: Optional[int] = None, autotune: bool = False,
-                 graph: bool = False, matrix_home: Optional[str] = None):
+                 graph: bool = False, matrix_home: Optional[str] = None,
+                 air_density: float = 1.0, coarse_keep_all: bool = False):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -195,6 +210,8 @@ class Simulator:
             opt.coarse_size = coarse_size
         opt.autotune = 1 if autotune else 0
         opt.graph = 1 if graph else 0
+        opt.air_density = air_density
+        opt.coarse_keep_all = 1 if coarse_keep_all else 0
         if matrix_home is not None:
             if matrix_home not in MATRIX_HOMES[1:]:
                 raise ValueError(f"matrix_home must be one of {MATRIX_HOMES[1:]}")
@@ -236,6 +253,11 @@ class Simulator:
         self.max_steps = max_steps
         self.n_steps = 0
         self.n_loss = 0
+        # rollouts run on this handle so far: the autograd path checks that a backward
+        # pass still refers to the rollout of its own forward pass
+        self.generation = 0
+        # ClothRollout: accept SIM_E_NOT_CONVERGED (with a warning) instead of raising
+        self.allow_not_converged = False
 
     def close(self):
         if self._h is not None:
@@ -265,8 +287,11 @@ class Simulator:
 
     def rollout(self, n_steps: int, x0: torch.Tensor, v0: Optional[torch.Tensor] = None,
                 forces: Optional[torch.Tensor] = None, material: Optional[torch.Tensor] = None,
-                loss_frames: Optional[Sequence[int]] = None, x_out: Optional[torch.Tensor] = None):
-        """Run ``n_steps`` steps. Returns positions at the loss frames [n_loss, 3, V]."""
+                loss_frames: Optional[Sequence[int]] = None, x_out: Optional[torch.Tensor] = None,
+                wind: Optional[torch.Tensor] = None):
+        """Run ``n_steps`` steps. Returns positions at the loss frames [n_loss, 3, V].
+        ``wind`` [n_instances, 3] float64 is each sheet's wind velocity (None: no
+        aerodynamic force)."""
         V = self.n_verts
         frames = np.arange(1, n_steps + 1, dtype=np.int32) if loss_frames is None else \
             np.ascontiguousarray(loss_frames, dtype=np.int32)
@@ -274,27 +299,32 @@ class Simulator:
         self._need(v0, (3, V), "v0")
         self._need(forces, (n_steps, 3, V), "forces")
         self._need(material, (self.n_instances, 3), "material", torch.float64)
+        self._need(wind, (self.n_instances, 3), "wind", torch.float64)
         if x_out is None:
             x_out = torch.empty((frames.size, 3, V), dtype=self.dtype, device=x0.device)
         self._need(x_out, (frames.size, 3, V), "x_out")
         st = self._lib.sim_rollout(self._h, int(n_steps), _ptr(x0), _ptr(v0), _ptr(forces),
-                                   _ptr(material),
+                                   _ptr(material), _ptr(wind),
                                    frames.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                    int(frames.size), _ptr(x_out), _stream())
         self._check(st, "sim_rollout")
         # the adjoint re-reads these; keep them alive
-        self._keep = (forces, material)
+        self._keep = (forces, material, wind)
+        self.has_wind = wind is not None
         self.n_steps = n_steps
         self.n_loss = int(frames.size)
         self.loss_frames = frames
+        self.generation += 1
         return x_out
 
     def adjoint(self, dl_dx: torch.Tensor, want_forces: bool = True, want_x0: bool = True,
-                want_v0: bool = True, want_material: bool = True, out: Optional[dict] = None):
+                want_v0: bool = True, want_material: bool = True, out: Optional[dict] = None,
+                want_wind: Optional[bool] = None):
         """Gradients of the loss whose frame gradients are ``dl_dx`` [n_loss, 3, V].
 
-        ``out`` may hold preallocated result tensors (keys material, forces, x0, v0);
-        passing the same ones on every call lets a graph-mode handle replay."""
+        ``out`` may hold preallocated result tensors (keys material, wind, forces, x0,
+        v0); passing the same ones on every call lets a graph-mode handle replay. The
+        wind gradient is returned when the rollout had a wind (``want_wind`` None)."""
         V = self.n_verts
         self._need(dl_dx, (self.n_loss, 3, V), "dl_dx")
         dev = dl_dx.device
@@ -308,13 +338,16 @@ class Simulator:
             self._need(t, shape, key, dtype)
             return t
         g_mat = buf("material", want_material, (self.n_instances, 3), torch.float64)
+        if want_wind is None:
+            want_wind = getattr(self, "has_wind", False)
+        g_w = buf("wind", want_wind, (self.n_instances, 3), torch.float64)
         g_F = buf("forces", want_forces, (self.n_steps, 3, V), self.dtype)
         g_x0 = buf("x0", want_x0, (3, V), self.dtype)
         g_v0 = buf("v0", want_v0, (3, V), self.dtype)
-        st = self._lib.sim_adjoint(self._h, _ptr(dl_dx), _ptr(g_mat), _ptr(g_F), _ptr(g_x0),
-                                   _ptr(g_v0), _stream())
+        st = self._lib.sim_adjoint(self._h, _ptr(dl_dx), _ptr(g_mat), _ptr(g_w), _ptr(g_F),
+                                   _ptr(g_x0), _ptr(g_v0), _stream())
         self._check(st, "sim_adjoint")
-        return dict(material=g_mat, forces=g_F, x0=g_x0, v0=g_v0)
+        return dict(material=g_mat, wind=g_w, forces=g_F, x0=g_x0, v0=g_v0)
 
     def sync(self, allow_not_converged: bool = False) -> int:
         """Wait for the stream; raise on a sticky device error."""
@@ -351,35 +384,56 @@ class Simulator:
         return f.reshape(self.n_steps, self.n_instances), a.reshape(self.n_steps, self.n_instances)
 
 
+def _sync_checked(sim: Simulator, what: str):
+    st = sim.sync(allow_not_converged=sim.allow_not_converged)
+    if st == SIM_E_NOT_CONVERGED:
+        warnings.warn(f"{what}: a CG solve did not converge (cg_max_iter or unverified "
+                      "residual); results use the last iterate", RuntimeWarning)
+
+
 class ClothRollout(torch.autograd.Function):
-    """Differentiable rollout: (material, forces, x0, v0) -> positions at the loss frames.
+    """Differentiable rollout: (material, forces, x0, v0, wind) -> positions at the loss
+    frames.
 
     User-facing layout is vertex-major: forces [n_steps, V, 3], x0/v0 [V, 3],
-    output [n_loss, V, 3]; material [n_instances, 3] float64. The backward pass
-    is the library's adjoint; double backward is not supported.
+    output [n_loss, V, 3]; material and wind [n_instances, 3] float64 (wind None:
+    no aerodynamic force). The backward pass is the library's adjoint of the
+    handle's most recent rollout, so it raises if another rollout ran on the same
+    handle in between; a solve that did not converge raises too unless
+    ``sim.allow_not_converged`` is set (then it warns). Double backward is not
+    supported.
     """
 
     @staticmethod
-    def forward(ctx, sim: Simulator, n_steps: int, loss_frames, material, forces, x0, v0):
+    def forward(ctx, sim: Simulator, n_steps: int, loss_frames, material, forces, x0, v0,
+                wind=None):
         soa = lambda t: None if t is None else t.transpose(-1, -2).contiguous()
         xo = sim.rollout(n_steps, soa(x0), soa(v0), soa(forces), material.contiguous(),
-                         loss_frames)
-        sim.sync(allow_not_converged=True)
+                         loss_frames, wind=None if wind is None else wind.contiguous())
+        _sync_checked(sim, "rollout")
         ctx.sim = sim
+        ctx.generation = sim.generation
         ctx.has_forces = forces is not None
         ctx.has_v0 = v0 is not None
+        ctx.has_wind = wind is not None
         return xo.transpose(-1, -2).contiguous()
 
     @staticmethod
     def backward(ctx, g):
         sim = ctx.sim
-        r = sim.adjoint(g.transpose(-1, -2).contiguous(), want_forces=ctx.has_forces)
-        sim.sync(allow_not_converged=True)
+        if sim.generation != ctx.generation:
+            raise RuntimeError("the simulator handle has run another rollout since this "
+                               "forward pass; its adjoint would belong to that rollout "
+                               "(use one handle per pending backward pass)")
+        r = sim.adjoint(g.transpose(-1, -2).contiguous(), want_forces=ctx.has_forces,
+                        want_wind=ctx.has_wind)
+        _sync_checked(sim, "adjoint")
         aos = lambda t: None if t is None else t.transpose(-1, -2).contiguous()
         return (None, None, None, r["material"], aos(r["forces"]), aos(r["x0"]),
-                aos(r["v0"]) if ctx.has_v0 else None)
+                aos(r["v0"]) if ctx.has_v0 else None, r["wind"] if ctx.has_wind else None)
 
 
-def rollout(sim: Simulator, n_steps: int, material, x0, v0=None, forces=None, loss_frames=None):
+def rollout(sim: Simulator, n_steps: int, material, x0, v0=None, forces=None, loss_frames=None,
+            wind=None):
     """Differentiable rollout through the library (see ClothRollout)."""
-    return ClothRollout.apply(sim, n_steps, loss_frames, material, forces, x0, v0)
+    return ClothRollout.apply(sim, n_steps, loss_frames, material, forces, x0, v0, wind)

@@ -159,7 +159,8 @@ def test_one_step_and_no_loss_frames():
     g = s.adjoint(xo.clone())
     s.sync()
     for k, v in g.items():
-        assert torch.count_nonzero(v).item() == 0, k
+        if v is not None:
+            assert torch.count_nonzero(v).item() == 0, k
 
 
 def test_fp32_stored_matrix():

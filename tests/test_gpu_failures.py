@@ -1,0 +1,123 @@
+"""Failure handling of the library on the GPU, each condition forced from the host so
+that every kernel still exits normally: non-finite input forces, a solve capped at
+one iteration, a tolerance below FP64 rounding (the solver's restart cap), a negative
+stretching stiffness (an indefinite step matrix), and calls out of order. The status
+the caller sees is checked, and that the handle keeps working afterwards."""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import make_sim, note
+from paper_2203_11938_amd import sim as S, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def small(steps=5, **kw):
+    w = W.workload("C1", steps=steps, forces="gauss")
+    inst = W.make_instances(w)[0]
+    return w, inst, make_sim(w, [inst], **kw)
+
+
+def tensors(s, inst, w):
+    import torch
+    dev = torch.device("cuda:0")
+    x0 = torch.tensor(W.to_soa(inst.x0), dtype=s.dtype, device=dev)
+    F = torch.tensor(W.to_soa(inst.forces), dtype=s.dtype, device=dev)
+    return x0, F
+
+
+def test_nonfinite_forces_then_recovery():
+    w, inst, s = small()
+    x0, F = tensors(s, inst, w)
+    bad = F.clone()
+    bad[2, 1, 7] = float("nan")
+    note("failure: a NaN in the forces of step 3")
+    s.rollout(w.steps, x0, None, bad)
+    assert s.status() == S.SIM_E_NONFINITE
+    # the handle stays valid: a clean rollout afterwards reports success
+    xo = s.rollout(w.steps, x0, None, F)
+    assert s.status() == S.SIM_OK
+    assert np.isfinite(xo.cpu().numpy()).all()
+    s.close()
+
+
+def test_cg_capped_at_one_iteration_completes_rollout():
+    w, inst, s = small(cg_max_iter=1)
+    x0, F = tensors(s, inst, w)
+    xo = s.rollout(w.steps, x0, None, F)
+    st = s.status()
+    note(f"failure: cg_max_iter = 1 gives status {S.status_name(st)}")
+    assert st == S.SIM_E_NOT_CONVERGED
+    assert np.isfinite(xo.cpu().numpy()).all()
+    g = s.adjoint((xo - x0[None]).contiguous())
+    assert s.status() == S.SIM_E_NOT_CONVERGED
+    assert all(np.isfinite(v.cpu().numpy()).all() for v in g.values() if v is not None)
+    s.close()
+
+
+def test_unreachable_tolerance_ends_unverified():
+    """A tolerance below FP64 rounding: the recursive residual keeps meeting it while
+    the true residual cannot, so after the restart cap the solve ends unverified and
+    is reported as not converged, with the last true residual (above the tolerance)."""
+    w, inst, s = small(steps=2, cg_tol=1e-19, cg_max_iter=20000)
+    x0, F = tensors(s, inst, w)
+    xo = s.rollout(w.steps, x0, None, F)
+    st = s.status()
+    stats = s.stats()
+    note(f"failure: tol 1e-19 gives {S.status_name(st)}, largest solve "
+         f"{stats['cg_iters_max']} iterations, reported residual {stats['max_rel_residual']:.2e}")
+    assert st == S.SIM_E_NOT_CONVERGED
+    assert stats["cg_iters_max"] < 20000        # ended by the restart cap, not the iteration cap
+    assert stats["max_rel_residual"] > 1e-19
+    assert np.isfinite(xo.cpu().numpy()).all()
+    s.close()
+
+
+def test_negative_stiffness_is_indefinite_in_library_and_oracle():
+    """k_s < 0 makes the membrane block negative: with in-plane loads only (no
+    gravity), the first preconditioned direction already has u^T A u < 0."""
+    import dataclasses
+    import torch
+    w, inst, s = small(steps=2, gravity=(0.0, 0.0, 0.0))
+    forces = 100.0 * inst.forces
+    forces[:, :, 2] = 0.0
+    inst = dataclasses.replace(inst, forces=forces)
+    x0, F = tensors(s, inst, w)
+    mat = torch.tensor([[-1e3, 1e-4, 0.1]], dtype=torch.float64, device=x0.device)
+    s.rollout(w.steps, x0, None, F, mat)
+    st = s.status()
+    o = oracle.Oracle(inst.tris, inst.rest, inst.pins, -1e3, 1e-4, 0.1, dt=w.dt,
+                      gravity=(0.0, 0.0, 0.0), cg_tol=1e-10)
+    _, _, _, ost = o.rollout(w.steps, inst.x0, None, inst.forces, check=False)
+    note(f"failure: k_s = -1e3 gives {S.status_name(st)} (oracle status {ost})")
+    assert st == S.SIM_E_INDEFINITE
+    assert ost == oracle.ORC_E_INDEFINITE
+    xo = s.rollout(w.steps, x0, None, F)
+    assert s.status() == S.SIM_OK
+    s.close()
+
+
+def test_calls_out_of_order_on_a_live_handle():
+    import ctypes
+    w, inst, s = small(steps=2)
+    lib = S.load_library()
+    # adjoint before any rollout
+    assert lib.sim_adjoint(s._h, None, None, None, None, None, None, None) == S.SIM_E_STATE
+    x0, F = tensors(s, inst, w)
+    xo = s.rollout(w.steps, x0, None, F)
+    assert s.status() == S.SIM_OK
+    g = xo.clone()
+    # a wind gradient for a rollout without wind
+    import torch
+    gw = torch.zeros((1, 3), dtype=torch.float64, device=x0.device)
+    assert lib.sim_adjoint(s._h, ctypes.c_void_p(g.data_ptr()), None,
+                           ctypes.c_void_p(gw.data_ptr()), None, None, None,
+                           None) == S.SIM_E_INVALID
+    # loss frames out of order
+    frames = np.array([2, 1], np.int32)
+    with pytest.raises(S.SimError) as e:
+        s.rollout(w.steps, x0, None, F, loss_frames=frames)
+    assert e.value.code == S.SIM_E_INVALID
+    s.close()

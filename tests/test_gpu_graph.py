@@ -26,7 +26,7 @@ def _run(s, steps, x0, F, x_out, dl, outs):
     s.rollout(steps, x0, None, F, x_out=x_out)
     g = s.adjoint(dl, out=outs)
     s.sync()
-    return x_out.cpu().numpy().copy(), {k: v.cpu().numpy().copy() for k, v in g.items()}
+    return x_out.cpu().numpy().copy(), {k: v.cpu().numpy().copy() for k, v in g.items() if v is not None}
 
 
 @pytest.mark.parametrize("checkpoint", [0, 7])

@@ -59,8 +59,9 @@ def test_adjoint_before_rollout_and_bad_arguments_without_gpu():
     from paper_2203_11938_amd import sim
     lib = sim.load_library()
     # NULL handles and out-of-order calls are rejected before any device work
-    assert lib.sim_adjoint(None, None, None, None, None, None, None) == sim.SIM_E_INVALID
-    assert lib.sim_rollout(None, 1, None, None, None, None, None, 0, None, None) == sim.SIM_E_INVALID
+    assert lib.sim_adjoint(None, None, None, None, None, None, None, None) == sim.SIM_E_INVALID
+    assert lib.sim_rollout(None, 1, None, None, None, None, None, None, 0, None,
+                           None) == sim.SIM_E_INVALID
     h = ctypes.c_void_p()
     assert lib.sim_create(None, None, None, 0, None, 0.01, None, ctypes.byref(h)) == sim.SIM_E_INVALID
     assert not h.value
@@ -89,3 +90,52 @@ def test_matrix_home_option_without_gpu():
                               None, 0, ctypes.byref(mat), 0.01, ctypes.byref(opt),
                               ctypes.byref(h)) == sim.SIM_E_INVALID
         assert not h.value
+
+
+def _create(lib, sim, tris, rest, pins=None, material=(1.0, 1.0, 1.0), **opts):
+    """sim_create through the C ABI with host arrays; returns (status, handle)."""
+    import numpy as np
+    tris = np.ascontiguousarray(tris, np.int32)
+    rest = np.ascontiguousarray(rest, np.float64)
+    mesh = sim._Mesh()
+    mesh.n_verts, mesh.n_tris = rest.shape[0], tris.shape[0]
+    mesh.tris = tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    mat = sim._Material()
+    mat.stretch, mat.bend, mat.density = material
+    opt = sim._Options()
+    lib.sim_default_options(ctypes.byref(opt))
+    for k, v in opts.items():
+        setattr(opt, k, v)
+    p = None
+    n = 0
+    if pins is not None:
+        pins = np.ascontiguousarray(pins, np.int32)
+        p = pins.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        n = pins.size
+    h = ctypes.c_void_p()
+    st = lib.sim_create(ctypes.byref(mesh), rest.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        p, n, ctypes.byref(mat), 0.01, ctypes.byref(opt), ctypes.byref(h))
+    return st, h
+
+
+def test_create_time_failures_without_gpu():
+    """Mesh and argument errors are found on the host, before any device work: a rest
+    triangle of zero area (SIM_E_MESH), a pin index outside the mesh and a negative
+    air density (SIM_E_INVALID); no handle is returned."""
+    import numpy as np
+    from paper_2203_11938_amd import sim, workloads as W
+    lib = sim.load_library()
+    rest, tris = W.grid_sheet(3)
+    flat = rest.copy()
+    flat[4] = 0.5 * (flat[3] + flat[5])   # the two triangles on the middle row's left
+    flat[[0, 1, 2], 1] = flat[3, 1]        # lie on one line: zero area
+    st, h = _create(lib, sim, tris, flat)
+    assert st == sim.SIM_E_MESH and not h.value
+    st, h = _create(lib, sim, tris, rest, pins=[0, 9])
+    assert st == sim.SIM_E_INVALID and not h.value
+    st, h = _create(lib, sim, tris, rest, pins=[-1])
+    assert st == sim.SIM_E_INVALID and not h.value
+    st, h = _create(lib, sim, tris, rest, air_density=-1.0)
+    assert st == sim.SIM_E_INVALID and not h.value
+    st, h = _create(lib, sim, np.array([[0, 1, 1]]), rest)
+    assert st == sim.SIM_E_MESH and not h.value

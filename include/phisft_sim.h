@@ -77,7 +77,8 @@ typedef enum {
   SIM_E_HIP = -4,           /* HIP runtime error (text in sim_last_error) */
   SIM_E_NOT_CONVERGED = -5, /* a CG solve stopped at cg_max_iter, or its recurrences kept
                                meeting cg_tol while the true residual did not (16
-                               restarts); the rollout continues with the last iterate */
+                               restarts, then a final check of the true residual); the
+                               rollout continues with the last iterate */
   SIM_E_INDEFINITE = -6,    /* CG breakdown: p.Ap <= 0 or a singular diagonal block */
   SIM_E_NONFINITE = -7,     /* NaN/Inf in inputs, system or state */
   SIM_E_STATE = -8          /* call out of order (e.g. adjoint without a rollout) */
@@ -194,9 +195,9 @@ typedef struct {
   int64_t cg_iters_recompute; /* forward solves repeated by checkpoint recompute */
   int64_t cg_iters_adjoint;
   int32_t cg_iters_max;       /* largest single solve */
-  double max_rel_residual;    /* largest final ||r||/||b|| of any solve (the true residual
-                                 of the last restart when a solve ends unverified; the
-                                 recursive estimate when it stops at cg_max_iter) */
+  double max_rel_residual;    /* largest final ||r||/||b|| of any solve (the true
+                                 residual ||b - A Delta v|| unless a solve stopped at
+                                 cg_max_iter: then the recursive estimate) */
   int32_t device_status;      /* sticky device status (sim_status value) */
   int32_t rows_per_block;     /* solver launch shape in use */
   int32_t blocks;             /* solver workgroups per launch */

@@ -1463,6 +1463,7 @@ __device__ __forceinline__ void spmv_reg(const TM (&Ar)[kRegRowBlocks][9],
               (double)Ar[k][r * 3 + 2] * g[2][k];
 }
 
+// Restarts from the true residual per solve; one more verifies the final iterate.
 constexpr int kMaxRestarts = 16;
 
 // Preconditioned pipelined CG (Ghysels & Vanroose 2014) from x = 0: one global
@@ -2007,8 +2008,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     }
   }
 
-  // rr_true: the squared residual at the last (re)start, where r = b - A x exactly
-  double bnorm = 0.0, rr = 0.0, rr_true = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
+  double bnorm = 0.0, rr = 0.0, gamma_prev = 1.0, alpha_prev = 1.0;
   int it = 0, flag = 0, fresh = 1, restarts = 0;
   bool restart = false;
   while (ok) {
@@ -2138,20 +2138,19 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       flag = ST_NONFINITE;
       break;
     }
-    if (fresh) rr_true = rr;
     if (bnorm == 0.0) break;
     if (sqrt(rr) <= a.tol * bnorm) {
       // accept only a true residual: right after a (re)start r = b - A x exactly
       if (fresh) break;
-      if (restarts >= kMaxRestarts) {
-        // the recurrences keep meeting the tolerance while the true residual does
-        // not: stop unverified, reporting the last true residual
-        flag = ST_NOT_CONVERGED;
-        rr = rr_true;
-        break;
-      }
       restart = true;
       continue;
+    }
+    if (fresh && restarts > kMaxRestarts) {
+      // the restart after the last allowed one verified x and found it short of the
+      // tolerance (the recurrences kept meeting it while the true residual did not):
+      // stop, reporting that true residual
+      flag = ST_NOT_CONVERGED;
+      break;
     }
     if (it >= a.max_iter) {
       flag = ST_NOT_CONVERGED;
@@ -2191,15 +2190,10 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     const double denom = fresh ? delta : delta - beta * gamma / alpha_prev;
     if (!(denom > 0.0)) {
       // Right after a (re)start denom = u^T A u: A is not positive definite. Later, the
-      // recurrences have drifted (rounding): restart them from the true residual, unless
-      // the restarts are used up (then the solve ends unverified).
+      // recurrences have drifted (rounding): restart them from the true residual (past
+      // the restart cap, that restart ends the solve unless it meets the tolerance).
       if (fresh) {
         flag = ST_INDEFINITE;
-        break;
-      }
-      if (restarts >= kMaxRestarts) {
-        flag = ST_NOT_CONVERGED;
-        rr = rr_true;
         break;
       }
       restart = true;
@@ -2572,6 +2566,7 @@ __global__ void k_fill_double(double* p, long n, double v) {
 
 // --------------------------------------------------------------- launchers
 static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
+
 
 void launch_fill_int(int* p, int n, int v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);

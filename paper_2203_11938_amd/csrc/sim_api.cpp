@@ -86,6 +86,7 @@ struct sim_s {
 
   // most recent rollout
   bool have_rollout = false;
+  bool have_adjoint = false;   // an adjoint ran since that rollout (its statistics count)
   int n_steps = 0;
   std::vector<int> frames;
   const void* forces = nullptr;
@@ -624,6 +625,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   HIPCHECK(s, hipMemset(s->it_fwd, 0, st * 4));
   HIPCHECK(s, hipMemset(s->it_rec, 0, st * 4));
   HIPCHECK(s, hipMemset(s->it_adj, 0, st * 4));
+  HIPCHECK(s, hipMemset(s->res_fwd, 0, st * 8));
+  HIPCHECK(s, hipMemset(s->res_rec, 0, st * 8));
+  HIPCHECK(s, hipMemset(s->res_adj, 0, st * 8));
   HIPCHECK(s, hipDeviceSynchronize());
 
   // ---- solver launch shape: the rule's choice, or the fastest candidate measured on
@@ -902,6 +906,48 @@ sim_status graphed(sim_t* s, sim_t::GraphCache& gc, const std::vector<uintptr_t>
   return SIM_OK;
 }
 
+// Argument checks and bookkeeping shared by the rollout entry points.
+sim_status begin_rollout(sim_t* s, int n_steps, const void* x0, const void* forces,
+                         const void* material, const void* wind, const int32_t* loss_frames,
+                         int n_loss, void* x_out, void* stream) {
+  if (!s) return SIM_E_INVALID;
+  if (n_steps < 1 || n_steps > s->max_steps || !x0 || n_loss < 0 ||
+      (n_loss > 0 && (!loss_frames || !x_out))) {
+    s->err = "invalid rollout arguments";
+    return SIM_E_INVALID;
+  }
+  int prev = 0;
+  for (int k = 0; k < n_loss; ++k) {
+    if (loss_frames[k] <= prev || loss_frames[k] > n_steps) {
+      s->err = "loss frames must be strictly increasing within 1..n_steps";
+      return SIM_E_INVALID;
+    }
+    prev = loss_frames[k];
+  }
+  if (wind) {
+    s->err = "wind is not supported by this build";
+    return SIM_E_INVALID;
+  }
+  s->have_rollout = false;
+  s->have_adjoint = false;
+  s->n_steps = n_steps;
+  s->frames.assign(loss_frames, loss_frames + n_loss);
+  s->forces = forces;
+  s->material = material ? static_cast<const double*>(material) : s->mat_default;
+  s->wind = static_cast<const double*>(wind);
+  s->stream = static_cast<hipStream_t>(stream);
+  return SIM_OK;
+}
+
+sim_status run_rollout(sim_t* s, int n_steps, const void* x0, const void* v0, void* x_out,
+                       hipStream_t q) {
+  if (s->prec == SIM_FP64)
+    return s->mprec == SIM_FP64 ? rollout_impl<double, double>(s, n_steps, x0, v0, x_out, q)
+                                : rollout_impl<double, float>(s, n_steps, x0, v0, x_out, q);
+  return s->mprec == SIM_FP64 ? rollout_impl<float, double>(s, n_steps, x0, v0, x_out, q)
+                              : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, q);
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -978,40 +1024,13 @@ sim_status sim_create(const sim_mesh* mesh, const double* rest_pos, const int32_
 sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0,
                        const void* forces, const void* material, const void* wind,
                        const int32_t* loss_frames, int32_t n_loss, void* x_out, void* stream) {
-  if (!s) return SIM_E_INVALID;
-  if (n_steps < 1 || n_steps > s->max_steps || !x0 || n_loss < 0 || (n_loss > 0 && (!loss_frames || !x_out))) {
-    s->err = "invalid rollout arguments";
-    return SIM_E_INVALID;
-  }
-  int prev = 0;
-  for (int k = 0; k < n_loss; ++k) {
-    if (loss_frames[k] <= prev || loss_frames[k] > n_steps) {
-      s->err = "loss frames must be strictly increasing within 1..n_steps";
-      return SIM_E_INVALID;
-    }
-    prev = loss_frames[k];
-  }
-  s->have_rollout = false;
-  s->n_steps = n_steps;
-  s->frames.assign(loss_frames, loss_frames + n_loss);
-  if (wind) {
-    s->err = "wind is not supported by this build";
-    return SIM_E_INVALID;
-  }
-  s->forces = forces;
-  s->material = material ? static_cast<const double*>(material) : s->mat_default;
-  s->wind = static_cast<const double*>(wind);
-  s->stream = static_cast<hipStream_t>(stream);
+  TRY(begin_rollout(s, n_steps, x0, forces, material, wind, loss_frames, n_loss, x_out, stream));
   std::vector<uintptr_t> key = {(uintptr_t)n_steps, (uintptr_t)x0, (uintptr_t)v0,
                                 (uintptr_t)forces, (uintptr_t)s->material, (uintptr_t)wind,
                                 (uintptr_t)x_out};
   key.insert(key.end(), s->frames.begin(), s->frames.end());
   const sim_status st = graphed(s, s->gfwd, key, s->stream, [&](hipStream_t q) {
-    if (s->prec == SIM_FP64)
-      return s->mprec == SIM_FP64 ? rollout_impl<double, double>(s, n_steps, x0, v0, x_out, q)
-                                  : rollout_impl<double, float>(s, n_steps, x0, v0, x_out, q);
-    return s->mprec == SIM_FP64 ? rollout_impl<float, double>(s, n_steps, x0, v0, x_out, q)
-                                : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, q);
+    return run_rollout(s, n_steps, x0, v0, x_out, q);
   });
   if (st == SIM_OK) s->have_rollout = true;
   return st;
@@ -1037,6 +1056,7 @@ sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl
   std::vector<uintptr_t> key = {(uintptr_t)dl_dx, (uintptr_t)dl_dmaterial, (uintptr_t)dl_dwind,
                                 (uintptr_t)dl_dforces, (uintptr_t)dl_dx0, (uintptr_t)dl_dv0};
   key.insert(key.end(), s->gfwd.key.begin(), s->gfwd.key.end());
+  s->have_adjoint = true;
   return graphed(s, s->gadj, key, s->stream, [&](hipStream_t q) {
     if (s->prec == SIM_FP64)
       return s->mprec == SIM_FP64
@@ -1067,10 +1087,14 @@ sim_status sim_sync_status(sim_t* s) {
   std::vector<double> rf((size_t)n * ni), ra((size_t)n * ni);
   if (n > 0) {
     (void)hipMemcpy(itf.data(), s->it_fwd, itf.size() * 4, hipMemcpyDeviceToHost);
-    (void)hipMemcpy(itr.data(), s->it_rec, itr.size() * 4, hipMemcpyDeviceToHost);
-    (void)hipMemcpy(ita.data(), s->it_adj, ita.size() * 4, hipMemcpyDeviceToHost);
     (void)hipMemcpy(rf.data(), s->res_fwd, rf.size() * 8, hipMemcpyDeviceToHost);
-    (void)hipMemcpy(ra.data(), s->res_adj, ra.size() * 8, hipMemcpyDeviceToHost);
+    if (s->have_adjoint) {
+      // the adjoint's solves (and the checkpoint recompute's) belong to this rollout only
+      // once an adjoint has run since it
+      (void)hipMemcpy(itr.data(), s->it_rec, itr.size() * 4, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(ita.data(), s->it_adj, ita.size() * 4, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(ra.data(), s->res_adj, ra.size() * 8, hipMemcpyDeviceToHost);
+    }
   }
   sim_stats& S = s->stats;
   S.n_steps = n;

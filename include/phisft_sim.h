@@ -276,6 +276,23 @@ sim_status sim_rollout(sim_t* sim, int32_t n_steps, const void* x0, const void* 
                        const void* forces, const void* material, const void* wind,
                        const int32_t* loss_frames, int32_t n_loss, void* x_out, void* stream);
 
+/* sim_rollout for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Same arguments,
+ * results and errors as sim_rollout (bitwise the same outputs), and it allocates
+ * nothing: the solver's exchange buffers (partial sums, tagged publications, barrier
+ * counters, the global copies of the preconditioned vectors; about 136 bytes per
+ * vertex plus about 1 KB per solver workgroup) live in a static device array of
+ * 8 MiB that each GPU the library runs on holds until the process ends (sheets up to
+ * about 60,000 vertices; larger handles get SIM_E_INVALID). Every call on one GPU
+ * shares that array, so calls that overlap on one GPU (on different streams or
+ * threads) race; the array keeps the last call's contents, and each solver launch
+ * clears what must start at zero. Handles created with the graph option are refused
+ * (SIM_E_INVALID). A later sim_adjoint works as after sim_rollout. */
+sim_status sim_rollout_noalloc(sim_t* sim, int32_t n_steps, const void* x0, const void* v0,
+                               const void* forces, const void* material, const void* wind,
+                               const int32_t* loss_frames, int32_t n_loss, void* x_out,
+                               void* stream);
+
 /* Adjoint of the most recent rollout for a loss with gradient dl_dx
  * (device [n_loss][3][V], one slice per loss frame).
  *   dl_dmaterial  device double [n_instances][3] (dL/dk_s, dL/dk_b, dL/dd) or NULL

@@ -99,4 +99,10 @@ void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0,
                       hipStream_t st);
 void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st);
 
+// Bytes of the static device array behind the allocation-free rollout's solver
+// exchange buffers (one copy per GPU, held for the process's lifetime).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+// Device address of that array on the current device (looked up once per device).
+hipError_t noalloc_scratch(void** out);
+
 }  // namespace phisft

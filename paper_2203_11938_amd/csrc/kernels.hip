@@ -30,9 +30,16 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 #include "sim_internal.h"
+
+// Solver exchange buffers of the allocation-free rollout (partial sums, tagged
+// publications, barrier counters, the preconditioned vectors' global copies). Host
+// code never passes this name to a kernel: it is a host-side stand-in, and kernels
+// get the device address that noalloc_scratch looks up per device.
+static __device__ __align__(256) unsigned char scratch[phisft::kNoAllocScratchBytes];
 
 namespace phisft {
 
@@ -2567,6 +2574,26 @@ __global__ void k_fill_double(double* p, long n, double v) {
 // --------------------------------------------------------------- launchers
 static inline int blocks_for(long n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Each GPU holds its own copy of the scratch array at its own address: resolved once
+// per device, with that device current, and kept.
+hipError_t noalloc_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 void launch_fill_int(int* p, int n, int v, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);

@@ -948,6 +948,38 @@ sim_status run_rollout(sim_t* s, int n_steps, const void* x0, const void* v0, vo
                               : rollout_impl<float, float>(s, n_steps, x0, v0, x_out, q);
 }
 
+// The solver's exchange buffers (the ones sim_create allocates for the handle: the
+// global copies of the preconditioned vectors, the tagged publications, the partial
+// sums, the barrier counters and abort flag, the coarse restriction partials) laid
+// out 256-byte aligned in the scratch array at base, of cap bytes. Every launch of
+// the solver clears what must start at zero (counters, flag, tagged words) with a
+// fill kernel; the rest is written before it is read.
+sim_status noalloc_work(sim_t* s, char* base, size_t cap, SolverWork* w, double** part) {
+  const size_t nv = s->L.nv, nwg = s->plan.nwg;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base + off;
+    off += (bytes + 255) / 256 * 256;
+    return p;
+  };
+  *w = s->sw;
+  w->zbuf = reinterpret_cast<double*>(take(3 * nv * 8));
+  w->pbuf = reinterpret_cast<double*>(take(6 * nv * 8));
+  w->tbuf = reinterpret_cast<unsigned long long*>(take(8 * nv * 8));
+  w->red = reinterpret_cast<double*>(take(6 * nwg * 8));
+  w->tred = reinterpret_cast<unsigned long long*>(take(2 * nwg * kTagSlots * 16));
+  w->barrier = reinterpret_cast<int*>(take((size_t)s->sw.barrier_ints * 4));
+  w->abort_flag = reinterpret_cast<int*>(take(4));
+  *part = s->L.nagg > 0 ? reinterpret_cast<double*>(take(nwg * kMaxWgAgg * 6 * 8)) : nullptr;
+  if (off > cap) {
+    s->err = "the solver's exchange buffers (" + std::to_string(off) +
+             " bytes) exceed the allocation-free rollout's scratch array (" +
+             std::to_string(cap) + " bytes)";
+    return SIM_E_INVALID;
+  }
+  return SIM_OK;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -1032,6 +1064,37 @@ sim_status sim_rollout(sim_t* s, int32_t n_steps, const void* x0, const void* v0
   const sim_status st = graphed(s, s->gfwd, key, s->stream, [&](hipStream_t q) {
     return run_rollout(s, n_steps, x0, v0, x_out, q);
   });
+  if (st == SIM_OK) s->have_rollout = true;
+  return st;
+}
+
+sim_status sim_rollout_noalloc(sim_t* s, int32_t n_steps, const void* x0, const void* v0,
+                               const void* forces, const void* material, const void* wind,
+                               const int32_t* loss_frames, int32_t n_loss, void* x_out,
+                               void* stream) {
+  if (!s) return SIM_E_INVALID;
+  if (s->use_graph) {
+    s->err = "sim_rollout_noalloc needs a handle without the graph option";
+    return SIM_E_INVALID;
+  }
+  TRY(begin_rollout(s, n_steps, x0, forces, material, wind, loss_frames, n_loss, x_out, stream));
+  void* base = nullptr;
+  HIPCHECK(s, noalloc_scratch(&base));
+  SolverWork w{};
+  double* part = nullptr;
+  TRY(noalloc_work(s, static_cast<char*>(base), kNoAllocScratchBytes, &w, &part));
+  // the handle's own exchange buffers are swapped out while the launches are enqueued
+  // (kernels take them by value); no timing events are recorded
+  const SolverWork saved = s->sw;
+  double* saved_part = s->coarse.part;
+  const bool saved_timing = s->timing;
+  s->sw = w;
+  s->coarse.part = part;
+  s->timing = false;
+  const sim_status st = run_rollout(s, n_steps, x0, v0, x_out, s->stream);
+  s->sw = saved;
+  s->coarse.part = saved_part;
+  s->timing = saved_timing;
   if (st == SIM_OK) s->have_rollout = true;
   return st;
 }

@@ -88,7 +88,8 @@ class _Stats(ctypes.Structure):
 
 _lib = None
 
-EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout", "sim_adjoint",
+EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout",
+           "sim_rollout_noalloc", "sim_adjoint",
            "sim_sync_status", "sim_set_timing", "sim_get_stats", "sim_get_cg_iters",
            "sim_get_instance_status",
            "sim_status_string", "sim_last_error", "sim_destroy")
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.POINTER(_Material), ctypes.c_double,
                                    ctypes.POINTER(_Options), ctypes.POINTER(vp)]),
         "sim_rollout": (i32, [vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp, vp]),
+        "sim_rollout_noalloc": (i32, [vp, i32, vp, vp, vp, vp, vp, ctypes.POINTER(i32), i32, vp,
+                                      vp]),
         "sim_adjoint": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "sim_sync_status": (i32, [vp]),
         "sim_set_timing": (i32, [vp, i32]),
@@ -288,10 +291,11 @@ class Simulator:
     def rollout(self, n_steps: int, x0: torch.Tensor, v0: Optional[torch.Tensor] = None,
                 forces: Optional[torch.Tensor] = None, material: Optional[torch.Tensor] = None,
                 loss_frames: Optional[Sequence[int]] = None, x_out: Optional[torch.Tensor] = None,
-                wind: Optional[torch.Tensor] = None):
+                wind: Optional[torch.Tensor] = None, noalloc: bool = False):
         """Run ``n_steps`` steps. Returns positions at the loss frames [n_loss, 3, V].
         ``wind`` [n_instances, 3] float64 is each sheet's wind velocity (None: no
-        aerodynamic force)."""
+        aerodynamic force). ``noalloc`` calls the allocation-free entry point
+        (sim_rollout_noalloc); pass ``x_out`` too so that nothing is allocated."""
         V = self.n_verts
         frames = np.arange(1, n_steps + 1, dtype=np.int32) if loss_frames is None else \
             np.ascontiguousarray(loss_frames, dtype=np.int32)
@@ -303,11 +307,11 @@ class Simulator:
         if x_out is None:
             x_out = torch.empty((frames.size, 3, V), dtype=self.dtype, device=x0.device)
         self._need(x_out, (frames.size, 3, V), "x_out")
-        st = self._lib.sim_rollout(self._h, int(n_steps), _ptr(x0), _ptr(v0), _ptr(forces),
-                                   _ptr(material), _ptr(wind),
-                                   frames.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                   int(frames.size), _ptr(x_out), _stream())
-        self._check(st, "sim_rollout")
+        fn = self._lib.sim_rollout_noalloc if noalloc else self._lib.sim_rollout
+        st = fn(self._h, int(n_steps), _ptr(x0), _ptr(v0), _ptr(forces), _ptr(material),
+                _ptr(wind), frames.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                int(frames.size), _ptr(x_out), _stream())
+        self._check(st, "sim_rollout_noalloc" if noalloc else "sim_rollout")
         # the adjoint re-reads these; keep them alive
         self._keep = (forces, material, wind)
         self.has_wind = wind is not None

@@ -69,11 +69,13 @@ def _load():
         "orc_step_residual": (c_int, [P, D, D, D, D, D, D]),
         "orc_step": (c_int, [P, D, D, D, D, D, D, I]),
         "orc_rollout": (c_int, [P, c_int, D, D, D, I, c_int, D, D, I]),
-        "orc_gradient": (c_int, [P, c_int, D, D, D, I, c_int, D, D, D, D, D, I, I]),
+        "orc_gradient": (c_int, [P, c_int, D, D, D, I, c_int, D, D, D, D, D, D, I, I]),
         "orc_pattern": (None, [P, I, I]),
         "orc_system_blocks": (c_int, [P, D, D, D, D, D]),
         "orc_adjoint_rhs": (None, [P, D, D, D]),
-        "orc_adjoint_update": (None, [P, D, D, D, D, D, D, D, D]),
+        "orc_adjoint_update": (None, [P, D, D, D, D, D, D, D, D, D, D]),
+        "orc_set_wind": (c_int, [P, c_int, c_double, c_double, c_double, c_double]),
+        "orc_wind_force": (None, [P, D, D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -202,6 +204,25 @@ class Oracle:
     MEMBRANE_GAUSS_NEWTON = 0
     MEMBRANE_EXACT = 1
     MEMBRANE_TENSION = 2
+
+    def set_wind(self, wind=None, air_density=1.0):
+        """Wind velocity w [m/s] (Eq. 2's w) and air density [kg/m^3] of the
+        aerodynamic force (reading R19; the paper fixes the density at 1 kg/m^3,
+        Sec. 3.4). None switches the force off."""
+        on = wind is not None
+        w = (0.0, 0.0, 0.0) if wind is None else tuple(float(c) for c in wind)
+        st = _load().orc_set_wind(self._h, 1 if on else 0, *w, float(air_density))
+        if st != ORC_OK:
+            raise OracleError(st, "set_wind")
+        self.wind = None if wind is None else np.array(w)
+
+    def wind_force(self, x, v):
+        """The aerodynamic force alone at (x, v) [V, 3] (reading R19)."""
+        x = _f64(x, (self.nv, 3))
+        v = _f64(v, (self.nv, 3))
+        f = np.zeros((self.nv, 3))
+        _load().orc_wind_force(self._h, _d(x), _d(v), _d(f))
+        return f
 
     def set_membrane_system(self, mode: int):
         """Stress term of the system matrix's membrane block (reading R9):
@@ -341,18 +362,19 @@ class Oracle:
         frames = np.ascontiguousarray(loss_frames, dtype=np.int32)
         dl_dx = _f64(dl_dx, (frames.size, self.nv, 3))
         gm = np.zeros(3)
+        gw = np.zeros(3)
         gF = np.zeros((n_steps, self.nv, 3))
         gx0 = np.zeros((self.nv, 3))
         gv0 = np.zeros((self.nv, 3))
         itf = np.zeros(n_steps, dtype=np.int32)
         ita = np.zeros(n_steps, dtype=np.int32)
         st = _load().orc_gradient(self._h, int(n_steps), _d(x0), _d(v0), _d(forces), _i(frames),
-                                  int(frames.size), _d(dl_dx), _d(gm), _d(gF), _d(gx0), _d(gv0),
-                                  _i(itf), _i(ita))
+                                  int(frames.size), _d(dl_dx), _d(gm), _d(gw), _d(gF), _d(gx0),
+                                  _d(gv0), _i(itf), _i(ita))
         if check and st != ORC_OK:
             raise OracleError(st, "gradient")
-        return dict(material=gm, forces=gF, x0=gx0, v0=gv0, iters_fwd=itf, iters_adj=ita,
-                    status=st)
+        return dict(material=gm, wind=gw, forces=gF, x0=gx0, v0=gv0, iters_fwd=itf,
+                    iters_adj=ita, status=st)
 
     # ------------------------------------------- exact-solve driver (golden files)
     def pattern(self):
@@ -430,6 +452,7 @@ class Oracle:
         gv = np.zeros((self.nv, 3))
         u = np.zeros((self.nv, 3))
         gm = np.zeros(3)
+        gw = np.zeros(3)
         gF = np.zeros((n_steps, self.nv, 3))
         lib = _load()
         fi = len(frames) - 1
@@ -443,9 +466,10 @@ class Oracle:
             mu = np.ascontiguousarray(lu.solve(u.ravel()).reshape(self.nv, 3))
             gF[s - 1] = self.dt * mu
             xp = np.ascontiguousarray(X[s - 1])
+            vp = np.ascontiguousarray(Vv[s - 1])
             vs = np.ascontiguousarray(Vv[s])
             dvs = np.ascontiguousarray(DV[s])
-            lib.orc_adjoint_update(self._h, _d(xp), _d(vs), _d(dvs), _d(mu), _d(u), _d(gx),
-                                   _d(gv), _d(gm))
-        return dict(x=xo, loss=float(np.sum((xo - targets) ** 2)), material=gm, forces=gF,
-                    x0=gx, v0=gv)
+            lib.orc_adjoint_update(self._h, _d(xp), _d(vp), _d(vs), _d(dvs), _d(mu), _d(u),
+                                   _d(gx), _d(gv), _d(gm), _d(gw))
+        return dict(x=xo, loss=float(np.sum((xo - targets) ** 2)), material=gm, wind=gw,
+                    forces=gF, x0=gx, v0=gv)

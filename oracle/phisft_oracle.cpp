@@ -33,6 +33,13 @@
 //       wherever the force itself is differentiated and the derivative of
 //       K_sys in the state-derivative term.
 //   R11 pinned vertices keep v = 0 and x = x_0 (Dirichlet rows/columns).
+//   R19 wind (Eq. 2's w, a velocity; air density fixed, Sec. 3.4): every triangle
+//       feels F_t = rho_air * area_t * |s| s n, n its unit normal at x_{t-1},
+//       area_t its rest area, s = n . (w - mean of its vertices' v_{t-1}); each
+//       vertex takes F_t / 3. Its velocity Jacobian enters the step matrix as
+//       -h df/dv (Eq. 4-5); its position Jacobian is left out of the matrix (it is
+//       not symmetric) and acts through the right-hand side only. The adjoint
+//       differentiates exactly this step.
 //
 // Independence: nothing here is shared with the GPU library. Element stiffness
 // blocks are obtained by probing the Hessian-vector product with unit vectors,
@@ -88,6 +95,35 @@ inline Dual atan2(Dual y, Dual x) {
 inline double value_of(double a) { return a; }
 inline double value_of(const Dual& a) { return a.v; }
 inline double deriv_of(const Dual& a) { return a.d; }
+
+// Hyper-dual numbers f(x + a e1 + b e2 + ab e1 e2) with e1^2 = e2^2 = 0: the ab part
+// carries the exact mixed second derivative (used for the wind force's terms in the
+// adjoint, where the velocity Jacobian is differentiated once more).
+struct HDual {
+  double v, a, b, ab;
+  HDual() : v(0.0), a(0.0), b(0.0), ab(0.0) {}
+  HDual(double x) : v(x), a(0.0), b(0.0), ab(0.0) {}  // NOLINT: implicit promotion is intended
+  HDual(double x, double da, double db, double dab) : v(x), a(da), b(db), ab(dab) {}
+};
+inline HDual operator+(HDual p, HDual q) { return HDual(p.v + q.v, p.a + q.a, p.b + q.b, p.ab + q.ab); }
+inline HDual operator-(HDual p, HDual q) { return HDual(p.v - q.v, p.a - q.a, p.b - q.b, p.ab - q.ab); }
+inline HDual operator-(HDual p) { return HDual(-p.v, -p.a, -p.b, -p.ab); }
+inline HDual operator*(HDual p, HDual q) {
+  return HDual(p.v * q.v, p.a * q.v + p.v * q.a, p.b * q.v + p.v * q.b,
+               p.ab * q.v + p.a * q.b + p.b * q.a + p.v * q.ab);
+}
+inline HDual recip(HDual q) {
+  // 1/q: f = 1/v, f' = -1/v^2, f'' = 2/v^3
+  const double f = 1.0 / q.v, f1 = -f * f, f2 = 2.0 * f * f * f;
+  return HDual(f, f1 * q.a, f1 * q.b, f1 * q.ab + f2 * q.a * q.b);
+}
+inline HDual operator/(HDual p, HDual q) { return p * recip(q); }
+inline HDual sqrt(HDual q) {
+  const double f = std::sqrt(q.v), f1 = 0.5 / f, f2 = -0.25 / (f * q.v);
+  return HDual(f, f1 * q.a, f1 * q.b, f1 * q.ab + f2 * q.a * q.b);
+}
+inline double value_of(const HDual& a) { return a.v; }
+template <class S> inline S absval(const S& a) { return value_of(a) >= 0.0 ? a : -a; }
 using std::atan2;
 using std::sqrt;
 
@@ -273,6 +309,27 @@ void hinge_theta_grad(const S* x0, const S* x1, const S* x2, const S* x3, S* g0,
   }
 }
 
+// ------------------------------------------------- aerodynamic force (R19)
+// Total force of the wind on one triangle (each vertex takes a third):
+// rho_area * |s| s n with n = N / |N|, N = (x_b - x_a) x (x_c - x_a), and
+// s = n . (w - (v_a + v_b + v_c) / 3).
+template <class S>
+void aero_force(const S* xa, const S* xb, const S* xc, const S* va, const S* vb, const S* vc,
+                const S* w, double rho_area, S* F) {
+  S e1[3], e2[3], N[3], n[3], rel[3];
+  sub3(xb, xa, e1);
+  sub3(xc, xa, e2);
+  cross3(e1, e2, N);
+  S ln = sqrt(dot3(N, N));
+  for (int k = 0; k < 3; ++k) {
+    n[k] = N[k] / ln;
+    rel[k] = w[k] - (va[k] + vb[k] + vc[k]) / 3.0;
+  }
+  S sn = dot3(n, rel);
+  S mag = absval(sn) * sn * rho_area;
+  for (int k = 0; k < 3; ++k) F[k] = mag * n[k];
+}
+
 // ------------------------------------------------------------------ problem
 struct Problem {
   int nv = 0, nt = 0, nh = 0;
@@ -292,6 +349,10 @@ struct Problem {
   // Stress term of the system matrix's membrane block: GEO_EXACT (default, the
   // true Hessian), GEO_TENSION (tension part only) or GEO_NONE (Gauss-Newton).
   int mem_geo = GEO_EXACT;
+  // wind (R19): off unless set; velocity w [m/s] and air density [kg/m^3]
+  bool wind_on = false;
+  double wind[3] = {0, 0, 0};
+  double rho_air = 1.0;
   std::vector<int> rowptr, col;  // CSR pattern of the vertex blocks
   int last_status = ORC_OK;
 };
@@ -606,9 +667,50 @@ bool invert3(const double* a, double* inv) {
   return true;
 }
 
-// System matrix A = M + h^2 K_sys with Dirichlet rows/columns of pinned vertices.
-void system_matrix(const Problem& P, const std::vector<double>& K, std::vector<double>& A) {
+// Wind force (R19) at (x, v), added to f [V][3].
+void wind_force(const Problem& P, const double* x, const double* v, double* f) {
+  for (int t = 0; t < P.nt; ++t) {
+    const int* a = &P.tri[3 * t];
+    double F[3];
+    aero_force<double>(&x[3 * a[0]], &x[3 * a[1]], &x[3 * a[2]], &v[3 * a[0]], &v[3 * a[1]],
+                       &v[3 * a[2]], P.wind, P.rho_air * P.area[t], F);
+    for (int q = 0; q < 3; ++q)
+      for (int k = 0; k < 3; ++k) f[3 * a[q] + k] += F[k] / 3.0;
+  }
+}
+
+// D = -df_wind/dv in CSR blocks, each element's velocity Jacobian probed column by
+// column with dual numbers.
+void wind_damping(const Problem& P, const double* x, const double* v, std::vector<double>& D) {
+  D.assign(9 * P.col.size(), 0.0);
+  for (int t = 0; t < P.nt; ++t) {
+    const int* a = &P.tri[3 * t];
+    Dual X[3][3], W[3];
+    for (int q = 0; q < 3; ++q)
+      for (int k = 0; k < 3; ++k) X[q][k] = Dual(x[3 * a[q] + k]);
+    for (int k = 0; k < 3; ++k) W[k] = Dual(P.wind[k]);
+    for (int b = 0; b < 3; ++b)
+      for (int m = 0; m < 3; ++m) {
+        Dual Vd[3][3], F[3];
+        for (int q = 0; q < 3; ++q)
+          for (int k = 0; k < 3; ++k) Vd[q][k] = Dual(v[3 * a[q] + k], (q == b && k == m) ? 1.0 : 0.0);
+        aero_force<Dual>(X[0], X[1], X[2], Vd[0], Vd[1], Vd[2], W, P.rho_air * P.area[t], F);
+        // column (b, m): d f_q / d v_{b,m} = dF / 3 for every vertex q of the triangle
+        for (int q = 0; q < 3; ++q) {
+          int s = find_slot(P, a[q], a[b]);
+          for (int k = 0; k < 3; ++k) D[9 * s + 3 * k + m] -= deriv_of(F[k]) / 3.0;
+        }
+      }
+  }
+}
+
+// System matrix A = M + h D + h^2 K_sys (D the wind damping at (x, v), zero without
+// wind) with Dirichlet rows/columns of pinned vertices.
+void system_matrix(const Problem& P, const double* x, const double* v, const std::vector<double>& K,
+                   std::vector<double>& A) {
   A.assign(K.size(), 0.0);
+  std::vector<double> D;
+  if (P.wind_on) wind_damping(P, x, v, D);
   double h2 = P.h * P.h;
   for (int i = 0; i < P.nv; ++i)
     for (int s = P.rowptr[i]; s < P.rowptr[i + 1]; ++s) {
@@ -619,7 +721,7 @@ void system_matrix(const Problem& P, const std::vector<double>& K, std::vector<d
           for (int k = 0; k < 3; ++k) blk[4 * k] = 1.0;
         continue;
       }
-      for (int q = 0; q < 9; ++q) blk[q] = h2 * K[9 * s + q];
+      for (int q = 0; q < 9; ++q) blk[q] = h2 * K[9 * s + q] + (P.wind_on ? P.h * D[9 * s + q] : 0.0);
       if (i == j) {
         double m = P.dens * P.varea[i];
         for (int k = 0; k < 3; ++k) blk[4 * k] += m;
@@ -687,6 +789,7 @@ void step_rhs(const Problem& P, const double* x, const double* v, const double* 
   int n = 3 * P.nv;
   std::vector<double> f(n), Kv(n);
   internal_force(P, x, P.ks, P.kb, f.data());
+  if (P.wind_on) wind_force(P, x, v, f.data());
   csr_apply(P, K, v, Kv.data());
   for (int i = 0; i < P.nv; ++i) {
     double m = P.dens * P.varea[i];
@@ -710,7 +813,7 @@ int one_step(const Problem& P, const double* x, const double* v, const double* F
   int n = 3 * P.nv;
   std::vector<double> K, A, b(n), dv(n);
   assemble_ksys(P, x, K);
-  system_matrix(P, K, A);
+  system_matrix(P, x, v, K, A);
   step_rhs(P, x, v, F, K, b.data());
   if (!all_finite(b.data(), n) || !all_finite(A.data(), A.size())) return ORC_E_NONFINITE;
   int st = pcg(P, A, b.data(), dv.data(), iters);
@@ -775,16 +878,48 @@ void adjoint_rhs(const Problem& P, const double* gx, const double* gv, double* u
       u[3 * i + k] = P.pinned[i] ? 0.0 : gv[3 * i + k] + P.h * gx[3 * i + k];
 }
 
+// The wind's part of one backward step (R19): with G = mu . f_wind(x, v, w) and A's
+// wind block h D = -h df_wind/dv, the step's b and A contribute h dG/dc and
+// -h d(mu^T D dv_s)/dc = h d^2 G(x, v + e dv_s, w)/dc de to the gradient with respect
+// to every input c of every triangle (its positions, velocities and w), all at
+// (x_{s-1}, v_{s-1}). Each triangle is evaluated in hyper-dual numbers: part a seeds c,
+// part b seeds the velocities with dv_s. Adds to wx, wv [V][3] and ww[3].
+void wind_adjoint(const Problem& P, const double* xp, const double* vp, const double* dvs,
+                  const double* mu, double* wx, double* wv, double* ww) {
+  for (int t = 0; t < P.nt; ++t) {
+    const int* a = &P.tri[3 * t];
+    for (int c = 0; c < 21; ++c) {   // 9 position, 9 velocity and 3 wind coordinates
+      HDual X[3][3], V[3][3], Wd[3], F[3];
+      for (int q = 0; q < 3; ++q)
+        for (int k = 0; k < 3; ++k) {
+          X[q][k] = HDual(xp[3 * a[q] + k], c == 3 * q + k ? 1.0 : 0.0, 0.0, 0.0);
+          V[q][k] = HDual(vp[3 * a[q] + k], c == 9 + 3 * q + k ? 1.0 : 0.0, dvs[3 * a[q] + k], 0.0);
+        }
+      for (int k = 0; k < 3; ++k) Wd[k] = HDual(P.wind[k], c == 18 + k ? 1.0 : 0.0, 0.0, 0.0);
+      aero_force<HDual>(X[0], X[1], X[2], V[0], V[1], V[2], Wd, P.rho_air * P.area[t], F);
+      HDual G(0.0);
+      for (int q = 0; q < 3; ++q)
+        for (int k = 0; k < 3; ++k) G = G + HDual(mu[3 * a[q] + k] / 3.0) * F[k];
+      const double d = P.h * (G.a + G.ab);
+      if (c < 9) wx[3 * a[c / 3] + c % 3] += d;
+      else if (c < 18) wv[3 * a[(c - 9) / 3] + (c - 9) % 3] += d;
+      else ww[c - 18] += d;
+    }
+  }
+}
+
 // Steps 5-9 of one backward step of the implicit differentiation of Eq. 4, given
-// the adjoint solution mu of A(x_{s-1}) mu = u, the state x_{s-1}, the new
-// velocity v_s and the increment dv_s: accumulates the material gradient
-// (dL/dk_s, dL/dk_b, dL/dd) in gmat and replaces (gx, gv) by the gradients with
-// respect to (x_{s-1}, v_{s-1}).
-void adjoint_update(const Problem& P, const double* xp, const double* vs, const double* dvs,
-                    const double* mu, const double* u, double* gx, double* gv, double* gmat) {
+// the adjoint solution mu of A(x_{s-1}) mu = u, the state (x_{s-1}, v_{s-1}), the
+// new velocity v_s and the increment dv_s: accumulates the material gradient
+// (dL/dk_s, dL/dk_b, dL/dd) in gmat and the wind gradient dL/dw in gwind, and
+// replaces (gx, gv) by the gradients with respect to (x_{s-1}, v_{s-1}).
+void adjoint_update(const Problem& P, const double* xp, const double* vp, const double* vs,
+                    const double* dvs, const double* mu, const double* u, double* gx, double* gv,
+                    double* gmat, double* gwind) {
   const int n = 3 * P.nv;
   const double h1 = P.h, h2 = P.h * P.h;
-  std::vector<double> tmp(n), tmp2(n), fh(n);
+  std::vector<double> tmp(n), tmp2(n), fh(n), wx(n, 0.0), wv(n, 0.0);
+  if (P.wind_on) wind_adjoint(P, xp, vp, dvs, mu, wx.data(), wv.data(), gwind);
   // 5. dL/dk_s += mu . (h f_m/k_s - h^2 (K_m/k_s) v_s)
   internal_force(P, xp, 1.0, 0.0, fh.data());
   stiffness_apply(P, xp, vs, 1.0, 0.0, false, tmp.data());
@@ -801,11 +936,13 @@ void adjoint_update(const Problem& P, const double* xp, const double* vs, const 
   stiffness_apply(P, xp, mu, P.ks, P.kb, true, tmp.data());
   third_contraction(P, xp, mu, vs, tmp2.data());
   for (int k = 0; k < n; ++k) gx[k] -= h1 * tmp[k] + h2 * tmp2[k];
-  // 9. gv = mask(u - h^2 K_sys mu)
+  // 9. gv = mask(u - h^2 K_sys mu), plus the wind's velocity terms
   stiffness_apply(P, xp, mu, P.ks, P.kb, false, tmp.data());
   for (int i = 0; i < P.nv; ++i)
     for (int k = 0; k < 3; ++k)
-      gv[3 * i + k] = P.pinned[i] ? 0.0 : u[3 * i + k] - h2 * tmp[3 * i + k];
+      gv[3 * i + k] = P.pinned[i] ? 0.0 : u[3 * i + k] - h2 * tmp[3 * i + k] + wv[3 * i + k];
+  if (P.wind_on)
+    for (int k = 0; k < n; ++k) gx[k] += wx[k];
 }
 
 }  // namespace
@@ -915,7 +1052,7 @@ int orc_system(void* h, const double* x, const double* v, const double* F, doubl
       for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
   std::vector<double> K, A;
   assemble_ksys(*P, x, K);
-  system_matrix(*P, K, A);
+  system_matrix(*P, x, vm.data(), K, A);
   step_rhs(*P, x, vm.data(), F, K, b);
   std::fill(A_dense, A_dense + (size_t)n * n, 0.0);
   for (int i = 0; i < P->nv; ++i)
@@ -938,7 +1075,7 @@ int orc_solve_step(void* h, const double* x, const double* v, const double* F, d
       for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
   std::vector<double> K, A, b(n);
   assemble_ksys(*P, x, K);
-  system_matrix(*P, K, A);
+  system_matrix(*P, x, vm.data(), K, A);
   step_rhs(*P, x, vm.data(), F, K, b.data());
   return pcg(*P, A, b.data(), dv, iters);
 }
@@ -955,7 +1092,7 @@ int orc_step_residual(void* h, const double* x, const double* v, const double* F
       for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
   std::vector<double> K, A, b(n), Adv(n);
   assemble_ksys(*P, x, K);
-  system_matrix(*P, K, A);
+  system_matrix(*P, x, vm.data(), K, A);
   step_rhs(*P, x, vm.data(), F, K, b.data());
   csr_apply(*P, A, dv, Adv.data());
   double bn = 0.0;
@@ -1005,7 +1142,8 @@ int orc_rollout(void* h, int nsteps, const double* x0, const double* v0, const d
 // dl_dx0, dl_dv0 [V][3]. Any output pointer may be NULL.
 int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const double* forces,
                  const int* loss_frames, int nloss, const double* dl_dx, double* dl_dmat,
-                 double* dl_dF, double* dl_dx0, double* dl_dv0, int* iters_fwd, int* iters_adj) {
+                 double* dl_dwind, double* dl_dF, double* dl_dx0, double* dl_dv0, int* iters_fwd,
+                 int* iters_adj) {
   Problem* P = static_cast<Problem*>(h);
   if (nsteps < 1 || !valid_frames(loss_frames, nloss, nsteps)) return ORC_E_INVALID;
   int n = 3 * P->nv;
@@ -1014,7 +1152,7 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
   if (st != ORC_OK && st != ORC_E_NOT_CONVERGED) return st;
 
   std::vector<double> gx(n, 0.0), gv(n, 0.0), u(n), mu(n), K, A;
-  double gmat[3] = {0.0, 0.0, 0.0};
+  double gmat[3] = {0.0, 0.0, 0.0}, gwind[3] = {0.0, 0.0, 0.0};
   int frame = nloss - 1;
   for (int s = nsteps; s >= 1; --s) {
     const double* xp = &X[(size_t)(s - 1) * n];
@@ -1027,7 +1165,7 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
     adjoint_rhs(*P, gx.data(), gv.data(), u.data());
     // 3. A(x_{s-1}) mu = u  (A is symmetric)
     assemble_ksys(*P, xp, K);
-    system_matrix(*P, K, A);
+    system_matrix(*P, xp, &Vv[(size_t)(s - 1) * n], K, A);
     int it = 0;
     int r = pcg(*P, A, u.data(), mu.data(), &it);
     if (iters_adj) iters_adj[s - 1] = it;
@@ -1037,8 +1175,8 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
     if (dl_dF)
       for (int k = 0; k < n; ++k) dl_dF[(size_t)(s - 1) * n + k] = P->h * mu[k];
     // 5.-9. material, state and velocity gradients through the step
-    adjoint_update(*P, xp, &Vv[(size_t)s * n], &DV[(size_t)s * n], mu.data(), u.data(), gx.data(),
-                   gv.data(), gmat);
+    adjoint_update(*P, xp, &Vv[(size_t)(s - 1) * n], &Vv[(size_t)s * n], &DV[(size_t)s * n],
+                   mu.data(), u.data(), gx.data(), gv.data(), gmat, gwind);
   }
   double gks = gmat[0], gkb = gmat[1], gd = gmat[2];
   if (dl_dmat) {
@@ -1046,6 +1184,8 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
     dl_dmat[1] = gkb;
     dl_dmat[2] = gd;
   }
+  if (dl_dwind)
+    for (int k = 0; k < 3; ++k) dl_dwind[k] = gwind[k];
   if (dl_dx0) std::copy(gx.begin(), gx.end(), dl_dx0);
   if (dl_dv0) std::copy(gv.begin(), gv.end(), dl_dv0);
   P->last_status = st;
@@ -1073,7 +1213,7 @@ int orc_system_blocks(void* h, const double* x, const double* v, const double* F
       for (int k = 0; k < 3; ++k) vm[3 * i + k] = 0.0;
   std::vector<double> K, A;
   assemble_ksys(*P, x, K);
-  system_matrix(*P, K, A);
+  system_matrix(*P, x, vm.data(), K, A);
   step_rhs(*P, x, vm.data(), F, K, b);
   std::copy(A.begin(), A.end(), A_blocks);
   return all_finite(b, n) && all_finite(A.data(), A.size()) ? ORC_OK : ORC_E_NONFINITE;
@@ -1084,12 +1224,34 @@ void orc_adjoint_rhs(void* h, const double* gx, const double* gv, double* u) {
   adjoint_rhs(*static_cast<Problem*>(h), gx, gv, u);
 }
 
-// The rest of one backward step once mu solves A(x_{s-1}) mu = u: accumulates
-// (dL/dk_s, dL/dk_b, dL/dd) into gmat[3] and replaces (gx, gv) in place by the
-// gradients with respect to (x_{s-1}, v_{s-1}). dL/dF_{s-1} is h mu.
-void orc_adjoint_update(void* h, const double* xp, const double* vs, const double* dvs,
-                        const double* mu, const double* u, double* gx, double* gv, double* gmat) {
-  adjoint_update(*static_cast<Problem*>(h), xp, vs, dvs, mu, u, gx, gv, gmat);
+// The rest of one backward step once mu solves A(x_{s-1}, v_{s-1}) mu = u: accumulates
+// (dL/dk_s, dL/dk_b, dL/dd) into gmat[3] and dL/dw into gwind[3], and replaces (gx, gv)
+// in place by the gradients with respect to (x_{s-1}, v_{s-1}). dL/dF_{s-1} is h mu.
+void orc_adjoint_update(void* h, const double* xp, const double* vp, const double* vs,
+                        const double* dvs, const double* mu, const double* u, double* gx,
+                        double* gv, double* gmat, double* gwind) {
+  adjoint_update(*static_cast<Problem*>(h), xp, vp, vs, dvs, mu, u, gx, gv, gmat, gwind);
+}
+
+// Wind (R19): on != 0 switches the aerodynamic force on with velocity (wx, wy, wz)
+// [m/s] and air density rho [kg/m^3].
+int orc_set_wind(void* h, int on, double wx, double wy, double wz, double rho) {
+  Problem* P = static_cast<Problem*>(h);
+  if (!std::isfinite(wx) || !std::isfinite(wy) || !std::isfinite(wz) || !(rho >= 0.0))
+    return ORC_E_INVALID;
+  P->wind_on = on != 0;
+  P->wind[0] = wx;
+  P->wind[1] = wy;
+  P->wind[2] = wz;
+  P->rho_air = rho;
+  return ORC_OK;
+}
+
+// The wind force alone at (x, v) [V][3] (zero when the wind is off).
+void orc_wind_force(void* h, const double* x, const double* v, double* f) {
+  Problem* P = static_cast<Problem*>(h);
+  std::fill(f, f + 3 * P->nv, 0.0);
+  if (P->wind_on) wind_force(*P, x, v, f);
 }
 
 }  // extern "C"

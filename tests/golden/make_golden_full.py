@@ -10,6 +10,7 @@ arrays an FP32 handle receives; the loss is L = sum over the loss frames of
 
     python tests/golden/make_golden_full.py c3
     python tests/golden/make_golden_full.py c4 --workers 4
+    python tests/golden/make_golden_full.py c4t --workers 4
     python tests/golden/make_golden_full.py c5 --workers 6
 
 Large intermediates (the 200x200 trajectory) go to --scratch (default
@@ -79,6 +80,42 @@ def c3(args):
 
 
 # ------------------------------------------------------------- batched sheets
+def c4t_sheet(b):
+    """A sheet of the batched workload under the tension-clamped membrane system
+    (the recorded variant of reading R9, SPD in every state)."""
+    w = W.workload("C4")
+    inst = W.as_given(W.make_instances(w)[b], w.precision)
+    frames = w.loss_frames()
+    o = make_oracle(inst, w)
+    o.set_membrane_system(oracle.Oracle.MEMBRANE_TENSION)
+    t0 = time.time()
+    g = o.gradient_exact(w.steps, inst.x0, inst.v0, inst.forces, frames,
+                         W.loss_targets(w, inst, frames, sheet=b))
+    return dict(sheet=b, nv=inst.n_verts, x=g["x"][-1], material=g["material"], dl_dx0=g["x0"],
+                dl_dF_norm=float(np.linalg.norm(g["forces"])), loss=g["loss"],
+                seconds=time.time() - t0)
+
+
+def c4t(args):
+    w = W.workload("C4")
+    n = len(W.make_instances(w))
+    log(f"C4 (tension membrane system): {n} sheets, {w.steps} steps, {args.workers} processes")
+    t0 = time.time()
+    with mp.get_context("fork").Pool(args.workers) as pool:
+        res = sorted(pool.imap_unordered(c4t_sheet, range(n)), key=lambda r: r["sheet"])
+    nv = np.array([r["nv"] for r in res])
+    out = dict(source=SOLVER + "; tension-clamped membrane block in the step matrix",
+               workload="C4 tension", steps=w.steps, seconds=time.time() - t0, sheet_nv=nv,
+               x=f32(np.concatenate([r["x"] for r in res])),
+               dl_dx0=f32(np.concatenate([r["dl_dx0"] for r in res])),
+               material=np.array([r["material"] for r in res]),
+               dl_dF_norm=np.array([r["dl_dF_norm"] for r in res]),
+               loss=np.array([r["loss"] for r in res]))
+    path = os.path.join(HERE, "c4_tension_oracle.npz")
+    np.savez_compressed(path, **out)
+    log(f"wrote {path}")
+
+
 def c4_sheet(b):
     w = W.workload("C4")
     inst = W.as_given(W.make_instances(w)[b], w.precision)
@@ -220,7 +257,10 @@ def c5(args):
         xs = np.ascontiguousarray(X[s - 1])
         vs = np.ascontiguousarray(Vv[s])
         dvs = np.ascontiguousarray(DV[s])
-        lib.orc_adjoint_update(o._h, d(xs), d(vs), d(dvs), d(mu), d(u), d(gx), d(gv), d(gm))
+        vp = np.ascontiguousarray(Vv[s - 1])
+        gw = np.zeros(3)
+        lib.orc_adjoint_update(o._h, d(xs), d(vp), d(vs), d(dvs), d(mu), d(u), d(gx), d(gv), d(gm),
+                               d(gw))
         if s % 10 == 0:
             log(f"C5 backward step {s} ({time.time() - t1:.0f} s)")
     for p in procs:
@@ -240,13 +280,13 @@ def c5(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["c3", "c4", "c5"])
+    ap.add_argument("which", choices=["c3", "c4", "c4t", "c5"])
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--steps", type=int, default=0, help="C5: a shorter rollout (test runs)")
     ap.add_argument("--scratch", default="/tmp/phisft_golden")
     ap.add_argument("--reuse", action="store_true", help="C5: reuse stored forward states")
     args = ap.parse_args()
-    dict(c3=c3, c4=c4, c5=c5)[args.which](args)
+    dict(c3=c3, c4=c4, c4t=c4t, c5=c5)[args.which](args)
 
 
 if __name__ == "__main__":

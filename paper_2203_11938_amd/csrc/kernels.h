@@ -15,6 +15,7 @@ struct AssembleArgs {
   double h;
   double g[3];
   int want_rhs;        // 0: matrix and preconditioner only (adjoint re-assembly)
+  int wind;            // 1: add the elements' wind force and damping blocks (h D)
   TM* A;               // [maxnz][9][nv]
   TM* Jinv;            // [9][nv]
   double* b;           // [3][nv]
@@ -47,12 +48,17 @@ struct AdjArgs {
   double* gx;          // [3][nv] running dL/dx
   double* gv;          // [3][nv] running dL/dv
   T* dl_dF;            // [3][nv] slice of dL/dF for step s, or nullptr
+  const double* wind;  // [ninst][3] wind velocity, or nullptr (no aerodynamic force)
+  double rho;          // air density
 };
 
 void launch_fill_int(int* p, int n, int v, hipStream_t st);
 void launch_fill_double(double* p, long n, double v, hipStream_t st);
 
-void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* mat, int* status,
+// Element pass at (x, v): forces and stiffness blocks, and with a wind velocity
+// (wind != nullptr, [ninst][3]) the triangles' aerodynamic force and damping blocks.
+void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* v,
+                     const double* mat, const double* wind, double rho, int* status,
                      hipStream_t st);
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st);
@@ -97,7 +103,10 @@ void launch_adj_rows(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStre
 template <typename T>
 void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0, T* dv0,
                       hipStream_t st);
-void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st);
+// Per-sheet sums of the material (out_mat [ninst][3]) and wind (out_wind [ninst][3])
+// gradient partials; either output may be nullptr.
+void launch_material_sum(const Mesh& m, const Elem& el, double* out_mat, double* out_wind,
+                         hipStream_t st);
 
 // Bytes of the static device array behind the allocation-free rollout's solver
 // exchange buffers (one copy per GPU, held for the process's lifetime).

@@ -345,10 +345,31 @@ __device__ __forceinline__ void hinge_load(const Mesh& m, const double* __restri
   }
 }
 
+// Aerodynamic force of a triangle with vertices at xa, xa + e1, xa + e2 for a wind
+// relative to its mean vertex velocity rel: unit normal n, s = n . rel, and its
+// |N| = 2 x deformed area.
+__device__ __forceinline__ void wind_frame(const double e1[3], const double e2[3],
+                                           const double rel[3], double n[3], double& sn,
+                                           double& ln) {
+  const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+  ln = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) n[k] = N[k] / ln;
+  sn = n[0] * rel[0] + n[1] * rel[1] + n[2] * rel[2];
+}
+
 // ------------------------------------------------------ forward: elements
-// Threads [0, nt) take triangles, [nt, nt + nh) hinges.
+// Threads [0, nt) take triangles, [nt, nt + nh) hinges. With a wind (wind != nullptr,
+// the sheets' velocities w), every triangle also gets its aerodynamic force
+// rho area |s| s n (n its unit normal at x, s = n . (w - its mean vertex velocity at v),
+// area its rest area), a third to each vertex, and the factor c = 2 rho area |s| / 9 of
+// its damping blocks: every 3x3 block of its -df/dv is c n n^T.
 __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double* __restrict__ x,
-                                                  const double* __restrict__ mat, int* status) {
+                                                  const double* __restrict__ vel,
+                                                  const double* __restrict__ mat,
+                                                  const double* __restrict__ wind, double rho,
+                                                  int* status) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid < m.nt) {
     const int t = gid, nt = m.nt;
@@ -405,6 +426,26 @@ __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double*
             el.tri_K[((i * 3 + j) * 9 + r * 3 + c) * nt + t] = k;
           }
       }
+    if (wind) {
+      double e1[3], e2[3], rel[3], n[3], sn, ln;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double xa = x[r * m.nv + v[0]];
+        e1[r] = x[r * m.nv + v[1]] - xa;
+        e2[r] = x[r * m.nv + v[2]] - xa;
+        rel[r] = wind[3 * inst + r] -
+                 (vel[r * m.nv + v[0]] + vel[r * m.nv + v[1]] + vel[r * m.nv + v[2]]) / 3.0;
+      }
+      wind_frame(e1, e2, rel, n, sn, ln);
+      const double ra = rho * s.area, mag = ra * fabs(sn) * sn;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        el.tri_fw[r * nt + t] = mag * n[r] / 3.0;
+        el.tri_wn[r * nt + t] = n[r];
+        ok = ok && isfinite(mag * n[r]);
+      }
+      el.tri_wn[3 * nt + t] = 2.0 * ra * fabs(sn) / 9.0;
+    }
     if (!ok) set_status(status, inst, ST_NONFINITE);
   } else if (gid < m.nt + m.nh) {
     const int e = gid - m.nt, nh = m.nh;
@@ -430,10 +471,12 @@ __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double*
 }
 
 // ----------------------------------------------------- forward: assembly
-// Sum of the stiffness contributions of slot s (fixed order).
-__device__ __forceinline__ void slot_block(const Mesh& m, const Elem& el, int s, double K[9]) {
+// Sum of the stiffness contributions of slot s (fixed order); with wind, also the
+// triangles' damping blocks c n n^T in D.
+__device__ __forceinline__ void slot_block(const Mesh& m, const Elem& el, int s, bool wind,
+                                           double K[9], double D[9]) {
 #pragma unroll
-  for (int q = 0; q < 9; ++q) K[q] = 0.0;
+  for (int q = 0; q < 9; ++q) K[q] = D[q] = 0.0;
   const int nt = m.nt, nh = m.nh;
   for (int c = m.slot_ptr[s]; c < m.slot_ptr[s + 1]; ++c) {
     int ref = m.slot_ref[c];
@@ -441,6 +484,14 @@ __device__ __forceinline__ void slot_block(const Mesh& m, const Elem& el, int s,
       int t = ref / 9, ab = ref - 9 * (ref / 9);
 #pragma unroll
       for (int q = 0; q < 9; ++q) K[q] += el.tri_K[(ab * 9 + q) * nt + t];
+      if (wind) {
+        const double n[3] = {el.tri_wn[t], el.tri_wn[nt + t], el.tri_wn[2 * nt + t]};
+        const double cw = el.tri_wn[3 * nt + t];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) D[r * 3 + q] += cw * n[r] * n[q];
+      }
     } else {
       int r2 = -ref - 1;
       int e = r2 >> 4, a = (r2 >> 2) & 3, b = r2 & 3;
@@ -503,8 +554,8 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
 #pragma unroll
       for (int q = 0; q < 9; ++q) Ab[q] = 0.0;
     } else {
-      double K[9];
-      slot_block(m, el, s, K);
+      double K[9], D[9];
+      slot_block(m, el, s, a.wind != 0, K, D);
       const bool pin_j = m.pinned[j] != 0;
       if (a.want_rhs && !pin_j) {
         double vj[3] = {a.v[j], a.v[nv + j], a.v[2 * nv + j]};
@@ -515,8 +566,13 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
 #pragma unroll
         for (int q = 0; q < 9; ++q) Ab[q] = (i == j && (q % 4) == 0) ? 1.0 : 0.0;
       } else {
+        if (a.wind) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Ab[q] = h2 * K[q];
+          for (int q = 0; q < 9; ++q) Ab[q] = h2 * K[q] + h * D[q];
+        } else {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) Ab[q] = h2 * K[q];
+        }
         if (i == j) {
           Ab[0] += mass;
           Ab[4] += mass;
@@ -550,6 +606,10 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
       int t = ref / 3, va = ref - 3 * (ref / 3);
 #pragma unroll
       for (int r = 0; r < 3; ++r) f[r] += el.tri_f[(va * 3 + r) * m.nt + t];
+      if (a.wind) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) f[r] += el.tri_fw[r * m.nt + t];
+      }
     } else {
       int r2 = -ref - 1;
       int e = r2 >> 2, va = r2 & 3;
@@ -2412,6 +2472,54 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
         part += mu[i][r] * (-h * A * pf) - h2 * vv[i][r] * (A * qs);
       }
     el.acc_ks[t] += part;
+    if (a.wind) {
+      // The wind's share of the step: h f_w in b and h D in A, so the adjoint takes the
+      // gradient of Phi = h (mu . f_w - mu^T D dv) over the triangle's positions,
+      // velocities v_{s-1} and the wind w. With mean vertex values mb (of mu) and db (of
+      // dv = v_s - v_{s-1}), s = n . (w - mean v_{s-1}), a = n . mb, b = n . db and
+      // ra = rho area: Phi = h ra |s| a (s - 2 b), so
+      //   dPhi/ds = 2 h ra a (|s| - sgn(s) b)      (n held fixed)
+      //   dPhi/dn = dPhi/ds (w - mean v) + h ra |s| ((s - 2 b) mb - 2 a db),
+      // through n = N / |N| and N = (x_b - x_a) x (x_c - x_a) to the positions; s gives
+      // dPhi/dw = dPhi/ds n and dPhi/dv_j = -dPhi/ds n / 3 for each vertex j.
+      const double* wv = a.wind + 3 * m.tri_inst[t];
+      double e1[3], e2[3], rel[3], mb[3], db[3], n[3], sn, ln;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double xa = a.x[r * nv + v[0]];
+        e1[r] = a.x[r * nv + v[1]] - xa;
+        e2[r] = a.x[r * nv + v[2]] - xa;
+        const double p0 = a.vp[r * nv + v[0]], p1 = a.vp[r * nv + v[1]], p2 = a.vp[r * nv + v[2]];
+        rel[r] = wv[r] - (p0 + p1 + p2) / 3.0;
+        mb[r] = (mu[0][r] + mu[1][r] + mu[2][r]) / 3.0;
+        db[r] = ((vv[0][r] - p0) + (vv[1][r] - p1) + (vv[2][r] - p2)) / 3.0;
+      }
+      wind_frame(e1, e2, rel, n, sn, ln);
+      const double ra = a.rho * s.area, as = fabs(sn), sg = sn >= 0.0 ? 1.0 : -1.0;
+      const double an = n[0] * mb[0] + n[1] * mb[1] + n[2] * mb[2];
+      const double bn = n[0] * db[0] + n[1] * db[1] + n[2] * db[2];
+      const double dps = 2.0 * h * ra * an * (as - sg * bn);
+      double gn[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        gn[r] = dps * rel[r] + h * ra * as * ((sn - 2.0 * bn) * mb[r] - 2.0 * an * db[r]);
+      const double ng = n[0] * gn[0] + n[1] * gn[1] + n[2] * gn[2];
+      double gN[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) gN[r] = (gn[r] - n[r] * ng) / ln;
+      const double gb[3] = {e2[1] * gN[2] - e2[2] * gN[1], e2[2] * gN[0] - e2[0] * gN[2],
+                            e2[0] * gN[1] - e2[1] * gN[0]};
+      const double gc[3] = {gN[1] * e1[2] - gN[2] * e1[1], gN[2] * e1[0] - gN[0] * e1[2],
+                            gN[0] * e1[1] - gN[1] * e1[0]};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        el.tri_ag[r * nt + t] -= gb[r] + gc[r];
+        el.tri_ag[(3 + r) * nt + t] += gb[r];
+        el.tri_ag[(6 + r) * nt + t] += gc[r];
+        el.tri_wv[r * nt + t] = -dps * n[r] / 3.0;
+        el.acc_w[r * nt + t] += dps * n[r];
+      }
+    }
   } else if (gid < m.nt + m.nh) {
     const int e = gid - m.nt, nh = m.nh;
     int v[4];
@@ -2464,7 +2572,7 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
   const int nv = m.nv;
   if (i >= nv) return;
   const double h = a.h, h2 = a.h * a.h;
-  double ag[3] = {0.0, 0.0, 0.0}, ak[3] = {0.0, 0.0, 0.0};
+  double ag[3] = {0.0, 0.0, 0.0}, ak[3] = {0.0, 0.0, 0.0}, aw[3] = {0.0, 0.0, 0.0};
   for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
     int ref = m.vinc_ref[c];
     if (ref >= 0) {
@@ -2473,6 +2581,10 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
       for (int r = 0; r < 3; ++r) {
         ag[r] += el.tri_ag[(va * 3 + r) * m.nt + t];
         ak[r] += el.tri_ak[(va * 3 + r) * m.nt + t];
+      }
+      if (a.wind) {
+#pragma unroll
+        for (int r = 0; r < 3; ++r) aw[r] += el.tri_wv[r * m.nt + t];
       }
     } else {
       int r2 = -ref - 1;
@@ -2491,7 +2603,8 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
   for (int r = 0; r < 3; ++r) {
     const double mu = a.mu[r * nv + i];
     a.gx[r * nv + i] += ag[r];
-    a.gv[r * nv + i] = pin ? 0.0 : a.u[r * nv + i] - h2 * ak[r];
+    a.gv[r * nv + i] = pin ? 0.0 : (a.wind ? a.u[r * nv + i] - h2 * ak[r] + aw[r]
+                                           : a.u[r * nv + i] - h2 * ak[r]);
     if (a.dl_dF) a.dl_dF[r * nv + m.vold[i]] = (T)(h * mu);
     const double dv = pin ? 0.0 : a.vs[r * nv + i] - a.vp[r * nv + i];
     dpart += mu * (h * varea * a.g[r] - varea * dv);
@@ -2512,8 +2625,10 @@ __global__ void __launch_bounds__(256) k_adj_final(int nv, const int* __restrict
   if (dv0) dv0[o] = (T)gv[k];
 }
 
-// One workgroup per sheet: fixed-order sums of the per-element partials.
-__global__ void __launch_bounds__(256) k_material_sum(Mesh m, Elem el, double* __restrict__ out) {
+// One workgroup per sheet: fixed-order sums of the per-element partials (the material
+// gradient into out, and with out_wind the wind gradient).
+__global__ void __launch_bounds__(256) k_material_sum(Mesh m, Elem el, double* __restrict__ out,
+                                                      double* __restrict__ out_wind) {
   __shared__ double s_part[3][4];
   const int inst = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -2541,9 +2656,32 @@ __global__ void __launch_bounds__(256) k_material_sum(Mesh m, Elem el, double* _
       r1 += s_part[1][q];
       r2 += s_part[2][q];
     }
-    out[3 * inst + 0] = r0;
-    out[3 * inst + 1] = r1;
-    out[3 * inst + 2] = r2;
+    if (out) {
+      out[3 * inst + 0] = r0;
+      out[3 * inst + 1] = r1;
+      out[3 * inst + 2] = r2;
+    }
+  }
+  if (!out_wind) return;   // uniform
+  double w3[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nt; k += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w3[c] += el.acc_w[c * m.nt + toff + k];
+  __syncthreads();   // s_part is reused
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    w3[c] = wave_sum(w3[c]);
+    if (lane == 0) s_part[c][wave] = w3[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double r = 0.0;
+      for (int q = 0; q < nwaves; ++q) r += s_part[c][q];
+      out_wind[3 * inst + c] = r;
+    }
   }
 }
 
@@ -2603,11 +2741,12 @@ void launch_fill_double(double* p, long n, double v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_double, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
 }
 
-void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* mat, int* status,
+void launch_elements(const Mesh& m, const Elem& el, const double* x, const double* v,
+                     const double* mat, const double* wind, double rho, int* status,
                      hipStream_t st) {
   long n = (long)m.nt + m.nh;
-  hipLaunchKernelGGL(k_elements, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, mat,
-                     status);
+  hipLaunchKernelGGL(k_elements, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, v, mat,
+                     wind, rho, status);
 }
 
 template <typename T, typename TM>
@@ -2788,8 +2927,10 @@ void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0,
                      m.vold, gx, gv, dx0, dv0);
 }
 
-void launch_material_sum(const Mesh& m, const Elem& el, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_material_sum, dim3(m.ninst), dim3(256), 0, st, m, el, out);
+void launch_material_sum(const Mesh& m, const Elem& el, double* out_mat, double* out_wind,
+                         hipStream_t st) {
+  if (!out_mat && !out_wind) return;
+  hipLaunchKernelGGL(k_material_sum, dim3(m.ninst), dim3(256), 0, st, m, el, out_mat, out_wind);
 }
 
 #define PHISFT_INSTANTIATE_ASM(T, TM)                                                             \

@@ -268,7 +268,7 @@ sim_status autotune(sim_t* s, const std::vector<HostPlan>& cands, const std::vec
   HIPCHECK(s, hipMemcpy(x, xr.data(), 3 * (size_t)nv * 8, hipMemcpyHostToDevice));
   hipStream_t st = nullptr;
   launch_fill_double(s->gv, 3L * nv, 0.0, st);
-  launch_elements(s->mesh, s->el, x, s->mat_default, s->status, st);
+  launch_elements(s->mesh, s->el, x, s->gv, s->mat_default, nullptr, 0.0, s->status, st);
   AssembleArgs<double, TM> a{};
   a.v = s->gv;
   a.forces = nullptr;
@@ -564,6 +564,10 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, nt * 8, &q)); el.acc_ks = (double*)q;
   TRY(alloc(s, nh * 8, &q)); el.acc_kb = (double*)q;
   TRY(alloc(s, nv * 8, &q)); el.acc_d = (double*)q;
+  TRY(alloc(s, 3 * nt * 8, &q)); el.tri_fw = (double*)q;
+  TRY(alloc(s, 4 * nt * 8, &q)); el.tri_wn = (double*)q;
+  TRY(alloc(s, 3 * nt * 8, &q)); el.tri_wv = (double*)q;
+  TRY(alloc(s, 3 * nt * 8, &q)); el.acc_w = (double*)q;
   TRY(alloc(s, (size_t)L.maxnz * 9 * nv * s->msize, &s->A));
   TRY(alloc(s, 9 * nv * s->msize, &s->Jinv));
   TRY(alloc(s, 3 * nv * 8, &q)); s->rhs = (double*)q;
@@ -708,7 +712,7 @@ void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, cons
   const double* vp = xp + 3 * (size_t)nv;
   double* xn = reinterpret_cast<double*>(sn);
   double* vn = xn + 3 * (size_t)nv;
-  launch_elements(s->mesh, s->el, xp, mat, s->status, st);
+  launch_elements(s->mesh, s->el, xp, vp, mat, s->wind, s->rho_air, s->status, st);
   AssembleArgs<T, TM> a{};
   a.v = vp;
   a.forces = F;
@@ -716,6 +720,7 @@ void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, cons
   a.h = s->h;
   for (int k = 0; k < 3; ++k) a.g[k] = s->grav[k];
   a.want_rhs = 1;
+  a.wind = s->wind ? 1 : 0;
   a.A = static_cast<TM*>(s->A);
   a.Jinv = static_cast<TM*>(s->Jinv);
   a.b = s->rhs;
@@ -779,7 +784,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   const double* vs = reinterpret_cast<const double*>(sn) + 3 * (size_t)nv;
   double* u = s->rhs;  // the adjoint right-hand side reuses the forward rhs buffer
   launch_adj_pre<T>(s->mesh, dl, s->h, s->gx, s->gv, u, s->status, st);
-  launch_elements(s->mesh, s->el, xp, s->material, s->status, st);
+  launch_elements(s->mesh, s->el, xp, vp, s->material, s->wind, s->rho_air, s->status, st);
   AssembleArgs<T, TM> a{};
   a.v = vp;
   a.forces = nullptr;
@@ -787,6 +792,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   a.h = s->h;
   for (int q = 0; q < 3; ++q) a.g[q] = s->grav[q];
   a.want_rhs = 0;
+  a.wind = s->wind ? 1 : 0;
   a.A = static_cast<TM*>(s->A);
   a.Jinv = static_cast<TM*>(s->Jinv);
   a.b = nullptr;
@@ -822,16 +828,19 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   j.gx = s->gx;
   j.gv = s->gv;
   j.dl_dF = dlF;
+  j.wind = s->wind;
+  j.rho = s->rho_air;
   launch_adj_elements<T>(s->mesh, s->el, j, st);
   launch_adj_rows<T>(s->mesh, s->el, j, st);
 }
 
 template <typename T, typename TM>
-sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF, void* dl_dx0,
-                        void* dl_dv0, hipStream_t st) {
+sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dwind, void* dl_dF,
+                        void* dl_dx0, void* dl_dv0, hipStream_t st) {
   const int nv = s->L.nv, ni = s->L.ninst, n = s->n_steps;
   launch_fill_double(s->gx, 3L * nv, 0.0, st);
   launch_fill_double(s->gv, 3L * nv, 0.0, st);
+  if (s->wind) launch_fill_double(s->el.acc_w, 3L * s->L.nt, 0.0, st);
   launch_fill_double(s->el.acc_ks, s->L.nt, 0.0, st);
   launch_fill_double(s->el.acc_kb, s->L.nh, 0.0, st);
   launch_fill_double(s->el.acc_d, nv, 0.0, st);
@@ -859,7 +868,8 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dF,
     }
   }
   launch_adj_final<T>(s->mesh, s->gx, s->gv, static_cast<T*>(dl_dx0), static_cast<T*>(dl_dv0), st);
-  if (dl_dmat) launch_material_sum(s->mesh, s->el, static_cast<double*>(dl_dmat), st);
+  launch_material_sum(s->mesh, s->el, static_cast<double*>(dl_dmat), static_cast<double*>(dl_dwind),
+                      st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(s, e, "adjoint launch");
   return SIM_OK;
@@ -923,10 +933,6 @@ sim_status begin_rollout(sim_t* s, int n_steps, const void* x0, const void* forc
       return SIM_E_INVALID;
     }
     prev = loss_frames[k];
-  }
-  if (wind) {
-    s->err = "wind is not supported by this build";
-    return SIM_E_INVALID;
   }
   s->have_rollout = false;
   s->have_adjoint = false;
@@ -1123,11 +1129,15 @@ sim_status sim_adjoint(sim_t* s, const void* dl_dx, void* dl_dmaterial, void* dl
   return graphed(s, s->gadj, key, s->stream, [&](hipStream_t q) {
     if (s->prec == SIM_FP64)
       return s->mprec == SIM_FP64
-                 ? adjoint_impl<double, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q)
-                 : adjoint_impl<double, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q);
+                 ? adjoint_impl<double, double>(s, dl_dx, dl_dmaterial, dl_dwind, dl_dforces,
+                                                dl_dx0, dl_dv0, q)
+                 : adjoint_impl<double, float>(s, dl_dx, dl_dmaterial, dl_dwind, dl_dforces,
+                                               dl_dx0, dl_dv0, q);
     return s->mprec == SIM_FP64
-               ? adjoint_impl<float, double>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q)
-               : adjoint_impl<float, float>(s, dl_dx, dl_dmaterial, dl_dforces, dl_dx0, dl_dv0, q);
+               ? adjoint_impl<float, double>(s, dl_dx, dl_dmaterial, dl_dwind, dl_dforces, dl_dx0,
+                                             dl_dv0, q)
+               : adjoint_impl<float, float>(s, dl_dx, dl_dmaterial, dl_dwind, dl_dforces, dl_dx0,
+                                            dl_dv0, q);
   });
 }
 

@@ -74,6 +74,12 @@ struct Elem {
   double* acc_ks;   // [nt] dL/dk_s partial sums over steps
   double* acc_kb;   // [nh]
   double* acc_d;    // [nv]
+  // wind (aerodynamic force of each triangle, used when the rollout has a wind)
+  double* tri_fw;   // [3][nt]  a vertex's share (a third) of the triangle's wind force
+  double* tri_wn;   // [4][nt]  unit normal n and c = 2 rho area |s| / 9: every 3x3 block
+                    //          of the triangle's -df/dv is c n n^T
+  double* tri_wv;   // [3][nt]  adjoint: each vertex's velocity-gradient term
+  double* acc_w;    // [3][nt]  dL/dw partial sums over steps
 };
 
 // Coarse space of the two-level preconditioner M^-1 = B^-1 + P A_c^-1 P^T (B: the

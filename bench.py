@@ -1,15 +1,17 @@
 """Benchmark: one full gradient (rollout + adjoint) of the differentiable cloth step.
 
 Workload (headline): a 64x64-vertex sheet (0.5 m, 7938 triangles), 100 steps of
-0.01 s, top corners pinned, per-step Gaussian wind load 0.05 N/m^2, material
-k_s 1e3 N/m, k_b 1e-4 N m, d 0.1 kg/m^2, FP32 state with FP64 solver vectors,
-CG tolerance 1e-7, every state stored. Loss: summed squared distance to a target
-rollout (material scaled by seeded factors). A benchmark "step" is one gradient.
+0.01 s, top corners pinned, per-step Gaussian load 0.05 N/m^2 on each vertex's area
+share, material k_s 1e3 N/m, k_b 1e-4 N m, d 0.1 kg/m^2, FP32 arrays at the
+boundary with FP64 state, element arithmetic and solver vectors, CG tolerance 1e-7,
+every state stored. Loss: summed squared distance to a target rollout (material
+scaled by seeded factors). A benchmark "step" is one gradient.
 
 Prints one JSON line with the throughput in vertex-steps/s (vertices x simulated
 steps / wall time of rollout + adjoint, inputs resident on the GPU), the roofline
-of the dominant kernel (the persistent PCG) and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+of the dominant kernel (the persistent PCG), the 200x200 sheet's gradient with its
+own roofline (sub-object "c5"), and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
 """
 
 from __future__ import annotations
@@ -65,7 +67,25 @@ def block_pattern_size(tris, nv: int) -> int:
     return int(np.unique(allp[:, 0] * nv + allp[:, 1]).size)
 
 
-def cpu_baseline(w, inst, sample_steps: int):
+def host_cpu() -> dict:
+    """The host's CPU model and core counts (the oracle runs on one of them)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(model=model, logical_cpus=os.cpu_count(), usable_cpus=usable)
+
+
+def cpu_baseline(w, inst, sample_steps: int, gpu_iters_per_solve: float):
     import numpy as np
     import oracle
     o = oracle.Oracle(inst.tris, inst.rest, inst.pins, *inst.material.as_tuple(), dt=w.dt,
@@ -75,12 +95,17 @@ def cpu_baseline(w, inst, sample_steps: int):
     xo, _, _, _ = o.rollout(sample_steps, inst.x0, inst.v0, F, frames)
     tgt = inst.x0[None] + 0.01
     t0 = time.perf_counter()
-    o.gradient(sample_steps, inst.x0, inst.v0, F, frames, 2.0 * (xo - tgt))
+    g = o.gradient(sample_steps, inst.x0, inst.v0, F, frames, 2.0 * (xo - tgt))
     dt = time.perf_counter() - t0
+    its = float(np.mean(np.concatenate([g["iters_fwd"], g["iters_adj"]])))
     return dict(value=inst.n_verts * sample_steps / dt, unit="vertex-steps/s", cores=1,
-                kind="oracle",
+                kind="oracle", host=host_cpu(),
                 sample=f"first {sample_steps} of the {w.steps} steps of the same sheet, rollout "
-                       f"+ adjoint in one single-threaded FP64 call ({dt:.1f} s)")
+                       f"+ adjoint in one single-threaded FP64 call ({dt:.1f} s)",
+                solver=f"the oracle solves each step by block-Jacobi CG ({its:.0f} iterations "
+                       f"per solve); the GPU by pipelined CG with a three-level preconditioner "
+                       f"({gpu_iters_per_solve:.0f} per solve): the ratio mixes algorithm and "
+                       "hardware")
 
 
 def sequential_comparison(w, insts, batched_ms, steps, membrane, autotune):
@@ -190,6 +215,12 @@ def main():
     ap.add_argument("--sequential", action="store_true",
                     help="batched workloads: also time one handle per sheet, run back to back, "
                          "and report the batched speed-up")
+    ap.add_argument("--c5-steps", type=int, default=3, metavar="K",
+                    help="also time K gradients of the 200x200 sheet (C5) after one warm-up, "
+                         "reported in the 'c5' sub-object with its own roofline (0: skip)")
+    ap.add_argument("--chamfer-steps", type=int, default=10, metavar="K",
+                    help="also time K Chamfer-distance calls (Eq. 10) of 65,536 x 40,000 points, "
+                         "reported in the 'chamfer' sub-object (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (untimed), the "
                          "known-size reference for scaling HBM byte counters")
@@ -218,13 +249,145 @@ def main():
         del a, b
     print(f"bench: workload {w.name}, {len(insts)} sheet(s), {w.steps} steps", file=sys.stderr,
           flush=True)
+    run = timed_gradients(w, insts, args.steps, args.warmup, args.membrane,
+                          not args.no_autotune, args.coarse_size)
+    sim, st, ms, value = run["sim"], run["stats"], run["ms"], run["value"]
+    sides = [int(round(np.sqrt(i.n_verts))) for i in insts]
+    roof = roofline(sim, insts, st, run["sheet_iters"], run["iters"], run["wall"],
+                    measured_traffic(w.name))
+    lib = S.library_identity()
+    out = dict(metric="vertex-steps/s forward+adjoint (ms per gradient, 100-step 64\u00d764 "
+                      "sheet); % HBM peak",
+               value=round(value, 1), unit="vertex-steps/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload=(f"{w.name}: {w.n}x{w.n} sheet" if len(insts) == 1 else
+                                     f"{w.name}: {len(insts)} sheets of {min(sides)}..{max(sides)} per side") +
+                           f", {w.steps} steps of {w.dt} s, rollout + adjoint",
+                           sheets=len(insts), vertices=sim.n_verts, sim_steps=w.steps,
+                           cg_tol=w.cg_tol, cg_iters_per_gradient=run["iters"] // args.steps,
+                           solver_blocks=st["blocks"], rows_per_block=st["rows_per_block"],
+                           matrix_precision=sim.matrix_precision, membrane=args.membrane,
+                           forces="N(0, 0.05^2) N/m^2 per vertex times its area share"
+                           if w.forces == "gauss" else w.forces,
+                           coarse_aggregates=st["coarse_aggregates"],
+                           coarse_max_dim=st["coarse_max_dim"],
+                           autotuned=bool(st["autotuned"]),
+                           autotune_candidates=st["autotune_candidates"],
+                           solver_matrix=S.MATRIX_HOMES[st["solver_matrix_home"]],
+                           solver_launches_per_solve=st["solver_launches_per_solve"],
+                           solver_wg_per_cu=st["solver_wg_per_cu"],
+                           coarse_rows_lds=bool(st["coarse_rows_lds"]),
+                           device_bytes=int(st["device_bytes"]),
+                           device_status=S.status_name(sim.status()),
+                           library=lib),
+               roofline=roof)
+    sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
+    if args.graph:
+        print("bench: graph-mode handle", file=sys.stderr, flush=True)
+        out["graph_mode"] = variant_timing(w, sheets, run["x0"], run["v0"], run["F"], run["tgt"],
+                                           w.loss_frames(), args.steps, args.warmup,
+                                           args.membrane, not args.no_autotune, graph=True)
+    if args.checkpoint_report > 0 and w.checkpoint_every == 0:
+        print(f"bench: checkpoint every {args.checkpoint_report}", file=sys.stderr, flush=True)
+        out["checkpointed"] = variant_timing(w, sheets, run["x0"], run["v0"], run["F"], run["tgt"],
+                                             w.loss_frames(), args.steps, args.warmup,
+                                             args.membrane, not args.no_autotune,
+                                             checkpoint_every=args.checkpoint_report)
+    if args.sequential and len(insts) > 1:
+        out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
+                                                             args.membrane, not args.no_autotune)
+    gpu_ips = run["iters"] / max(1, args.steps * w.steps * 2 * len(insts))
+    sim.close()
+    del run
+    if args.c5_steps > 0 and w.name != "C5":
+        # the 200x200 sheet (300 steps, checkpoint every 30): its own timed gradients and
+        # solver roofline, next to the headline
+        w5 = W.workload("C5")
+        insts5 = W.make_instances(w5)
+        print(f"bench: C5, 200x200 sheet, {w5.steps} steps", file=sys.stderr, flush=True)
+        r5 = timed_gradients(w5, insts5, args.c5_steps, 1, args.membrane, not args.no_autotune,
+                             args.coarse_size)
+        st5 = r5["stats"]
+        out["c5"] = dict(workload="C5: 200x200 sheet, 300 steps of 0.005 s, checkpoint every 30, "
+                                  "rollout + adjoint",
+                         steps=args.c5_steps, warmup=1, ms_per_gradient=round(r5["ms"], 3),
+                         value=round(r5["value"], 1), unit="vertex-steps/s",
+                         cg_iters_per_gradient=r5["iters"] // args.c5_steps,
+                         cg_iters_recompute=int(st5["cg_iters_recompute"]),
+                         device_bytes=int(st5["device_bytes"]),
+                         coarse_store_slots=int(st5["coarse_store_slots"]),
+                         solver_blocks=st5["blocks"], rows_per_block=st5["rows_per_block"],
+                         roofline=roofline(r5["sim"], insts5, st5, r5["sheet_iters"],
+                                           r5["iters"], r5["wall"], measured_traffic("C5")))
+        r5["sim"].close()
+        del r5
+    if args.chamfer_steps > 0:
+        print("bench: Chamfer distance", file=sys.stderr, flush=True)
+        out["chamfer"] = chamfer_timing(65536, 40000, args.chamfer_steps, 3)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps, gpu_ips)
+    print(json.dumps(out), flush=True)
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X
+
+
+def chamfer_timing(n_g: int, n_m: int, steps: int, warmup: int):
+    """The Chamfer distance (Eq. 10) of a 65,536-point scan against the 40,000 points of
+    a 200x200 reconstruction (seeded synthetic clouds), timed with HIP events around
+    every call on its stream. Roofline: ALU-bound; 8 FLOP per point pair and direction
+    (3 differences, 3 squares, 2 additions), 2 n_g n_m pairs per call."""
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+    g, m = W.chamfer_points(n_g, n_m)
+    dev = torch.device("cuda:0")
+    gt = torch.tensor(np.ascontiguousarray(g.T), dtype=torch.float32, device=dev)
+    mt = torch.tensor(np.ascontiguousarray(m.T), dtype=torch.float32, device=dev)
+    ws = torch.empty(S.load_library().sim_chamfer_workspace_bytes(n_g, n_m), dtype=torch.uint8,
+                     device=dev)
+    for _ in range(warmup):
+        S.chamfer(gt, mt, workspace=ws)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        ch = S.chamfer(gt, mt, workspace=ws)
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    flops = 8.0 * 2.0 * n_g * n_m
+    achieved = flops / (ms * 1e-3) / 1e12
+    return dict(workload=f"Chamfer distance (Eq. 10): {n_g} scan points vs {n_m} "
+                         "reconstruction points, both directions, FP32 distances, FP64 means",
+                steps=steps, warmup=warmup, ms_per_call=round(ms, 4),
+                wall_ms_per_call=round(1e3 * wall / steps, 4),
+                value=round(2.0 * n_g * n_m / (ms * 1e-3), 1), unit="point pairs/s",
+                chamfer=float(ch.item()),
+                roofline=dict(bound="alu", achieved=round(achieved, 2),
+                              peak=FP32_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
+                              kernel="k_chamfer_nn (HIP events around the whole call: "
+                                     "the fill, unpack and sum launches around it included)"))
+
+
+def timed_gradients(w, insts, steps, warmup, membrane, autotune, coarse_size):
+    """A handle over the workload's sheets, warm-up gradients, then `steps` timed
+    gradients (rollout + adjoint, inputs resident on the device) with solver timing on."""
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+    dev = torch.device("cuda:0")
     sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
     sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
                       checkpoint_every=w.checkpoint_every, max_steps=w.steps,
-                      membrane=args.membrane, autotune=not args.no_autotune,
-                      coarse_size=args.coarse_size)
+                      membrane=membrane, autotune=autotune, coarse_size=coarse_size)
     dt = sim.dtype
-    V = sim.n_verts
     x0 = torch.tensor(W.to_soa(np.concatenate([i.x0 for i in insts])), dtype=dt, device=dev)
     v0 = torch.tensor(W.to_soa(np.concatenate([i.v0 for i in insts])), dtype=dt, device=dev)
     F = torch.tensor(W.to_soa(np.concatenate([i.forces for i in insts], axis=1)), dtype=dt,
@@ -238,10 +401,9 @@ def main():
 
     def gradient():
         xo = sim.rollout(w.steps, x0, v0, F, None, frames)
-        g = sim.adjoint((2.0 * (xo - tgt)).contiguous())
-        return g
+        return sim.adjoint((2.0 * (xo - tgt)).contiguous())
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         gradient()
         sim.status()
     sim.set_timing(True)
@@ -249,7 +411,7 @@ def main():
     sheet_iters = np.zeros(len(insts))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         gradient()
         sim.status()
         st = sim.stats()
@@ -260,72 +422,40 @@ def main():
             sheet_iters += st["cg_iters_recompute"]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    st = sim.stats()
-    sides = [int(round(np.sqrt(i.n_verts))) for i in insts]
-    ms = 1e3 * wall / args.steps
-    value = V * w.steps * args.steps / wall
+    ms = 1e3 * wall / steps
+    return dict(sim=sim, stats=sim.stats(), wall=wall, ms=ms, iters=int(iters),
+                sheet_iters=sheet_iters, value=sim.n_verts * w.steps * steps / wall,
+                x0=x0, v0=v0, F=F, tgt=tgt)
 
-    # roofline of the solver: algorithmic bytes per CG iteration -- the operator read once
-    # (9 entries + a 4 B column index per non-zero 3x3 block, in the stored precision) plus
-    # 192 B per vertex for one pass over the solver vectors
+
+def roofline(sim, insts, st, sheet_iters, iters, wall, traffic):
+    """Roofline of the persistent solver: algorithmic bytes per CG iteration are the
+    operator read once (9 entries in the stored precision + a 4-byte column index per
+    non-zero 3x3 block) plus one pass over each solver vector: 336 B per vertex with the
+    solver's FP64 vectors (p 24, A p 48, x 48, r 48, block-Jacobi inverse 72, z 48, the
+    p update 48), 192 B with FP32 ones (the FP32 yardstick, reported beside it). A batched
+    launch iterates every sheet on its own, so each sheet's iterations are weighted with
+    its own bytes per iteration."""
+    import numpy as np
     msize = 8 if sim.matrix_precision == "fp64" else 4
-    b_iter = (9 * msize + 4) * st["nnz_blocks"] + 192 * V
-    # a batched launch iterates every sheet on its own: weight each sheet's iterations
-    # with its own bytes per iteration
-    sheet_b = np.array([(9 * msize + 4) * block_pattern_size(i.tris, i.n_verts) + 192 * i.n_verts
-                        for i in insts], dtype=np.float64)
-    launches = st["solver_launches"]
-    avg_ms = st["solver_ms"] / max(launches, 1)
-    bytes_per_launch = float(np.dot(sheet_b, sheet_iters)) / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w.name)
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+    nnz = np.array([block_pattern_size(i.tris, i.n_verts) for i in insts], dtype=np.float64)
+    nv = np.array([i.n_verts for i in insts], dtype=np.float64)
+    b64 = (9 * msize + 4) * nnz + 336 * nv
+    b32 = 40 * nnz + 192 * nv
+    launches = max(st["solver_launches"], 1)
+    avg_ms = st["solver_ms"] / launches
+    per_launch = float(np.dot(b64, sheet_iters)) / launches
+    per_launch32 = float(np.dot(b32, sheet_iters)) / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    achieved32 = per_launch32 / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic, 1),
                 kernel="k_pcg", avg_launch_ms=round(avg_ms, 4),
-                cg_iters_per_launch=round(iters / max(launches, 1), 1),
+                cg_iters_per_launch=round(iters / launches, 1),
+                bytes_per_cg_iter=int(b64.sum()) if len(insts) == 1 else None,
+                frac_fp32_yardstick=round(achieved32 / HBM_PEAK_GBS, 4),
                 solver_share_of_wall=round(st["solver_ms"] / (wall * 1e3), 3))
-
-    out = dict(metric="vertex-steps/s forward+adjoint (ms per gradient, 100-step 64\u00d764 "
-                      "sheet); % HBM peak",
-               value=round(value, 1), unit="vertex-steps/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=round(ms, 3), higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-               config=dict(workload=(f"{w.name}: {w.n}x{w.n} sheet" if len(insts) == 1 else
-                                     f"{w.name}: {len(insts)} sheets of {min(sides)}..{max(sides)} per side") +
-                           f", {w.steps} steps of {w.dt} s, rollout + adjoint",
-                           sheets=len(insts), vertices=V, sim_steps=w.steps,
-                           cg_tol=w.cg_tol, cg_iters_per_gradient=iters // args.steps,
-                           solver_blocks=st["blocks"], rows_per_block=st["rows_per_block"],
-                           matrix_precision=sim.matrix_precision, membrane=args.membrane,
-                           coarse_aggregates=st["coarse_aggregates"],
-                           coarse_max_dim=st["coarse_max_dim"], bytes_per_cg_iter=b_iter,
-                           autotuned=bool(st["autotuned"]),
-                           autotune_candidates=st["autotune_candidates"],
-                           solver_matrix=S.MATRIX_HOMES[st["solver_matrix_home"]],
-                           solver_launches_per_solve=st["solver_launches_per_solve"],
-                           solver_wg_per_cu=st["solver_wg_per_cu"],
-                           coarse_rows_lds=bool(st["coarse_rows_lds"]),
-                           device_status=S.status_name(sim.status())),
-               roofline=roof)
-    if args.graph:
-        print("bench: graph-mode handle", file=sys.stderr, flush=True)
-        out["graph_mode"] = variant_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
-                                           args.warmup, args.membrane, not args.no_autotune,
-                                           graph=True)
-    if args.checkpoint_report > 0 and w.checkpoint_every == 0:
-        print(f"bench: checkpoint every {args.checkpoint_report}", file=sys.stderr, flush=True)
-        out["checkpointed"] = variant_timing(w, sheets, x0, v0, F, tgt, frames, args.steps,
-                                             args.warmup, args.membrane, not args.no_autotune,
-                                             checkpoint_every=args.checkpoint_report)
-    if args.sequential and len(insts) > 1:
-        out["batched_vs_sequential"] = sequential_comparison(w, insts, ms, args.steps,
-                                                             args.membrane, not args.no_autotune)
-    if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps)
-    print(json.dumps(out), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

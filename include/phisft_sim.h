@@ -61,6 +61,7 @@
 #ifndef PHISFT_SIM_H
 #define PHISFT_SIM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -325,6 +326,24 @@ sim_status sim_get_cg_iters(const sim_t* sim, int32_t* forward, int32_t* adjoint
 /* Sticky device status of each instance (sim_status values) as of the last
  * sim_sync_status; out has n_instances entries. Host memory. */
 sim_status sim_get_instance_status(const sim_t* sim, int32_t* out);
+
+/* Chamfer distance between two point sets (the paper's evaluation metric, Sec. 4.2,
+ * Eq. 10): Ch(G, M) = 1/|G| sum_g min_m |g - m|^2 + 1/|M| sum_m min_g |m - g|^2.
+ *   g, m        device float [3][n_g], [3][n_m] points (SoA, like the simulator's state)
+ *   ch          device double [1]: the result (NaN if a coordinate is not finite)
+ *   d_g, i_g    device float / int32 [n_g] or NULL: each g's smallest squared distance
+ *               to M and the index of the first m that attains it (ties: the smallest
+ *               index); d_m, i_m the same for M into G
+ *   workspace   device memory of at least sim_chamfer_workspace_bytes(n_g, n_m)
+ *               bytes, owned by the caller (nothing is allocated)
+ * Squared distances are formed coordinate by coordinate in FP32 and the means are
+ * summed in FP64 in a fixed order: the result is deterministic. Stream-ordered on
+ * `stream`. Errors: SIM_E_INVALID (NULL pointers, n_g or n_m < 1, workspace too
+ * small), SIM_E_HIP. */
+size_t sim_chamfer_workspace_bytes(int32_t n_g, int32_t n_m);
+sim_status sim_chamfer(const float* g, int32_t n_g, const float* m, int32_t n_m, double* ch,
+                       float* d_g, int32_t* i_g, float* d_m, int32_t* i_m, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 const char* sim_status_string(sim_status s);
 const char* sim_last_error(const sim_t* sim);

@@ -91,7 +91,7 @@ _lib = None
 EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout",
            "sim_rollout_noalloc", "sim_adjoint",
            "sim_sync_status", "sim_set_timing", "sim_get_stats", "sim_get_cg_iters",
-           "sim_get_instance_status",
+           "sim_get_instance_status", "sim_chamfer_workspace_bytes", "sim_chamfer",
            "sim_status_string", "sim_last_error", "sim_destroy")
 
 
@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH):
         "sim_get_stats": (i32, [vp, ctypes.POINTER(_Stats)]),
         "sim_get_cg_iters": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "sim_get_instance_status": (i32, [vp, ctypes.POINTER(i32)]),
+        "sim_chamfer_workspace_bytes": (ctypes.c_size_t, [i32, i32]),
+        "sim_chamfer": (i32, [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sim_status_string": (ctypes.c_char_p, [i32]),
         "sim_last_error": (ctypes.c_char_p, [vp]),
         "sim_destroy": (None, [vp]),
@@ -155,6 +157,37 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def chamfer(g: torch.Tensor, m: torch.Tensor, nearest: bool = False,
+            workspace: Optional[torch.Tensor] = None):
+    """Chamfer distance (Eq. 10) of the point sets g [3, n_g] and m [3, n_m] (float32
+    CUDA tensors, SoA) through sim_chamfer. Returns a float64 tensor [1]; with
+    ``nearest`` also each point's smallest squared distance and nearest index in the
+    other set (d_g, i_g, d_m, i_m). ``workspace``: a uint8 CUDA tensor of at least
+    sim_chamfer_workspace_bytes bytes, reused across calls (allocated here if None)."""
+    lib = load_library()
+    for t, name in ((g, "g"), (m, "m")):
+        if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous() or t.dim() != 2 \
+                or t.shape[0] != 3:
+            raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor [3, N]")
+    ng, nm = int(g.shape[1]), int(m.shape[1])
+    need = lib.sim_chamfer_workspace_bytes(ng, nm)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=g.device)
+    ch = torch.empty(1, dtype=torch.float64, device=g.device)
+    out = {}
+    if nearest:
+        out = dict(d_g=torch.empty(ng, dtype=torch.float32, device=g.device),
+                   i_g=torch.empty(ng, dtype=torch.int32, device=g.device),
+                   d_m=torch.empty(nm, dtype=torch.float32, device=g.device),
+                   i_m=torch.empty(nm, dtype=torch.int32, device=g.device))
+    st = lib.sim_chamfer(_ptr(g), ng, _ptr(m), nm, _ptr(ch), _ptr(out.get("d_g")),
+                         _ptr(out.get("i_g")), _ptr(out.get("d_m")), _ptr(out.get("i_m")),
+                         _ptr(workspace), workspace.numel(), _stream())
+    if st != SIM_OK:
+        raise SimError(st, "sim_chamfer: " + lib.sim_status_string(st).decode())
+    return (ch, out) if nearest else ch
 
 
 @dataclass

@@ -240,6 +240,27 @@ def fd_directions(w: Workload, count: int, shape) -> np.ndarray:
     return d
 
 
+def chamfer_points(n_g: int, n_m: int, seed: int = 7000):
+    """Point sets for the Chamfer distance (Eq. 10), vertex-major float64: G, a noisy
+    scan of a folded sheet (uniform samples of a smooth height field over the 0.5 m
+    square plus N(0, (1 mm)^2) noise per coordinate, like a depth camera's point cloud),
+    and M, points sampled from a reconstruction of it that is off by a smooth 3 mm
+    misfit. Seeded (PCG64); the paper's captured clouds are not available."""
+    g_rng = np.random.Generator(np.random.PCG64(seed))
+
+    def surface(u, v, misfit):
+        z = 0.04 * np.sin(3.0 * np.pi * u / SHEET_SIDE) * np.cos(2.0 * np.pi * v / SHEET_SIDE) \
+            + 0.02 * np.sin(np.pi * (u + v) / SHEET_SIDE)
+        z = z + misfit * np.sin(5.0 * np.pi * u / SHEET_SIDE + 1.0) * np.sin(4.0 * np.pi * v / SHEET_SIDE)
+        return np.stack([u, v, z], axis=1)
+
+    ug, vg = g_rng.uniform(0.0, SHEET_SIDE, size=(2, n_g))
+    g = surface(ug, vg, 0.0) + g_rng.normal(0.0, 1e-3, size=(n_g, 3))
+    um, vm = g_rng.uniform(0.0, SHEET_SIDE, size=(2, n_m))
+    m = surface(um, vm, 3e-3)
+    return g, m
+
+
 def as_given(inst: Instance, precision: str) -> Instance:
     """The instance's inputs as a handle of the given precision receives them: an FP32
     handle takes x0, v0 and the forces as float32, so a reference fed the same rounded

@@ -221,6 +221,10 @@ def main():
     ap.add_argument("--chamfer-steps", type=int, default=10, metavar="K",
                     help="also time K Chamfer-distance calls (Eq. 10) of 65,536 x 40,000 points, "
                          "reported in the 'chamfer' sub-object (0: skip)")
+    ap.add_argument("--window-iters", type=int, default=10, metavar="K",
+                    help="also time K iterations of the adaptive-window Adam loop on a 17x17 "
+                         "sheet with all 40 frames active, reported in the 'window' "
+                         "sub-object (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (untimed), the "
                          "known-size reference for scaling HBM byte counters")
@@ -325,6 +329,9 @@ def main():
     if args.chamfer_steps > 0:
         print("bench: Chamfer distance", file=sys.stderr, flush=True)
         out["chamfer"] = chamfer_timing(65536, 40000, args.chamfer_steps, 3)
+    if args.window_iters > 0:
+        print("bench: adaptive-window Adam loop", file=sys.stderr, flush=True)
+        out["window"] = window_timing(args.window_iters, 2)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, insts[0], args.cpu_sample_steps, gpu_ips)
@@ -374,6 +381,47 @@ def chamfer_timing(n_g: int, n_m: int, steps: int, warmup: int):
                               frac=round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
                               kernel="k_chamfer_nn (HIP events around the whole call: "
                                      "the fill, unpack and sum launches around it included)"))
+
+
+def window_timing(iters: int, warmup: int):
+    """Iterations of the outer loop (Sec. 3.3-3.4) on the paper's sequence size (a
+    289-vertex sheet, 40 frames), every frame active: each is a rollout over the 40
+    frames, the frame energies, the adjoint and the Adam steps, plus the host's read of
+    the energies that decides the window. The observed frames are the library's own
+    rollout under the hidden parameters of the seeded problem (FP64, CG tolerance 1e-10).
+    Wall clock per iteration."""
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+    from paper_2203_11938_amd.optimize import AdaptiveWindowAdam
+    p = W.window_problem()
+    w, i = p.workload, p.instance
+    dev = torch.device("cuda:0")
+    s = S.Simulator([S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple())], dt=w.dt,
+                    precision=w.precision, cg_tol=w.cg_tol, max_steps=w.steps)
+    x0 = torch.tensor(W.to_soa(i.x0), dtype=s.dtype, device=dev)
+    truth = torch.tensor(np.array(p.true_material)[None], device=dev)
+    tgt = s.rollout(w.steps, x0, None, None, truth, None,
+                    wind=torch.tensor(p.true_wind[None], device=dev)).clone()
+    s.sync()
+    drv = AdaptiveWindowAdam(s, tgt, x0, torch.tensor(np.array(p.guess_material)[None], device=dev),
+                             wind=torch.tensor(p.guess_wind[None], device=dev), first=w.steps)
+    drv.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = drv.run(iters)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / iters
+    st = s.stats()
+    out = dict(workload=f"adaptive-window Adam loop: {w.n}x{w.n} sheet ({i.n_verts} vertices), "
+                        f"{w.steps} frames of {w.dt} s all active, material + wind + forces, "
+                        "lr 1e-3, FP64",
+               iterations=iters, warmup=warmup, ms_per_iteration=round(ms, 3),
+               value=round(1e3 / ms, 2), unit="iterations/s",
+               loss_first=recs[0].loss, loss_last=recs[-1].loss,
+               cg_iters_last_gradient=int(st["cg_iters_forward"] + st["cg_iters_adjoint"]))
+    s.close()
+    return out
 
 
 def timed_gradients(w, insts, steps, warmup, membrane, autotune, coarse_size):

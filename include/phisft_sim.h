@@ -327,6 +327,39 @@ sim_status sim_get_cg_iters(const sim_t* sim, int32_t* forward, int32_t* adjoint
  * sim_sync_status; out has n_instances entries. Host memory. */
 sim_status sim_get_instance_status(const sim_t* sim, int32_t* out);
 
+/* The outer optimisation of the paper (Sec. 3.3, adaptive temporal window; Sec. 3.4,
+ * Adam with learning rate 1e-3) repeats rollout + adjoint over the active frames; these
+ * two calls hold its device arithmetic (paper_2203_11938_amd/optimize.py drives them).
+ *
+ * sim_frame_loss: per frame f < n_frames and sheet b, the energy
+ * E[f][b] = sum over the sheet's vertices of |x_f,i - target_f,i|^2 (the 3D stand-in
+ * for the per-frame reconstruction energy), summed in FP64 in a fixed order, and its
+ * gradient dl_dx = 2 (x - target) (dl_dx may be NULL).
+ *   x, target   device [n_frames][3][V] in the handle's precision (caller's order)
+ *   energy      device double [n_frames][n_instances]
+ * Errors: SIM_E_INVALID, SIM_E_HIP. */
+sim_status sim_frame_loss(sim_t* sim, int32_t n_frames, const void* x, const void* target,
+                          double* energy, void* dl_dx, void* stream);
+
+/* Lumped vertex areas (a third of the incident rest-triangle areas; the mass is the
+ * density times this) in the caller's vertex order: host double [V]. */
+sim_status sim_get_vertex_areas(const sim_t* sim, double* out);
+
+/* One Adam step (Kingma and Ba 2015) on n parameters: with theta the optimised variable,
+ *   m1 <- b1 m1 + (1 - b1) g,  m2 <- b2 m2 + (1 - b2) g^2,
+ *   theta <- theta - lr (m1 / (1 - b1^t)) / (sqrt(m2 / (1 - b2^t)) + eps),
+ * where the stored parameter p is theta itself, exp(theta) (log_space != 0, for
+ * positive material parameters) or scale[e % period] * theta (scale != NULL, e.g. a
+ * vertex's area share for forces read as loads), and g is dL/dtheta from dL/dp.
+ *   param, grad  device [n], FP32 or FP64 (precision); m1, m2 device double [n]
+ *   t            step number, from 1
+ * Errors: SIM_E_INVALID (bad sizes or hyper-parameters, scale with log_space),
+ * SIM_E_HIP. */
+sim_status sim_adam_step(void* param, int32_t precision, const void* grad, double* m1, double* m2,
+                         int64_t n, const double* scale, int32_t period, int32_t log_space,
+                         double lr, double beta1, double beta2, double eps, int32_t t,
+                         void* stream);
+
 /* Chamfer distance between two point sets (the paper's evaluation metric, Sec. 4.2,
  * Eq. 10): Ch(G, M) = 1/|G| sum_g min_m |g - m|^2 + 1/|M| sum_m min_g |m - g|^2.
  *   g, m        device float [3][n_g], [3][n_m] points (SoA, like the simulator's state)

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libphisft_sim.so")
-SOURCES = ["kernels.hip", "chamfer.hip", "mesh_prep.cpp", "sim_api.cpp"]
+SOURCES = ["kernels.hip", "chamfer.hip", "optim.hip", "mesh_prep.cpp", "sim_api.cpp"]
 ARCH = "gfx950"
 
 

@@ -20,7 +20,7 @@
 
 #include "../../include/phisft_sim.h"
 
-namespace {
+namespace phisft {
 
 constexpr int kChThreads = 256;
 constexpr int kChQ = 4;                          // query points per lane
@@ -164,14 +164,14 @@ __global__ void __launch_bounds__(kChThreads) k_chamfer_sum(const double* pg, in
   }
 }
 
-inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 struct ChamferLayout {
   size_t best_g, best_m, part_g, part_m, bad, total;
   int nbg, nbm;
 };
 
-ChamferLayout chamfer_layout(int ng, int nm) {
+static ChamferLayout chamfer_layout(int ng, int nm) {
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   ChamferLayout L{};
   L.nbg = cdiv(ng, kChThreads);
@@ -185,7 +185,9 @@ ChamferLayout chamfer_layout(int ng, int nm) {
   return L;
 }
 
-}  // namespace
+}  // namespace phisft
+
+using namespace phisft;
 
 extern "C" {
 

@@ -108,6 +108,13 @@ void launch_adj_final(const Mesh& m, const double* gx, const double* gv, T* dx0,
 void launch_material_sum(const Mesh& m, const Elem& el, double* out_mat, double* out_wind,
                          hipStream_t st);
 
+// Per loss frame and sheet: E = sum over the sheet's vertices of |x - target|^2 (FP64,
+// fixed order) into energy [nframes][ninst], and dl = 2 (x - target) when dl != nullptr.
+// Arrays [nframes][3][nv] in the caller's vertex order; voff/vcount: device [ninst].
+template <typename T>
+void launch_frame_loss(const T* x, const T* tgt, int nv, const int* voff, const int* vcount,
+                       int ninst, int nframes, double* energy, T* dl, hipStream_t st);
+
 // Bytes of the static device array behind the allocation-free rollout's solver
 // exchange buffers (one copy per GPU, held for the process's lifetime).
 constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;

@@ -1195,6 +1195,35 @@ sim_status sim_sync_status(sim_t* s) {
   return st;
 }
 
+sim_status sim_frame_loss(sim_t* s, int32_t n_frames, const void* x, const void* target,
+                          double* energy, void* dl_dx, void* stream) {
+  if (!s) return SIM_E_INVALID;
+  if (n_frames < 0 || (n_frames > 0 && (!x || !target || !energy))) {
+    s->err = "invalid frame-loss arguments";
+    return SIM_E_INVALID;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Mesh& m = s->mesh;
+  if (s->prec == SIM_FP64)
+    launch_frame_loss<double>(static_cast<const double*>(x), static_cast<const double*>(target),
+                              m.nv, m.inst_voff, m.inst_nv, m.ninst, n_frames, energy,
+                              static_cast<double*>(dl_dx), st);
+  else
+    launch_frame_loss<float>(static_cast<const float*>(x), static_cast<const float*>(target), m.nv,
+                             m.inst_voff, m.inst_nv, m.ninst, n_frames, energy,
+                             static_cast<float*>(dl_dx), st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "frame loss launch");
+  return SIM_OK;
+}
+
+sim_status sim_get_vertex_areas(const sim_t* s, double* out) {
+  if (!s || !out) return SIM_E_INVALID;
+  // internal vertex i is the caller's vertex vold[i] of the same sheet range
+  for (int i = 0; i < s->L.nv; ++i) out[s->L.vold[i]] = s->L.varea[i];
+  return SIM_OK;
+}
+
 sim_status sim_set_timing(sim_t* s, int32_t enable) {
   if (!s) return SIM_E_INVALID;
   s->timing = enable != 0;

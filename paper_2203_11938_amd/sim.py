@@ -91,7 +91,8 @@ _lib = None
 EXPORTS = ("sim_default_options", "sim_create", "sim_create_batch", "sim_rollout",
            "sim_rollout_noalloc", "sim_adjoint",
            "sim_sync_status", "sim_set_timing", "sim_get_stats", "sim_get_cg_iters",
-           "sim_get_instance_status", "sim_chamfer_workspace_bytes", "sim_chamfer",
+           "sim_get_instance_status", "sim_frame_loss", "sim_get_vertex_areas",
+           "sim_adam_step", "sim_chamfer_workspace_bytes", "sim_chamfer",
            "sim_status_string", "sim_last_error", "sim_destroy")
 
 
@@ -124,6 +125,10 @@ def load_library(path: str = LIB_PATH):
         "sim_get_stats": (i32, [vp, ctypes.POINTER(_Stats)]),
         "sim_get_cg_iters": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "sim_get_instance_status": (i32, [vp, ctypes.POINTER(i32)]),
+        "sim_frame_loss": (i32, [vp, i32, vp, vp, vp, vp, vp]),
+        "sim_get_vertex_areas": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "sim_adam_step": (i32, [vp, i32, vp, vp, vp, ctypes.c_int64, vp, i32, i32, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, i32, vp]),
         "sim_chamfer_workspace_bytes": (ctypes.c_size_t, [i32, i32]),
         "sim_chamfer": (i32, [vp, i32, vp, i32, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
         "sim_status_string": (ctypes.c_char_p, [i32]),
@@ -157,6 +162,27 @@ def _ptr(t: Optional[torch.Tensor]):
 
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+              t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, log_space: bool = False, scale: Optional[torch.Tensor] = None,
+              n: Optional[int] = None):
+    """One Adam step in place on the first n entries of param (sim_adam_step); m1, m2
+    float64 moments of param's size; scale [period] float64 or None."""
+    lib = load_library()
+    if param.dtype not in (torch.float32, torch.float64) or grad.dtype != param.dtype:
+        raise ValueError("param and grad must share a float32 or float64 dtype")
+    for t_, name in ((param, "param"), (grad, "grad"), (m1, "m1"), (m2, "m2")):
+        if not t_.is_cuda or not t_.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous CUDA tensor")
+    n = param.numel() if n is None else int(n)
+    prec = SIM_FP64 if param.dtype == torch.float64 else SIM_FP32
+    st = lib.sim_adam_step(_ptr(param), prec, _ptr(grad), _ptr(m1), _ptr(m2), n, _ptr(scale),
+                           0 if scale is None else int(scale.numel()), 1 if log_space else 0,
+                           lr, beta1, beta2, eps, int(t), _stream())
+    if st != SIM_OK:
+        raise SimError(st, "sim_adam_step: " + lib.sim_status_string(st).decode())
 
 
 def chamfer(g: torch.Tensor, m: torch.Tensor, nearest: bool = False,
@@ -409,6 +435,26 @@ class Simulator:
         out = np.zeros(self.n_instances, dtype=np.int32)
         self._check(self._lib.sim_get_instance_status(self._h, out.ctypes.data_as(
             ctypes.POINTER(ctypes.c_int32))), "sim_get_instance_status")
+        return out
+
+    def frame_loss(self, x: torch.Tensor, target: torch.Tensor, energy: torch.Tensor,
+                   dl_dx: Optional[torch.Tensor] = None):
+        """Per frame and sheet, sum |x - target|^2 into energy [n_frames, n_instances]
+        (float64) and 2 (x - target) into dl_dx (sim_frame_loss); x, target, dl_dx
+        [n_frames, 3, V] in the handle's precision."""
+        nf = int(x.shape[0])
+        self._need(x, (nf, 3, self.n_verts), "x")
+        self._need(target, (nf, 3, self.n_verts), "target")
+        self._need(energy, (nf, self.n_instances), "energy", torch.float64)
+        self._need(dl_dx, (nf, 3, self.n_verts), "dl_dx")
+        self._check(self._lib.sim_frame_loss(self._h, nf, _ptr(x), _ptr(target), _ptr(energy),
+                                             _ptr(dl_dx), _stream()), "sim_frame_loss")
+
+    def vertex_areas(self) -> np.ndarray:
+        """Lumped vertex areas [V] (caller's order)."""
+        out = np.zeros(self.n_verts)
+        self._check(self._lib.sim_get_vertex_areas(
+            self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "sim_get_vertex_areas")
         return out
 
     def cg_iters(self):

@@ -261,6 +261,35 @@ def chamfer_points(n_g: int, n_m: int, seed: int = 7000):
     return g, m
 
 
+@dataclass
+class WindowProblem:
+    """Inputs of the outer-loop (window + Adam) workload: a sheet, the hidden parameters
+    that produced its observed sequence, and the optimiser's starting guess."""
+    workload: Workload
+    instance: Instance
+    true_material: tuple
+    true_wind: np.ndarray        # [3] m/s
+    guess_material: tuple
+    guess_wind: np.ndarray       # [3] m/s (zero, as the paper initialises it)
+
+
+def window_problem(n: int = 17, frames: int = 40, precision: str = "fp64",
+                   cg_tol: float = 1e-10) -> WindowProblem:
+    """A stand-in for one of the paper's sequences (~300-vertex template, ~40 frames,
+    Sec. 4): an n x n sheet hanging from its two top corners, 10 ms steps. The observed
+    frames are a rollout under hidden parameters: (k_s, k_b, d) of the default material
+    times seeded U[0.5, 2] factors (stream 0) and a wind of seeded direction and speed
+    U[1, 3] m/s (stream 5). The optimiser starts from the default material, zero wind
+    and zero forces. Seeds: workload number 7."""
+    w = Workload("N3", 7, n, frames, 0.01, "top2", precision=precision, cg_tol=cg_tol)
+    inst = _instance(w, n, w.material, rng(7, 1), rng(7, 2), rng(7, 0))
+    g = rng(7, 5)
+    d = g.normal(size=3)
+    wind = d / np.linalg.norm(d) * g.uniform(1.0, 3.0)
+    true_mat = tuple(np.array(w.material.as_tuple()) * inst.target_factors)
+    return WindowProblem(w, inst, true_mat, wind, w.material.as_tuple(), np.zeros(3))
+
+
 def as_given(inst: Instance, precision: str) -> Instance:
     """The instance's inputs as a handle of the given precision receives them: an FP32
     handle takes x0, v0 and the forces as float32, so a reference fed the same rounded

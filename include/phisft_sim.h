@@ -160,9 +160,9 @@ typedef struct {
                                more than 320 aggregates uses larger ones. The solution
                                still meets cg_tol on the true residual. Each step's
                                operators (FP32 A_c^-1, offsets, 6x6 blocks) are kept
-                               for the adjoint: for every step when that fits 16 GB
-                               (with checkpointing, recomputed steps reuse them too),
-                               else for one checkpoint segment, else not at all.      */
+                               for the adjoint: without checkpointing for every step
+                               when that fits 16 GB, else not at all (rebuilt in the
+                               adjoint); with checkpointing see coarse_keep_all       */
   int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
                                (rows per workgroup; matrix rows in registers, in LDS or
                                streamed; rows of the coarse inverse in LDS or streamed;

@@ -1681,6 +1681,7 @@ struct CoarseRow {
   const float* XL;       // the same rows in LDS (stride nc), or nullptr
   const double* part;    // restriction partial sums
   int nc, np, nrow, ok;
+  int nwm;               // most partial slots (workgroups) of any aggregate of the sheet
 };
 
 // e_q = sum_c X[q][c] w_c for the NR rows of this workgroup: the wavefronts take
@@ -1735,14 +1736,15 @@ __device__ __forceinline__ void coarse_rows_at(const CoarseRow& cr_, const doubl
   else coarse_rows<NR, false>(cr_.X, cr_.np, cr_.nc, s_wc, s_red, s_e);
 }
 
-// After the cluster barrier that publishes the partial sums: the sheet's coarse
-// residual w_c into LDS (every column sums its aggregate's partials of up to
-// kMaxAggWg workgroups; index -1 reads entry 0 with weight 0, so the loads carry no
-// branches and one pass issues them together). The caller synchronises the
-// workgroup before w_c is read. Skipped when the step's inversion failed.
-__device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s_pidx,
-                                              double* s_wc) {
-  if (!cr_.ok) return;
+// After the partial sums are published: the sheet's coarse residual w_c into LDS.
+// Every column sums its aggregate's partials in slot order, reading the NW slots an
+// aggregate can have (NW: the most workgroups any aggregate of the sheet spans, a
+// compile-time count so that one pass issues its loads together; slot -1 reads entry 0
+// with weight 0, no branches around the loads). The caller synchronises the workgroup
+// before w_c is read. Skipped when the step's inversion failed.
+template <int NW>
+__device__ __forceinline__ void coarse_gather_n(const CoarseRow& cr_, const int* s_pidx,
+                                                double* s_wc) {
   const int tid = threadIdx.x;
   const int nc = cr_.nc;
   constexpr int CU = 8;
@@ -1754,7 +1756,7 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
       const int t = col / 6, q = col - 6 * t;
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < kMaxAggWg; ++k) {
+      for (int k = 0; k < NW; ++k) {
         const int pi = s_pidx[t * kMaxAggWg + k];
         const double v = __hip_atomic_load(const_cast<double*>(cr_.part) + (size_t)max(pi, 0) * 6 + q,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1768,28 +1770,39 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
   }
 }
 
+__device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s_pidx,
+                                              double* s_wc) {
+  if (!cr_.ok) return;
+  switch (cr_.nwm) {   // uniform
+    case 1: coarse_gather_n<1>(cr_, s_pidx, s_wc); break;
+    case 2: coarse_gather_n<2>(cr_, s_pidx, s_wc); break;
+    case 3: coarse_gather_n<3>(cr_, s_pidx, s_wc); break;
+    default: coarse_gather_n<kMaxAggWg>(cr_, s_pidx, s_wc); break;
+  }
+}
+
 // Tagged counterparts of coarse_gather and collect3, reading the partials of the
 // iteration's tagged publication (slot base trp = [nwg][kTagSlots][2] words): loads are
 // issued together, then each entry is re-read until it carries `tag`. False on a
 // time-out or an abort (per thread; the caller combines).
-__device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const int* s_pidx,
-                                                     double* s_wc,
-                                                     const unsigned long long* trp,
-                                                     unsigned tag, int* abort_flag) {
-  if (!cr_.ok) return true;
+template <int NW>
+__device__ __forceinline__ bool coarse_gather_tagged_n(const CoarseRow& cr_, const int* s_pidx,
+                                                       double* s_wc,
+                                                       const unsigned long long* trp,
+                                                       unsigned tag, int* abort_flag) {
   const int tid = threadIdx.x;
   const int nc = cr_.nc;
   constexpr int CU = 4;
   bool ok = true;
   for (int col0 = tid; col0 < nc; col0 += CU * blockDim.x) {
-    unsigned long long w0[CU][kMaxAggWg], w1[CU][kMaxAggWg];
-    const unsigned long long* adr[CU][kMaxAggWg];
+    unsigned long long w0[CU][NW], w1[CU][NW];
+    const unsigned long long* adr[CU][NW];
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
       const int col = min(col0 + u * (int)blockDim.x, nc - 1);
       const int t = col / 6, q = col - 6 * t;
 #pragma unroll
-      for (int k = 0; k < kMaxAggWg; ++k) {
+      for (int k = 0; k < NW; ++k) {
         const int pi = max(s_pidx[t * kMaxAggWg + k], 0);
         adr[u][k] = trp + ((size_t)(pi / kMaxWgAgg) * kTagSlots + 3 + (pi % kMaxWgAgg) * 6 + q) * 2;
         load_tagged(adr[u][k], w0[u][k], w1[u][k]);
@@ -1802,7 +1815,7 @@ __device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const
       const int t = col / 6;
       double acc = 0.0;
 #pragma unroll
-      for (int k = 0; k < kMaxAggWg; ++k) {
+      for (int k = 0; k < NW; ++k) {
         if (s_pidx[t * kMaxAggWg + k] < 0) continue;
         ok = ok && poll_tagged(adr[u][k], tag, abort_flag, w0[u][k], w1[u][k]);
         acc += tag_value(w0[u][k], w1[u][k]);
@@ -1811,6 +1824,19 @@ __device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const
     }
   }
   return ok;
+}
+
+__device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const int* s_pidx,
+                                                     double* s_wc,
+                                                     const unsigned long long* trp,
+                                                     unsigned tag, int* abort_flag) {
+  if (!cr_.ok) return true;
+  switch (cr_.nwm) {   // uniform
+    case 1: return coarse_gather_tagged_n<1>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    case 2: return coarse_gather_tagged_n<2>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    case 3: return coarse_gather_tagged_n<3>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    default: return coarse_gather_tagged_n<kMaxAggWg>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+  }
 }
 
 __device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, int iw0, int nwg,
@@ -2000,6 +2026,14 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
         pi = w2 * kMaxWgAgg + (a - cs.wg_agg0[w2]);
       }
       s_pidx[e] = pi;
+    }
+    // most workgroups any aggregate of the sheet spans (the gathers read no more
+    // partial slots per aggregate): every wavefront reduces the whole list
+    {
+      int nm = 1;
+      for (int t = tid & 63; t < nag; t += 64) nm = max(nm, cs.agg_nwg[ag0 + t]);
+      for (int o = 32; o > 0; o >>= 1) nm = max(nm, __shfl_xor(nm, o));
+      crow.nwm = min(nm, kMaxAggWg);
     }
     const int np = cs.inst_np[inst];
     crow.X = cs.xinv + cs.inst_coff[inst] + (size_t)6 * (wa0 - ag0) * np;

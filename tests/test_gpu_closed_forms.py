@@ -144,8 +144,9 @@ def test_momentum_identity_full_size(n, steps):
     with m = d A, dL/dd = -(h^2 / d) sum_{r<T} (T - r) <a, sum_i F_{r,i}>. The sheet
     crumples under random forces, so the tension membrane system keeps every step SPD.
 
-    Gates: the positions' identity, dL/dv0, dL/dF and the vertex sum of dL/dx0 (the
-    stiffness terms cancel exactly in it) to 1e-8. Per vertex, dL/dx0 = m_i a (about
+    Gates: the positions' identity, dL/dF and the vertex sum of dL/dx0 (the stiffness
+    terms cancel exactly in it) to 1e-8, dL/dv0 to 1e-8 or twice the attained relative
+    residual of the solves if that is larger (it inherits the residual). Per vertex, dL/dx0 = m_i a (about
     1e-6 kg times a) is what remains after stiffness terms h K mu cancel, and they
     cancel only for an exact adjoint: the solves' residual (cg_tol relative) shows up
     amplified by about h k_s V / (d L^2), the ratio of a vertex's stiffness term to its
@@ -191,8 +192,12 @@ def test_momentum_identity_full_size(n, steps):
          ", ".join(f"{k} {e:.2e}" for k, e in {**tight, **loose}.items()) +
          f" (amplification {amp:.1e}); cg iters {st['cg_iters_forward']}")
     assert np.abs(com - ref).max() <= 1e-9 * np.abs(ref).max()
+    # dL/dv0 is M mu on free rows: it carries the adjoint solves' relative residual
+    # about one to one, so its gate follows the residual they attained (at the floor
+    # the unpinned sheet leaves, above cg_tol)
+    res = max(cg_tol, st["max_rel_residual"])
     for k, e in tight.items():
-        assert e <= 1e-8, (k, e)
+        assert e <= (max(1e-8, 2 * res) if k == "v0" else 1e-8), (k, e, res)
     for k, e in loose.items():
         assert e <= 10 * cg_tol * amp, (k, e, amp)
     s.close()

@@ -76,6 +76,9 @@ def _load():
         "orc_adjoint_update": (None, [P, D, D, D, D, D, D, D, D, D, D]),
         "orc_set_wind": (c_int, [P, c_int, c_double, c_double, c_double, c_double]),
         "orc_wind_force": (None, [P, D, D, D]),
+        "orc_set_material": (c_int, [P, c_int, D, D]),
+        "orc_num_material": (c_int, [P]),
+        "orc_get_material_frames": (None, [P, D, D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -216,6 +219,36 @@ class Oracle:
             raise OracleError(st, "set_wind")
         self.wind = None if wind is None else np.array(w)
 
+    def set_material_wang(self, stretch=None, bend=None):
+        """Anisotropic strain-dependent material (readings R20, R21): stretch table
+        [4, 6] (warp, weft, shear, area measures x strain segments) in N/m and bend table
+        [3, 5] (0, 45, 90 degree directions x angle segments) in N m. None: the
+        isotropic model (k_s, k_b of set_params). Density stays that of set_params."""
+        lib = _load()
+        if stretch is None:
+            st = lib.orc_set_material(self._h, 0, None, None)
+            self.wang = None
+        else:
+            S = _f64(stretch, (4, 6)).ravel()
+            B = _f64(bend, (3, 5)).ravel()
+            st = lib.orc_set_material(self._h, 1, _d(S), _d(B))
+            self.wang = (S.reshape(4, 6).copy(), B.reshape(3, 5).copy())
+        if st != ORC_OK:
+            raise OracleError(st, "set_material")
+
+    @property
+    def nmat(self):
+        """Entries of the material gradient: 3 (k_s, k_b, d) or 40 (S, B, d)."""
+        return _load().orc_num_material(self._h)
+
+    def material_frames(self):
+        """Measure tensors N_1..N_4 of every triangle (local frame; N_00, N_01, N_11)
+        [nt, 4, 3] and every hinge's direction weights [nh, 3] (readings R20, R21)."""
+        N = np.zeros((self.nt, 4, 3))
+        w = np.zeros((self.nh, 3))
+        _load().orc_get_material_frames(self._h, _d(N), _d(w))
+        return N, w
+
     def wind_force(self, x, v):
         """The aerodynamic force alone at (x, v) [V, 3] (reading R19)."""
         x = _f64(x, (self.nv, 3))
@@ -355,13 +388,14 @@ class Oracle:
         return xo, vf, iters, st
 
     def gradient(self, n_steps, x0, v0, forces, loss_frames, dl_dx, check=True):
-        """Rollout + adjoint: dL/d(k_s, k_b, d), dL/dF [n_steps, V, 3], dL/dx0, dL/dv0."""
+        """Rollout + adjoint: the material gradient (dL/d(k_s, k_b, d), or dL/d(S, B, d)
+        [40] with the anisotropic model), dL/dF [n_steps, V, 3], dL/dx0, dL/dv0."""
         x0 = _f64(x0, (self.nv, 3))
         v0 = np.zeros((self.nv, 3)) if v0 is None else _f64(v0, (self.nv, 3))
         forces = _f64(forces, (n_steps, self.nv, 3)) if forces is not None else None
         frames = np.ascontiguousarray(loss_frames, dtype=np.int32)
         dl_dx = _f64(dl_dx, (frames.size, self.nv, 3))
-        gm = np.zeros(3)
+        gm = np.zeros(self.nmat)
         gw = np.zeros(3)
         gF = np.zeros((n_steps, self.nv, 3))
         gx0 = np.zeros((self.nv, 3))
@@ -442,7 +476,8 @@ class Oracle:
         L = sum over the loss frames of |x_s - target_s|^2 (dL/dx_s = 2 (x_s - target_s)).
         The backward sweep is the oracle's own (orc_adjoint_rhs, orc_adjoint_update)
         around an exact solve of A(x_{s-1}) mu = u. Returns the positions at the loss
-        frames, the loss and dL/d(k_s, k_b, d), dL/dF, dL/dx0, dL/dv0."""
+        frames, the loss and the material gradient (3 or 40 entries), dL/dF, dL/dx0,
+        dL/dv0."""
         frames = [int(f) for f in loss_frames]
         X, Vv, DV = states if states is not None else self.rollout_exact(n_steps, x0, v0, forces)
         targets = np.asarray(targets, dtype=np.float64)
@@ -451,7 +486,7 @@ class Oracle:
         gx = np.zeros((self.nv, 3))
         gv = np.zeros((self.nv, 3))
         u = np.zeros((self.nv, 3))
-        gm = np.zeros(3)
+        gm = np.zeros(self.nmat)
         gw = np.zeros(3)
         gF = np.zeros((n_steps, self.nv, 3))
         lib = _load()

@@ -33,6 +33,21 @@
 //       wherever the force itself is differentiated and the derivative of
 //       K_sys in the state-derivative term.
 //   R11 pinned vertices keep v = 0 and x = x_0 (Dirichlet rows/columns).
+//   R20 stretch, anisotropic model (orc_set_material, model 1; the paper's S in R^24,
+//       from Wang et al., whose formulas it does not give): four measures of the Green
+//       strain in the sheet's material frame (u: the rest x axis projected into the
+//       triangle's plane, the rest y axis where x is nearly normal to it; v = n x u):
+//       s_1 = G_uu (warp), s_2 = G_vv (weft), s_3 = sqrt(2) G_uv (shear), s_4 = G_uu +
+//       G_vv (area). Each has a piecewise-linear stress sigma_k(|s|) whose slope is
+//       S[k][j] [N/m] on strain segment j (breaks 0, 0.25, 0.5, 1, 2, 4 %); the energy
+//       density is sum_k psi_k(|s_k|) with psi' = sigma (even in s). S[k][j] = k_s for
+//       k = 1..3 and S[4][j] = 0 give R7.
+//   R21 bending, anisotropic model (the paper's B in R^15): the hinge energy
+//       c_e Phi(theta - theta_rest), Phi(d) = 2 psi(|d|) with a piecewise-linear
+//       sigma(|d|) whose slope on angle segment j (breaks 0, 0.05, 0.1, 0.2, 0.4 rad)
+//       interpolates B[0][j], B[1][j], B[2][j] linearly in the angle between the
+//       bending direction (in-plane, normal to the rest edge) and the warp axis u of
+//       the hinge's first triangle, at 0, 45 and 90 degrees. B = k_b gives R8.
 //   R19 wind (Eq. 2's w, a velocity; air density fixed, Sec. 3.4): every triangle
 //       feels F_t = rho_air * area_t * |s| s n, n its unit normal at x_{t-1},
 //       area_t its rest area, s = n . (w - mean of its vertices' v_{t-1}); each
@@ -255,6 +270,121 @@ void membrane_hvp(const S* xa, const S* xb, const S* xc, const S* ua, const S* u
   scatter_ds(Q, B, oa, ob, oc);
 }
 
+// ------------------------------------------- anisotropic material (R20, R21)
+constexpr int kWangStretch = 24, kWangBend = 15, kWangParams = 40;
+const double kStrainBreaks[6] = {0.0, 0.0025, 0.005, 0.01, 0.02, 0.04};
+const double kBendBreaks[5] = {0.0, 0.05, 0.1, 0.2, 0.4};
+
+// Piecewise-linear response of a deformation measure t >= 0 whose stiffness is k[j] on
+// [b_j, b_{j+1}) (the last segment unbounded): sigma(t) = integral of the stiffness
+// from 0 to t, psi(t) = integral of sigma from 0 to t, kt = the stiffness at t.
+template <class S>
+void pw_response(const S& t, const double* k, const double* b, int n, S& sigma, S& psi,
+                 double& kt) {
+  double sig = 0.0, ps = 0.0;
+  int j = 0;
+  while (j + 1 < n && value_of(t) >= b[j + 1]) {
+    const double len = b[j + 1] - b[j];
+    ps += sig * len + 0.5 * k[j] * len * len;
+    sig += k[j] * len;
+    ++j;
+  }
+  S r = t - b[j];
+  psi = ps + sig * r + 0.5 * k[j] * r * r;
+  sigma = sig + k[j] * r;
+  kt = k[j];
+}
+
+// N : G for a symmetric 2x2 N stored as (N_00, N_01, N_11).
+template <class S> S ncontract(const double* N, S G[2][2]) {
+  return N[0] * G[0][0] + N[1] * (G[0][1] + G[1][0]) + N[2] * G[1][1];
+}
+
+// R20 energy density W(G) of a triangle whose four measure tensors (local frame) are
+// N[0..11]; also the second Piola stress dW/dG and each measure's segment stiffness.
+template <class S>
+S wang_stress(S G[2][2], const double* N, const double* Sp, S S2[2][2], double c[4]) {
+  S W(0.0);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) S2[a][b] = S(0.0);
+  for (int k = 0; k < 4; ++k) {
+    const double* Nk = &N[3 * k];
+    S sk = ncontract(Nk, G);
+    const bool neg = value_of(sk) < 0.0;
+    S t = neg ? -sk : sk;
+    S sig, psi;
+    pw_response(t, &Sp[6 * k], kStrainBreaks, 6, sig, psi, c[k]);
+    S sg = neg ? -sig : sig;
+    S2[0][0] = S2[0][0] + sg * Nk[0];
+    S2[0][1] = S2[0][1] + sg * Nk[1];
+    S2[1][0] = S2[1][0] + sg * Nk[1];
+    S2[1][1] = S2[1][1] + sg * Nk[2];
+    W = W + psi;
+  }
+  return W;
+}
+
+template <class S>
+S wang_membrane_energy(const S* xa, const S* xb, const S* xc, const double* B, double area,
+                       const double* N, const double* Sp) {
+  S F[3][2], G[2][2], S2[2][2];
+  double c[4];
+  deformation_gradient(xa, xb, xc, B, F);
+  green_strain(F, G);
+  return area * wang_stress(G, N, Sp, S2, c);
+}
+
+// dE/dx: dE/dD_s = area F S2 B^T.
+template <class S>
+void wang_membrane_gradient(const S* xa, const S* xb, const S* xc, const double* B, double area,
+                            const double* N, const double* Sp, S* ga, S* gb, S* gc) {
+  S F[3][2], G[2][2], S2[2][2], Q[3][2];
+  double c[4];
+  deformation_gradient(xa, xb, xc, B, F);
+  green_strain(F, G);
+  wang_stress(G, N, Sp, S2, c);
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 2; ++k) Q[r][k] = area * (F[r][0] * S2[0][k] + F[r][1] * S2[1][k]);
+  scatter_ds(Q, B, ga, gb, gc);
+}
+
+// Hessian-vector product along u: dP = dF S2' + F dS2, dS2 = sum_k c_k (N_k : dG) N_k
+// (the stiffness of each measure is constant on its segment); S2' = S2 (GEO_EXACT) or 0
+// (GEO_NONE).
+template <class S>
+void wang_membrane_hvp(const S* xa, const S* xb, const S* xc, const S* ua, const S* ub,
+                       const S* uc, const double* B, double area, const double* N,
+                       const double* Sp, int geo, S* oa, S* ob, S* oc) {
+  S F[3][2], G[2][2], S2[2][2], dF[3][2], dG[2][2], dS[2][2], Q[3][2];
+  double c[4];
+  deformation_gradient(xa, xb, xc, B, F);
+  green_strain(F, G);
+  wang_stress(G, N, Sp, S2, c);
+  deformation_gradient(ua, ub, uc, B, dF);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      S s1 = F[0][a] * dF[0][b] + F[1][a] * dF[1][b] + F[2][a] * dF[2][b];
+      S s2 = dF[0][a] * F[0][b] + dF[1][a] * F[1][b] + dF[2][a] * F[2][b];
+      dG[a][b] = 0.5 * (s1 + s2);
+      dS[a][b] = S(0.0);
+    }
+  for (int k = 0; k < 4; ++k) {
+    const double* Nk = &N[3 * k];
+    S m = c[k] * ncontract(Nk, dG);
+    dS[0][0] = dS[0][0] + m * Nk[0];
+    dS[0][1] = dS[0][1] + m * Nk[1];
+    dS[1][0] = dS[1][0] + m * Nk[1];
+    dS[1][1] = dS[1][1] + m * Nk[2];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 2; ++k) {
+      S t = F[r][0] * dS[0][k] + F[r][1] * dS[1][k];
+      if (geo == GEO_EXACT) t = t + dF[r][0] * S2[0][k] + dF[r][1] * S2[1][k];
+      Q[r][k] = area * t;
+    }
+  scatter_ds(Q, B, oa, ob, oc);
+}
+
 // ------------------------------------------------------------- bending (R8)
 // Hinge (x0, x1 | x2, x3): edge x0 -> x1, triangle (x0, x1, x2) and the
 // neighbour (x1, x0, x3). theta = atan2((n1 x n2) . e, n1 . n2) with unit normals.
@@ -355,7 +485,95 @@ struct Problem {
   double rho_air = 1.0;
   std::vector<int> rowptr, col;  // CSR pattern of the vertex blocks
   int last_status = ORC_OK;
+  // anisotropic material (R20, R21): on when wang; per triangle the four measure
+  // tensors in its local frame [nt][4][3], per hinge the direction weights [nh][3]
+  bool wang = false;
+  double wS[kWangStretch] = {}, wB[kWangBend] = {};
+  std::vector<double> Nm, hdw;
 };
+
+// The stiffness parameters of the internal forces: the isotropic scales (k_s, k_b) or
+// the anisotropic tables. The adjoint evaluates forces and stiffness products with
+// unit parameters (the model is linear in every parameter for a fixed state).
+struct Mat {
+  bool wang = false;
+  double ks = 0.0, kb = 0.0;
+  double S[kWangStretch] = {}, B[kWangBend] = {};
+};
+
+Mat iso_mat(double ks, double kb) {
+  Mat M;
+  M.ks = ks;
+  M.kb = kb;
+  return M;
+}
+
+Mat problem_mat(const Problem& P) {
+  Mat M = iso_mat(P.ks, P.kb);
+  M.wang = P.wang;
+  std::copy(P.wS, P.wS + kWangStretch, M.S);
+  std::copy(P.wB, P.wB + kWangBend, M.B);
+  return M;
+}
+
+// Hinge e's bending response at the angle change dth: the force scale s = dE/dtheta
+// and the Gauss-Newton weight w = d^2E/dtheta^2 (and the energy).
+void hinge_response(const Problem& P, const Mat& M, int e, double dth, double& s, double& w,
+                    double* energy = nullptr) {
+  const double ce = P.hce[e];
+  if (!M.wang) {
+    s = 2.0 * M.kb * ce * dth;
+    w = 2.0 * M.kb * ce;
+    if (energy) *energy = M.kb * ce * dth * dth;
+    return;
+  }
+  double keff[5];
+  for (int j = 0; j < 5; ++j) {
+    keff[j] = 0.0;
+    for (int a = 0; a < 3; ++a) keff[j] += P.hdw[3 * e + a] * M.B[5 * a + j];
+  }
+  const double t = std::fabs(dth);
+  double sig, psi, kt;
+  pw_response(t, keff, kBendBreaks, 5, sig, psi, kt);
+  s = 2.0 * ce * (dth < 0.0 ? -sig : sig);
+  w = 2.0 * ce * kt;
+  if (energy) *energy = 2.0 * ce * psi;
+}
+
+template <class S>
+void mem_gradient(const Problem& P, const Mat& M, int t, const S* xa, const S* xb, const S* xc,
+                  S* ga, S* gb, S* gc) {
+  if (M.wang)
+    wang_membrane_gradient<S>(xa, xb, xc, &P.Bm[4 * t], P.area[t], &P.Nm[12 * t], M.S, ga, gb, gc);
+  else
+    membrane_gradient<S>(xa, xb, xc, &P.Bm[4 * t], P.area[t], M.ks, ga, gb, gc);
+}
+
+template <class S>
+void mem_hvp(const Problem& P, const Mat& M, int t, const S* xa, const S* xb, const S* xc,
+             const S* ua, const S* ub, const S* uc, int geo, S* oa, S* ob, S* oc) {
+  if (M.wang)
+    wang_membrane_hvp<S>(xa, xb, xc, ua, ub, uc, &P.Bm[4 * t], P.area[t], &P.Nm[12 * t], M.S, geo,
+                         oa, ob, oc);
+  else
+    membrane_hvp<S>(xa, xb, xc, ua, ub, uc, &P.Bm[4 * t], P.area[t], M.ks, geo, oa, ob, oc);
+}
+
+// The warp axis of a rest plane with unit normal n: the x axis projected into the plane,
+// or the y axis where x is within about 0.06 degrees of the normal (R20).
+void material_axis(const double* n, double* u) {
+  double ax[3] = {1.0, 0.0, 0.0};
+  double d = dot3(ax, n);
+  for (int k = 0; k < 3; ++k) u[k] = ax[k] - d * n[k];
+  double l = std::sqrt(dot3(u, u));
+  if (!(l > 1e-3)) {
+    double ay[3] = {0.0, 1.0, 0.0};
+    d = dot3(ay, n);
+    for (int k = 0; k < 3; ++k) u[k] = ay[k] - d * n[k];
+    l = std::sqrt(dot3(u, u));
+  }
+  for (int k = 0; k < 3; ++k) u[k] /= l;
+}
 
 int build_problem(Problem& P, int nv, int nt, const int* tris, const double* rest, const int* pins,
                   int npins) {
@@ -385,6 +603,7 @@ int build_problem(Problem& P, int nv, int nt, const int* tris, const double* res
 
   // Rest frame per triangle: e1 along X_b - X_a, e2 = n x e1 (in-plane), D_m in that frame.
   P.Bm.assign(4 * nt, 0.0);
+  P.Nm.clear();
   P.area.assign(nt, 0.0);
   P.varea.assign(nv, 0.0);
   for (int t = 0; t < nt; ++t) {
@@ -411,6 +630,15 @@ int build_problem(Problem& P, int nv, int nt, const int* tris, const double* res
     P.Bm[4 * t + 2] = -Dm10 / det;
     P.Bm[4 * t + 3] = Dm00 / det;
     for (int k = 0; k < 3; ++k) P.varea[P.tri[3 * t + k]] += P.area[t] / 3.0;
+    // material frame (R20): u = the rest x axis projected into the plane (y if x is
+    // nearly normal to it), v = n x u, written in the local frame (e1, e2)
+    double u3[3];
+    material_axis(n, u3);
+    const double u0 = dot3(u3, e1), u1 = dot3(u3, e2);
+    const double v0 = -u1, v1 = u0, r2 = std::sqrt(2.0);
+    const double Nt[12] = {u0 * u0, u0 * u1, u1 * u1, v0 * v0, v0 * v1, v1 * v1,
+                           r2 * u0 * v0, (u0 * v1 + v0 * u1) / r2, r2 * u1 * v1, 1.0, 0.0, 1.0};
+    P.Nm.insert(P.Nm.end(), Nt, Nt + 12);
   }
 
   // Hinges: every edge used once in each direction by two triangles.
@@ -426,6 +654,7 @@ int build_problem(Problem& P, int nv, int nt, const int* tris, const double* res
   P.hv.clear();
   P.hce.clear();
   P.hrest.clear();
+  P.hdw.clear();
   for (auto& kv : directed) {
     int i = kv.first.first, j = kv.first.second;
     if (i > j) continue;  // visit each undirected edge once, from its smaller endpoint
@@ -441,6 +670,24 @@ int build_problem(Problem& P, int nv, int nt, const int* tris, const double* res
     sub3(&rest[3 * j], &rest[3 * i], e);
     P.hce.push_back(3.0 * dot3(e, e) / (P.area[t1] + P.area[t2]));
     P.hrest.push_back(hinge_theta(&rest[3 * i], &rest[3 * j], &rest[3 * o1], &rest[3 * o2]));
+    // bending direction (R21): in the first triangle's plane, normal to the edge; its
+    // angle phi to that triangle's warp axis, folded into [0, 90] degrees, weights the
+    // 0, 45 and 90 degree tables linearly
+    double d2[3], n1[3], ue[3], bd[3], u3[3];
+    sub3(&rest[3 * o1], &rest[3 * i], d2);
+    cross3(e, d2, n1);
+    const double ln1 = std::sqrt(dot3(n1, n1)), le = std::sqrt(dot3(e, e));
+    for (int k = 0; k < 3; ++k) {
+      n1[k] /= ln1;
+      ue[k] = e[k] / le;
+    }
+    cross3(n1, ue, bd);
+    material_axis(n1, u3);
+    const double cphi = std::min(1.0, std::fabs(dot3(bd, u3)));
+    const double q = std::acos(cphi) / (std::atan(1.0));   // phi / 45 degrees, in [0, 2]
+    P.hdw.push_back(q <= 1.0 ? 1.0 - q : 0.0);
+    P.hdw.push_back(q <= 1.0 ? q : 2.0 - q);
+    P.hdw.push_back(q <= 1.0 ? 0.0 : q - 1.0);
   }
   P.nh = (int)P.hce.size();
 
@@ -467,32 +714,37 @@ int build_problem(Problem& P, int nv, int nt, const int* tris, const double* res
 // ----------------------------------------------------- global force routines
 // Internal energy E = E_m + E_b.
 double internal_energy(const Problem& P, const double* x, double* em_out, double* eb_out) {
+  const Mat M = problem_mat(P);
   double em = 0, eb = 0;
   for (int t = 0; t < P.nt; ++t) {
     const int* v = &P.tri[3 * t];
-    em += membrane_energy<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &P.Bm[4 * t],
-                                  P.area[t], P.ks);
+    if (M.wang)
+      em += wang_membrane_energy<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &P.Bm[4 * t],
+                                         P.area[t], &P.Nm[12 * t], M.S);
+    else
+      em += membrane_energy<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &P.Bm[4 * t],
+                                    P.area[t], P.ks);
   }
   for (int e = 0; e < P.nh; ++e) {
     const int* v = &P.hv[4 * e];
     double th = hinge_theta<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]]);
-    double dth = th - P.hrest[e];
-    eb += P.kb * P.hce[e] * dth * dth;
+    double s, w, en;
+    hinge_response(P, M, e, th - P.hrest[e], s, w, &en);
+    eb += en;
   }
   if (em_out) *em_out = em;
   if (eb_out) *eb_out = eb;
   return em + eb;
 }
 
-// Internal force f = -dE/dx with separate stiffness scales (used with ks or kb = 1
-// for the material derivatives of the adjoint).
-void internal_force(const Problem& P, const double* x, double ks, double kb, double* f) {
+// Internal force f = -dE/dx for the stiffness parameters M (the adjoint passes unit
+// parameters for the material derivatives).
+void internal_force(const Problem& P, const double* x, const Mat& M, double* f) {
   std::fill(f, f + 3 * P.nv, 0.0);
   for (int t = 0; t < P.nt; ++t) {
     const int* v = &P.tri[3 * t];
     double g[3][3];
-    membrane_gradient<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &P.Bm[4 * t], P.area[t],
-                              ks, g[0], g[1], g[2]);
+    mem_gradient<double>(P, M, t, &x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], g[0], g[1], g[2]);
     for (int a = 0; a < 3; ++a)
       for (int k = 0; k < 3; ++k) f[3 * v[a] + k] -= g[a][k];
   }
@@ -502,24 +754,24 @@ void internal_force(const Problem& P, const double* x, double ks, double kb, dou
     const double* X[4] = {&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]]};
     double th = hinge_theta<double>(X[0], X[1], X[2], X[3]);
     hinge_theta_grad<double>(X[0], X[1], X[2], X[3], g[0], g[1], g[2], g[3]);
-    double s = 2.0 * kb * P.hce[e] * (th - P.hrest[e]);
+    double s, w;
+    hinge_response(P, M, e, th - P.hrest[e], s, w);
     for (int a = 0; a < 4; ++a)
       for (int k = 0; k < 3; ++k) f[3 * v[a] + k] -= s * g[a][k];
   }
 }
 
-// out = K u. exact = true: the true Hessian of E (membrane scale ks, bending
-// scale kb). exact = false: the system matrix K_sys (Gauss-Newton bending and
-// the configured membrane block).
-void stiffness_apply(const Problem& P, const double* x, const double* u, double ks, double kb,
-                     bool exact, double* out) {
+// out = K u. exact = true: the true Hessian of E (for the parameters M). exact =
+// false: the system matrix K_sys (Gauss-Newton bending and the configured membrane
+// block).
+void stiffness_apply(const Problem& P, const double* x, const double* u, const Mat& M, bool exact,
+                     double* out) {
   std::fill(out, out + 3 * P.nv, 0.0);
   for (int t = 0; t < P.nt; ++t) {
     const int* v = &P.tri[3 * t];
     double o[3][3];
-    membrane_hvp<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &u[3 * v[0]], &u[3 * v[1]],
-                         &u[3 * v[2]], &P.Bm[4 * t], P.area[t], ks, exact ? GEO_EXACT : P.mem_geo,
-                         o[0], o[1], o[2]);
+    mem_hvp<double>(P, M, t, &x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &u[3 * v[0]], &u[3 * v[1]],
+                    &u[3 * v[2]], exact ? GEO_EXACT : P.mem_geo, o[0], o[1], o[2]);
     for (int a = 0; a < 3; ++a)
       for (int k = 0; k < 3; ++k) out[3 * v[a] + k] += o[a][k];
   }
@@ -528,19 +780,19 @@ void stiffness_apply(const Problem& P, const double* x, const double* u, double 
     double g[4][3];
     const double* X[4] = {&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]]};
     hinge_theta_grad<double>(X[0], X[1], X[2], X[3], g[0], g[1], g[2], g[3]);
-    double w = 2.0 * kb * P.hce[e];
+    double th = hinge_theta<double>(X[0], X[1], X[2], X[3]);
+    double s, w;
+    hinge_response(P, M, e, th - P.hrest[e], s, w);
     double gu = 0;
     for (int a = 0; a < 4; ++a) gu += dot3(g[a], &u[3 * v[a]]);
     for (int a = 0; a < 4; ++a)
       for (int k = 0; k < 3; ++k) out[3 * v[a] + k] += w * gu * g[a][k];
     if (exact) {
-      // (theta - theta_rest) * Hess(theta) u, the directional derivative of grad(theta).
+      // s * Hess(theta) u, the directional derivative of grad(theta) along u
       Dual Xd[4][3], gd[4][3];
       for (int a = 0; a < 4; ++a)
         for (int k = 0; k < 3; ++k) Xd[a][k] = Dual(X[a][k], u[3 * v[a] + k]);
       hinge_theta_grad<Dual>(Xd[0], Xd[1], Xd[2], Xd[3], gd[0], gd[1], gd[2], gd[3]);
-      double th = hinge_theta<double>(X[0], X[1], X[2], X[3]);
-      double s = w * (th - P.hrest[e]);
       for (int a = 0; a < 4; ++a)
         for (int k = 0; k < 3; ++k) out[3 * v[a] + k] += s * deriv_of(gd[a][k]);
     }
@@ -551,6 +803,7 @@ void stiffness_apply(const Problem& P, const double* x, const double* u, double 
 // along every one of its coordinates.
 void third_contraction(const Problem& P, const double* x, const double* mu, const double* w,
                        double* out) {
+  const Mat M = problem_mat(P);
   std::fill(out, out + 3 * P.nv, 0.0);
   for (int t = 0; t < P.nt; ++t) {
     const int* v = &P.tri[3 * t];
@@ -562,8 +815,7 @@ void third_contraction(const Problem& P, const double* x, const double* mu, cons
             X[b][m] = Dual(x[3 * v[b] + m], (a == b && k == m) ? 1.0 : 0.0);
             W[b][m] = Dual(w[3 * v[b] + m]);
           }
-        membrane_hvp<Dual>(X[0], X[1], X[2], W[0], W[1], W[2], &P.Bm[4 * t], P.area[t], P.ks,
-                           P.mem_geo, o[0], o[1], o[2]);
+        mem_hvp<Dual>(P, M, t, X[0], X[1], X[2], W[0], W[1], W[2], P.mem_geo, o[0], o[1], o[2]);
         double s = 0;
         for (int b = 0; b < 3; ++b)
           for (int m = 0; m < 3; ++m) s += mu[3 * v[b] + m] * deriv_of(o[b][m]);
@@ -572,7 +824,12 @@ void third_contraction(const Problem& P, const double* x, const double* mu, cons
   }
   for (int e = 0; e < P.nh; ++e) {
     const int* v = &P.hv[4 * e];
-    double wgt = 2.0 * P.kb * P.hce[e];
+    // the Gauss-Newton weight: constant in x on the angle segment (R8: everywhere)
+    double s_unused, wgt;
+    hinge_response(P, M, e,
+                   hinge_theta<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]]) -
+                       P.hrest[e],
+                   s_unused, wgt);
     for (int a = 0; a < 4; ++a)
       for (int k = 0; k < 3; ++k) {
         Dual X[4][3], g[4][3];
@@ -603,6 +860,7 @@ int find_slot(const Problem& P, int i, int j) {
 // K_sys blocks (nnzb * 9, row-major 3x3), assembled by probing each element's
 // Hessian-vector product with unit vectors.
 void assemble_ksys(const Problem& P, const double* x, std::vector<double>& K) {
+  const Mat M = problem_mat(P);
   K.assign(9 * P.col.size(), 0.0);
   for (int t = 0; t < P.nt; ++t) {
     const int* v = &P.tri[3 * t];
@@ -612,8 +870,7 @@ void assemble_ksys(const Problem& P, const double* x, std::vector<double>& K) {
         double U[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
         U[b][m] = 1.0;
         double o[3][3];
-        membrane_hvp<double>(X[0], X[1], X[2], U[0], U[1], U[2], &P.Bm[4 * t], P.area[t], P.ks,
-                             P.mem_geo, o[0], o[1], o[2]);
+        mem_hvp<double>(P, M, t, X[0], X[1], X[2], U[0], U[1], U[2], P.mem_geo, o[0], o[1], o[2]);
         // column (b, m) of the element Hessian
         for (int a = 0; a < 3; ++a) {
           int s = find_slot(P, v[a], v[b]);
@@ -626,7 +883,11 @@ void assemble_ksys(const Problem& P, const double* x, std::vector<double>& K) {
     double g[4][3];
     hinge_theta_grad<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]], g[0], g[1],
                              g[2], g[3]);
-    double w = 2.0 * P.kb * P.hce[e];
+    double s_unused, w;
+    hinge_response(P, M, e,
+                   hinge_theta<double>(&x[3 * v[0]], &x[3 * v[1]], &x[3 * v[2]], &x[3 * v[3]]) -
+                       P.hrest[e],
+                   s_unused, w);
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         int s = find_slot(P, v[a], v[b]);
@@ -788,7 +1049,7 @@ void step_rhs(const Problem& P, const double* x, const double* v, const double* 
               const std::vector<double>& K, double* b) {
   int n = 3 * P.nv;
   std::vector<double> f(n), Kv(n);
-  internal_force(P, x, P.ks, P.kb, f.data());
+  internal_force(P, x, problem_mat(P), f.data());
   if (P.wind_on) wind_force(P, x, v, f.data());
   csr_apply(P, K, v, Kv.data());
   for (int i = 0; i < P.nv; ++i) {
@@ -910,8 +1171,9 @@ void wind_adjoint(const Problem& P, const double* xp, const double* vp, const do
 
 // Steps 5-9 of one backward step of the implicit differentiation of Eq. 4, given
 // the adjoint solution mu of A(x_{s-1}) mu = u, the state (x_{s-1}, v_{s-1}), the
-// new velocity v_s and the increment dv_s: accumulates the material gradient
-// (dL/dk_s, dL/dk_b, dL/dd) in gmat and the wind gradient dL/dw in gwind, and
+// new velocity v_s and the increment dv_s: accumulates the material gradient in gmat
+// ((dL/dk_s, dL/dk_b, dL/dd), or (dL/dS [24], dL/dB [15], dL/dd) with the anisotropic
+// model) and the wind gradient dL/dw in gwind, and
 // replaces (gx, gv) by the gradients with respect to (x_{s-1}, v_{s-1}).
 void adjoint_update(const Problem& P, const double* xp, const double* vp, const double* vs,
                     const double* dvs, const double* mu, const double* u, double* gx, double* gv,
@@ -920,24 +1182,31 @@ void adjoint_update(const Problem& P, const double* xp, const double* vp, const 
   const double h1 = P.h, h2 = P.h * P.h;
   std::vector<double> tmp(n), tmp2(n), fh(n), wx(n, 0.0), wv(n, 0.0);
   if (P.wind_on) wind_adjoint(P, xp, vp, dvs, mu, wx.data(), wv.data(), gwind);
-  // 5. dL/dk_s += mu . (h f_m/k_s - h^2 (K_m/k_s) v_s)
-  internal_force(P, xp, 1.0, 0.0, fh.data());
-  stiffness_apply(P, xp, vs, 1.0, 0.0, false, tmp.data());
-  for (int k = 0; k < n; ++k) gmat[0] += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
-  // 6. dL/dk_b += mu . (h f_b/k_b - h^2 (K_b,GN/k_b) v_s)
-  internal_force(P, xp, 0.0, 1.0, fh.data());
-  stiffness_apply(P, xp, vs, 0.0, 1.0, false, tmp.data());
-  for (int k = 0; k < n; ++k) gmat[1] += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
-  // 7. dL/dd += mu . (h A_vert g - A_vert dv_s)
+  // 5.-6. each stiffness parameter theta (the force and K_sys are linear in it):
+  // dL/dtheta += mu . (h f_theta - h^2 K_sys,theta v_s), f_theta and K_sys,theta those of
+  // the unit parameter
+  const Mat M = problem_mat(P);
+  const int nstiff = M.wang ? kWangStretch + kWangBend : 2;
+  for (int q = 0; q < nstiff; ++q) {
+    Mat U;
+    U.wang = M.wang;
+    if (!M.wang) (q == 0 ? U.ks : U.kb) = 1.0;
+    else if (q < kWangStretch) U.S[q] = 1.0;
+    else U.B[q - kWangStretch] = 1.0;
+    internal_force(P, xp, U, fh.data());
+    stiffness_apply(P, xp, vs, U, false, tmp.data());
+    for (int k = 0; k < n; ++k) gmat[q] += mu[k] * (h1 * fh[k] - h2 * tmp[k]);
+  }
+  // 7. dL/dd += mu . (h A_vert g - A_vert dv_s)  (the last material entry)
   for (int i = 0; i < P.nv; ++i)
     for (int k = 0; k < 3; ++k)
-      gmat[2] += mu[3 * i + k] * P.varea[i] * (h1 * P.grav[k] - dvs[3 * i + k]);
+      gmat[nstiff] += mu[3 * i + k] * P.varea[i] * (h1 * P.grav[k] - dvs[3 * i + k]);
   // 8. gx -= h K_exact mu + h^2 grad_x(mu^T K_sys v_s)
-  stiffness_apply(P, xp, mu, P.ks, P.kb, true, tmp.data());
+  stiffness_apply(P, xp, mu, M, true, tmp.data());
   third_contraction(P, xp, mu, vs, tmp2.data());
   for (int k = 0; k < n; ++k) gx[k] -= h1 * tmp[k] + h2 * tmp2[k];
   // 9. gv = mask(u - h^2 K_sys mu), plus the wind's velocity terms
-  stiffness_apply(P, xp, mu, P.ks, P.kb, false, tmp.data());
+  stiffness_apply(P, xp, mu, M, false, tmp.data());
   for (int i = 0; i < P.nv; ++i)
     for (int k = 0; k < 3; ++k)
       gv[3 * i + k] = P.pinned[i] ? 0.0 : u[3 * i + k] - h2 * tmp[3 * i + k] + wv[3 * i + k];
@@ -985,6 +1254,7 @@ int orc_set_params(void* h, double ks, double kb, double dens, double dt, double
 // 2 = tension part, 0 = none (Gauss-Newton).
 int orc_set_membrane_system(void* h, int geo) {
   if (geo < GEO_NONE || geo > GEO_TENSION) return ORC_E_INVALID;
+  if (geo == GEO_TENSION && static_cast<Problem*>(h)->wang) return ORC_E_INVALID;
   static_cast<Problem*>(h)->mem_geo = geo;
   return ORC_OK;
 }
@@ -1009,17 +1279,17 @@ double orc_energy(void* h, const double* x, double* em, double* eb) {
 
 void orc_internal_force(void* h, const double* x, double* f) {
   Problem* P = static_cast<Problem*>(h);
-  internal_force(*P, x, P->ks, P->kb, f);
+  internal_force(*P, x, problem_mat(*P), f);
 }
 
 void orc_ksys_apply(void* h, const double* x, const double* u, double* out) {
   Problem* P = static_cast<Problem*>(h);
-  stiffness_apply(*P, x, u, P->ks, P->kb, false, out);
+  stiffness_apply(*P, x, u, problem_mat(*P), false, out);
 }
 
 void orc_kexact_apply(void* h, const double* x, const double* u, double* out) {
   Problem* P = static_cast<Problem*>(h);
-  stiffness_apply(*P, x, u, P->ks, P->kb, true, out);
+  stiffness_apply(*P, x, u, problem_mat(*P), true, out);
 }
 
 void orc_ksys_assembled_apply(void* h, const double* x, const double* u, double* out) {
@@ -1138,7 +1408,8 @@ int orc_rollout(void* h, int nsteps, const double* x0, const double* v0, const d
 
 // Rollout followed by the adjoint sweep (implicit differentiation of Eq. 4 with
 // a per-frame loss whose gradient dl_dx [nloss][V][3] the caller supplies).
-// Outputs: dl_dmat = (dL/dk_s, dL/dk_b, dL/dd); dl_dF [nsteps][V][3];
+// Outputs: dl_dmat = (dL/dk_s, dL/dk_b, dL/dd), or [40] = (dL/dS, dL/dB, dL/dd) with the
+// anisotropic model; dl_dF [nsteps][V][3];
 // dl_dx0, dl_dv0 [V][3]. Any output pointer may be NULL.
 int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const double* forces,
                  const int* loss_frames, int nloss, const double* dl_dx, double* dl_dmat,
@@ -1152,7 +1423,7 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
   if (st != ORC_OK && st != ORC_E_NOT_CONVERGED) return st;
 
   std::vector<double> gx(n, 0.0), gv(n, 0.0), u(n), mu(n), K, A;
-  double gmat[3] = {0.0, 0.0, 0.0}, gwind[3] = {0.0, 0.0, 0.0};
+  double gmat[kWangParams] = {}, gwind[3] = {0.0, 0.0, 0.0};
   int frame = nloss - 1;
   for (int s = nsteps; s >= 1; --s) {
     const double* xp = &X[(size_t)(s - 1) * n];
@@ -1178,12 +1449,8 @@ int orc_gradient(void* h, int nsteps, const double* x0, const double* v0, const 
     adjoint_update(*P, xp, &Vv[(size_t)(s - 1) * n], &Vv[(size_t)s * n], &DV[(size_t)s * n],
                    mu.data(), u.data(), gx.data(), gv.data(), gmat, gwind);
   }
-  double gks = gmat[0], gkb = gmat[1], gd = gmat[2];
-  if (dl_dmat) {
-    dl_dmat[0] = gks;
-    dl_dmat[1] = gkb;
-    dl_dmat[2] = gd;
-  }
+  if (dl_dmat)
+    for (int q = 0; q < (P->wang ? kWangParams : 3); ++q) dl_dmat[q] = gmat[q];
   if (dl_dwind)
     for (int k = 0; k < 3; ++k) dl_dwind[k] = gwind[k];
   if (dl_dx0) std::copy(gx.begin(), gx.end(), dl_dx0);
@@ -1225,7 +1492,8 @@ void orc_adjoint_rhs(void* h, const double* gx, const double* gv, double* u) {
 }
 
 // The rest of one backward step once mu solves A(x_{s-1}, v_{s-1}) mu = u: accumulates
-// (dL/dk_s, dL/dk_b, dL/dd) into gmat[3] and dL/dw into gwind[3], and replaces (gx, gv)
+// (dL/dk_s, dL/dk_b, dL/dd) into gmat[3] (anisotropic model: gmat[40]) and dL/dw into
+// gwind[3], and replaces (gx, gv)
 // in place by the gradients with respect to (x_{s-1}, v_{s-1}). dL/dF_{s-1} is h mu.
 void orc_adjoint_update(void* h, const double* xp, const double* vp, const double* vs,
                         const double* dvs, const double* mu, const double* u, double* gx,
@@ -1235,6 +1503,36 @@ void orc_adjoint_update(void* h, const double* xp, const double* vp, const doubl
 
 // Wind (R19): on != 0 switches the aerodynamic force on with velocity (wx, wy, wz)
 // [m/s] and air density rho [kg/m^3].
+// Material model of the internal forces: 0 = isotropic (k_s, k_b of orc_set_params),
+// 1 = anisotropic (R20, R21) with stretch table S [4][6] and bend table B [3][5];
+// density stays that of orc_set_params. The anisotropic model takes the exact or the
+// Gauss-Newton membrane block, not the tension variant.
+int orc_set_material(void* h, int model, const double* S24, const double* B15) {
+  Problem* P = static_cast<Problem*>(h);
+  if (model != 0 && model != 1) return ORC_E_INVALID;
+  if (model == 1) {
+    if (!S24 || !B15 || P->mem_geo == GEO_TENSION) return ORC_E_INVALID;
+    for (int q = 0; q < kWangStretch; ++q)
+      if (!std::isfinite(S24[q])) return ORC_E_NONFINITE;
+    for (int q = 0; q < kWangBend; ++q)
+      if (!std::isfinite(B15[q])) return ORC_E_NONFINITE;
+    std::copy(S24, S24 + kWangStretch, P->wS);
+    std::copy(B15, B15 + kWangBend, P->wB);
+  }
+  P->wang = model == 1;
+  return ORC_OK;
+}
+
+int orc_num_material(void* h) { return static_cast<Problem*>(h)->wang ? kWangParams : 3; }
+
+// The anisotropic model's geometry: per triangle the measure tensors N_1..N_4 in its
+// local frame (N_00, N_01, N_11 each) [nt][12], per hinge the direction weights [nh][3].
+void orc_get_material_frames(void* h, double* N12, double* hdw) {
+  Problem* P = static_cast<Problem*>(h);
+  if (N12) std::copy(P->Nm.begin(), P->Nm.end(), N12);
+  if (hdw) std::copy(P->hdw.begin(), P->hdw.end(), hdw);
+}
+
 int orc_set_wind(void* h, int on, double wx, double wy, double wz, double rho) {
   Problem* P = static_cast<Problem*>(h);
   if (!std::isfinite(wx) || !std::isfinite(wy) || !std::isfinite(wz) || !(rho >= 0.0))

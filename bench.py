@@ -225,6 +225,9 @@ def main():
                     help="also time K iterations of the adaptive-window Adam loop on a 17x17 "
                          "sheet with all 40 frames active, reported in the 'window' "
                          "sub-object (0: skip)")
+    ap.add_argument("--wang-steps", type=int, default=2, metavar="K",
+                    help="also time K gradients of the headline sheet with the anisotropic "
+                         "strain-dependent material, reported in the 'wang' sub-object (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run three plain device copies of MIB MiB (untimed), the "
                          "known-size reference for scaling HBM byte counters")
@@ -329,6 +332,9 @@ def main():
     if args.chamfer_steps > 0:
         print("bench: Chamfer distance", file=sys.stderr, flush=True)
         out["chamfer"] = chamfer_timing(65536, 40000, args.chamfer_steps, 3)
+    if args.wang_steps > 0 and len(insts) == 1:
+        print("bench: anisotropic material", file=sys.stderr, flush=True)
+        out["wang"] = wang_timing(w, insts, args.wang_steps, 1, not args.no_autotune)
     if args.window_iters > 0:
         print("bench: adaptive-window Adam loop", file=sys.stderr, flush=True)
         out["window"] = window_timing(args.window_iters, 2)
@@ -421,6 +427,59 @@ def window_timing(iters: int, warmup: int):
                loss_first=recs[0].loss, loss_last=recs[-1].loss,
                cg_iters_last_gradient=int(st["cg_iters_forward"] + st["cg_iters_adjoint"]))
     s.close()
+    return out
+
+
+def wang_timing(w, insts, steps, warmup, autotune):
+    """The headline gradient with the anisotropic strain-dependent material (stretch
+    table S [4][6], bend table B [3][5]): seeded tables of factors U[0.5, 2] around the
+    workload's (k_s, k_b), an area term of 0.3 k_s; the target rollout scales S, B and d
+    by the workload's target factors. Same timing as the headline."""
+    import numpy as np
+    import torch
+    from paper_2203_11938_amd import sim as S, workloads as W
+    dev = torch.device("cuda:0")
+    g = np.random.default_rng(9001)
+    ks, kb, d = insts[0].material.as_tuple()
+    St = np.exp(g.uniform(np.log(0.5), np.log(2.0), size=(4, 6))) * ks
+    St[3] *= 0.3
+    Bt = np.exp(g.uniform(np.log(0.5), np.log(2.0), size=(3, 5))) * kb
+    f = insts[0].target_factors
+    mat = torch.tensor(S.wang_material(St, Bt, d)[None], device=dev)
+    mat_t = torch.tensor(S.wang_material(St * f[0], Bt * f[1], d * f[2])[None], device=dev)
+    sheets = [S.Sheet(i.tris, i.rest, i.pins, *i.material.as_tuple()) for i in insts]
+    sim = S.Simulator(sheets, dt=w.dt, precision=w.precision, cg_tol=w.cg_tol,
+                      max_steps=w.steps, autotune=autotune, material_model="wang")
+    dt = sim.dtype
+    x0 = torch.tensor(W.to_soa(insts[0].x0), dtype=dt, device=dev)
+    F = torch.tensor(W.to_soa(insts[0].forces), dtype=dt, device=dev)
+    frames = w.loss_frames()
+    tgt = sim.rollout(w.steps, x0, None, F, mat_t, frames).clone()
+    sim.status()
+
+    def gradient():
+        xo = sim.rollout(w.steps, x0, None, F, mat, frames)
+        return sim.adjoint((2.0 * (xo - tgt)).contiguous())
+
+    for _ in range(warmup):
+        gradient()
+        sim.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        gradient()
+        sim.status()
+        st = sim.stats()
+        iters += st["cg_iters_forward"] + st["cg_iters_adjoint"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = dict(workload=f"{w.name}: {w.n}x{w.n} sheet, {w.steps} steps of {w.dt} s, rollout + "
+                        "adjoint, anisotropic material (40 material gradient entries)",
+               steps=steps, warmup=warmup, ms_per_gradient=round(1e3 * wall / steps, 3),
+               value=round(sim.n_verts * w.steps * steps / wall, 1), unit="vertex-steps/s",
+               cg_iters_per_gradient=iters // steps, device_status=S.status_name(sim.status()))
+    sim.close()
     return out
 
 

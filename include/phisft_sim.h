@@ -3,9 +3,10 @@
  *
  * What it computes (Kairanda et al., "phi-SfT", CVPR 2022, Sec. 3.1):
  *   * the deformation model S_t = PS(S_{t-1}; phi_{t-1}) (Eq. 1) with
- *     phi = {d, S, B, w, F_t} (Eq. 2): areal density d, stretching stiffness
- *     k_s (a scalar reduction of S), bending stiffness k_b (a scalar reduction
- *     of B), an optional wind velocity w driving an aerodynamic force (air
+ *     phi = {d, S, B, w, F_t} (Eq. 2): areal density d, stretching stiffness S
+ *     and bending stiffness B (scalars k_s, k_b, or strain-dependent anisotropic
+ *     tables S in R^24, B in R^15; see sim_material_model), an optional wind
+ *     velocity w driving an aerodynamic force (air
  *     density fixed, Sec. 3.4; see sim_rollout) and per-step, per-vertex
  *     corrective forces F_t;
  *   * per step one linearised backward-Euler update (Eq. 4 with the force
@@ -19,14 +20,16 @@
  *         v_t = v_{t-1} + Delta v,   x_t = x_{t-1} + h v_t
  *     with M the lumped mass (density times a third of the incident triangle
  *     areas), f = -dE/dx for E = sum_tri area (k_s/2) |G|_F^2 (Green strain G)
- *     + sum_hinge k_b c_e (theta - theta_rest)^2, and K_sys the system
- *     stiffness (membrane Hessian, see sim_membrane_system, plus the
- *     Gauss-Newton bending Hessian 2 k_b c_e grad(theta) grad(theta)^T), and
+ *     + sum_hinge k_b c_e (theta - theta_rest)^2 (or the anisotropic energy of
+ *     sim_material_model), and K_sys the system stiffness (membrane Hessian, see
+ *     sim_membrane_system, plus the Gauss-Newton bending Hessian
+ *     d^2E/dtheta^2 grad(theta) grad(theta)^T), and
  *     D = -df/dv the velocity Jacobian of the aerodynamic force (zero without
  *     wind);
  *   * the adjoint of that rollout (the paper's backward pass by implicit
  *     differentiation of Eq. 4): gradients of a per-frame loss with respect to
- *     (k_s, k_b, d), the wind velocity w, the forces F_t and the initial state
+ *     the material (k_s, k_b, d or S, B, d), the wind velocity w, the forces F_t
+ *     and the initial state
  *     (x_0, v_0).
  * Collisions (Eq. 6) are not part of this library.
  *
@@ -36,8 +39,10 @@
  *              A batch handle concatenates its instances' vertices in order.
  *   dtype      Device state arrays (x0, v0, forces, x_out, dl_dx, dl_dforces,
  *              dl_dx0, dl_dv0) are float for SIM_FP32 and double for SIM_FP64.
- *              Material arrays are always double, [n_instances][3] =
- *              (k_s [N/m], k_b [N m], d [kg/m^2]).
+ *              Material arrays are always double, [n_instances][n_mat]: with
+ *              SIM_MATERIAL_ISOTROPIC n_mat = 3, (k_s [N/m], k_b [N m], d [kg/m^2]);
+ *              with SIM_MATERIAL_WANG n_mat = SIM_WANG_PARAMS = 40, the stretch
+ *              table S [4][6] [N/m], the bend table B [3][5] [N m], then d.
  *   Units      SI. Gravity defaults to (0, 0, -9.81) m/s^2.
  *   Ownership  sim_create copies mesh, rest positions and pins. The caller owns
  *              every device pointer passed to sim_rollout / sim_adjoint. The
@@ -99,6 +104,33 @@ typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
  *                         instance at the rest state), so gradients taken there
  *                         depend on rounding. */
 typedef enum { SIM_MEMBRANE_EXACT = 0, SIM_MEMBRANE_TENSION = 1 } sim_membrane_system;
+
+/* Material model of the internal forces (the paper's S and B, Eq. 2, after Wang et
+ * al., whose formulas the paper does not give; sim_options.material_model).
+ *   SIM_MATERIAL_ISOTROPIC  E = sum_tri area (k_s/2) |G|_F^2 + sum_hinge k_b c_e
+ *                           (theta - theta_rest)^2: scalar stand-ins for S and B.
+ *   SIM_MATERIAL_WANG       strain-dependent, anisotropic (S in R^24, B in R^15):
+ *     stretch  four measures of the Green strain G in the sheet's material frame (u:
+ *              the rest x axis projected into the triangle's plane, the rest y axis
+ *              where x is within 0.06 degrees of its normal; v = n x u): s_1 = G_uu
+ *              (warp), s_2 = G_vv (weft), s_3 = sqrt(2) G_uv (shear), s_4 = G_uu + G_vv
+ *              (area). Measure k has a piecewise-linear stress sigma_k(|s|) whose slope
+ *              is S[k][j] on strain segment j (breaks SIM_WANG_STRAIN_BREAKS: 0, 0.25,
+ *              0.5, 1, 2, 4 %, the last segment open); the energy is
+ *              sum_tri area sum_k psi_k(|s_k|) with psi_k' = sigma_k.
+ *     bending  sum_hinge c_e Phi_e(theta - theta_rest), Phi(d) = 2 psi(|d|), psi' the
+ *              piecewise-linear moment whose slope on angle segment j (breaks 0, 0.05,
+ *              0.1, 0.2, 0.4 rad) is B[0][j], B[1][j], B[2][j] interpolated linearly in
+ *              the angle (0, 45, 90 degrees) between the bending direction (in the
+ *              plane of the hinge's first triangle, normal to the edge) and that
+ *              plane's warp axis.
+ *     S[0..2][j] = k_s, S[3][j] = 0 and B[a][j] = k_b give the isotropic model; the
+ *     membrane block of K_sys is the exact Hessian (SIM_MEMBRANE_TENSION is refused).
+ *     The create-time sim_material (k_s, k_b, d) becomes such isotropic tables. */
+typedef enum { SIM_MATERIAL_ISOTROPIC = 0, SIM_MATERIAL_WANG = 1 } sim_material_model;
+#define SIM_WANG_STRETCH 24
+#define SIM_WANG_BEND 15
+#define SIM_WANG_PARAMS 40
 
 /* Where the persistent solver keeps its workgroup's rows of the system matrix during
  * a solve. Every home computes the same products in the same order (bitwise equal
@@ -185,6 +217,8 @@ typedef struct {
                                bounded by checkpoint_every; recomputed steps rebuild
                                theirs), 1 keeps every step's when they fit 16 GB (the
                                recompute then reuses the forward's: faster, more memory) */
+  int32_t material_model;   /* sim_material_model (default SIM_MATERIAL_ISOTROPIC): sets
+                               the material arrays' n_mat (3 or SIM_WANG_PARAMS)        */
 } sim_options;
 
 /* Per-handle statistics of the most recent rollout/adjoint (filled by
@@ -219,12 +253,14 @@ typedef struct {
   int64_t device_bytes;       /* device memory the handle holds (workspace, trajectory or
                                  checkpoints, kept coarse operators, tables) */
   int32_t coarse_store_slots; /* steps whose coarse operators are kept for the adjoint */
+  int32_t material_params;    /* n_mat of the material arrays (3 or SIM_WANG_PARAMS) */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,
  * store every state, gravity (0,0,-9.81), max_steps 1000, tuned rows per block,
  * exact membrane Hessian, FP64 system matrix, aggregates of 64 vertices, air
- * density 1 kg/m^3, coarse operators of one checkpoint segment kept. */
+ * density 1 kg/m^3, coarse operators of one checkpoint segment kept, isotropic
+ * material. */
 void sim_default_options(sim_options* opt);
 
 /* Creates a handle for one sheet.
@@ -258,7 +294,8 @@ sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* con
  *   x0, v0       device [3][V] initial state; v0 may be NULL (zero). Pinned
  *                vertices keep x0 and zero velocity.
  *   forces       device [n_steps][3][V]: forces[s-1] acts in step s; NULL = none
- *   material     device double [n_instances][3]; NULL = the create-time materials
+ *   material     device double [n_instances][n_mat] (see dtype); NULL = the
+ *                create-time materials
  *   wind         device double [n_instances][3]: the wind velocity w [m/s] of each
  *                sheet (Eq. 2's w), or NULL for no aerodynamic force. Given a wind,
  *                every triangle t feels rho_air * area_t * |s| s n in the step's
@@ -296,7 +333,8 @@ sim_status sim_rollout_noalloc(sim_t* sim, int32_t n_steps, const void* x0, cons
 
 /* Adjoint of the most recent rollout for a loss with gradient dl_dx
  * (device [n_loss][3][V], one slice per loss frame).
- *   dl_dmaterial  device double [n_instances][3] (dL/dk_s, dL/dk_b, dL/dd) or NULL
+ *   dl_dmaterial  device double [n_instances][n_mat] (dL/dk_s, dL/dk_b, dL/dd, or
+ *                 dL/dS, dL/dB, dL/dd) or NULL
  *   dl_dwind      device double [n_instances][3] (dL/dw) or NULL; must be NULL when
  *                 the rollout had no wind
  *   dl_dforces    device [n_steps][3][V] or NULL

@@ -365,6 +365,98 @@ __device__ __forceinline__ void wind_frame(const double e1[3], const double e2[3
 // rho area |s| s n (n its unit normal at x, s = n . (w - its mean vertex velocity at v),
 // area its rest area), a third to each vertex, and the factor c = 2 rho area |s| / 9 of
 // its damping blocks: every 3x3 block of its -df/dv is c n n^T.
+// ------------------------------------------ anisotropic strain-dependent material
+// Piecewise-linear responses: stiffness k_j on segment j of the deformation measure t,
+// breaks at 0, 0.25, 0.5, 1, 2, 4 % strain (stretch) and 0, 0.05, 0.1, 0.2, 0.4 rad
+// (bending), the last segment open. sigma(t) = sum_j k_j part_j(t), part_j(t) the length
+// of [0, t] inside segment j (also d sigma / d k_j); the stiffness at t is k of t's
+// segment.
+template <bool STRAIN>
+__device__ __forceinline__ double wang_break(int j) {
+  if constexpr (STRAIN)
+    return j == 0 ? 0.0 : j == 1 ? 0.0025 : j == 2 ? 0.005 : j == 3 ? 0.01 : j == 4 ? 0.02 : 0.04;
+  else
+    return j == 0 ? 0.0 : j == 1 ? 0.05 : j == 2 ? 0.1 : j == 3 ? 0.2 : 0.4;
+}
+
+template <int N, bool STRAIN>
+__device__ __forceinline__ double seg_part(int j, double t) {
+  const double d = t - wang_break<STRAIN>(j);
+  if (d <= 0.0) return 0.0;
+  return j == N - 1 ? d : fmin(d, wang_break<STRAIN>(j + 1) - wang_break<STRAIN>(j));
+}
+
+template <int N, bool STRAIN>
+__device__ __forceinline__ int seg_of(double t) {
+  int j = 0;
+#pragma unroll
+  for (int q = 1; q < N; ++q) j = t >= wang_break<STRAIN>(q) ? q : j;
+  return j;
+}
+
+// N : X for a symmetric measure tensor stored as (N_00, N_01, N_11).
+__device__ __forceinline__ double ncon(const double N[3], const double X[2][2]) {
+  return N[0] * X[0][0] + N[1] * (X[0][1] + X[1][0]) + N[2] * X[1][1];
+}
+
+// Stretch response of a triangle (anisotropic material): the second Piola stress Sg =
+// sum_k sgn(s_k) sigma_k(|s_k|) N_k of the strain G, each measure's s_k and segment
+// stiffness c_k. Stretch table St [4][6].
+__device__ __forceinline__ void wang_stretch(const double N[4][3], const double* St,
+                                             const double G[2][2], double Sg[2][2],
+                                             double sk[4], double c[4]) {
+  Sg[0][0] = Sg[0][1] = Sg[1][0] = Sg[1][1] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    sk[k] = ncon(N[k], G);
+    const double t = fabs(sk[k]);
+    double sig = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sig += St[6 * k + j] * seg_part<6, true>(j, t);
+    c[k] = St[6 * k + seg_of<6, true>(t)];
+    const double sg = sk[k] < 0.0 ? -sig : sig;
+    Sg[0][0] += sg * N[k][0];
+    Sg[0][1] += sg * N[k][1];
+    Sg[1][0] += sg * N[k][1];
+    Sg[1][1] += sg * N[k][2];
+  }
+}
+
+// Bending response of hinge e at the angle change dth: sc = dE/dtheta, w =
+// d^2E/dtheta^2 (isotropic: 2 k_b c_e dth and 2 k_b c_e).
+template <bool WANG>
+__device__ __forceinline__ void hinge_response(const Mesh& m, const double* mat, int e, double dth,
+                                               double& sc, double& w) {
+  const int inst = m.hin_inst[e];
+  const double ce = m.hin_ce[e];
+  if constexpr (!WANG) {
+    w = 2.0 * mat[m.matn * inst + 1] * ce;
+    sc = w * dth;
+    return;
+  }
+  const double* Bt = mat + m.matn * inst + kWangStretch;
+  const double d0 = m.hin_dw[e], d1 = m.hin_dw[m.nh + e], d2 = m.hin_dw[2 * m.nh + e];
+  const double t = fabs(dth);
+  const int sj = seg_of<5, false>(t);
+  double sig = 0.0, kt = 0.0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const double kj = d0 * Bt[j] + d1 * Bt[5 + j] + d2 * Bt[10 + j];
+    sig += kj * seg_part<5, false>(j, t);
+    kt = j == sj ? kj : kt;
+  }
+  sc = 2.0 * ce * (dth < 0.0 ? -sig : sig);
+  w = 2.0 * ce * kt;
+}
+
+__device__ __forceinline__ void load_measures(const Mesh& m, int t, double N[4][3]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) N[k][q] = m.tri_N[(3 * k + q) * m.nt + t];
+}
+
+template <bool WANG>
 __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double* __restrict__ x,
                                                   const double* __restrict__ vel,
                                                   const double* __restrict__ mat,
@@ -377,55 +469,104 @@ __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double*
     int v[3];
     tri_load(m, x, t, s, v);
     const int inst = m.tri_inst[t];
-    double ak = s.area * mat[3 * inst + 0];
-    // stress term of the system block: G itself (exact Hessian) or its tension part
-    double Gp[2][2];
-    if (m.tension) {
-      tension(eig2(s.G), Gp);
+    if constexpr (WANG) {
+      // anisotropic stretch: f_i = -A F Sg w_i,
+      // K_ij = A [ (w_i^T Sg w_j) I + sum_k c_k (F N_k w_i)(F N_k w_j)^T ]
+      double N[4][3], Sg[2][2], sk[4], c[4];
+      load_measures(m, t, N);
+      wang_stretch(N, mat + m.matn * inst, s.G, Sg, sk, c);
+      bool okw = true;
+      double FNw[4][3][3];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double n0 = N[k][0] * s.w[i][0] + N[k][1] * s.w[i][1];
+          const double n1 = N[k][1] * s.w[i][0] + N[k][2] * s.w[i][1];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) FNw[k][i][r] = s.F[r][0] * n0 + s.F[r][1] * n1;
+        }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double sw0 = Sg[0][0] * s.w[i][0] + Sg[0][1] * s.w[i][1];
+        const double sw1 = Sg[1][0] * s.w[i][0] + Sg[1][1] * s.w[i][1];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const double f = -s.area * (s.F[r][0] * sw0 + s.F[r][1] * sw1);
+          okw = okw && isfinite(f);
+          el.tri_f[(i * 3 + r) * nt + t] = f;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          const double gij = s.w[i][0] * (Sg[0][0] * s.w[j][0] + Sg[0][1] * s.w[j][1]) +
+                             s.w[i][1] * (Sg[1][0] * s.w[j][0] + Sg[1][1] * s.w[j][1]);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              double k = r == q ? gij : 0.0;
+#pragma unroll
+              for (int a = 0; a < 4; ++a) k += c[a] * FNw[a][i][r] * FNw[a][j][q];
+              el.tri_K[((i * 3 + j) * 9 + r * 3 + q) * nt + t] = s.area * k;
+            }
+        }
+      if (!okw) set_status(status, inst, ST_NONFINITE);
     } else {
+      double ak = s.area * mat[m.matn * inst + 0];
+      // stress term of the system block: G itself (exact Hessian) or its tension part
+      double Gp[2][2];
+      if (m.tension) {
+        tension(eig2(s.G), Gp);
+      } else {
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) Gp[p][q] = s.G[p][q];
+          for (int q = 0; q < 2; ++q) Gp[p][q] = s.G[p][q];
+      }
+      double aw[3][3];  // a_i = F w_i
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) aw[i][r] = s.F[r][0] * s.w[i][0] + s.F[r][1] * s.w[i][1];
+      bool ok = true;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double gw0 = s.G[0][0] * s.w[i][0] + s.G[0][1] * s.w[i][1];
+        double gw1 = s.G[1][0] * s.w[i][0] + s.G[1][1] * s.w[i][1];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double f = -ak * (s.F[r][0] * gw0 + s.F[r][1] * gw1);
+          ok = ok && isfinite(f);
+          el.tri_f[(i * 3 + r) * nt + t] = f;
+        }
+      }
+      double FF[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) FF[r][c] = s.F[r][0] * s.F[c][0] + s.F[r][1] * s.F[c][1];
+      // K_ij = area k_s [ (w_i^T G' w_j) I + 1/2 (w_i . w_j) F F^T + 1/2 (F w_j)(F w_i)^T ]
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          double gij = s.w[i][0] * (Gp[0][0] * s.w[j][0] + Gp[0][1] * s.w[j][1]) +
+                       s.w[i][1] * (Gp[1][0] * s.w[j][0] + Gp[1][1] * s.w[j][1]);
+          double cij = s.w[i][0] * s.w[j][0] + s.w[i][1] * s.w[j][1];
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              double k = ak * ((r == c ? gij : 0.0) + 0.5 * cij * FF[r][c] + 0.5 * aw[j][r] * aw[i][c]);
+              el.tri_K[((i * 3 + j) * 9 + r * 3 + c) * nt + t] = k;
+            }
+        }
+      if (!ok) set_status(status, inst, ST_NONFINITE);
     }
-    double aw[3][3];  // a_i = F w_i
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) aw[i][r] = s.F[r][0] * s.w[i][0] + s.F[r][1] * s.w[i][1];
     bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double gw0 = s.G[0][0] * s.w[i][0] + s.G[0][1] * s.w[i][1];
-      double gw1 = s.G[1][0] * s.w[i][0] + s.G[1][1] * s.w[i][1];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        double f = -ak * (s.F[r][0] * gw0 + s.F[r][1] * gw1);
-        ok = ok && isfinite(f);
-        el.tri_f[(i * 3 + r) * nt + t] = f;
-      }
-    }
-    double FF[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) FF[r][c] = s.F[r][0] * s.F[c][0] + s.F[r][1] * s.F[c][1];
-    // K_ij = area k_s [ (w_i^T G' w_j) I + 1/2 (w_i . w_j) F F^T + 1/2 (F w_j)(F w_i)^T ]
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        double gij = s.w[i][0] * (Gp[0][0] * s.w[j][0] + Gp[0][1] * s.w[j][1]) +
-                     s.w[i][1] * (Gp[1][0] * s.w[j][0] + Gp[1][1] * s.w[j][1]);
-        double cij = s.w[i][0] * s.w[j][0] + s.w[i][1] * s.w[j][1];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            double k = ak * ((r == c ? gij : 0.0) + 0.5 * cij * FF[r][c] + 0.5 * aw[j][r] * aw[i][c]);
-            el.tri_K[((i * 3 + j) * 9 + r * 3 + c) * nt + t] = k;
-          }
-      }
     if (wind) {
       double e1[3], e2[3], rel[3], n[3], sn, ln;
 #pragma unroll
@@ -454,8 +595,8 @@ __global__ void __launch_bounds__(256) k_elements(Mesh m, Elem el, const double*
     hinge_load(m, x, e, v, X);
     double th = hinge_theta(X);
     hinge_grad<double>(X, g);
-    double w = 2.0 * mat[3 * m.hin_inst[e] + 1] * m.hin_ce[e];
-    double s = w * (th - m.hin_rest[e]);
+    double s, w;
+    hinge_response<WANG>(m, mat, e, th - m.hin_rest[e], s, w);
     bool ok = isfinite(s);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -542,7 +683,7 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   const bool live = i0 < nv;
   const int i = live ? i0 : nv - 1;
   const int inst = m.vert_inst[i];
-  const double mass = a.mat[3 * inst + 2] * m.varea[i];
+  const double mass = a.mat[m.matn * inst + m.matn - 1] * m.varea[i];
   const bool pin_i = m.pinned[i] != 0;
   const double h = a.h, h2 = a.h * a.h;
   double kv[3] = {0.0, 0.0, 0.0};
@@ -2415,7 +2556,7 @@ __global__ void __launch_bounds__(256) k_adj_pre(int nv, const int* __restrict__
 //   ag = -h K_exact mu - h^2 grad_x(mu^T K_sys(x) v_s)   (state gradient)
 //   ak = K_sys mu                                         (velocity gradient)
 //   acc_ks += mu . (h f_m/k_s - h^2 (K_sys,m/k_s) v_s), acc_kb likewise.
-template <typename T>
+template <typename T, bool WANG>
 __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T> a) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nv = m.nv;
@@ -2425,7 +2566,7 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
     Tri s;
     int v[3];
     tri_load(m, a.x, t, s, v);
-    const double ks = a.mat[3 * m.tri_inst[t] + 0];
+    const double ks = a.mat[m.matn * m.tri_inst[t] + 0];
     double mu[3][3], vv[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -2462,50 +2603,112 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
         S2[p][q] = 0.5 * (fv + vf);
         S1[p][q] = 0.5 * (mv + vm);
       }
-    // stress term of K_sys and its derivative along S1
-    double Gp[2][2], Y[2][2];
-    if (m.tension) {
-      Eig2 eg = eig2(s.G);
-      tension(eg, Gp);
-      tension_deriv(eg, S1, Y);
-    } else {
+    if constexpr (WANG) {
+      // anisotropic stretch (exact membrane block, measure stiffnesses c_k constant on
+      // their segments): with C : X = sum_k c_k (N_k : X) N_k,
+      //   K mu at vertex i = A (dF_mu Sg + F (C : S3)) w_i,
+      //   grad_x (mu^T K v) at vertex i = A (F (C : S1) + dF_mu (C : S2) + dF_v (C : S3)) w_i,
+      // and for the table entry (k, j): d Sg / dS[k][j] = sgn(s_k) part_j(|s_k|) N_k,
+      // d c_k / dS[k][j] = [j is s_k's segment].
+      const int inst = m.tri_inst[t];
+      double N[4][3], Sg[2][2], sk[4], c[4];
+      load_measures(m, t, N);
+      wang_stretch(N, a.mat + m.matn * inst, s.G, Sg, sk, c);
+      double CS1[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, CS2[2][2] = {{0.0, 0.0}, {0.0, 0.0}},
+             CS3[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+      double n1[4], n2[4], n3[4];
 #pragma unroll
-      for (int p = 0; p < 2; ++p)
+      for (int k = 0; k < 4; ++k) {
+        n1[k] = ncon(N[k], S1);
+        n2[k] = ncon(N[k], S2);
+        n3[k] = ncon(N[k], S3);
+        const double m1 = c[k] * n1[k], m2 = c[k] * n2[k], m3 = c[k] * n3[k];
+        const double Nm[2][2] = {{N[k][0], N[k][1]}, {N[k][1], N[k][2]}};
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          Gp[p][q] = s.G[p][q];
-          Y[p][q] = S1[p][q];
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            CS1[p][q] += m1 * Nm[p][q];
+            CS2[p][q] += m2 * Nm[p][q];
+            CS3[p][q] += m3 * Nm[p][q];
+          }
+      }
+      const double A = s.area;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double qe = 0.0, qt = 0.0;
+#pragma unroll
+          for (int c2 = 0; c2 < 2; ++c2) {
+            const double e2 = dFm[r][0] * Sg[0][c2] + dFm[r][1] * Sg[1][c2] +
+                              s.F[r][0] * CS3[0][c2] + s.F[r][1] * CS3[1][c2];
+            const double t2 = s.F[r][0] * CS1[0][c2] + s.F[r][1] * CS1[1][c2] +
+                              dFm[r][0] * CS2[0][c2] + dFm[r][1] * CS2[1][c2] +
+                              dFv[r][0] * CS3[0][c2] + dFv[r][1] * CS3[1][c2];
+            qe += e2 * s.w[i][c2];
+            qt += t2 * s.w[i][c2];
+          }
+          el.tri_ag[(i * 3 + r) * nt + t] = -h * A * qe - h2 * A * qt;
+          el.tri_ak[(i * 3 + r) * nt + t] = A * qe;
         }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double tk = fabs(sk[k]), sg = sk[k] < 0.0 ? -1.0 : 1.0;
+        const int sj = seg_of<6, true>(tk);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          const double dp = sg * seg_part<6, true>(j, tk);
+          el.acc_ws[(6 * k + j) * nt + t] +=
+              -h * A * dp * n3[k] - h2 * A * (dp * n1[k] + (j == sj ? n3[k] * n2[k] : 0.0));
+        }
+      }
+    } else {
+      // stress term of K_sys and its derivative along S1
+      double Gp[2][2], Y[2][2];
+      if (m.tension) {
+        Eig2 eg = eig2(s.G);
+        tension(eg, Gp);
+        tension_deriv(eg, S1, Y);
+      } else {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            Gp[p][q] = s.G[p][q];
+            Y[p][q] = S1[p][q];
+          }
+      }
+      // 3x2 matrices, all without the area * k_s factor
+      double Qe[3][2], Qs[3][2], Qt[3][2], Pf[3][2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          double fs3 = s.F[r][0] * S3[0][c] + s.F[r][1] * S3[1][c];
+          Qe[r][c] = dFm[r][0] * s.G[0][c] + dFm[r][1] * s.G[1][c] + fs3;
+          Qs[r][c] = dFm[r][0] * Gp[0][c] + dFm[r][1] * Gp[1][c] + fs3;
+          Qt[r][c] = s.F[r][0] * Y[0][c] + s.F[r][1] * Y[1][c] + dFm[r][0] * S2[0][c] +
+                     dFm[r][1] * S2[1][c] + dFv[r][0] * S3[0][c] + dFv[r][1] * S3[1][c];
+          Pf[r][c] = s.F[r][0] * s.G[0][c] + s.F[r][1] * s.G[1][c];
+        }
+      const double A = s.area, ak = s.area * ks;
+      double part = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          double qe = Qe[r][0] * s.w[i][0] + Qe[r][1] * s.w[i][1];
+          double qs = Qs[r][0] * s.w[i][0] + Qs[r][1] * s.w[i][1];
+          double qt = Qt[r][0] * s.w[i][0] + Qt[r][1] * s.w[i][1];
+          double pf = Pf[r][0] * s.w[i][0] + Pf[r][1] * s.w[i][1];
+          el.tri_ag[(i * 3 + r) * nt + t] = -h * ak * qe - h2 * ak * qt;
+          el.tri_ak[(i * 3 + r) * nt + t] = ak * qs;
+          // unit-stiffness force -A pf, unit-stiffness K_sys mu = A qs (symmetric: v.K mu)
+          part += mu[i][r] * (-h * A * pf) - h2 * vv[i][r] * (A * qs);
+        }
+      el.acc_ks[t] += part;
     }
-    // 3x2 matrices, all without the area * k_s factor
-    double Qe[3][2], Qs[3][2], Qt[3][2], Pf[3][2];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        double fs3 = s.F[r][0] * S3[0][c] + s.F[r][1] * S3[1][c];
-        Qe[r][c] = dFm[r][0] * s.G[0][c] + dFm[r][1] * s.G[1][c] + fs3;
-        Qs[r][c] = dFm[r][0] * Gp[0][c] + dFm[r][1] * Gp[1][c] + fs3;
-        Qt[r][c] = s.F[r][0] * Y[0][c] + s.F[r][1] * Y[1][c] + dFm[r][0] * S2[0][c] +
-                   dFm[r][1] * S2[1][c] + dFv[r][0] * S3[0][c] + dFv[r][1] * S3[1][c];
-        Pf[r][c] = s.F[r][0] * s.G[0][c] + s.F[r][1] * s.G[1][c];
-      }
-    const double A = s.area, ak = s.area * ks;
-    double part = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        double qe = Qe[r][0] * s.w[i][0] + Qe[r][1] * s.w[i][1];
-        double qs = Qs[r][0] * s.w[i][0] + Qs[r][1] * s.w[i][1];
-        double qt = Qt[r][0] * s.w[i][0] + Qt[r][1] * s.w[i][1];
-        double pf = Pf[r][0] * s.w[i][0] + Pf[r][1] * s.w[i][1];
-        el.tri_ag[(i * 3 + r) * nt + t] = -h * ak * qe - h2 * ak * qt;
-        el.tri_ak[(i * 3 + r) * nt + t] = ak * qs;
-        // unit-stiffness force -A pf, unit-stiffness K_sys mu = A qs (symmetric: v.K mu)
-        part += mu[i][r] * (-h * A * pf) - h2 * vv[i][r] * (A * qs);
-      }
-    el.acc_ks[t] += part;
     if (a.wind) {
       // The wind's share of the step: h f_w in b and h D in A, so the adjoint takes the
       // gradient of Phi = h (mu . f_w - mu^T D dv) over the triangle's positions,
@@ -2569,8 +2772,9 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
     const double th = hinge_theta(X);
     hinge_grad<double>(X, g);
     const double ce = m.hin_ce[e];
-    const double wgt = 2.0 * a.mat[3 * m.hin_inst[e] + 1] * ce;
     const double dth = th - m.hin_rest[e];
+    double sc, wgt;   // dE/dtheta, d^2E/dtheta^2
+    hinge_response<WANG>(m, a.mat, e, dth, sc, wgt);
     double gm = 0.0, gv = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -2579,8 +2783,9 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
         gm += g[i][c] * mu[i][c];
         gv += g[i][c] * vv[i][c];
       }
-    // y = (h dth + h^2 gv) mu + h^2 gm v; Hess(theta) y by one dual pass of grad(theta)
-    const double cm = h * dth + h2 * gv, cv = h2 * gm;
+    // y = (h sc + h^2 wgt gv) mu + h^2 wgt gm v; Hess(theta) y by one dual pass of
+    // grad(theta)
+    const double cm = h * sc + h2 * wgt * gv, cv = h2 * wgt * gm;
     dual Xd[4][3], gd[4][3];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -2591,10 +2796,26 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        el.hin_ag[(i * 3 + c) * nh + e] = -wgt * (h * gm * g[i][c] + gd[i][c].d);
+        el.hin_ag[(i * 3 + c) * nh + e] = -(wgt * h * gm * g[i][c] + gd[i][c].d);
         el.hin_ak[(i * 3 + c) * nh + e] = wgt * gm * g[i][c];
       }
-    el.acc_kb[e] += -2.0 * ce * gm * (h * dth + h2 * gv);
+    if constexpr (!WANG) {
+      el.acc_kb[e] += -2.0 * ce * gm * (h * dth + h2 * gv);
+    } else {
+      // table entry (a, j): d sc = 2 c_e d_a sgn part_j(|dth|), d wgt = 2 c_e d_a [j is the
+      // segment]
+      const double t = fabs(dth), sg = dth < 0.0 ? -1.0 : 1.0;
+      const int sj = seg_of<5, false>(t);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double db = 2.0 * ce * m.hin_dw[b * nh + e];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const double dsc = db * sg * seg_part<5, false>(j, t), dw = j == sj ? db : 0.0;
+          el.acc_wb[(5 * b + j) * nh + e] += -h * gm * dsc - h2 * gm * gv * dw;
+        }
+      }
+    }
   }
 }
 
@@ -2670,30 +2891,54 @@ __global__ void __launch_bounds__(256) k_material_sum(Mesh m, Elem el, double* _
   const int toff = m.inst_toff[inst], nt = m.inst_nt[inst];
   const int hoff = m.inst_hoff[inst], nh = m.inst_nh[inst];
   const int voff = m.inst_voff[inst], nv = m.inst_nv[inst];
-  for (int k = threadIdx.x; k < nt; k += blockDim.x) t0 += el.acc_ks[toff + k];
-  for (int k = threadIdx.x; k < nh; k += blockDim.x) t1 += el.acc_kb[hoff + k];
-  for (int k = threadIdx.x; k < nv; k += blockDim.x) t2 += el.acc_d[voff + k];
-  t0 = wave_sum(t0);
-  t1 = wave_sum(t1);
-  t2 = wave_sum(t2);
-  if (lane == 0) {
-    s_part[0][wave] = t0;
-    s_part[1][wave] = t1;
-    s_part[2][wave] = t2;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (m.wang) {
+    // 24 stretch and 15 bend table entries, then the density: one fixed-order sum each
     const int nwaves = (blockDim.x + 63) >> 6;
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-    for (int q = 0; q < nwaves; ++q) {
-      r0 += s_part[0][q];
-      r1 += s_part[1][q];
-      r2 += s_part[2][q];
+    for (int q = 0; q < kWangParams; ++q) {
+      double v = 0.0;
+      if (q < kWangStretch)
+        for (int k = threadIdx.x; k < nt; k += blockDim.x) v += el.acc_ws[(size_t)q * m.nt + toff + k];
+      else if (q < kWangStretch + kWangBend)
+        for (int k = threadIdx.x; k < nh; k += blockDim.x)
+          v += el.acc_wb[(size_t)(q - kWangStretch) * m.nh + hoff + k];
+      else
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) v += el.acc_d[voff + k];
+      v = wave_sum(v);
+      __syncthreads();   // the previous entry's partials have been read
+      if (lane == 0) s_part[0][wave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0 && out) {
+        double r = 0.0;
+        for (int w = 0; w < nwaves; ++w) r += s_part[0][w];
+        out[kWangParams * inst + q] = r;
+      }
     }
-    if (out) {
-      out[3 * inst + 0] = r0;
-      out[3 * inst + 1] = r1;
-      out[3 * inst + 2] = r2;
+  } else {
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) t0 += el.acc_ks[toff + k];
+    for (int k = threadIdx.x; k < nh; k += blockDim.x) t1 += el.acc_kb[hoff + k];
+    for (int k = threadIdx.x; k < nv; k += blockDim.x) t2 += el.acc_d[voff + k];
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    t2 = wave_sum(t2);
+    if (lane == 0) {
+      s_part[0][wave] = t0;
+      s_part[1][wave] = t1;
+      s_part[2][wave] = t2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nwaves = (blockDim.x + 63) >> 6;
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+      for (int q = 0; q < nwaves; ++q) {
+        r0 += s_part[0][q];
+        r1 += s_part[1][q];
+        r2 += s_part[2][q];
+      }
+      if (out) {
+        out[3 * inst + 0] = r0;
+        out[3 * inst + 1] = r1;
+        out[3 * inst + 2] = r2;
+      }
     }
   }
   if (!out_wind) return;   // uniform
@@ -2779,8 +3024,12 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
                      const double* mat, const double* wind, double rho, int* status,
                      hipStream_t st) {
   long n = (long)m.nt + m.nh;
-  hipLaunchKernelGGL(k_elements, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, v, mat,
-                     wind, rho, status);
+  if (m.wang)
+    hipLaunchKernelGGL(k_elements<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, v,
+                       mat, wind, rho, status);
+  else
+    hipLaunchKernelGGL(k_elements<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, x, v,
+                       mat, wind, rho, status);
 }
 
 template <typename T, typename TM>
@@ -2946,7 +3195,11 @@ void launch_adj_pre(const Mesh& m, const T* dl, double h, double* gx, const doub
 template <typename T>
 void launch_adj_elements(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st) {
   long n = (long)m.nt + m.nh;
-  hipLaunchKernelGGL(k_adj_elements<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, a);
+  if (m.wang)
+    hipLaunchKernelGGL((k_adj_elements<T, true>), dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el, a);
+  else
+    hipLaunchKernelGGL((k_adj_elements<T, false>), dim3(blocks_for(n, 256)), dim3(256), 0, st, m, el,
+                       a);
 }
 
 template <typename T>

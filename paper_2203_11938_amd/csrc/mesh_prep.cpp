@@ -73,6 +73,23 @@ void rcb(const std::vector<double>& rest, std::vector<int>& ids, int lo, int hi,
   rcb(rest, ids, mid, hi, leaf, inner);
 }
 
+// Warp axis of a rest plane with unit normal n: the x axis projected into the plane
+// (the y axis where x is within about 0.06 degrees of the normal), unit length.
+void warp_axis(const double n[3], double u[3]) {
+  const double ax[3] = {1.0, 0.0, 0.0}, ay[3] = {0.0, 1.0, 0.0};
+  const double* a = ax;
+  double d = vdot(a, n);
+  for (int k = 0; k < 3; ++k) u[k] = a[k] - d * n[k];
+  double l = std::sqrt(vdot(u, u));
+  if (!(l > 1e-3)) {
+    a = ay;
+    d = vdot(a, n);
+    for (int k = 0; k < 3; ++k) u[k] = a[k] - d * n[k];
+    l = std::sqrt(vdot(u, u));
+  }
+  for (int k = 0; k < 3; ++k) u[k] /= l;
+}
+
 // Coarse modes an aggregate supports: rigid motions (6) when its free vertices are
 // at least three and not collinear, translations (3) with one or two free vertices
 // (or collinear ones), none when every vertex is pinned.
@@ -181,10 +198,11 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
   L.vert_inst.assign(L.nv, 0);
   L.tri_v.assign(3 * (size_t)L.nt, 0);
   L.tri_B.assign(4 * (size_t)L.nt, 0.0);
+  L.tri_N.assign(12 * (size_t)L.nt, 0.0);
   L.tri_area.assign(L.nt, 0.0);
   L.tri_inst.assign(L.nt, 0);
   std::vector<int> hv;   // [nh][4] global
-  std::vector<double> hce, hrest;
+  std::vector<double> hce, hrest, hdw;
   std::vector<int> hinst;
 
   for (int b = 0; b < L.ninst; ++b) {
@@ -258,6 +276,19 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
       L.tri_B[3 * (size_t)L.nt + gt] = m00 / det;
       L.tri_area[gt] = 0.5 * det;
       L.tri_inst[gt] = b;
+      {
+        // strain measures of the anisotropic model in the local frame (e1, e2): warp
+        // u u^T, weft v v^T, shear (u v^T + v u^T) / sqrt 2, area I, with u the warp axis
+        // and v = n x u
+        double u3[3];
+        warp_axis(n, u3);
+        const double a0 = vdot(u3, e1), a1 = vdot(u3, e2), b0 = -a1, b1 = a0;
+        const double r2 = std::sqrt(2.0);
+        const double Nq[12] = {a0 * a0, a0 * a1, a1 * a1, b0 * b0, b0 * b1, b1 * b1,
+                               r2 * a0 * b0, (a0 * b1 + a1 * b0) / r2, r2 * a1 * b1,
+                               1.0, 0.0, 1.0};
+        for (int q = 0; q < 12; ++q) L.tri_N[q * (size_t)L.nt + gt] = Nq[q];
+      }
       for (int a = 0; a < 3; ++a) {
         L.tri_v[a * (size_t)L.nt + gt] = voff + v[a];
         L.varea[voff + v[a]] += L.tri_area[gt] / 3.0;
@@ -290,6 +321,25 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
         hce.push_back(3.0 * vdot(e, e) / (A1 + A2));
         hrest.push_back(rest_angle(&s.rest[3 * i], &s.rest[3 * j], &s.rest[3 * o], &s.rest[3 * o2]));
         hinst.push_back(b);
+        {
+          // bending direction: in the plane of the triangle (i, j, o), normal to the
+          // edge; its angle to that plane's warp axis, folded into [0, 90] degrees,
+          // weights the 0, 45 and 90 degree tables linearly
+          double d2[3], n1[3], ue[3], bd[3], u3[3];
+          vsub(&s.rest[3 * o], &s.rest[3 * i], d2);
+          vcross(e, d2, n1);
+          const double ln1 = std::sqrt(vdot(n1, n1)), le = std::sqrt(vdot(e, e));
+          for (int k = 0; k < 3; ++k) {
+            n1[k] /= ln1;
+            ue[k] = e[k] / le;
+          }
+          vcross(n1, ue, bd);
+          warp_axis(n1, u3);
+          const double q = std::acos(std::min(1.0, std::fabs(vdot(bd, u3)))) / std::atan(1.0);
+          hdw.push_back(q <= 1.0 ? 1.0 - q : 0.0);
+          hdw.push_back(q <= 1.0 ? q : 2.0 - q);
+          hdw.push_back(q <= 1.0 ? 0.0 : q - 1.0);
+        }
       }
     }
     L.inst_nh.push_back((int)hce.size() - L.inst_hoff.back());
@@ -305,6 +355,9 @@ int build_layout(const std::vector<HostSheet>& sheets_in, int agg_size, int max_
   L.hin_ce = hce;
   L.hin_rest = hrest;
   L.hin_inst = hinst;
+  L.hin_dw.assign(3 * (size_t)L.nh, 0.0);
+  for (int e = 0; e < L.nh; ++e)
+    for (int a = 0; a < 3; ++a) L.hin_dw[a * (size_t)L.nh + e] = hdw[3 * (size_t)e + a];
 
   // ---- block rows: neighbours through a triangle or a hinge, sorted, with self
   std::vector<std::vector<int>> nb(L.nv);

@@ -30,6 +30,10 @@ struct HostLayout {
   std::vector<int> hin_inst;
   std::vector<int> inst_voff, inst_nv, inst_toff, inst_nt, inst_hoff, inst_nh;
   std::vector<double> mat;    // [ninst][3] create-time materials
+  // anisotropic material frames: per triangle the strain measure tensors N_1..N_4 in its
+  // local frame [12][nt] (N_00, N_01, N_11 each), per hinge the bending direction
+  // weights of the 0, 45 and 90 degree tables [3][nh]
+  std::vector<double> tri_N, hin_dw;
   // vertex order: internal index -> caller's (global) index
   std::vector<int> vold;
   // coarse space: aggregates are runs of consecutive internal vertices of one sheet

@@ -338,7 +338,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       (o.autotune != 0 && o.autotune != 1) || (o.graph != 0 && o.graph != 1) ||
       o.matrix_home < SIM_MATRIX_AUTO || o.matrix_home > SIM_MATRIX_REGISTERS ||
       !(o.air_density >= 0.0) || !std::isfinite(o.air_density) ||
-      (o.coarse_keep_all != 0 && o.coarse_keep_all != 1)) {
+      (o.coarse_keep_all != 0 && o.coarse_keep_all != 1) ||
+      (o.material_model != SIM_MATERIAL_ISOTROPIC && o.material_model != SIM_MATERIAL_WANG) ||
+      (o.material_model == SIM_MATERIAL_WANG && o.membrane_system == SIM_MEMBRANE_TENSION)) {
     s->err = "invalid options";
     return SIM_E_INVALID;
   }
@@ -446,6 +448,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   m.ninst = L.ninst;
   m.maxnz = L.maxnz;
   m.tension = o.membrane_system == SIM_MEMBRANE_TENSION ? 1 : 0;
+  m.wang = o.material_model == SIM_MATERIAL_WANG ? 1 : 0;
+  m.matn = m.wang ? kWangParams : 3;
+  s->stats.material_params = m.matn;
   TRY(upload(s, L.varea, &m.varea));
   TRY(upload(s, L.pinned, &m.pinned));
   TRY(upload(s, L.vert_inst, &m.vert_inst));
@@ -471,7 +476,23 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(upload(s, L.inst_nh, &m.inst_nh));
   TRY(upload(s, L.vold, &m.vold));
   const double* md = nullptr;
-  TRY(upload(s, L.mat, &md));
+  if (m.wang) {
+    // the create-time (k_s, k_b, d) as anisotropic tables that reproduce the isotropic
+    // model: warp, weft and shear at k_s, no area term, every bend entry k_b
+    std::vector<double> wm;
+    for (int b = 0; b < L.ninst; ++b) {
+      for (int k = 0; k < 4; ++k)
+        for (int j = 0; j < 6; ++j) wm.push_back(k < 3 ? L.mat[3 * b] : 0.0);
+      for (int j = 0; j < kWangBend; ++j) wm.push_back(L.mat[3 * b + 1]);
+      wm.push_back(L.mat[3 * b + 2]);
+    }
+    TRY(upload(s, wm, &md));
+    TRY(upload(s, L.tri_N, &m.tri_N));
+    TRY(upload(s, L.hin_dw, &m.hin_dw));
+  } else {
+    TRY(upload(s, L.mat, &md));
+    m.tri_N = m.hin_dw = nullptr;
+  }
   s->mat_default = const_cast<double*>(md);
 
   // ---- coarse space
@@ -564,6 +585,11 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, nt * 8, &q)); el.acc_ks = (double*)q;
   TRY(alloc(s, nh * 8, &q)); el.acc_kb = (double*)q;
   TRY(alloc(s, nv * 8, &q)); el.acc_d = (double*)q;
+  el.acc_ws = el.acc_wb = nullptr;
+  if (s->mesh.wang) {
+    TRY(alloc(s, (size_t)kWangStretch * nt * 8, &q)); el.acc_ws = (double*)q;
+    TRY(alloc(s, (size_t)kWangBend * std::max<size_t>(nh, 1) * 8, &q)); el.acc_wb = (double*)q;
+  }
   TRY(alloc(s, 3 * nt * 8, &q)); el.tri_fw = (double*)q;
   TRY(alloc(s, 4 * nt * 8, &q)); el.tri_wn = (double*)q;
   TRY(alloc(s, 3 * nt * 8, &q)); el.tri_wv = (double*)q;
@@ -843,6 +869,10 @@ sim_status adjoint_impl(sim_t* s, const void* dl_dx, void* dl_dmat, void* dl_dwi
   if (s->wind) launch_fill_double(s->el.acc_w, 3L * s->L.nt, 0.0, st);
   launch_fill_double(s->el.acc_ks, s->L.nt, 0.0, st);
   launch_fill_double(s->el.acc_kb, s->L.nh, 0.0, st);
+  if (s->mesh.wang) {
+    launch_fill_double(s->el.acc_ws, (long)kWangStretch * s->L.nt, 0.0, st);
+    launch_fill_double(s->el.acc_wb, (long)kWangBend * s->L.nh, 0.0, st);
+  }
   launch_fill_double(s->el.acc_d, nv, 0.0, st);
   const T* dl = static_cast<const T*>(dl_dx);
   int f = (int)s->frames.size() - 1;
@@ -1009,6 +1039,7 @@ void sim_default_options(sim_options* o) {
   o->matrix_home = SIM_MATRIX_AUTO;
   o->air_density = 1.0;
   o->coarse_keep_all = 0;
+  o->material_model = SIM_MATERIAL_ISOTROPIC;
 }
 
 sim_status sim_create_batch(int32_t n, const sim_mesh* meshes, const double* const* rest_pos,

@@ -26,9 +26,18 @@ enum : int {
 //   triangle vertex (t, a):   t * 3 + a                   (>= 0)
 //   hinge vertex    (e, a):   -(e * 4 + a) - 1            (< 0)
 
+// Anisotropic material (the Wang-style tables): four strain measures x six strain
+// segments, three bending directions x five angle segments, then the density.
+constexpr int kWangStretch = 24, kWangBend = 15, kWangParams = 40;
+
 struct Mesh {
   int nv, nt, nh, ninst, maxnz;
   int tension;                  // 1: tension-clamped membrane block in K_sys, 0: exact Hessian
+  int wang;                     // 1: anisotropic strain-dependent material
+  int matn;                     // doubles per instance in the material arrays (3 or 40);
+                                // the density is the last
+  const double* tri_N;          // [12][nt] strain measure tensors (anisotropic material)
+  const double* hin_dw;         // [3][nh]  bending direction weights (anisotropic)
   // vertices
   const double* varea;          // [nv] lumped area (a third of incident triangle areas)
   const int* pinned;            // [nv] 1 = Dirichlet vertex
@@ -74,6 +83,8 @@ struct Elem {
   double* acc_ks;   // [nt] dL/dk_s partial sums over steps
   double* acc_kb;   // [nh]
   double* acc_d;    // [nv]
+  double* acc_ws;   // [24][nt] anisotropic material: dL/dS partial sums
+  double* acc_wb;   // [15][nh] dL/dB partial sums
   // wind (aerodynamic force of each triangle, used when the rollout has a wind)
   double* tri_fw;   // [3][nt]  a vertex's share (a third) of the triangle's wind force
   double* tri_wn;   // [4][nt]  unit normal n and c = 2 rho area |s| / 9: every 3x3 block

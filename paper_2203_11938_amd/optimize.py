@@ -16,11 +16,12 @@ known while only the first frames are active). The decision for the next iterati
 uses the energies of the current iteration's rollout, taken before its Adam step;
 for a batch handle the sheets' energies of a frame are added up.
 
-Parameters (the paper's phi without the unused ones): the material (k_s, k_b, d) of
-each sheet in log space, the wind velocity w, and the per-step forces F_t read as
-loads on each vertex's area share (the optimised variable is F / vertex area). Adam
-uses one step counter for all groups (the iteration number); forces of frames that
-were never active keep zero moments and do not move.
+Parameters (the paper's phi without the unused ones): the material of each sheet
+((k_s, k_b, d), or the anisotropic tables and d) in log space, the wind velocity w,
+and the per-step forces F_t read as loads on each vertex's area share (the optimised
+variable is F / vertex area). Adam uses one step counter for all groups (the
+iteration number); forces of frames that were never active keep zero moments and do
+not move.
 """
 
 from __future__ import annotations
@@ -70,7 +71,8 @@ class AdaptiveWindowAdam:
     """Optimises material, wind and forces of `sim`'s sheets against target positions.
 
     targets [n_frames, 3, V] and x0 [3, V] (v0 optional) in the handle's precision;
-    material [n_instances, 3] and wind [n_instances, 3] float64 initial guesses
+    material [n_instances, n_material] (positive entries: it is optimised through its
+    logarithm) and wind [n_instances, 3] float64 initial guesses
     (wind None: no aerodynamic force, not optimised); forces [n_frames, 3, V] initial
     guess (None: zero). Learning rates per group (the paper uses 1e-3 for all)."""
     sim: S.Simulator
@@ -98,6 +100,9 @@ class AdaptiveWindowAdam:
             raise ValueError("the handle's max_steps is shorter than the sequence")
         dev, dt, V, nb = self.x0.device, sim.dtype, sim.n_verts, sim.n_instances
         self.material = self.material.clone().contiguous()
+        if "material" in self.optimise and not bool((self.material > 0).all()):
+            raise ValueError("the material is optimised in log space: every entry must be "
+                             "positive (an anisotropic table without an area term has zeros)")
         if self.wind is not None:
             self.wind = self.wind.clone().contiguous()
         self.forces = (torch.zeros((self.n_frames, 3, V), dtype=dt, device=dev)
@@ -111,7 +116,8 @@ class AdaptiveWindowAdam:
         self._xo = torch.empty((self.n_frames, 3, V), dtype=dt, device=dev)
         self._dl = torch.empty_like(self._xo)
         self._energy = torch.empty((self.n_frames, nb), dtype=torch.float64, device=dev)
-        self._g = dict(material=torch.empty((nb, 3), dtype=torch.float64, device=dev),
+        self._g = dict(material=torch.empty((nb, sim.n_material), dtype=torch.float64,
+                                            device=dev),
                        forces=torch.empty((self.n_frames, 3, V), dtype=dt, device=dev),
                        x0=torch.empty((3, V), dtype=dt, device=dev),
                        v0=torch.empty((3, V), dtype=dt, device=dev))

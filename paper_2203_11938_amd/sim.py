@@ -6,7 +6,9 @@ If the library is missing this module raises -- there is no CPU fallback.
 
 Device tensors at the boundary are structure-of-arrays ``[..., 3, V]`` in the
 handle's precision (float32 for FP32, float64 for FP64); material arrays are
-float64 ``[n_instances, 3]`` = (k_s, k_b, d).
+float64 ``[n_instances, n_material]``: (k_s, k_b, d) for the isotropic model, or the
+anisotropic stretch table S [4, 6], bend table B [3, 5] and d (40 entries, see
+``wang_material``).
 """
 
 from __future__ import annotations
@@ -37,6 +39,18 @@ SIM_FP32 = 0
 SIM_FP64 = 1
 SIM_MEMBRANE_EXACT = 0
 SIM_MEMBRANE_TENSION = 1
+SIM_MATERIAL_ISOTROPIC = 0
+SIM_MATERIAL_WANG = 1
+SIM_WANG_PARAMS = 40
+
+
+def wang_material(stretch, bend, density) -> np.ndarray:
+    """The 40 material entries of one sheet for the anisotropic model: stretch table
+    [4, 6] (warp, weft, shear, area measures x strain segments) in N/m, bend table
+    [3, 5] (0, 45, 90 degree directions x angle segments) in N m, density in kg/m^2."""
+    S = np.asarray(stretch, dtype=np.float64).reshape(4, 6)
+    B = np.asarray(bend, dtype=np.float64).reshape(3, 5)
+    return np.concatenate([S.ravel(), B.ravel(), [float(density)]])
 
 
 class SimError(RuntimeError):
@@ -67,7 +81,7 @@ class _Options(ctypes.Structure):
                 ("matrix_precision", ctypes.c_int32), ("coarse_size", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("matrix_home", ctypes.c_int32), ("air_density", ctypes.c_double),
-                ("coarse_keep_all", ctypes.c_int32)]
+                ("coarse_keep_all", ctypes.c_int32), ("material_model", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -83,7 +97,8 @@ class _Stats(ctypes.Structure):
                 ("autotune_candidates", ctypes.c_int32), ("autotune_ms_per_iter", ctypes.c_double),
                 ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32),
                 ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("coarse_store_slots", ctypes.c_int32)]
+                ("device_bytes", ctypes.c_int64), ("coarse_store_slots", ctypes.c_int32),
+                ("material_params", ctypes.c_int32)]
 
 
 _lib = None
@@ -242,7 +257,8 @@ class Simulator:
     library's choice); ``air_density`` is the aerodynamic force's rho_air [kg/m^3]
     (acting in rollouts given a wind velocity); ``coarse_keep_all`` keeps every
     step's coarse operators under checkpointing (faster, memory not bounded by the
-    checkpoint interval).
+    checkpoint interval); ``material_model`` "wang" selects the anisotropic
+    strain-dependent material (material arrays of 40 entries per sheet).
     """
 
     def __init__(self, sheets: Sequence[Sheet], dt: float, precision: str = "fp32",
@@ -251,7 +267,8 @@ class Simulator:
                  membrane: str = "exact", matrix_precision: str = "fp64",
                  coarse_size: Optional[int] = None, autotune: bool = False,
                  graph: bool = False, matrix_home: Optional[str] = None,
-                 air_density: float = 1.0, coarse_keep_all: bool = False):
+                 air_density: float = 1.0, coarse_keep_all: bool = False,
+                 material_model: str = "isotropic"):
         lib = load_library()
         self._lib = lib
         self._h = None
@@ -274,6 +291,11 @@ class Simulator:
         opt.graph = 1 if graph else 0
         opt.air_density = air_density
         opt.coarse_keep_all = 1 if coarse_keep_all else 0
+        if material_model not in ("isotropic", "wang"):
+            raise ValueError("material_model must be 'isotropic' or 'wang'")
+        opt.material_model = SIM_MATERIAL_WANG if material_model == "wang" else SIM_MATERIAL_ISOTROPIC
+        self.material_model = material_model
+        self.n_material = SIM_WANG_PARAMS if material_model == "wang" else 3
         if matrix_home is not None:
             if matrix_home not in MATRIX_HOMES[1:]:
                 raise ValueError(f"matrix_home must be one of {MATRIX_HOMES[1:]}")
@@ -361,7 +383,7 @@ class Simulator:
         self._need(x0, (3, V), "x0")
         self._need(v0, (3, V), "v0")
         self._need(forces, (n_steps, 3, V), "forces")
-        self._need(material, (self.n_instances, 3), "material", torch.float64)
+        self._need(material, (self.n_instances, self.n_material), "material", torch.float64)
         self._need(wind, (self.n_instances, 3), "wind", torch.float64)
         if x_out is None:
             x_out = torch.empty((frames.size, 3, V), dtype=self.dtype, device=x0.device)
@@ -400,7 +422,7 @@ class Simulator:
                 return torch.empty(shape, dtype=dtype, device=dev)
             self._need(t, shape, key, dtype)
             return t
-        g_mat = buf("material", want_material, (self.n_instances, 3), torch.float64)
+        g_mat = buf("material", want_material, (self.n_instances, self.n_material), torch.float64)
         if want_wind is None:
             want_wind = getattr(self, "has_wind", False)
         g_w = buf("wind", want_wind, (self.n_instances, 3), torch.float64)
@@ -479,7 +501,8 @@ class ClothRollout(torch.autograd.Function):
     frames.
 
     User-facing layout is vertex-major: forces [n_steps, V, 3], x0/v0 [V, 3],
-    output [n_loss, V, 3]; material and wind [n_instances, 3] float64 (wind None:
+    output [n_loss, V, 3]; material [n_instances, n_material] and wind [n_instances, 3]
+    float64 (wind None:
     no aerodynamic force). The backward pass is the library's adjoint of the
     handle's most recent rollout, so it raises if another rollout ran on the same
     handle in between; a solve that did not converge raises too unless

@@ -139,3 +139,26 @@ def test_create_time_failures_without_gpu():
     assert st == sim.SIM_E_INVALID and not h.value
     st, h = _create(lib, sim, np.array([[0, 1, 1]]), rest)
     assert st == sim.SIM_E_MESH and not h.value
+    # an unknown material model, and the anisotropic model with the tension membrane
+    st, h = _create(lib, sim, tris, rest, material_model=2)
+    assert st == sim.SIM_E_INVALID and not h.value
+    st, h = _create(lib, sim, tris, rest, material_model=sim.SIM_MATERIAL_WANG,
+                    membrane_system=sim.SIM_MEMBRANE_TENSION)
+    assert st == sim.SIM_E_INVALID and not h.value
+
+
+def test_material_model_defaults_and_layout():
+    """The default model is the isotropic one; the anisotropic material vector is the
+    stretch table, the bend table and the density, in that order."""
+    import numpy as np
+    from paper_2203_11938_amd import sim
+    lib = sim.load_library()
+    opt = sim._Options()
+    lib.sim_default_options(ctypes.byref(opt))
+    assert opt.material_model == sim.SIM_MATERIAL_ISOTROPIC
+    St = np.arange(24.0).reshape(4, 6)
+    Bt = 100.0 + np.arange(15.0).reshape(3, 5)
+    v = sim.wang_material(St, Bt, 0.2)
+    assert v.shape == (sim.SIM_WANG_PARAMS,)
+    assert np.array_equal(v[:24], St.ravel()) and np.array_equal(v[24:39], Bt.ravel())
+    assert v[39] == 0.2

@@ -1363,7 +1363,8 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
 constexpr int kTagWgMax = 64;
 
 // Tagged publication of a vertex's three doubles of a row vector as four 64-bit words
-// (vertex-major, [nv][4]), each holding a 16-bit tag (from the publication's number,
+// (word-major, [4][nv]: each store instruction of a wavefront fills whole cache lines),
+// each holding a 16-bit tag (from the publication's number,
 // the same in every workgroup of a sheet, never 0) above 48 of the 192 value bits. A
 // 64-bit store is single-copy atomic, so a reader that sees the expected tag in all
 // four words has the values published with it: no flag, no fence, no separate round
@@ -1380,19 +1381,20 @@ __device__ __forceinline__ unsigned long long vtag(unsigned pub) {
 
 constexpr unsigned long long kLow48 = (1ull << 48) - 1;
 
-__device__ __forceinline__ void publish_tagged(unsigned long long* tb, int i, const double v[3],
-                                               unsigned pub) {
+__device__ __forceinline__ void publish_tagged(unsigned long long* tb, int i, int nv,
+                                               const double v[3], unsigned pub) {
   const unsigned long long t = vtag(pub);
   const unsigned long long a = (unsigned long long)__double_as_longlong(v[0]);
   const unsigned long long b = (unsigned long long)__double_as_longlong(v[1]);
   const unsigned long long c = (unsigned long long)__double_as_longlong(v[2]);
-  unsigned long long* p = tb + (size_t)i * 4;
+  unsigned long long* p = tb + i;
+  const size_t s = (size_t)nv;
   __hip_atomic_store(p, t | (a & kLow48), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 1, t | (a >> 48) | ((b & 0xffffffffull) << 16), __ATOMIC_RELAXED,
+  __hip_atomic_store(p + s, t | (a >> 48) | ((b & 0xffffffffull) << 16), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 2, t | (b >> 32) | ((c & 0xffffull) << 32), __ATOMIC_RELAXED,
+  __hip_atomic_store(p + 2 * s, t | (b >> 32) | ((c & 0xffffull) << 32), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(p + 3, t | (c >> 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 3 * s, t | (c >> 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The three doubles of four words published together (tags already checked).
@@ -1448,7 +1450,7 @@ __device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigne
 // round trip per batch, not per vertex). False (every thread) on a time-out or an
 // abort; the caller then stops.
 constexpr int kHaloBatch = 4;
-__device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb,
+__device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
                                                  const int* __restrict__ hidx, int nh,
                                                  double* __restrict__ vl, int R, int RH,
                                                  unsigned pub, int* abort_flag) {
@@ -1463,16 +1465,16 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb,
 #pragma unroll
     for (int u = 0; u < kHaloBatch; ++u) {
       // vertices past the end re-read the last one (no branches around the loads)
-      unsigned long long* p = const_cast<unsigned long long*>(tb) + (size_t)hidx[min(h0 + u * nb, nh - 1)] * 4;
+      unsigned long long* p = const_cast<unsigned long long*>(tb) + hidx[min(h0 + u * nb, nh - 1)];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        w[u][k] = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        w[u][k] = __hip_atomic_load(p + (size_t)k * nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int u = 0; u < kHaloBatch; ++u) {
       const int h = h0 + u * nb;
       if (h >= nh) break;
-      unsigned long long* p = const_cast<unsigned long long*>(tb) + (size_t)hidx[h] * 4;
+      unsigned long long* p = const_cast<unsigned long long*>(tb) + hidx[h];
       int spins = 0;
       while (ok && ((w[u][0] ^ t) >> 48 | (w[u][1] ^ t) >> 48 | (w[u][2] ^ t) >> 48 |
                     (w[u][3] ^ t) >> 48) != 0) {
@@ -1484,7 +1486,7 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb,
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          w[u][k] = __hip_atomic_load(p + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          w[u][k] = __hip_atomic_load(p + (size_t)k * nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (ok) {
         double v[3];
@@ -2406,12 +2408,12 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       unsigned long long* tb = w.tbuf + (size_t)par * 4 * nv;
       ++nep;
       if (act) {
-        publish_tagged(tb, i, mm, (unsigned)nep);
+        publish_tagged(tb, i, nv, mm, (unsigned)nep);
 #pragma unroll
         for (int c = 0; c < 3; ++c) ml[c * RH + tid] = mm[c];
       }
       PHASE_ADD(4, wall_clock64() - t5);
-      if (!halo_load_tagged(tb, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
+      if (!halo_load_tagged(tb, nv, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
         if (tid == 0) {
           __hip_atomic_store(w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           set_status(a.status, inst, ST_TIMEOUT);
@@ -3115,7 +3117,7 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
   z.n[1] = 1;
   if (coarse) {
     z.p[2] = reinterpret_cast<int*>(w.tbuf);
-    z.n[2] = 16 * m.nv;   // [2][nv][4] 64-bit words
+    z.n[2] = 16 * m.nv;   // [2][4][nv] 64-bit words
     z.p[3] = reinterpret_cast<int*>(w.tred);
     z.n[3] = w.tred_ints;
   }

@@ -602,7 +602,7 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
   TRY(alloc(s, 3 * nv * 8, &q)); s->gv = (double*)q;
   TRY(alloc(s, 3 * nv * 8, &q)); s->sw.zbuf = (double*)q;
   TRY(alloc(s, 6 * nv * 8, &q)); s->sw.pbuf = (double*)q;
-  TRY(alloc(s, 8 * nv * 8, &q)); s->sw.tbuf = (unsigned long long*)q;   // [2][nv][4]
+  TRY(alloc(s, 8 * nv * 8, &q)); s->sw.tbuf = (unsigned long long*)q;   // [2][4][nv]
   TRY(alloc(s, 4, &q)); s->sw.abort_flag = (int*)q;
   if (coarse) {
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;

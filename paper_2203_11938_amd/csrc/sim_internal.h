@@ -205,7 +205,7 @@ constexpr int kTagSlots = 3 + 6 * kMaxWgAgg;
 struct SolverWork {
   double* zbuf;            // [3][nv]     preconditioned initial residual, gathered once
   double* pbuf;            // [2][3][nv]  m = M^-1 w of even / odd iterations
-  unsigned long long* tbuf;  // [2][nv][4] the same, published as tagged 64-bit words
+  unsigned long long* tbuf;  // [2][4][nv] the same, published as tagged 64-bit words
                              // (tag << 32 | 32 data bits), zeroed before each launch
   double* red;             // [2][nwg][3] per-workgroup partial sums
   unsigned long long* tred;  // [2][nwg][kTagSlots][2] the same and the coarse restriction

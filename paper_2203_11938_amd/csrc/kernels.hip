@@ -1020,17 +1020,30 @@ __global__ void __launch_bounds__(64) k_gj_pivot0(Coarse c) {
   if (lane == 0) c.ok[inst] = good ? 1 : 0;
 }
 
-// 32x32 tile product in LDS: each of the 256 threads forms 4 entries of X Y.
-__device__ __forceinline__ void tile_mul4(const double (*X)[kGjTile + 1], const double (*Y)[kGjTile + 1],
-                                          double out[4]) {
+// 32x32 tile product X Y from LDS on the matrix cores (256 threads): wavefront w forms
+// the 16x16 block (w / 2, w % 2) with eight FP64 16x16x4 MFMAs (A operand: lane l holds
+// row l % 16, column l / 16 of the 16x4 slice; B operand: row l / 16, column l % 16);
+// lane l's four results are the entries tile_rc(i) = (16 (w / 2) + l / 16 + 4 i,
+// 16 (w % 2) + l % 16), i = 0..3.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void tile_rc(int i, int& r, int& q) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  r = 16 * (w >> 1) + (lane >> 4) + 4 * i;
+  q = 16 * (w & 1) + (lane & 15);
+}
+
+__device__ __forceinline__ void tile_mul_mfma(const double (*X)[kGjTile + 1],
+                                              const double (*Y)[kGjTile + 1], double out[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 16 * (w >> 1), c0 = 16 * (w & 1);
+  dbl4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int e = threadIdx.x + k * 256, r = e / kGjTile, q = e % kGjTile;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int p = 0; p < kGjTile; ++p) acc += X[r][p] * Y[p][q];
-    out[k] = acc;
-  }
+  for (int k0 = 0; k0 < kGjTile; k0 += 4)
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(X[r0 + (lane & 15)][k0 + (lane >> 4)],
+                                             Y[k0 + (lane >> 4)][c0 + (lane & 15)], c, 0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
 }
 
 // Blocked symmetric sweep (the in-place inverse of an SPD matrix that keeps every
@@ -1061,12 +1074,14 @@ __global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
   }
   __syncthreads();
   double o[4];
-  tile_mul4(X, Y, o);
+  tile_mul_mfma(X, Y, o);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int e = tid + k * 256, r = e / T, q = e % T;
+    int r, q;
+    tile_rc(k, r, q);
     C[r * T + q] = o[k];
-    D[r * T + q] = X[r][q];
+    const int e = tid + k * 256;
+    D[e] = X[e / T][e % T];
   }
 }
 
@@ -1106,15 +1121,17 @@ __device__ __forceinline__ void gj_next_panel(const Coarse& c, int K, int ninst,
     Y[e / T][e % T] = __hip_atomic_load(Pn + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   double o[4];
-  tile_mul4(X, Y, o);
+  tile_mul_mfma(X, Y, o);
   const long long par = ((K + 1) & 1) * c.gj_half;
   double* C = c.gj_c + par + c.inst_boff[inst] + (size_t)t * T * T;
   double* D = c.gj_r + par + c.inst_boff[inst] + (size_t)t * T * T;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int e = threadIdx.x + k * 256, r = e / T, q = e % T;
+    int r, q;
+    tile_rc(k, r, q);
     C[r * T + q] = o[k];
-    D[r * T + q] = X[r][q];
+    const int e = threadIdx.x + k * 256;
+    D[e] = X[e / T][e % T];
   }
 }
 
@@ -1179,11 +1196,12 @@ __global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
   }
   __syncthreads();
   double o[4];
-  tile_mul4(X, Y, o);
+  tile_mul_mfma(X, Y, o);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int e = tid + k * 256, r = e / T, q = e % T;
+    int r, q;
+    tile_rc(k, r, q);
     double* dst = M + (size_t)(i * T + r) * np + j * T + q;
     const double v = *dst - o[k];
     *dst = v;

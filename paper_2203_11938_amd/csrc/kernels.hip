@@ -1853,7 +1853,7 @@ template <int NR, bool XLDS>
 __device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld, int nc,
                                             const double* s_wc, double* s_red, double* s_e) {
   constexpr int NP = NR <= 8 ? 8 : (NR <= 16 ? 16 : 32);
-  constexpr int TU = NR <= 6 ? 4 : (NR <= 12 ? 2 : 1);
+  constexpr int TU = NR <= 6 ? 4 : (NR <= 12 ? 3 : 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int ntile = (nc + 63) >> 6;

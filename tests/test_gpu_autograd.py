@@ -47,3 +47,42 @@ def test_autograd_matches_oracle(with_v0):
         if k != "x":
             assert v <= 1e-6, (k, v)
     s.close()
+
+
+def test_backward_refuses_a_later_rollout_on_the_handle():
+    """Two forward passes on one handle, then the first one's backward: the handle's
+    adjoint belongs to the second rollout, so the backward raises instead of returning
+    the wrong trajectory's gradients; the second graph's backward still works."""
+    w = W.workload("C2", n=8, steps=5, precision="fp64", cg_tol=1e-10)
+    inst = W.make_instances(w)[0]
+    s = make_sim(w, [inst])
+    f64 = dict(dtype=torch.float64, device=torch.device("cuda:0"))
+    mat = torch.tensor([inst.material.as_tuple()], **f64, requires_grad=True)
+    x0 = torch.tensor(inst.x0, **f64)
+    F1 = torch.tensor(inst.forces, **f64, requires_grad=True)
+    F2 = torch.tensor(2.0 * inst.forces, **f64, requires_grad=True)
+    x1 = S.rollout(s, w.steps, mat, x0, None, F1)
+    x2 = S.rollout(s, w.steps, mat, x0, None, F2)
+    with pytest.raises(RuntimeError, match="another rollout"):
+        x1.sum().backward()
+    x2.sum().backward()
+    assert F2.grad is not None and torch.isfinite(F2.grad).all()
+    s.close()
+
+
+def test_unconverged_forward_raises_unless_allowed():
+    """A solve capped at one iteration does not converge: the autograd path raises by
+    default and warns when the handle allows it."""
+    w = W.workload("C2", n=8, steps=3, precision="fp64", cg_tol=1e-12)
+    inst = W.make_instances(w)[0]
+    s = make_sim(w, [inst], cg_max_iter=1)
+    f64 = dict(dtype=torch.float64, device=torch.device("cuda:0"))
+    mat = torch.tensor([inst.material.as_tuple()], **f64, requires_grad=True)
+    x0 = torch.tensor(inst.x0, **f64)
+    with pytest.raises(S.SimError):
+        S.rollout(s, w.steps, mat, x0)
+    s.allow_not_converged = True
+    with pytest.warns(RuntimeWarning):
+        x = S.rollout(s, w.steps, mat, x0)
+    assert torch.isfinite(x).all()
+    s.close()

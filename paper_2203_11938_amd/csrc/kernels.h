@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "sim_internal.h"
 
 namespace phisft {
@@ -80,12 +82,17 @@ template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
                 const PcgArgs<TM>& a, hipStream_t st);
 // Coarse operator of the step at positions x and assembled matrix A: frames,
-// Galerkin product and its in-place blocked Gauss-Jordan inverse (host arrays
-// gja_count / gjb_count: tasks of each pivot step). No-op without a coarse space.
+// Galerkin product and its in-place blocked symmetric sweep (one launch per group of
+// sheets; sweep_groups: first workgroup of each group, then the total). No-op without
+// a coarse space.
 template <typename TM>
 void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
-                         long long coarse_doubles, const int* gja_count, const int* gjb_count,
+                         long long coarse_doubles, const std::vector<int>& sweep_groups,
                          hipStream_t st);
+// Dynamic LDS of the sweep kernel and its co-resident workgroups per CU for a given
+// number of tiles held per workgroup.
+size_t gj_sweep_lds(int tiles_per_wg);
+hipError_t gj_sweep_occupancy(int tiles_per_wg, int* blocks_per_cu);
 // Caller-layout arrays (x0, v0, x_out, dL/dx) are indexed through m.vold.
 template <typename T>
 void launch_update(const Mesh& m, const double* xp, const double* vp, const double* dv, double h,

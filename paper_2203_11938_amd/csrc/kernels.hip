@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "kernels.h"
 #include "sim_internal.h"
@@ -970,54 +971,56 @@ __global__ void __launch_bounds__(256) k_coarse_dead(Coarse c, int ninst) {
   }
 }
 
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  int2 t = *reinterpret_cast<int2*>(&v);
-  t.x = __builtin_amdgcn_readlane(t.x, l);
-  t.y = __builtin_amdgcn_readlane(t.y, l);
-  return *reinterpret_cast<double*>(&t);
+// Reciprocal by Newton-Raphson refinement of the hardware estimate (two steps of
+// x <- x + x (1 - a x), each squaring the relative error).
+__device__ __forceinline__ double recip_nr(double a) {
+  double x = __builtin_amdgcn_rcp(a);
+  x = fma(x, fma(-a, x, 1.0), x);
+  return fma(x, fma(-a, x, 1.0), x);
 }
 
-// In-place Gauss-Jordan inverse of a 32x32 symmetric positive definite tile held one
-// row per lane (lanes 0..31 of the wavefront; other lanes compute nothing useful).
-// No pivoting: every pivot of an SPD matrix is positive; false if one is not.
-__device__ __forceinline__ bool gj_tile_inverse(double (&a)[kGjTile], int lane) {
+// In-place symmetric sweep of a 32x32 symmetric positive definite tile on one
+// wavefront: for every pivot k in turn, with d = 1 / a_kk,
+//   a_ij -= a_ik a_kj d (i, j != k),  a_ik = a_ik d,  a_kj = a_kj d,  a_kk = -d,
+// which leaves -A^-1 and keeps every intermediate matrix symmetric. Lane l holds row
+// l & 31, columns 16 (l >> 5) .. + 15. Row k of the pivot step is column k (symmetry):
+// the lanes holding column k write it to s_col and every lane reads the part of it
+// that its columns need (in-order LDS access within the wavefront, no barrier). No
+// pivoting: every pivot of an SPD matrix is positive; false if one is not.
+__device__ __forceinline__ bool gj_sweep_tile(double (&a)[16], double* s_col, int lane) {
+  const int r = lane & 31, h = lane >> 5;
   bool good = true;
+#pragma unroll 1
+  for (int kh = 0; kh < 2; ++kh) {
 #pragma unroll
-  for (int p = 0; p < kGjTile; ++p) {
-    double row[kGjTile];
+    for (int kq = 0; kq < 16; ++kq) {
+      const int k = 16 * kh + kq;
+      if (h == kh) s_col[r] = a[kq];
+      asm volatile("" ::: "memory");
+      double row[16];
 #pragma unroll
-    for (int j = 0; j < kGjTile; ++j) row[j] = readlane_d(a[j], p);
-    const double piv = row[p];
-    good = good && piv > 0.0 && isfinite(piv);
-    const double d = 1.0 / piv;
-    // one update for every row, a_j -= f s_j, with the scaled pivot row s_j = row_j d
-    // and s_p = 1 + d: other rows (f = a_p) get a_p - f (1 + d) = -f d in the pivot
-    // column; the pivot row itself (f = a_pp - 1) gets a_pj - (a_pp - 1) a_pj d = a_pj d
-    // and a_pp - (a_pp - 1)(1 + d) = d. No per-element selects.
-    const double f = lane == p ? a[p] - 1.0 : a[p];
-    const double fd = f * d;
+      for (int q = 0; q < 16; ++q) row[q] = s_col[16 * h + q];
+      const double f = s_col[r], piv = s_col[k];
+      asm volatile("" ::: "memory");
+      good = good && piv > 0.0 && isfinite(piv);
+      const double d = recip_nr(piv);
+      // one formula for every entry, s a_ij + g a_kj: off the pivot row s = 1, g = -a_ik d;
+      // on it s = 0, g = d (a_kj d formed directly: the scale of the tile never enters as
+      // a cancellation); column k becomes -g
+      const bool pr = r == k;
+      const double g = pr ? d : -f * d, sc = pr ? 0.0 : 1.0;
 #pragma unroll
-    for (int j = 0; j < kGjTile; ++j) a[j] -= j == p ? f * (1.0 + d) : fd * row[j];
+      for (int q = 0; q < 16; ++q) {
+        const double upd = fma(g, row[q], sc * a[q]);
+        a[q] = (q == kq && h == kh) ? -g : upd;
+      }
+      // every entry's update is formed in its own step (the compiler would otherwise
+      // defer each to its next use and keep every step's row alive)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) asm volatile("" : "+v"(a[q]));
+    }
   }
   return good;
-}
-
-// Inverse of the sheet's first pivot tile (one wavefront per sheet).
-__global__ void __launch_bounds__(64) k_gj_pivot0(Coarse c) {
-  const int inst = blockIdx.x, lane = threadIdx.x;
-  const int np = c.inst_np[inst];
-  if (np == 0) return;
-  const double* M = c.mat + c.inst_coff[inst];
-  double a[kGjTile];
-#pragma unroll
-  for (int j = 0; j < kGjTile; ++j) a[j] = lane < kGjTile ? M[(size_t)lane * np + j] : 0.0;
-  const bool good = gj_tile_inverse(a, lane);
-  double* P = c.gj_pinv + (size_t)inst * kGjTile * kGjTile;
-  if (lane < kGjTile) {
-#pragma unroll
-    for (int j = 0; j < kGjTile; ++j) P[lane * kGjTile + j] = a[j];
-  }
-  if (lane == 0) c.ok[inst] = good ? 1 : 0;
 }
 
 // 32x32 tile product X Y from LDS on the matrix cores (256 threads): wavefront w forms
@@ -1046,219 +1049,277 @@ __device__ __forceinline__ void tile_mul_mfma(const double (*X)[kGjTile + 1],
   for (int i = 0; i < 4; ++i) out[i] = c[i];
 }
 
-// Blocked symmetric sweep (the in-place inverse of an SPD matrix that keeps every
-// intermediate matrix symmetric, so only the tiles (i, j), i <= j, are stored and
-// updated): for each pivot tile K with P = M_KK^-1,
-//   M_ij -= M_iK P M_Kj (i, j != K),  M_iK = M_iK P,  M_Kj = P M_Kj,  M_KK = -P,
-// and after the last pivot M = -A_c^-1.
-// Step K, first half: for every t != K the column panel D_t = M_tK (read from the
-// stored tile (t, K) or, below the diagonal, as the transpose of (K, t)) and
-// C_t = D_t P. One 256-thread workgroup per task; panels are stored tile-major.
-__global__ void __launch_bounds__(256) k_gj_cols(Coarse c, int K, int ninst) {
-  constexpr int T = kGjTile;
-  __shared__ double X[T][T + 1], Y[T][T + 1];
-  const int task = c.gja_ptr[K] + blockIdx.x, tid = threadIdx.x;
-  const int inst = c.gja_inst[task], t = c.gja_t[task];
-  if (!c.ok[inst]) return;
-  const int np = c.inst_np[inst];
-  const double* M = c.mat + c.inst_coff[inst];
-  const long long par = (K & 1) * c.gj_half;
-  double* C = c.gj_c + par + c.inst_boff[inst] + (size_t)t * T * T;
-  double* D = c.gj_r + par + c.inst_boff[inst] + (size_t)t * T * T;
-  const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
-  for (int e = tid; e < T * T; e += 256) {
-    const int r = e / T, q = e % T;
-    if (t < K) X[r][q] = M[(size_t)(t * T + r) * np + K * T + q];
-    else X[q][r] = M[(size_t)(K * T + r) * np + t * T + q];   // coalesced read, LDS transpose
-    Y[r][q] = P[r * T + q];
-  }
-  __syncthreads();
-  double o[4];
-  tile_mul_mfma(X, Y, o);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int r, q;
-    tile_rc(k, r, q);
-    C[r * T + q] = o[k];
-    const int e = tid + k * 256;
-    D[e] = X[e / T][e % T];
-  }
-}
-
-// Polls of a panel workgroup for the next pivot's inverse (seconds, far beyond the
-// microseconds the inverse takes).
+// Polls of the sweep's bounded waits (seconds, far beyond the microseconds a step takes).
 constexpr int kGjSpinLimit = 1 << 22;
 
-// The panels of step K + 1 for tile t != K + 1, formed by the workgroup that has just
-// written the tile of row / column K + 1 holding M_{t,K+1} (in X, oriented as D_t, i.e.
-// rows of tile t): D_t = that tile, C_t = D_t P_{K+1}, once the workgroup inverting
-// pivot tile K + 1 (listed first in the launch, so dispatched before this one) has
-// stored P_{K+1}. The wait is bounded; on a time-out the step's coarse correction is
-// switched off (ok = 0), as for a failed pivot.
-__device__ __forceinline__ void gj_next_panel(const Coarse& c, int K, int ninst, int inst, int t,
-                                              double (*X)[kGjTile + 1], double (*Y)[kGjTile + 1]) {
-  constexpr int T = kGjTile;
+// Thread 0 waits (bounded) until *flag >= target; every thread returns false once the
+// sheet's inversion has failed or the wait timed out (which marks it failed: the step
+// then runs without its coarse correction, as after a failed pivot).
+__device__ __forceinline__ bool sweep_wait(int* flag, int target, int* ok) {
   __shared__ int s_go;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int spins = 0;
-    bool ready = true;
-    while (__hip_atomic_load(c.gj_ready + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < K + 2) {
+    int spins = 0, go = 1;
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        go = 0;
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kGjSpinLimit) {
-        ready = false;
+        __hip_atomic_store(ok, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        go = 0;
         break;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    if (!ready) __hip_atomic_store(c.ok + inst, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_go = ready && __hip_atomic_load(c.ok + inst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (go && __hip_atomic_load(ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) go = 0;
+    s_go = go;
   }
   __syncthreads();
-  if (!s_go) return;
-  // P_{K+1} was written by another workgroup of this launch: coherent loads
-  double* Pn = c.gj_pinv + ((size_t)((K + 1) & 1) * ninst + inst) * T * T;
-  for (int e = threadIdx.x; e < T * T; e += 256)
-    Y[e / T][e % T] = __hip_atomic_load(Pn + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return s_go != 0;
+}
+
+// Releases everything this workgroup wrote: every wavefront's stores are written back
+// (an agent-scope release per wavefront: the workgroup barrier alone does not wait for
+// the other wavefronts' stores), then thread 0 moves the flag.
+__device__ __forceinline__ void sweep_signal(int* flag, int value, bool add) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  double o[4];
-  tile_mul_mfma(X, Y, o);
-  const long long par = ((K + 1) & 1) * c.gj_half;
-  double* C = c.gj_c + par + c.inst_boff[inst] + (size_t)t * T * T;
-  double* D = c.gj_r + par + c.inst_boff[inst] + (size_t)t * T * T;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int r, q;
-    tile_rc(k, r, q);
-    C[r * T + q] = o[k];
-    const int e = threadIdx.x + k * 256;
-    D[e] = X[e / T][e % T];
+  if (threadIdx.x == 0) {
+    if (add) __hip_atomic_fetch_add(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Step K, second half: every stored tile (i, j), i <= j, of the sheet:
-//   i, j != K: M_ij -= C_i D_j^T;   j = K: M_iK = C_i;   i = K: M_Kj = C_j^T;
-//   (K, K): -P. The tile (K+1, K+1) then inverts itself as the next pivot, and the
-// workgroups of the other tiles of row and column K + 1 form step K + 1's panels from
-// their new values (so step K + 1 needs no launch of k_gj_cols).
-__global__ void __launch_bounds__(256) k_gj_update(Coarse c, int K, int ninst) {
+// 32x32 blocks written by other workgroups of the launch into LDS (all loads issued
+// before any is stored), each as stored or transposed. Every block the sweep publishes
+// has an address of its own, written once per launch and read only after its flag, so
+// no cache of the reader can hold an older copy: ordinary (cached) loads are coherent
+// here, and the readers of one chiplet share its L2 copy.
+template <int NB>
+__device__ __forceinline__ void sweep_load(const double* const (&src)[NB],
+                                           double (*const (&dst)[NB])[kGjTile + 1],
+                                           const bool (&transpose)[NB]) {
   constexpr int T = kGjTile;
+  double v[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[b][k] = src[b][threadIdx.x + 256 * k];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = threadIdx.x + 256 * k, r = e / T, q = e % T;
+      if (transpose[b]) dst[b][q][r] = v[b][k];
+      else dst[b][r][q] = v[b][k];
+    }
+}
+
+// Blocked symmetric sweep of every sheet's coarse matrix, one launch per step: the
+// in-place inverse of an SPD matrix that keeps every intermediate matrix symmetric,
+// so only the tiles (i, j), i <= j, are stored and updated. For each pivot tile K with
+// P = M_KK^-1:
+//   M_ij -= M_iK P M_Kj (i, j != K),  M_iK = M_iK P,  M_Kj = P M_Kj,  M_KK = -P,
+// and after the last pivot M = -A_c^-1. Expressed with the column panel D_t = M_tK and
+// C_t = D_t P (t != K): M_ij -= C_i D_j^T, M_iK = C_i, M_Kj = C_j^T.
+// Each workgroup owns up to c.sw_tpw tiles of one sheet and keeps them in LDS for the
+// whole sweep (read from the assembled matrix at the start; at the end A_c^-1 = -M is
+// written as the solver's exactly symmetric FP32 copy). Per pivot step K:
+//   1. the owner of tile (K+1, K+1) updates it with step K's panels, inverts it on one
+//      wavefront (the sweep of the tile gives -P_{K+1} = its value after step K+1 at
+//      once) and publishes P_{K+1};
+//   2. every other tile is updated as soon as the two panels it needs are published;
+//   3. the owners of the other tiles of row and column K+1 form step K+1's panels from
+//      their new values and P_{K+1}, and publish them.
+// Pivot step 0's inverse and panels come from an initial phase. Every step's panels and
+// inverse pivot tile have addresses of their own (nothing is rewritten within a launch,
+// so readers need no wait beyond the flag). Sync flags per sheet, each on a cache line
+// of its own (zero before the launch): pivot (1 + the last pivot step whose inverse is
+// published) and per panel t (1 + the last step whose panel t is published). All waits
+// are bounded; a failed pivot or a time-out sets ok = 0 and every workgroup of the
+// sheet stops.
+__global__ void __launch_bounds__(256) k_gj_sweep(Coarse c, int ninst, int wg0) {
+  constexpr int T = kGjTile;
+  extern __shared__ __align__(16) unsigned char sw_lds[];
+  double (*Mt)[T][T + 1] = reinterpret_cast<double (*)[T][T + 1]>(sw_lds);
   __shared__ double X[T][T + 1], Y[T][T + 1];
-  const int task = c.gjb_ptr[K] + blockIdx.x, tid = threadIdx.x;
-  const int inst = c.gjb_inst[task], ij = c.gjb_ij[task];
-  if (!c.ok[inst]) return;
-  const int i = ij >> 16, j = ij & 0xffff;
+  __shared__ double s_col[T];
+  const int w = wg0 + blockIdx.x, tid = threadIdx.x, tpw = c.sw_tpw;
+  const int inst = c.sw_inst[w];
   const int np = c.inst_np[inst], nb = np / T;
-  double* M = c.mat + c.inst_coff[inst];
-  const long long par = (K & 1) * c.gj_half;
-  const double* Cb = c.gj_c + par + c.inst_boff[inst];
-  const double* Db = c.gj_r + par + c.inst_boff[inst];
-  const double* P = c.gj_pinv + ((size_t)(K & 1) * ninst + inst) * T * T;
-  const bool next = K + 1 < nb && (i == K + 1) != (j == K + 1);   // a tile of step K+1's panel
-  if (i == K && j == K) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + k * 256, r = e / T, q = e % T;
-      M[(size_t)(K * T + r) * np + K * T + q] = -P[r * T + q];
-    }
-    return;
-  }
-  if (j == K) {   // i < K
-    const double* Ci = Cb + (size_t)i * T * T;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + k * 256, r = e / T, q = e % T;
-      M[(size_t)(i * T + r) * np + K * T + q] = Ci[r * T + q];
-    }
-    return;
-  }
-  if (i == K) {   // j > K: the transpose of C_j, through LDS
-    const double* Cj = Cb + (size_t)j * T * T;
-    for (int e = tid; e < T * T; e += 256) {
-      const int r = e / T, q = e % T;
-      X[q][r] = Cj[r * T + q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = tid + k * 256, r = e / T, q = e % T;
-      M[(size_t)(K * T + r) * np + j * T + q] = X[r][q];
-    }
-    // tile (K, K+1) is M_{t,K+1} for t = K, already oriented as D_t
-    if (next) gj_next_panel(c, K, ninst, inst, K, X, Y);
-    return;
-  }
-  const double* Ci = Cb + (size_t)i * T * T;
-  const double* Dj = Db + (size_t)j * T * T;
-  for (int e = tid; e < T * T; e += 256) {
-    const int r = e / T, q = e % T;
-    X[r][q] = Ci[r * T + q];
-    Y[q][r] = Dj[r * T + q];   // Y = D_j^T
-  }
-  __syncthreads();
-  double o[4];
-  tile_mul_mfma(X, Y, o);
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int r, q;
-    tile_rc(k, r, q);
-    double* dst = M + (size_t)(i * T + r) * np + j * T + q;
-    const double v = *dst - o[k];
-    *dst = v;
-    // the new value in X for the next pivot or panel, oriented as D_t (rows of t)
-    if (i == K + 1 && j != K + 1) X[q][r] = v;
-    else X[r][q] = v;
-  }
-  if (i == K + 1 && j == K + 1 && K + 1 < nb) {
-    __syncthreads();
-    if (tid < 64) {
-      double a[T];
-#pragma unroll
-      for (int q = 0; q < T; ++q) a[q] = tid < T ? X[tid][q] : 0.0;
-      const bool good = gj_tile_inverse(a, tid);
-      double* Pn = c.gj_pinv + ((size_t)((K + 1) & 1) * ninst + inst) * T * T;
-      if (tid < T) {
-#pragma unroll
-        for (int q = 0; q < T; ++q) Pn[tid * T + q] = a[q];
-      }
-      if (tid == 0 && !good) __hip_atomic_store(c.ok + inst, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    // release P_{K+1} (and a failed pivot's ok = 0) to the panel workgroups
-    if (tid == 0) __hip_atomic_store(c.gj_ready + inst, K + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    return;
-  }
-  if (next) {
-    __syncthreads();
-    gj_next_panel(c, K, ninst, inst, i == K + 1 ? j : i, X, Y);
-  }
-}
-
-// The solver's copy of A_c^-1 = -M, rounded to FP32, from the stored upper tiles
-// (a tile below the diagonal is the transpose of its mirror; a diagonal tile is
-// averaged with its transpose, so the copy is exactly symmetric). One 32x32 tile per
-// workgroup (grid: tiles of the largest sheet x sheets). The coarse correction is a
-// preconditioner term, so its rounding only changes the iteration count, never the
-// converged residual.
-__global__ void __launch_bounds__(256) k_coarse_pack(Coarse c) {
-  constexpr int T = kGjTile;
-  __shared__ double A[T][T + 1];
-  const int inst = blockIdx.y, tid = threadIdx.x;
-  const int np = c.inst_np[inst], nb = np / T;
-  const int I = blockIdx.x / c.max_nb, J = blockIdx.x - I * c.max_nb;
-  if (I >= nb || J >= nb) return;
+  // flags, kSwFlag ints apart: pivot, then one per panel t
+  int* sync = c.sw_sync + (size_t)inst * c.sw_stride;
+  int* const piv_flag = sync;
+  auto panel_flag = [&](int t) { return sync + kSwFlag * (1 + t); };
+  int* ok = c.ok + inst;
   const double* M = c.mat + c.inst_coff[inst];
-  float* X = c.xinv + c.inst_coff[inst];
-  const int I0 = min(I, J), J0 = max(I, J);
-  for (int e = tid; e < T * T; e += 256) {
-    const int r = e / T, q = e % T;
-    A[r][q] = M[(size_t)(I0 * T + r) * np + J0 * T + q];
+  // step K's panels C_t, D_t at gj_c / gj_r + coff + (K nb + t) T^2, its inverse pivot
+  // tile at gj_pinv + boff + K T^2
+  const long long coff = c.inst_coff[inst], boff = c.inst_boff[inst];
+  // the workgroup's tiles (uniform; slots past nt hold -1)
+  __shared__ int ti[kSwMaxTiles], tj[kSwMaxTiles];
+  if (tid < kSwMaxTiles) {
+    const int ij = tid < tpw ? c.sw_ij[(size_t)w * tpw + tid] : -1;
+    ti[tid] = ij < 0 ? -1 : ij >> 16;
+    tj[tid] = ij < 0 ? -1 : ij & 0xffff;
   }
   __syncthreads();
-  for (int e = tid; e < T * T; e += 256) {
-    const int r = e / T, q = e % T;
-    const double v = I < J ? A[r][q] : (I > J ? A[q][r] : 0.5 * (A[r][q] + A[q][r]));
-    X[(size_t)(I * T + r) * np + J * T + q] = (float)(-v);
+  int nt = 0;
+  for (int s = 0; s < kSwMaxTiles; ++s)
+    if (ti[s] >= 0) nt = s + 1;
+#pragma unroll 1
+  for (int s = 0; s < nt; ++s) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k, r = e / T, q = e % T;
+      Mt[s][r][q] = M[(size_t)(ti[s] * T + r) * np + tj[s] * T + q];
+    }
+  }
+  __syncthreads();
+
+  // pivot tile K (held in slot s): sweep it in place (-P_K), publish P_K
+  auto invert = [&](int s, int K) {
+    __syncthreads();   // the tile's last update is complete
+    if (tid < 64) {
+      // the step waits for this wavefront: it goes first on its SIMD
+      __builtin_amdgcn_s_setprio(3);
+      double a[16];
+      const int r = tid & 31, h = tid >> 5;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = Mt[s][r][16 * h + q];
+      const bool good = gj_sweep_tile(a, s_col, tid);
+      double* P = c.gj_pinv + boff + (size_t)K * T * T;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        Mt[s][r][16 * h + q] = a[q];
+        P[r * T + 16 * h + q] = -a[q];
+      }
+      if (!good && tid == 0) __hip_atomic_store(ok, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_setprio(0);
+    }
+    sweep_signal(piv_flag, K + 1, false);
+  };
+  // panel t of step K from the tile in slot s (row / column K): D_t = M_tK oriented as
+  // rows of t, C_t = D_t P_K; false when the sheet's inversion stopped
+  auto panel = [&](int s, int t, int K) -> bool {
+    if (!sweep_wait(piv_flag, K + 1, ok)) return false;
+    const bool tr = ti[s] == K;   // tile (K, t): D_t is its transpose
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k, r = e / T, q = e % T;
+      if (tr) X[q][r] = Mt[s][r][q];
+      else X[r][q] = Mt[s][r][q];
+    }
+    {
+      const double* const src[1] = {c.gj_pinv + boff + (size_t)K * T * T};
+      double (*const dst[1])[T + 1] = {Y};
+      const bool tr1[1] = {false};
+      sweep_load<1>(src, dst, tr1);
+    }
+    __syncthreads();
+    double o[4];
+    tile_mul_mfma(X, Y, o);
+    double* C = c.gj_c + coff + ((size_t)K * nb + t) * T * T;
+    double* D = c.gj_r + coff + ((size_t)K * nb + t) * T * T;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int r, q;
+      tile_rc(k, r, q);
+      C[r * T + q] = o[k];
+      const int e = tid + 256 * k;
+      D[e] = X[e / T][e % T];
+    }
+    sweep_signal(panel_flag(t), K + 1, false);
+    return true;
+  };
+  // step K's update of the tile in slot s
+  auto update = [&](int s, int K) -> bool {
+    const int i = ti[s], j = tj[s];
+    const double* Cb = c.gj_c + coff + (size_t)K * nb * T * T;
+    const double* Db = c.gj_r + coff + (size_t)K * nb * T * T;
+    if (j == K || i == K) {   // M_iK = C_i, or M_Kj = C_j^T
+      const int t = j == K ? i : j;
+      if (!sweep_wait(panel_flag(t), K + 1, ok)) return false;
+      const double* const src[1] = {Cb + (size_t)t * T * T};
+      double (*const dst[1])[T + 1] = {Mt[s]};
+      const bool tr1[1] = {i == K};
+      sweep_load<1>(src, dst, tr1);
+      return true;
+    }
+    if (!sweep_wait(panel_flag(i), K + 1, ok)) return false;
+    if (j != i && !sweep_wait(panel_flag(j), K + 1, ok)) return false;
+    {
+      const double* const src[2] = {Cb + (size_t)i * T * T, Db + (size_t)j * T * T};
+      double (*const dst[2])[T + 1] = {X, Y};
+      const bool tr2[2] = {false, true};   // Y = D_j^T
+      sweep_load<2>(src, dst, tr2);
+    }
+    __syncthreads();
+    double o[4];
+    tile_mul_mfma(X, Y, o);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int r, q;
+      tile_rc(k, r, q);
+      Mt[s][r][q] -= o[k];
+    }
+    return true;
+  };
+
+  bool go = true;
+  // initial phase: pivot 0 and the panels of step 0
+#pragma unroll 1
+  for (int s = 0; s < nt; ++s)
+    if (ti[s] == 0 && tj[s] == 0) invert(s, 0);
+#pragma unroll 1
+  for (int s = 0; s < nt; ++s)
+    if (go && ti[s] == 0 && tj[s] > 0) go = panel(s, tj[s], 0);
+  for (int K = 0; K < nb && go; ++K) {
+    const int K1 = K + 1;
+    // the longest path of the step first: the next pivot tile, then the tiles of its row
+    // and column with step K + 1's panels, then the other tiles
+    int ps = -1;
+    for (int s = 0; s < nt; ++s)
+      if (K1 < nb && ti[s] == K1 && tj[s] == K1) ps = s;
+    if (ps >= 0) {
+      go = update(ps, K);
+      if (go) invert(ps, K1);
+    }
+#pragma unroll 1
+    for (int s = 0; s < nt; ++s) {
+      if (!go || K1 >= nb) break;
+      if (s == ps || (ti[s] != K1 && tj[s] != K1)) continue;
+      go = update(s, K);
+      if (go) go = panel(s, ti[s] == K1 ? tj[s] : ti[s], K1);
+    }
+#pragma unroll 1
+    for (int s = 0; s < nt; ++s) {
+      if (!go) break;
+      if (s == ps || (ti[s] == K && tj[s] == K) || (K1 < nb && (ti[s] == K1 || tj[s] == K1)))
+        continue;
+      go = update(s, K);
+    }
+  }
+  // every workgroup has finished: A_c^-1 = -M as the solver's FP32 copy (tiles below
+  // the diagonal as transposes, diagonal tiles averaged with their transpose)
+  __syncthreads();
+  if (!go || __hip_atomic_load(ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  float* Xo = c.xinv + c.inst_coff[inst];
+#pragma unroll 1
+  for (int s = 0; s < nt; ++s) {
+    const int I = ti[s], J = tj[s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = tid + 256 * k, r = e / T, q = e % T;
+      if (I == J) {
+        Xo[(size_t)(I * T + r) * np + J * T + q] = (float)(-0.5 * (Mt[s][r][q] + Mt[s][q][r]));
+      } else {
+        Xo[(size_t)(I * T + r) * np + J * T + q] = (float)(-Mt[s][r][q]);
+        Xo[(size_t)(J * T + r) * np + I * T + q] = (float)(-Mt[s][q][r]);
+      }
+    }
   }
 }
 
@@ -2262,6 +2323,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
         ul[c * RH + tid] = u[c];
       }
     }
+    // every wavefront wrote rows: each releases its own stores before the barrier
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (ok) ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
     if (ok) {
       halo_load(ub, nv, s_hidx, nh, ul, R, RH);
@@ -2287,6 +2350,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
           xl[c * RH + tid] = x[c];
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(xb, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
@@ -2313,6 +2377,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
           xl[c * RH + tid] = u[c];
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(ub, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
@@ -3169,7 +3234,7 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
 
 template <typename TM>
 void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const TM* A,
-                         long long coarse_doubles, const int* gja_count, const int* gjb_count,
+                         long long coarse_doubles, const std::vector<int>& sweep_groups,
                          hipStream_t st) {
   if (c.nagg == 0) return;
   hipLaunchKernelGGL(k_coarse_frame, dim3(c.nagg), dim3(64), 0, st, m, c, x);
@@ -3179,16 +3244,24 @@ void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const 
   if (c.nmid > 0) hipLaunchKernelGGL((k_mid_setup<TM>), dim3(c.nmid), dim3(64), 0, st, m, c, x, A);
   hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst, 256)), dim3(256), 0, st, c,
                      m.ninst);
-  launch_fill_int(c.gj_ready, m.ninst, 0, st);
-  hipLaunchKernelGGL(k_gj_pivot0, dim3(m.ninst), dim3(64), 0, st, c);
-  for (int K = 0; K < c.max_nb; ++K) {
-    // later steps' panels are formed by the previous update launch
-    if (K == 0 && gja_count[K] > 0)
-      hipLaunchKernelGGL(k_gj_cols, dim3(gja_count[K]), dim3(256), 0, st, c, K, m.ninst);
-    if (gjb_count[K] > 0)
-      hipLaunchKernelGGL(k_gj_update, dim3(gjb_count[K]), dim3(256), 0, st, c, K, m.ninst);
+  launch_fill_int(c.sw_sync, m.ninst * c.sw_stride, 0, st);
+  launch_fill_int(c.ok, m.ninst, 1, st);
+  // one launch per group of whole sheets whose workgroups are co-resident
+  const size_t lds = gj_sweep_lds(c.sw_tpw);
+  for (size_t g = 0; g + 1 < sweep_groups.size(); ++g) {
+    const int n = sweep_groups[g + 1] - sweep_groups[g];
+    if (n > 0)
+      hipLaunchKernelGGL(k_gj_sweep, dim3(n), dim3(256), lds, st, c, m.ninst, sweep_groups[g]);
   }
-  hipLaunchKernelGGL(k_coarse_pack, dim3(c.max_nb * c.max_nb, m.ninst), dim3(256), 0, st, c);
+}
+
+size_t gj_sweep_lds(int tiles_per_wg) {
+  return (size_t)tiles_per_wg * kGjTile * (kGjTile + 1) * sizeof(double);
+}
+
+hipError_t gj_sweep_occupancy(int tiles_per_wg, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, reinterpret_cast<const void*>(&k_gj_sweep), 256, gj_sweep_lds(tiles_per_wg));
 }
 
 template <typename T>
@@ -3255,7 +3328,7 @@ PHISFT_INSTANTIATE_ASM(double, double)
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \
-                                       long long, const int*, const int*, hipStream_t);          \
+                                       long long, const std::vector<int>&, hipStream_t);         \
   template void launch_update<T>(const Mesh&, const double*, const double*, const double*,        \
                                  double, double*, double*, T*, int*, hipStream_t);               \
   template void launch_init_state<T>(const Mesh&, const T*, const T*, double*, double*, int*,    \

@@ -63,7 +63,7 @@ struct sim_s {
   double* mrel_store = nullptr;
   double* minv_store = nullptr;
   std::vector<int> slot_step;             // step held by each slot, 0 = none
-  std::vector<int> gja_count, gjb_count;  // inversion tasks per pivot step
+  std::vector<int> sweep_groups;          // first sweep workgroup of each launch, then total
   void* A = nullptr;
   void* Jinv = nullptr;
   double* rhs = nullptr;
@@ -281,8 +281,7 @@ sim_status autotune(sim_t* s, const std::vector<HostPlan>& cands, const std::vec
   a.b = s->rhs;
   a.status = s->status;
   launch_assemble<double, TM>(s->mesh, s->el, a, st);
-  launch_coarse_setup<TM>(s->mesh, s->coarse, x, a.A, s->L.coarse_doubles, s->gja_count.data(),
-                          s->gjb_count.data(), st);
+  launch_coarse_setup<TM>(s->mesh, s->coarse, x, a.A, s->L.coarse_doubles, s->sweep_groups, st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -514,47 +513,48 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(upload(s, L.pair_ptr, &cs.pair_ptr));
     TRY(upload(s, L.pair_slot, &cs.pair_slot));
     TRY(upload(s, L.inst_np, &cs.inst_np));
-    // blocked Gauss-Jordan task lists per pivot tile K
+    // blocked symmetric sweep: the upper tiles of each sheet spread over co-resident
+    // workgroups (tile e of a sheet in row order -> workgroup e mod n, slot e / n), the
+    // fewest tiles per workgroup with which the largest sheet fits one launch; sheets
+    // grouped into launches of co-resident workgroups
     int max_nb = 0;
     for (int b = 0; b < L.ninst; ++b) max_nb = std::max(max_nb, L.inst_np[b] / kGjTile);
     cs.max_nb = max_nb;
-    std::vector<int> aptr(1, 0), ainst, at, bptr(1, 0), binst, bij;
-    for (int K = 0; K < max_nb; ++K) {
-      // every sheet's next pivot tile first: its workgroup also inverts it, the
-      // longest task of the launch, so it is dispatched before the others
-      for (int b = 0; b < L.ninst; ++b) {
-        const int nb = L.inst_np[b] / kGjTile;
-        if (K + 1 < nb) {
-          binst.push_back(b);
-          bij.push_back((K + 1) * 65536 + K + 1);
-        }
+    int tpw = 0, cap = 0;
+    const long long most_tiles = (long long)max_nb * (max_nb + 1) / 2;
+    for (int t = 1; t <= kSwMaxTiles && tpw == 0; ++t) {
+      int per_cu = 0;
+      HIPCHECK(s, gj_sweep_occupancy(t, &per_cu));
+      if ((long long)per_cu * ncu * t >= most_tiles && per_cu > 0) {
+        tpw = t;
+        cap = per_cu * ncu;
       }
-      for (int b = 0; b < L.ninst; ++b) {
-        const int nb = L.inst_np[b] / kGjTile;
-        if (nb <= K) continue;
-        for (int t = 0; t < nb; ++t) {
-          if (t == K) continue;
-          ainst.push_back(b);
-          at.push_back(t);
-        }
-        for (int i = 0; i < nb; ++i)   // the other stored upper tiles
-          for (int j = i; j < nb; ++j) {
-            if (i == K + 1 && j == K + 1) continue;
-            binst.push_back(b);
-            bij.push_back(i * 65536 + j);
-          }
-      }
-      aptr.push_back((int)ainst.size());
-      bptr.push_back((int)binst.size());
-      s->gja_count.push_back(aptr[K + 1] - aptr[K]);
-      s->gjb_count.push_back(bptr[K + 1] - bptr[K]);
     }
-    TRY(upload(s, aptr, &cs.gja_ptr));
-    TRY(upload(s, ainst, &cs.gja_inst));
-    TRY(upload(s, at, &cs.gja_t));
-    TRY(upload(s, bptr, &cs.gjb_ptr));
-    TRY(upload(s, binst, &cs.gjb_inst));
-    TRY(upload(s, bij, &cs.gjb_ij));
+    if (tpw == 0) {
+      s->err = "coarse operator too large for the co-resident sweep";
+      return SIM_E_INVALID;
+    }
+    cs.sw_tpw = tpw;
+    cs.sw_stride = (1 + max_nb) * kSwFlag;   // pivot, panels
+    std::vector<int> sw_inst, sw_ij;
+    s->sweep_groups.assign(1, 0);
+    for (int b = 0; b < L.ninst; ++b) {
+      const int nb = L.inst_np[b] / kGjTile;
+      const int ntile = nb * (nb + 1) / 2;
+      const int n = (ntile + tpw - 1) / tpw;
+      if (n == 0) continue;
+      if ((int)sw_inst.size() + n - s->sweep_groups.back() > cap)
+        s->sweep_groups.push_back((int)sw_inst.size());
+      const size_t w0 = sw_inst.size();
+      sw_inst.resize(w0 + n, b);
+      sw_ij.resize((w0 + n) * tpw, -1);
+      int e = 0;
+      for (int i = 0; i < nb; ++i)
+        for (int j = i; j < nb; ++j, ++e) sw_ij[(w0 + e % n) * tpw + e / n] = i * 65536 + j;
+    }
+    s->sweep_groups.push_back((int)sw_inst.size());
+    TRY(upload(s, sw_inst, &cs.sw_inst));
+    TRY(upload(s, sw_ij, &cs.sw_ij));
     std::vector<long long> boff;
     for (int b = 0; b < L.ninst; ++b) {
       boff.push_back(s->gj_doubles);
@@ -608,11 +608,11 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
     TRY(alloc(s, 3 * nv * 8, &q)); cs.crel = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.mat = (double*)q;
     TRY(alloc(s, (size_t)L.coarse_doubles * 4, &q)); cs.xinv = (float*)q;
-    TRY(alloc(s, 2 * (size_t)s->gj_doubles * 8, &q)); cs.gj_c = (double*)q;
-    TRY(alloc(s, 2 * (size_t)s->gj_doubles * 8, &q)); cs.gj_r = (double*)q;
-    cs.gj_half = s->gj_doubles;
-    TRY(alloc(s, 2 * ni * kGjTile * kGjTile * 8, &q)); cs.gj_pinv = (double*)q;
-    TRY(alloc(s, 4 * ni, &q)); cs.gj_ready = (int*)q;
+    // every sweep step's panels (as many doubles as the sheet's matrix) and inverse pivot
+    TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.gj_c = (double*)q;
+    TRY(alloc(s, (size_t)L.coarse_doubles * 8, &q)); cs.gj_r = (double*)q;
+    TRY(alloc(s, (size_t)s->gj_doubles * 8, &q)); cs.gj_pinv = (double*)q;
+    TRY(alloc(s, 4 * (size_t)ni * cs.sw_stride, &q)); cs.sw_sync = (int*)q;
     TRY(alloc(s, 4 * ni, &q)); cs.ok = (int*)q;
     TRY(alloc(s, 3 * nv * 8, &q)); cs.mid_crel = (double*)q;
     TRY(alloc(s, (size_t)L.nmid * 36 * 8, &q)); cs.mid_inv = (double*)q;
@@ -755,8 +755,7 @@ void forward_step(sim_t* s, int step, const char* sp, char* sn, const T* F, cons
   bool have = false;
   const Coarse cs = coarse_for_step(s, step, &have);
   if (!(reuse && have))
-    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
-                            s->gjb_count.data(), st);
+    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->sweep_groups, st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;
@@ -829,8 +828,7 @@ void adjoint_step(sim_t* s, int k, const char* sp, const char* sn, const T* dl, 
   bool have = false;
   const Coarse cs = coarse_for_step(s, k, &have);
   if (!have)
-    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->gja_count.data(),
-                            s->gjb_count.data(), st);
+    launch_coarse_setup<TM>(s->mesh, cs, xp, a.A, s->L.coarse_doubles, s->sweep_groups, st);
   PcgArgs<TM> c{};
   c.A = a.A;
   c.Jinv = a.Jinv;

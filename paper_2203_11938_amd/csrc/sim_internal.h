@@ -102,6 +102,8 @@ struct Elem {
 constexpr int kMaxWgAgg = 4;      // aggregates overlapping one solver workgroup
 constexpr int kMaxAggWg = 4;      // solver workgroups overlapping one aggregate
 constexpr int kGjTile = 32;       // tile of the blocked Gauss-Jordan inversion
+constexpr int kSwMaxTiles = 4;    // tiles one sweep workgroup holds in LDS at most
+constexpr int kSwFlag = 32;       // ints between two sweep flags (one cache line each)
 constexpr int kMid = 16;          // vertices per aggregate of the middle level
 
 struct Coarse {
@@ -122,13 +124,14 @@ struct Coarse {
   const int* pair_b;
   const int* pair_ptr;         // [npair+1]
   const int* pair_slot;        // matrix slots k*nv + i, i in a, column in b
-  // blocked Gauss-Jordan task lists, per pivot tile K (ptr arrays have max_nb + 1 entries)
-  const int* gja_ptr;          // column multipliers / pivot-row copies of step K
-  const int* gja_inst;
-  const int* gja_t;            // panel tile t != K of step K
-  const int* gjb_ptr;          // tile updates of step K
-  const int* gjb_inst;
-  const int* gjb_ij;           // i * 65536 + j, i <= j (stored upper tiles)
+  // blocked symmetric sweep: workgroup w holds the tiles sw_ij[w * sw_tpw ..] (i * 65536
+  // + j, i <= j, or -1) of sheet sw_inst[w]; sw_sync:
+  // per sheet sw_stride ints (flags kSwFlag apart: pivot, then one per panel)
+  int sw_tpw;
+  int sw_stride;
+  const int* sw_inst;
+  const int* sw_ij;
+  int* sw_sync;
   // solver-plan overlaps
   const int* wg_agg0;          // [nwg]
   const int* wg_nagg;          // [nwg]
@@ -136,17 +139,13 @@ struct Coarse {
   const int* agg_nwg;          // [nagg]
   // per-step data
   double* crel;                // [3][nv] x_i - c (zero where the rotations are not used)
-  double* mat;                 // A_c, swept in place to -A_c^-1 (FP64 work matrix, upper
-                               // tiles; the lower ones are written by the assembly only)
+  double* mat;                 // A_c as assembled (FP64); the sweep reads its upper tiles
+                               // once and keeps them in LDS
   float* xinv;                 // symmetrised FP32 copy of A_c^-1 read by the solver
-  double* gj_c;                // [2][...] per sheet [nb][32][32] C_t = M_tK P of step K
-  double* gj_r;                // [2][...] per sheet [nb][32][32] column panel D_t = M_tK
-                               // (both by the parity of K: one update launch reads step
-                               // K's panels while it writes step K + 1's)
-  long long gj_half;           // doubles per parity of gj_c / gj_r
-  double* gj_pinv;             // [2][ninst][32][32] inverse pivot tiles
-  int* gj_ready;               // [ninst] K + 1 once pivot tile K's inverse is stored
-  const long long* inst_boff;  // [ninst] offset of the sheet's gj_c / gj_r blocks (32 np)
+  double* gj_c;                // per sheet (at inst_coff) [nb steps][nb][32][32] C_t = M_tK P
+  double* gj_r;                // the same for the column panels D_t = M_tK
+  double* gj_pinv;             // per sheet (at inst_boff) [nb steps][32][32] inverse pivots
+  const long long* inst_boff;  // [ninst] offset of the sheet's inverse pivots (32 np)
   int* ok;                     // [ninst] 1 when this step's inversion succeeded
   double* part;                // [nwg][kMaxWgAgg][6] restriction partial sums
   // middle level: the six rigid motions of runs of kMid vertices, each with the

@@ -4,7 +4,7 @@
 //   k_elements      per triangle: deformation gradient F, Green strain G, force and
 //                   the nine 3x3 blocks of the system stiffness; per hinge: dihedral
 //                   angle, its gradient, force and Gauss-Newton weight.
-//   k_assemble      per vertex row (four lanes each), atomic-free: gathers the row's
+//   k_assemble      per vertex row (16 lanes each), atomic-free: gathers the row's
 //                   blocks in a fixed order into A = M + h^2 K_sys (ELL layout, pins
 //                   eliminated), the right-hand side b = h (f + M g + F_t - h K_sys v)
 //                   and the inverse of the diagonal block.
@@ -671,15 +671,19 @@ __device__ __forceinline__ bool inv3(const double a[9], double o[9]) {
   return true;
 }
 
-template <typename T, typename TM>
+template <typename T, typename TM, int L>
 __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<T, TM> a) {
-  // 64 rows per workgroup, 16 per wavefront: the four lanes l, l + 16, l + 32, l + 48
-  // of a wavefront share a row, each taking every fourth matrix slot and every fourth
-  // incident element; their partial sums meet through two lane exchanges, so every
-  // lane stays active up to there (lanes past the last row work on a copy of it and
-  // store nothing).
-  const int lane = threadIdx.x & 63, g = lane >> 4;
-  const int i0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * 16 + (lane & 15);
+  // L lanes per row (4, or 16 on small meshes, which would otherwise occupy few CUs),
+  // each taking every L-th matrix slot and every L-th incident element; their partial
+  // sums meet through lane exchanges, so every lane stays active up to there (lanes
+  // past the last row work on a copy of it and store nothing). L = 4: 16 rows per
+  // wavefront, lanes l, l + 16, l + 32, l + 48 share a row (two permlane swaps).
+  // L = 16: 4 rows per wavefront, each one 16-lane DPP row (a butterfly within it).
+  static_assert(L == 4 || L == 16, "lanes per row");
+  constexpr int RW = 64 / L;   // rows per wavefront
+  const int lane = threadIdx.x & 63;
+  const int g = L == 4 ? lane >> 4 : lane & 15, rw = L == 4 ? lane & 15 : lane >> 4;
+  const int i0 = (blockIdx.x * 4 + (int)(threadIdx.x >> 6)) * RW + rw;
   const int nv = m.nv;
   const bool live = i0 < nv;
   const int i = live ? i0 : nv - 1;
@@ -688,7 +692,7 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   const bool pin_i = m.pinned[i] != 0;
   const double h = a.h, h2 = a.h * a.h;
   double kv[3] = {0.0, 0.0, 0.0};
-  for (int k = g; k < m.maxnz; k += 4) {
+  for (int k = g; k < m.maxnz; k += L) {
     const int s = k * nv + i;
     const int j = m.ell_col[s];
     double Ab[9];
@@ -742,7 +746,7 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   }
   if (!a.want_rhs) return;   // uniform
   double f[3] = {0.0, 0.0, 0.0};
-  for (int c = m.vinc_ptr[i] + g; c < m.vinc_ptr[i + 1]; c += 4) {
+  for (int c = m.vinc_ptr[i] + g; c < m.vinc_ptr[i + 1]; c += L) {
     int ref = m.vinc_ref[c];
     if (ref >= 0) {
       int t = ref / 3, va = ref - 3 * (ref / 3);
@@ -761,10 +765,21 @@ __global__ void __launch_bounds__(256) k_assemble(Mesh m, Elem el, AssembleArgs<
   }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    kv[r] = swap_sum<16>(kv[r], kv[r]);
-    kv[r] = swap_sum<32>(kv[r], kv[r]);
-    f[r] = swap_sum<16>(f[r], f[r]);
-    f[r] = swap_sum<32>(f[r], f[r]);
+    if constexpr (L == 16) {
+      kv[r] += exch<8>(kv[r], lane);
+      kv[r] += exch<4>(kv[r], lane);
+      kv[r] += exch<2>(kv[r], lane);
+      kv[r] += exch<1>(kv[r], lane);
+      f[r] += exch<8>(f[r], lane);
+      f[r] += exch<4>(f[r], lane);
+      f[r] += exch<2>(f[r], lane);
+      f[r] += exch<1>(f[r], lane);
+    } else {
+      kv[r] = swap_sum<16>(kv[r], kv[r]);
+      kv[r] = swap_sum<32>(kv[r], kv[r]);
+      f[r] = swap_sum<16>(f[r], f[r]);
+      f[r] = swap_sum<32>(f[r], f[r]);
+    }
   }
   if (g != 0 || !live) return;
   double b[3];
@@ -820,19 +835,23 @@ __device__ __forceinline__ void mul33(const double* A, const double* B, double* 
     for (int q = 0; q < 3; ++q) C[r * 3 + q] = A[r * 3] * B[q] + A[r * 3 + 1] * B[3 + q] + A[r * 3 + 2] * B[6 + q];
 }
 
-// One wavefront per aggregate pair (a <= b): the 6x6 block sum over its matrix
-// slots of P_i^T A_ij P_j with P_i = [I | -[r_i]x], i.e.
+// One 256-thread workgroup per aggregate pair (a <= b): the 6x6 block sum over its
+// matrix slots of P_i^T A_ij P_j with P_i = [I | -[r_i]x], i.e.
 //   [[A, -A R_j], [R_i A, -R_i A R_j]];
 // written at (a, b) and, transposed, at (b, a). Unused modes give zero rows and
-// columns (their unit diagonal is set by k_coarse_dead).
+// columns (their unit diagonal is set by k_coarse_dead). The threads take the slots in
+// turn (four wavefronts keep more of the dependent gathers in flight); each wavefront
+// reduces its 36 sums together by recursive halving, then the wavefronts' sums are
+// added in order.
 template <typename TM>
-__global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const TM* __restrict__ A) {
-  const int p = blockIdx.x, lane = threadIdx.x, nv = m.nv;
+__global__ void __launch_bounds__(256) k_coarse_assemble(Mesh m, Coarse c, const TM* __restrict__ A) {
+  __shared__ double s_part[4][36];
+  const int p = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nv = m.nv;
   const int a = c.pair_a[p], b = c.pair_b[p];
   double acc[36];
 #pragma unroll
   for (int e = 0; e < 36; ++e) acc[e] = 0.0;
-  for (int t = c.pair_ptr[p] + lane; t < c.pair_ptr[p + 1]; t += 64) {
+  for (int t = c.pair_ptr[p] + tid; t < c.pair_ptr[p + 1]; t += 256) {
     const int s = c.pair_slot[t];
     const int k = s / nv, i = s - k * nv, j = m.ell_col[s];
     double Ab[9], Ri[9], Rj[9], AR[9], RA[9], RAR[9];
@@ -855,22 +874,23 @@ __global__ void __launch_bounds__(64) k_coarse_assemble(Mesh m, Coarse c, const 
         acc[(3 + r) * 6 + 3 + q] -= RAR[r * 3 + q];
       }
   }
+  double v[64];
 #pragma unroll
-  for (int e = 0; e < 36; ++e) acc[e] = wave_sum(acc[e]);
+  for (int e = 0; e < 64; ++e) v[e] = e < 36 ? acc[e] : 0.0;
+  const double t = wave_sums_scatter<64>(v, lane);   // lane l holds sum l
+  if (lane < 36) s_part[wave][lane] = t;
+  __syncthreads();
+  if (tid >= 36) return;
   const int inst = c.agg_inst[a];
   const int np = c.inst_np[inst];
   double* M = c.mat + c.inst_coff[inst];
   const int la = a - c.inst_agg0[inst], lb = b - c.inst_agg0[inst];
   const int ma = c.agg_modes[a], mb = c.agg_modes[b];
-#pragma unroll
-  for (int e = 0; e < 36; ++e) {
-    if (lane == e) {
-      const int r = e / 6, q = e % 6;
-      const double val = (r < ma && q < mb) ? acc[e] : 0.0;
-      M[(size_t)(6 * la + r) * np + 6 * lb + q] = val;
-      if (a != b) M[(size_t)(6 * lb + q) * np + 6 * la + r] = val;
-    }
-  }
+  const int r = tid / 6, q = tid % 6;
+  const double sum = ((s_part[0][tid] + s_part[1][tid]) + s_part[2][tid]) + s_part[3][tid];
+  const double val = (r < ma && q < mb) ? sum : 0.0;
+  M[(size_t)(6 * la + r) * np + 6 * lb + q] = val;
+  if (a != b) M[(size_t)(6 * lb + q) * np + 6 * la + r] = val;
 }
 
 // Middle level, one wavefront per run of kMid vertices: offsets of its members from
@@ -925,9 +945,19 @@ __global__ void __launch_bounds__(64) k_mid_setup(Mesh m, Coarse c, const double
         acc[(3 + r) * 6 + 3 + q] -= RAR[r * 3 + q];
       }
   }
+  // the 36 sums by recursive halving (lane l holds sum l), gathered for lane 0
+  __shared__ double s_acc[36];
+  {
+    double v[64];
 #pragma unroll
-  for (int e = 0; e < 36; ++e) acc[e] = wave_sum(acc[e]);
+    for (int e = 0; e < 64; ++e) v[e] = e < 36 ? acc[e] : 0.0;
+    const double t = wave_sums_scatter<64>(v, lane);
+    if (lane < 36) s_acc[lane] = t;
+  }
+  __syncthreads();
   if (lane == 0) {
+#pragma unroll
+    for (int e = 0; e < 36; ++e) acc[e] = s_acc[e];
     // Gauss-Jordan on the used modes (SPD: no pivoting); unused modes stay zero
     double g[36];
 #pragma unroll
@@ -957,7 +987,8 @@ __global__ void __launch_bounds__(64) k_mid_setup(Mesh m, Coarse c, const double
 }
 
 // Unit diagonal for the unused modes of every aggregate and for the padding rows
-// of every sheet (threads past the aggregates handle the sheets).
+// of every sheet (threads past the aggregates handle the sheets, and set the sheet's
+// success flag); the threads after those clear the sweep's flags.
 __global__ void __launch_bounds__(256) k_coarse_dead(Coarse c, int ninst) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a < c.nagg) {
@@ -968,6 +999,9 @@ __global__ void __launch_bounds__(256) k_coarse_dead(Coarse c, int ninst) {
     const int inst = a - c.nagg, np = c.inst_np[inst];
     double* M = c.mat + c.inst_coff[inst];
     for (int r = c.inst_nc[inst]; r < np; ++r) M[(size_t)r * np + r] = 1.0;
+    c.ok[inst] = 1;
+  } else if (a < c.nagg + ninst + ninst * c.sw_stride) {
+    c.sw_sync[a - c.nagg - ninst] = 0;
   }
 }
 
@@ -2906,14 +2940,19 @@ __global__ void __launch_bounds__(256) k_adj_elements(Mesh m, Elem el, AdjArgs<T
 
 // Per-vertex completion of one adjoint step: gather the element products,
 // gx -= ..., gv = mask(u - h^2 K_sys mu), dL/dF_{s-1} = h mu, density partial.
+// Sixteen lanes per vertex (one 16-lane DPP row), each taking every sixteenth incident
+// element; a butterfly within the row sums them and lane 0 of the row finishes.
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, g = lane & 15;
+  const int i0 = blockIdx.x * 16 + (int)(threadIdx.x >> 4);
   const int nv = m.nv;
-  if (i >= nv) return;
+  if (blockIdx.x * 16 + (int)((threadIdx.x >> 6) << 2) >= nv) return;   // a wavefront past the rows
+  const bool live = i0 < nv;   // lanes past the last row work on a copy of it
+  const int i = live ? i0 : nv - 1;
   const double h = a.h, h2 = a.h * a.h;
   double ag[3] = {0.0, 0.0, 0.0}, ak[3] = {0.0, 0.0, 0.0}, aw[3] = {0.0, 0.0, 0.0};
-  for (int c = m.vinc_ptr[i]; c < m.vinc_ptr[i + 1]; ++c) {
+  for (int c = m.vinc_ptr[i] + g; c < m.vinc_ptr[i + 1]; c += 16) {
     int ref = m.vinc_ref[c];
     if (ref >= 0) {
       int t = ref / 3, va = ref - 3 * (ref / 3);
@@ -2936,6 +2975,22 @@ __global__ void __launch_bounds__(256) k_adj_rows(Mesh m, Elem el, AdjArgs<T> a)
       }
     }
   }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    ag[r] += exch<8>(ag[r], lane);
+    ag[r] += exch<4>(ag[r], lane);
+    ag[r] += exch<2>(ag[r], lane);
+    ag[r] += exch<1>(ag[r], lane);
+    ak[r] += exch<8>(ak[r], lane);
+    ak[r] += exch<4>(ak[r], lane);
+    ak[r] += exch<2>(ak[r], lane);
+    ak[r] += exch<1>(ak[r], lane);
+    aw[r] += exch<8>(aw[r], lane);
+    aw[r] += exch<4>(aw[r], lane);
+    aw[r] += exch<2>(aw[r], lane);
+    aw[r] += exch<1>(aw[r], lane);
+  }
+  if (g != 0 || !live) return;
   const bool pin = m.pinned[i] != 0;
   const double varea = m.varea[i];
   double dpart = 0.0;
@@ -3119,7 +3174,9 @@ void launch_elements(const Mesh& m, const Elem& el, const double* x, const doubl
 
 template <typename T, typename TM>
 void launch_assemble(const Mesh& m, const Elem& el, const AssembleArgs<T, TM>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_assemble<T, TM>), dim3(blocks_for(m.nv, 64)), dim3(256), 0, st, m, el, a);
+  // sixteen lanes per row for every mesh size: the same summation order whatever the
+  // handle holds, so a sheet in a batch assembles bit for bit as on its own
+  hipLaunchKernelGGL((k_assemble<T, TM, 16>), dim3(blocks_for(m.nv, 16)), dim3(256), 0, st, m, el, a);
 }
 
 template <typename TM>
@@ -3240,12 +3297,10 @@ void launch_coarse_setup(const Mesh& m, const Coarse& c, const double* x, const 
   hipLaunchKernelGGL(k_coarse_frame, dim3(c.nagg), dim3(64), 0, st, m, c, x);
   launch_fill_double(c.mat, coarse_doubles, 0.0, st);
   if (c.npair > 0)
-    hipLaunchKernelGGL((k_coarse_assemble<TM>), dim3(c.npair), dim3(64), 0, st, m, c, A);
+    hipLaunchKernelGGL((k_coarse_assemble<TM>), dim3(c.npair), dim3(256), 0, st, m, c, A);
   if (c.nmid > 0) hipLaunchKernelGGL((k_mid_setup<TM>), dim3(c.nmid), dim3(64), 0, st, m, c, x, A);
-  hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst, 256)), dim3(256), 0, st, c,
-                     m.ninst);
-  launch_fill_int(c.sw_sync, m.ninst * c.sw_stride, 0, st);
-  launch_fill_int(c.ok, m.ninst, 1, st);
+  hipLaunchKernelGGL(k_coarse_dead, dim3(blocks_for(c.nagg + m.ninst + m.ninst * c.sw_stride, 256)),
+                     dim3(256), 0, st, c, m.ninst);
   // one launch per group of whole sheets whose workgroups are co-resident
   const size_t lds = gj_sweep_lds(c.sw_tpw);
   for (size_t g = 0; g + 1 < sweep_groups.size(); ++g) {
@@ -3297,7 +3352,7 @@ void launch_adj_elements(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hip
 
 template <typename T>
 void launch_adj_rows(const Mesh& m, const Elem& el, const AdjArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_rows<T>, dim3(blocks_for(m.nv, 256)), dim3(256), 0, st, m, el, a);
+  hipLaunchKernelGGL(k_adj_rows<T>, dim3(blocks_for(m.nv, 16)), dim3(256), 0, st, m, el, a);
 }
 
 template <typename T>

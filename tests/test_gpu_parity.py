@@ -164,3 +164,28 @@ def test_block_jacobi_only_matches_oracle():
     assert rel(out["forces"], ref["forces"]) <= 1e-4
     assert rel(out["x0"], ref["x0"]) <= 1e-4
     s.close()
+
+
+def test_coarse_space_cuts_iterations():
+    """The coarse level, whose inverse the one-launch sweep forms every step, is what
+    takes a 64x64 step from ~1,300 block-Jacobi CG iterations to ~110: a wrong,
+    inaccurate or disabled coarse inverse shows up as several times more iterations
+    (the true-residual test keeps the answers right either way, so parity alone would
+    not see it)."""
+    import torch
+    w = W.workload("H", steps=8)
+    inst = W.make_instances(w)[0]
+    dev = torch.device("cuda:0")
+    its = {}
+    for cs in (64, 0):
+        s = make_sim(w, [inst], coarse_size=cs)
+        x0 = torch.tensor(W.to_soa(inst.x0), dtype=s.dtype, device=dev)
+        F = torch.tensor(W.to_soa(inst.forces[:w.steps]), dtype=s.dtype, device=dev)
+        s.rollout(w.steps, x0, None, F, None, np.array([w.steps], np.int32))
+        assert s.status() == 0
+        its[cs] = float(s.cg_iters()[0].mean())
+        s.close()
+    note(f"64x64 sheet, {w.steps} steps: CG iterations per solve {its[64]:.0f} with the coarse "
+         f"space, {its[0]:.0f} block-Jacobi only")
+    assert its[64] <= 150
+    assert its[0] >= 5 * its[64]

@@ -1164,9 +1164,10 @@ __device__ __forceinline__ void sweep_load(const double* const (&src)[NB],
 //   1. the owner of tile (K+1, K+1) updates it with step K's panels, inverts it on one
 //      wavefront (the sweep of the tile gives -P_{K+1} = its value after step K+1 at
 //      once) and publishes P_{K+1};
-//   2. every other tile is updated as soon as the two panels it needs are published;
-//   3. the owners of the other tiles of row and column K+1 form step K+1's panels from
-//      their new values and P_{K+1}, and publish them.
+//   2. the owners of the other tiles of row and column K+1 update them, form step
+//      K+1's panels from their new values and P_{K+1}, and publish them;
+//   3. every other tile is updated as soon as the two panels it needs are published.
+// Each workgroup works through its tiles in that order (the longest path first).
 // Pivot step 0's inverse and panels come from an initial phase. Every step's panels and
 // inverse pivot tile have addresses of their own (nothing is rewritten within a launch,
 // so readers need no wait beyond the flag). Sync flags per sheet, each on a cache line
@@ -1336,8 +1337,10 @@ __global__ void __launch_bounds__(256) k_gj_sweep(Coarse c, int ninst, int wg0) 
       go = update(s, K);
     }
   }
-  // every workgroup has finished: A_c^-1 = -M as the solver's FP32 copy (tiles below
-  // the diagonal as transposes, diagonal tiles averaged with their transpose)
+  // this workgroup's tiles are final: A_c^-1 = -M as the solver's FP32 copy (tiles below
+  // the diagonal as transposes, diagonal tiles averaged with their transpose). A sheet
+  // whose inversion stopped (ok = 0, possibly set by another workgroup meanwhile) runs
+  // its solves without the copy, so a partial write is never read.
   __syncthreads();
   if (!go || __hip_atomic_load(ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
   float* Xo = c.xinv + c.inst_coff[inst];

@@ -101,7 +101,7 @@ struct Elem {
 // vertices keeps none). A_c = P^T A P is dense per sheet (nc = 6 x aggregates).
 constexpr int kMaxWgAgg = 4;      // aggregates overlapping one solver workgroup
 constexpr int kMaxAggWg = 4;      // solver workgroups overlapping one aggregate
-constexpr int kGjTile = 32;       // tile of the blocked Gauss-Jordan inversion
+constexpr int kGjTile = 32;       // tile of the blocked symmetric sweep (coarse inverse)
 constexpr int kSwMaxTiles = 4;    // tiles one sweep workgroup holds in LDS at most
 constexpr int kSwFlag = 32;       // ints between two sweep flags (one cache line each)
 constexpr int kMid = 16;          // vertices per aggregate of the middle level

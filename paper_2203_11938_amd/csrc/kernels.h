@@ -73,6 +73,19 @@ inline int pcg_threads(int rows) { return (rows + 63) / 64 * 64; }
 constexpr int kMaxRowBlocks = 32;
 // Rows of at most this many blocks can hold them in registers (kMatReg).
 constexpr int kRegRowBlocks = 13;
+// Every product A v sums a row's slots [0, kSpmvSplit) and [kSpmvSplit, maxnz)
+// separately and then adds the two (all matrix homes, so they agree bit for bit).
+// Register-resident rows in workgroups of at most kSplitRows rows run twice the
+// wavefronts: the second half holds and multiplies the rows' second slot range.
+constexpr int kSpmvSplit = 7;
+constexpr int kSplitRows = 128;
+inline bool pcg_split(int rows, int mat_home) {
+  return mat_home == kMatReg && pcg_threads(rows) <= kSplitRows;
+}
+// threads of a solver launch's workgroup
+inline int pcg_block(int rows, int mat_home) {
+  return pcg_split(rows, mat_home) ? 2 * pcg_threads(rows) : pcg_threads(rows);
+}
 template <typename TM>
 hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ);
 template <typename TM>

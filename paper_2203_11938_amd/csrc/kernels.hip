@@ -12,7 +12,9 @@
 //                   symmetric sweep, the FP32 copy; the 6x6 blocks of the middle level.
 //   k_pcg           persistent preconditioned pipelined CG: every workgroup owns a
 //                   row range, keeps its vectors in FP64 registers (matrix rows in
-//                   LDS or streamed); per iteration the workgroups of one sheet
+//                   registers, in LDS or streamed; register rows of small workgroups
+//                   split over two wavefront teams that each multiply half of every
+//                   row's blocks); per iteration the workgroups of one sheet
 //                   exchange their partial sums (tagged words, or a counter barrier
 //                   on large sheets) and publish the preconditioned vector as tagged
 //                   words that each workgroup polls for its halo only (reductions
@@ -1755,38 +1757,78 @@ __device__ __forceinline__ void applynb(const TM* __restrict__ Am, int stride, i
   }
 }
 
-// y = A v for this thread's row, v from the workgroup's LDS copy (own rows + halo).
-// CH: slots per batch of a streamed matrix (fewer when registers are scarce).
+// y = (slots kb..ke-1 of this thread's row) v, v from the workgroup's LDS copy (own
+// rows + halo). CH: slots per batch of a streamed matrix (fewer when registers are
+// scarce).
+template <typename TM, bool SB, int SCH>
+__device__ __forceinline__ void spmv_range(const TM* __restrict__ Am, int stride, int idx,
+                                           const int* __restrict__ Cl, int R, int tid, int kb,
+                                           int ke, const double* __restrict__ vl, int RH,
+                                           double y[3]) {
+  constexpr int CH = SB ? kChunk : SCH;
+  y[0] = y[1] = y[2] = 0.0;
+  for (int k0 = kb; k0 < ke; k0 += CH) {
+    double g[3][CH];
+    loadnb<CH, !SB>(Cl, R, tid, k0, ke, vl, RH, g);
+    applynb<TM, SB, CH>(Am, stride, idx, k0, ke, g, y);
+  }
+}
+
+// y = A v for this thread's row: slots [0, kSpmvSplit) and [kSpmvSplit, maxnz)
+// summed apart, then added.
 template <typename TM, bool SB, int SCH = kStreamChunk>
 __device__ __forceinline__ void spmv_row(const TM* __restrict__ Am, int stride, int idx,
                                          const int* __restrict__ Cl, int R, int tid, int maxnz,
                                          const double* __restrict__ vl, int RH, double y[3]) {
-  constexpr int CH = SB ? kChunk : SCH;
-  y[0] = y[1] = y[2] = 0.0;
-  for (int k0 = 0; k0 < maxnz; k0 += CH) {
-    double g[3][CH];
-    loadnb<CH, !SB>(Cl, R, tid, k0, maxnz, vl, RH, g);
-    applynb<TM, SB, CH>(Am, stride, idx, k0, maxnz, g, y);
-  }
+  double y2[3];
+  spmv_range<TM, SB, SCH>(Am, stride, idx, Cl, R, tid, 0, min(kSpmvSplit, maxnz), vl, RH, y);
+  spmv_range<TM, SB, SCH>(Am, stride, idx, Cl, R, tid, kSpmvSplit, maxnz, vl, RH, y2);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) y[r] += y2[r];
 }
 
-// y = A v for this thread's row with the row's blocks held in registers (copied once
-// per launch; slots past maxnz hold zero blocks): all neighbour values are read from
-// LDS first (local columns Cl as for the other products), then the products, in slot
-// order (the same operations in the same order as the streamed and LDS products).
-template <typename TM>
-__device__ __forceinline__ void spmv_reg(const TM (&Ar)[kRegRowBlocks][9],
-                                         const int* __restrict__ Cl, int R, int tid, int maxnz,
-                                         const double* __restrict__ vl, int RH, double y[3]) {
-  double g[3][kRegRowBlocks];
-  loadnb<kRegRowBlocks, true>(Cl, R, tid, 0, maxnz, vl, RH, g);
+// y = sum over held blocks k0..k1-1 of Ar[k] g[.][k], in slot order (the same
+// operations in the same order as the streamed and LDS products).
+template <typename TM, int NB>
+__device__ __forceinline__ void reg_products(const TM (&Ar)[NB][9], const double g[3][NB],
+                                             int k0, int k1, double y[3]) {
   y[0] = y[1] = y[2] = 0.0;
 #pragma unroll
-  for (int k = 0; k < kRegRowBlocks; ++k)
+  for (int k = 0; k < NB; ++k) {
+    if (k < k0 || k >= k1) continue;   // k0, k1 are compile-time after unrolling
 #pragma unroll
     for (int r = 0; r < 3; ++r)
       y[r] += (double)Ar[k][r * 3] * g[0][k] + (double)Ar[k][r * 3 + 1] * g[1][k] +
               (double)Ar[k][r * 3 + 2] * g[2][k];
+  }
+}
+
+// y = (slots kb..kb+NB-1 of this thread's row) v with those blocks held in registers
+// (copied once per launch; slots past maxnz hold zero blocks): all NB neighbour values
+// are read from LDS first (local columns Cl as for the other products; slots at or
+// past ke contribute zero), then the products.
+template <typename TM, int NB>
+__device__ __forceinline__ void spmv_reg_range(const TM (&Ar)[NB][9], const int* __restrict__ Cl,
+                                               int R, int tid, int kb, int ke,
+                                               const double* __restrict__ vl, int RH,
+                                               double y[3]) {
+  double g[3][NB];
+  loadnb<NB, true>(Cl, R, tid, kb, ke, vl, RH, g);
+  reg_products<TM, NB>(Ar, g, 0, NB, y);
+}
+
+// y = A v with the whole row in registers: one gather of all its neighbour values,
+// then the two slot ranges' sums, added.
+template <typename TM>
+__device__ __forceinline__ void spmv_reg(const TM (&Ar)[kRegRowBlocks][9],
+                                         const int* __restrict__ Cl, int R, int tid, int maxnz,
+                                         const double* __restrict__ vl, int RH, double y[3]) {
+  double g[3][kRegRowBlocks], y2[3];
+  loadnb<kRegRowBlocks, true>(Cl, R, tid, 0, maxnz, vl, RH, g);
+  reg_products<TM, kRegRowBlocks>(Ar, g, 0, kSpmvSplit, y);
+  reg_products<TM, kRegRowBlocks>(Ar, g, kSpmvSplit, kRegRowBlocks, y2);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) y[r] += y2[r];
 }
 
 // Restarts from the true residual per solve; one more verifies the final iterate.
@@ -1943,22 +1985,25 @@ struct CoarseRow {
   int nwm;               // most partial slots (workgroups) of any aggregate of the sheet
 };
 
-// e_q = sum_c X[q][c] w_c for the NR rows of this workgroup: the wavefronts take
-// 64-column tiles in turn, every lane accumulates all NR rows of its columns (NR x TU
-// independent loads per pass), then one recursive-halving reduction per wavefront and
-// a fixed-order sum over the wavefronts leave e in s_e[0..NR).
-template <int NR, bool XLDS>
+// e_q = sum_c X[q][c] w_c for the NR rows of this workgroup: the wavefronts that hold
+// rows (the first of TEAMS equal teams: the partition, and so the rounding, does not
+// depend on helper wavefronts) take 64-column tiles in turn, every lane accumulates
+// all NR rows of its columns (NR x TU independent loads per pass), then one
+// recursive-halving reduction per wavefront and a fixed-order sum over the wavefronts
+// leave e in s_e[0..NR).
+template <int NR, bool XLDS, int TEAMS>
 __device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld, int nc,
                                             const double* s_wc, double* s_red, double* s_e) {
   constexpr int NP = NR <= 8 ? 8 : (NR <= 16 ? 16 : 32);
   constexpr int TU = NR <= 6 ? 4 : (NR <= 12 ? 3 : 1);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nwaves = blockDim.x >> 6;
+  const int nwaves = (int)(blockDim.x >> 6) / TEAMS;
+  const bool rows = TEAMS == 1 || wave < nwaves;
   const int ntile = (nc + 63) >> 6;
   double acc[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-  for (int t0 = wave; t0 < ntile; t0 += TU * nwaves) {
+  for (int t0 = rows ? wave : ntile; t0 < ntile; t0 += TU * nwaves) {
     float xv[TU][NR];
     double wcv[TU];
 #pragma unroll
@@ -1978,7 +2023,7 @@ __device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld,
   const double t = wave_sums_scatter<NP>(acc, lane);
   constexpr int SH = (NP == 8 ? 3 : (NP == 16 ? 2 : 1));   // 6 - log2 NP
   const int idx = lane >> SH;
-  if ((lane & ((1 << SH) - 1)) == 0 && idx < NR) s_red[wave * 24 + idx] = t;
+  if ((lane & ((1 << SH) - 1)) == 0 && idx < NR && rows) s_red[wave * 24 + idx] = t;
   __syncthreads();
   if (tid < NR) {
     double e = 0.0;
@@ -1988,11 +2033,11 @@ __device__ __forceinline__ void coarse_rows(const float* __restrict__ X, int ld,
   __syncthreads();
 }
 
-template <int NR>
+template <int NR, int TEAMS>
 __device__ __forceinline__ void coarse_rows_at(const CoarseRow& cr_, const double* s_wc,
                                                double* s_red, double* s_e) {
-  if (cr_.XL) coarse_rows<NR, true>(cr_.XL, cr_.nc, cr_.nc, s_wc, s_red, s_e);
-  else coarse_rows<NR, false>(cr_.X, cr_.np, cr_.nc, s_wc, s_red, s_e);
+  if (cr_.XL) coarse_rows<NR, true, TEAMS>(cr_.XL, cr_.nc, cr_.nc, s_wc, s_red, s_e);
+  else coarse_rows<NR, false, TEAMS>(cr_.X, cr_.np, cr_.nc, s_wc, s_red, s_e);
 }
 
 // After the partial sums are published: the sheet's coarse residual w_c into LDS.
@@ -2130,16 +2175,17 @@ __device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, i
 
 // e = the rows of A_c^-1 belonging to this workgroup's aggregates times w_c (already
 // in LDS), then y += P_i e on this thread's row. Fixed summation order throughout.
-// Skipped when the step's inversion failed.
+// Skipped when the step's inversion failed. TEAMS: as for coarse_rows.
+template <int TEAMS>
 __device__ __forceinline__ void coarse_apply(const CoarseRow& cr_, int kloc, bool live,
                                              const double r[3], double y[3], const double* s_wc,
                                              double* s_red, double* s_e) {
   if (!cr_.ok) return;
   switch (cr_.nrow) {   // 6 x the workgroup's aggregates (uniform)
-    case 6: coarse_rows_at<6>(cr_, s_wc, s_red, s_e); break;
-    case 12: coarse_rows_at<12>(cr_, s_wc, s_red, s_e); break;
-    case 18: coarse_rows_at<18>(cr_, s_wc, s_red, s_e); break;
-    case 24: coarse_rows_at<24>(cr_, s_wc, s_red, s_e); break;
+    case 6: coarse_rows_at<6, TEAMS>(cr_, s_wc, s_red, s_e); break;
+    case 12: coarse_rows_at<12, TEAMS>(cr_, s_wc, s_red, s_e); break;
+    case 18: coarse_rows_at<18, TEAMS>(cr_, s_wc, s_red, s_e); break;
+    case 24: coarse_rows_at<24, TEAMS>(cr_, s_wc, s_red, s_e); break;
     default: break;
   }
   if (live) {
@@ -2151,6 +2197,7 @@ __device__ __forceinline__ void coarse_apply(const CoarseRow& cr_, int kloc, boo
 }
 
 // The whole coarse correction after the barrier that publishes the partial sums.
+template <int TEAMS>
 __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, bool live,
                                                const double r[3], double y[3],
                                                const int* s_pidx, double* s_wc, double* s_red,
@@ -2158,7 +2205,7 @@ __device__ __forceinline__ void coarse_correct(const CoarseRow& cr_, int kloc, b
   if (!cr_.ok) return;
   coarse_gather(cr_, s_pidx, s_wc);
   __syncthreads();
-  coarse_apply(cr_, kloc, live, r, y, s_wc, s_red, s_e);
+  coarse_apply<TEAMS>(cr_, kloc, live, r, y, s_wc, s_red, s_e);
 }
 
 // y += P1_i B1^-1 P1^T v on this thread's row: the middle-level correction. The run
@@ -2195,10 +2242,18 @@ __device__ __forceinline__ void mid_apply(const double* __restrict__ Bm, bool li
   }
 }
 
+// Kernel-only matrix home: register-resident rows split over two wavefront teams.
+constexpr int kMatRegHalf = 3;
+
 template <typename TM, int MM, bool COARSE, int OCC>
 __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, SolverWork w, Coarse cs,
                                              PcgArgs<TM> a) {
-  constexpr bool LDS_MATRIX = MM == kMatLds, REG_MATRIX = MM == kMatReg;
+  // SPLIT (rows of at most kSplitRows): the block is twice the row threads; threads
+  // PB + t hold slots [kSpmvSplit, maxnz) of row t in registers and compute that part
+  // of every product A v, and take part in everything else as rows that do not exist
+  constexpr bool SPLIT = MM == kMatRegHalf;
+  constexpr int TEAMS = SPLIT ? 2 : 1;
+  constexpr bool LDS_MATRIX = MM == kMatLds, REG_MATRIX = MM == kMatReg || SPLIT;
   static_assert(!REG_MATRIX || OCC == 1, "register-resident rows need the whole register file");
 #ifdef PHISFT_PHASES
   unsigned long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -2217,7 +2272,11 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   // RH: R plus the largest halo, rounded up to 8 (the stride of the vector copies)
   const int tid = threadIdx.x, R = plan.rows, RH = R + (plan.max_halo + 7) / 8 * 8;
   const int nv = m.nv, maxnz = m.maxnz;
-  const bool act = tid < nrows;
+  const int PB = SPLIT ? (int)blockDim.x / 2 : (int)blockDim.x;   // threads with rows
+  const bool helper = SPLIT && tid >= PB;
+  const int lrow = helper ? tid - PB : tid;   // the row whose blocks this thread holds
+  const bool act = tid < nrows;               // helpers: tid >= PB >= nrows
+  const bool hact = helper && lrow < nrows;
   const int i = row0 + (act ? tid : 0);
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
   const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
@@ -2233,27 +2292,54 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   double* s_wc = reinterpret_cast<double*>(Al + (LDS_MATRIX ? (size_t)maxnz * 9 * R : 0));
   double* s_red = s_wc + cs.max_nc;
   double* s_e = s_red + 4 * 6 * kMaxWgAgg;
-  double* s_mid = s_e + 6 * kMaxWgAgg;                             // [block / kMid][36]
-  int* s_pidx = reinterpret_cast<int*>(s_mid + (blockDim.x / kMid) * 36);
+  double* s_mid = s_e + 6 * kMaxWgAgg;                             // [PB / kMid][36]
+  int* s_pidx = reinterpret_cast<int*>(s_mid + (PB / kMid) * 36);
   float* s_x = reinterpret_cast<float*>(s_pidx + (cs.max_nc / 6) * kMaxAggWg);  // [nrow][nc]
   // matrix operand: LDS copy, or the assembled ELL array read in place
   const TM* Am = LDS_MATRIX ? Al : a.A;
   const int As = LDS_MATRIX ? R : nv;
   const int Ai = LDS_MATRIX ? tid : i;
-  // REG_MATRIX: the row's blocks, in registers for the launch
-  TM Ar[REG_MATRIX ? kRegRowBlocks : 1][9];
+  // REG_MATRIX: the row's blocks (SPLIT: one of its two slot ranges, from slot kr0),
+  // in registers for the launch
+  constexpr int NREG = SPLIT ? kSpmvSplit : (REG_MATRIX ? kRegRowBlocks : 1);
+  static_assert(!SPLIT || 2 * kSpmvSplit >= kRegRowBlocks, "two ranges hold a row");
+  TM Ar[NREG][9];
   if (REG_MATRIX) {
+    const int kr0 = helper ? kSpmvSplit : 0, ir = row0 + lrow;
 #pragma unroll
-    for (int k = 0; k < kRegRowBlocks; ++k) {
-      const bool in = act && k < maxnz;
-      const int j = in ? m.ell_col[k * nv + i] : -1;
+    for (int k = 0; k < NREG; ++k) {
+      const bool in = (act || hact) && kr0 + k < maxnz;
+      const int j = in ? m.ell_col[(kr0 + k) * nv + ir] : -1;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) Ar[k][q] = j < 0 ? TM(0) : a.A[(size_t)(k * 9 + q) * nv + i];
+      for (int q = 0; q < 9; ++q)
+        Ar[k][q] = j < 0 ? TM(0) : a.A[(size_t)((kr0 + k) * 9 + q) * nv + ir];
     }
   }
+  // y = A v for this thread's row; y is left unchanged on threads without a row. Every
+  // thread of the workgroup calls it (SPLIT: the second range's sums reach the row's
+  // thread through LDS, two buffers in turn: a helper rewrites one only after the
+  // next call's barrier, which every reader of the previous one has passed).
+  __shared__ double s_half[SPLIT ? 2 * 3 * kSplitRows : 1];
+  int nspmv = 0;
   auto spmv = [&](const double* vl, double y[3]) {
-    if constexpr (REG_MATRIX) spmv_reg<TM>(Ar, Cl, R, tid, maxnz, vl, RH, y);
-    else spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, vl, RH, y);
+    if constexpr (SPLIT) {
+      double t[3] = {0.0, 0.0, 0.0};
+      const int kb = helper ? kSpmvSplit : 0, ke = helper ? maxnz : min(kSpmvSplit, maxnz);
+      if (act || hact) spmv_reg_range<TM, kSpmvSplit>(Ar, Cl, R, lrow, kb, ke, vl, RH, t);
+      double* hb = s_half + (nspmv++ & 1) * 3 * kSplitRows;
+      if (hact) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hb[c * kSplitRows + lrow] = t[c];
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y[c] = t[c] + hb[c * kSplitRows + tid];
+      }
+    } else if (act) {
+      if constexpr (REG_MATRIX) spmv_reg<TM>(Ar, Cl, R, tid, maxnz, vl, RH, y);
+      else spmv_row<TM, LDS_MATRIX, SCH>(Am, As, Ai, Cl, R, tid, maxnz, vl, RH, y);
+    }
   };
   if (act) {
     for (int k = 0; k < maxnz; ++k) {
@@ -2328,7 +2414,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     for (int e = tid; e < nmw * 36; e += blockDim.x) s_mid[e] = cs.mid_inv[(size_t)m0 * 36 + e];
   }
   __syncthreads();
-  const double* Bm = s_mid + (tid / kMid) * 36;
+  const double* Bm = s_mid + (lrow / kMid) * 36;
 
   double J[9];
 #pragma unroll
@@ -2347,7 +2433,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     mid_apply(Bm, live, cr1, r, u);
     coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
     ok = cluster_barrier(bar, w.abort_flag, a.status, inst);
-    if (ok) coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
+    if (ok) coarse_correct<TEAMS>(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
   }
   // w_0 = A u_0 needs the neighbours' u_0 (LDS copy of parity 1; the loop starts at 0)
   double* ub = w.zbuf;
@@ -2366,7 +2452,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     if (ok) {
       halo_load(ub, nv, s_hidx, nh, ul, R, RH);
       __syncthreads();
-      if (act) spmv(ul, wv);
+      spmv(ul, wv);
     }
   }
 
@@ -2391,9 +2477,9 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(xb, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
+      double ax[3] = {0.0, 0.0, 0.0};
+      spmv(xl, ax);
       if (act) {
-        double ax[3];
-        spmv(xl, ax);
 #pragma unroll
         for (int c = 0; c < 3; ++c) r[c] = a.rhs[c * nv + i] - ax[c];
       }
@@ -2404,7 +2490,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
         mid_apply(Bm, live, cr1, r, u);
         coarse_restrict(cs.part, wg, wna, kf, kl, kloc, live, cr, r);
         if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
-        coarse_correct(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
+        coarse_correct<TEAMS>(crow, kloc, live, cr, u, s_pidx, s_wc, s_red, s_e);
       }
       __syncthreads();  // every thread is done reading xl before it is overwritten
       if (act) {
@@ -2418,7 +2504,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       if (!(ok = cluster_barrier(bar, w.abort_flag, a.status, inst))) break;
       halo_load(ub, nv, s_hidx, nh, xl, R, RH);
       __syncthreads();
-      if (act) spmv(xl, wv);
+      spmv(xl, wv);
 #pragma unroll
       for (int c = 0; c < 3; ++c) z[c] = q3[c] = sv[c] = p[c] = 0.0;
       fresh = 1;
@@ -2523,7 +2609,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     PHASE_T(t5);
     if (COARSE) {
       // m = M^-1 w needs the coarse correction before it is published for the SpMV
-      coarse_apply(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
+      coarse_apply<TEAMS>(crow, kloc, live, cr, mm, s_wc, s_red, s_e);
       PHASE_ADD(6, wall_clock64() - t5);
       unsigned long long* tb = w.tbuf + (size_t)par * 4 * nv;
       ++nep;
@@ -2543,8 +2629,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       }
       PHASE_ADD(5, wall_clock64() - t5);
     }
-    if (act) spmv(ml, nn);
-    else nn[0] = nn[1] = nn[2] = 0.0;
+    nn[0] = nn[1] = nn[2] = 0.0;
+    spmv(ml, nn);
     PHASE_T(t4);
     PHASE_ADD(0, t1 - t0);
     PHASE_ADD(1, t2 - t1);
@@ -3208,8 +3294,12 @@ static const void* pcg_entry_occ(int mat_home, bool coarse) {
   return reinterpret_cast<const void*>(&k_pcg<TM, kMatStream, false, OCC>);
 }
 
+// split: register-resident rows over two wavefront teams (pcg_split)
 template <typename TM>
-static const void* pcg_entry(int mat_home, bool coarse, int occ) {
+static const void* pcg_entry(int mat_home, bool coarse, int occ, bool split) {
+  if (mat_home == kMatReg && split)
+    return coarse ? reinterpret_cast<const void*>(&k_pcg<TM, kMatRegHalf, true, 1>)
+                  : reinterpret_cast<const void*>(&k_pcg<TM, kMatRegHalf, false, 1>);
   if (mat_home == kMatReg)
     return coarse ? reinterpret_cast<const void*>(&k_pcg<TM, kMatReg, true, 1>)
                   : reinterpret_cast<const void*>(&k_pcg<TM, kMatReg, false, 1>);
@@ -3228,8 +3318,12 @@ static bool pcg_shape_ok(int maxnz, int mat_home, int occ) {
 template <typename TM>
 hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ) {
   if (!pcg_shape_ok(maxnz, mat_home, occ)) return hipErrorInvalidValue;
-  return hipFuncSetAttribute(pcg_entry<TM>(mat_home, coarse, occ),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute(pcg_entry<TM>(mat_home, coarse, occ, false),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess && mat_home == kMatReg)
+    e = hipFuncSetAttribute(pcg_entry<TM>(mat_home, coarse, occ, true),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  return e;
 }
 
 template <typename TM>
@@ -3237,7 +3331,8 @@ hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int mat_home, bool coa
                          int* blocks_per_cu) {
   if (!pcg_shape_ok(maxnz, mat_home, occ)) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, pcg_entry<TM>(mat_home, coarse, occ), pcg_threads(rows), lds);
+      blocks_per_cu, pcg_entry<TM>(mat_home, coarse, occ, pcg_split(rows, mat_home)),
+      pcg_block(rows, mat_home), lds);
 }
 
 template <typename TM, int L, bool C, int O>
@@ -3271,7 +3366,13 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
   for (int g = 0; g < plan.ngroups; ++g) {
     SolverPlan pg = plan;
     pg.wg_base = plan.group_wg0_host[g];
-    const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base), block(pcg_threads(plan.rows));
+    const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base),
+        block(pcg_block(plan.rows, plan.mat_home));
+    if (pcg_split(plan.rows, plan.mat_home)) {
+      if (coarse) launch_pcg_v<TM, kMatRegHalf, true, 1>(grid, block, lds, st, m, pg, w, cs, a);
+      else launch_pcg_v<TM, kMatRegHalf, false, 1>(grid, block, lds, st, m, pg, w, cs, a);
+      continue;
+    }
     if (plan.mat_home == kMatReg) {
       // one workgroup per CU only (pcg_prepare rejects the rest)
       if (coarse) launch_pcg_v<TM, kMatReg, true, 1>(grid, block, lds, st, m, pg, w, cs, a);

@@ -399,7 +399,9 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       for (int xl : {xl_full, 0}) {
         const size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P0.max_halo, xl)
                                : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P0.max_halo, xl);
-        if (lds > lds_cap) continue;
+        // split register rows hand their second products over in 6 KB of static LDS
+        const size_t split_lds = pcg_split(rows, mode) ? 6 * kSplitRows * sizeof(double) : 0;
+        if (lds + split_lds > lds_cap) continue;
         // the one-workgroup-per-CU variant, and the two-per-CU one where it adds
         // co-resident workgroups
         int prev_cap = 0;

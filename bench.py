@@ -284,6 +284,7 @@ def main():
                            solver_matrix=S.MATRIX_HOMES[st["solver_matrix_home"]],
                            solver_launches_per_solve=st["solver_launches_per_solve"],
                            solver_wg_per_cu=st["solver_wg_per_cu"],
+                           solver_row_teams=st["solver_row_teams"],
                            coarse_rows_lds=bool(st["coarse_rows_lds"]),
                            device_bytes=int(st["device_bytes"]),
                            device_status=S.status_name(sim.status()),

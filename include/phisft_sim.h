@@ -254,6 +254,8 @@ typedef struct {
                                  checkpoints, kept coarse operators, tables) */
   int32_t coarse_store_slots; /* steps whose coarse operators are kept for the adjoint */
   int32_t material_params;    /* n_mat of the material arrays (3 or SIM_WANG_PARAMS) */
+  int32_t solver_row_teams;   /* 2: register-resident rows split over two wavefront teams
+                                 (workgroups of at most 128 rows), else 1 */
 } sim_stats;
 
 /* Fills *opt with the defaults: FP32 arrays, cg_tol 1e-7, cg_max_iter 20000,

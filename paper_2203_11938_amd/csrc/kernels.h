@@ -75,22 +75,23 @@ constexpr int kMaxRowBlocks = 32;
 constexpr int kRegRowBlocks = 13;
 // Every product A v sums a row's slots [0, kSpmvSplit) and [kSpmvSplit, maxnz)
 // separately and then adds the two (all matrix homes, so they agree bit for bit).
-// Register-resident rows in workgroups of at most kSplitRows rows run twice the
-// wavefronts: the second half holds and multiplies the rows' second slot range.
+// Register-resident rows in workgroups of at most kSplitRows rows may run twice the
+// wavefronts (SolverPlan::split): the second half holds and multiplies the rows'
+// second slot range.
 constexpr int kSpmvSplit = 7;
 constexpr int kSplitRows = 128;
-inline bool pcg_split(int rows, int mat_home) {
+inline bool pcg_can_split(int rows, int mat_home) {
   return mat_home == kMatReg && pcg_threads(rows) <= kSplitRows;
 }
 // threads of a solver launch's workgroup
-inline int pcg_block(int rows, int mat_home) {
-  return pcg_split(rows, mat_home) ? 2 * pcg_threads(rows) : pcg_threads(rows);
+inline int pcg_block(int rows, bool split) {
+  return split ? 2 * pcg_threads(rows) : pcg_threads(rows);
 }
 template <typename TM>
 hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ);
 template <typename TM>
 hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int mat_home, bool coarse, int occ,
-                         int* blocks_per_cu);
+                         bool split, int* blocks_per_cu);
 template <typename TM>
 void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, const Coarse& cs,
                 const PcgArgs<TM>& a, hipStream_t st);

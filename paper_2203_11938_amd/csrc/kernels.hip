@@ -3328,11 +3328,11 @@ hipError_t pcg_prepare(size_t lds, int maxnz, int mat_home, bool coarse, int occ
 
 template <typename TM>
 hipError_t pcg_occupancy(int rows, size_t lds, int maxnz, int mat_home, bool coarse, int occ,
-                         int* blocks_per_cu) {
+                         bool split, int* blocks_per_cu) {
   if (!pcg_shape_ok(maxnz, mat_home, occ)) return hipErrorInvalidValue;
+  if (split && !pcg_can_split(rows, mat_home)) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu, pcg_entry<TM>(mat_home, coarse, occ, pcg_split(rows, mat_home)),
-      pcg_block(rows, mat_home), lds);
+      blocks_per_cu, pcg_entry<TM>(mat_home, coarse, occ, split), pcg_block(rows, split), lds);
 }
 
 template <typename TM, int L, bool C, int O>
@@ -3367,8 +3367,8 @@ void launch_pcg(const Mesh& m, const SolverPlan& plan, const SolverWork& w, cons
     SolverPlan pg = plan;
     pg.wg_base = plan.group_wg0_host[g];
     const dim3 grid(plan.group_wg0_host[g + 1] - pg.wg_base),
-        block(pcg_block(plan.rows, plan.mat_home));
-    if (pcg_split(plan.rows, plan.mat_home)) {
+        block(pcg_block(plan.rows, plan.split != 0));
+    if (plan.split) {
       if (coarse) launch_pcg_v<TM, kMatRegHalf, true, 1>(grid, block, lds, st, m, pg, w, cs, a);
       else launch_pcg_v<TM, kMatRegHalf, false, 1>(grid, block, lds, st, m, pg, w, cs, a);
       continue;
@@ -3483,7 +3483,7 @@ PHISFT_INSTANTIATE_ASM(double, double)
 #define PHISFT_INSTANTIATE(T)                                                                    \
   template size_t pcg_lds_bytes<T>(int, int, int, int, int, int);                                \
   template hipError_t pcg_prepare<T>(size_t, int, int, bool, int);                               \
-  template hipError_t pcg_occupancy<T>(int, size_t, int, int, bool, int, int*);                  \
+  template hipError_t pcg_occupancy<T>(int, size_t, int, int, bool, int, bool, int*);            \
   template void launch_pcg<T>(const Mesh&, const SolverPlan&, const SolverWork&, const Coarse&, \
                               const PcgArgs<T>&, hipStream_t);                                   \
   template void launch_coarse_setup<T>(const Mesh&, const Coarse&, const double*, const T*,      \

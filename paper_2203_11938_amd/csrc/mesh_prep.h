@@ -56,6 +56,7 @@ struct HostLayout {
 
 struct HostPlan {
   int rows = 0, nwg = 0, mat_home = 1, occ = 1;   // mat_home: MatrixHome
+  int split = 0;   // register rows over two wavefront teams (SolverPlan::split)
   int barrier_slots = 0;   // root slots + group counter/flag slots
   std::vector<int> wg_inst, wg_row0, wg_nrows, inst_wg0, inst_nwg, inst_grp0;
   std::vector<int> group_wg0;  // solver launches: workgroup ranges of whole sheets

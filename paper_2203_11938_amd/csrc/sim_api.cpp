@@ -203,6 +203,7 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   p.rows = P.rows;
   p.mat_home = P.mat_home;
   p.occ = P.occ;
+  p.split = P.split;
   p.wg_base = 0;
   p.ngroups = (int)P.group_wg0.size() - 1;
   for (int g = 0; g <= p.ngroups; ++g) p.group_wg0_host[g] = P.group_wg0[g];
@@ -248,6 +249,7 @@ sim_status apply_plan(sim_t* s, const HostPlan& P) {
   s->stats.blocks = p.nwg;
   s->stats.solver_matrix_home = p.mat_home + 1;   // MatrixHome -> sim_matrix_home
   s->stats.solver_wg_per_cu = p.occ;
+  s->stats.solver_row_teams = p.split ? 2 : 1;
   s->stats.coarse_rows_lds = p.xl_floats > 0 ? 1 : 0;
   s->stats.solver_launches_per_solve = p.ngroups;
   return SIM_OK;
@@ -399,22 +401,27 @@ sim_status setup(sim_t* s, const std::vector<HostSheet>& sheets, double dt, cons
       for (int xl : {xl_full, 0}) {
         const size_t lds = m64 ? pcg_lds_bytes<double>(L.maxnz, rows, lm, cnc, P0.max_halo, xl)
                                : pcg_lds_bytes<float>(L.maxnz, rows, lm, cnc, P0.max_halo, xl);
-        // split register rows hand their second products over in 6 KB of static LDS
-        const size_t split_lds = pcg_split(rows, mode) ? 6 * kSplitRows * sizeof(double) : 0;
-        if (lds + split_lds > lds_cap) continue;
+        if (lds > lds_cap) continue;
         // the one-workgroup-per-CU variant, and the two-per-CU one where it adds
-        // co-resident workgroups
+        // co-resident workgroups; register rows of small workgroups also over two
+        // wavefront teams (tried first: equal launch counts then prefer it)
         int prev_cap = 0;
-        for (int occ = 1; occ <= (mode == kMatReg ? 1 : 2); ++occ) {
+        const int nvar = mode == kMatReg ? (pcg_can_split(rows, mode) ? 2 : 1) : 2;
+        for (int var = 0; var < nvar; ++var) {
+          const int occ = mode == kMatReg ? 1 : var + 1;
+          const bool split = mode == kMatReg && nvar == 2 && var == 0;
+          // split teams hand their second products over in 6 KB of static LDS
+          if (split && lds + 6 * kSplitRows * sizeof(double) > lds_cap) continue;
           HostPlan P = P0;
           P.xl_floats = xl;
           P.occ = occ;
+          P.split = split ? 1 : 0;
           hipError_t e = m64 ? pcg_prepare<double>(lds, L.maxnz, lm, coarse, occ)
                              : pcg_prepare<float>(lds, L.maxnz, lm, coarse, occ);
           if (e != hipSuccess) return hip_fail(s, e, "solver LDS attribute");
           int per_cu = 0;
-          e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, occ, &per_cu)
-                  : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, occ, &per_cu);
+          e = m64 ? pcg_occupancy<double>(rows, lds, L.maxnz, lm, coarse, occ, split, &per_cu)
+                  : pcg_occupancy<float>(rows, lds, L.maxnz, lm, coarse, occ, split, &per_cu);
           if (e != hipSuccess) return hip_fail(s, e, "solver occupancy");
           if (occ == 2 && per_cu <= prev_cap) continue;
           prev_cap = per_cu;

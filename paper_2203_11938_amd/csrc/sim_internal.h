@@ -181,6 +181,7 @@ struct SolverPlan {
   int group_wg0_host[kMaxSolverGroups + 1];  // workgroup ranges of the groups
   int mat_home;            // where the solver reads the matrix rows: MatrixHome
   int occ;                 // 1 or 2 workgroups of 256 threads per CU (kernel variant)
+  int split;               // 1: register rows over two wavefront teams (rows <= 128)
   int rows;                // rows per workgroup (LDS stride; block = rows rounded up to 64)
   const int* wg_inst;      // [nwg]
   const int* wg_row0;      // [nwg]

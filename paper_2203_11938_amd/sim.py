@@ -98,7 +98,7 @@ class _Stats(ctypes.Structure):
                 ("solver_wg_per_cu", ctypes.c_int32), ("coarse_rows_lds", ctypes.c_int32),
                 ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("coarse_store_slots", ctypes.c_int32),
-                ("material_params", ctypes.c_int32)]
+                ("material_params", ctypes.c_int32), ("solver_row_teams", ctypes.c_int32)]
 
 
 _lib = None

@@ -105,29 +105,36 @@ def test_batch_matches_single_instances():
         assert np.array_equal(batched["material"][b], single["material"][0]), b
 
 
-@pytest.mark.parametrize("coarse_size", [64, 0])
-def test_matrix_homes_are_bitwise_equal(coarse_size):
+@pytest.mark.parametrize("coarse_size,rows", [(64, 128), (0, 128), (64, 256)])
+def test_matrix_homes_are_bitwise_equal(coarse_size, rows):
     """Streamed, LDS-resident and register-resident matrix rows feed the same
     products in the same order: at the same launch shape (rows per workgroup, one
     workgroup per CU) the rollout and every gradient agree bit for bit; the
-    register-resident run also meets the FP64 gates against the oracle."""
+    register-resident run also meets the FP64 gates against the oracle. Register
+    rows of 128-row workgroups run over two wavefront teams (each multiplies one of
+    the row's two slot ranges); those of 256-row workgroups on one (whose FP64 rows do
+    not fit in LDS: streamed and registers only)."""
     w = W.workload("C2", steps=20, precision="fp64", cg_tol=1e-10)
     inst = W.make_instances(w)[0]
     tgt = inst.x0[None].repeat(w.steps, axis=0) + 0.01
     outs = {}
-    for home in ("streamed", "lds", "registers"):
-        s = make_sim(w, [inst], rows_per_block=128, matrix_home=home, coarse_size=coarse_size)
+    homes = ("streamed", "lds", "registers") if rows <= 128 else ("streamed", "registers")
+    for home in homes:
+        s = make_sim(w, [inst], rows_per_block=rows, matrix_home=home, coarse_size=coarse_size)
         st = s.stats()
         assert st["solver_matrix_home"] == ("auto", "streamed", "lds", "registers").index(home)
+        assert st["rows_per_block"] == rows
+        assert st["solver_row_teams"] == (2 if home == "registers" and rows <= 128 else 1)
         outs[home] = gpu_run(s, w, [inst], [tgt])
-        note(f"matrix home {home} (coarse {coarse_size}): workgroups per CU "
-             f"{st['solver_wg_per_cu']}, cg iters fwd {outs[home]['stats']['cg_iters_forward']}")
-    for home in ("lds", "registers"):
+        note(f"matrix home {home} (coarse {coarse_size}, rows {rows}): workgroups per CU "
+             f"{st['solver_wg_per_cu']}, row teams {st['solver_row_teams']}, "
+             f"cg iters fwd {outs[home]['stats']['cg_iters_forward']}")
+    for home in homes[1:]:
         for k in ("x", "forces", "x0", "v0", "material"):
             assert np.array_equal(outs[home][k], outs["streamed"][k]), (home, k)
     ref = oracle_reference(w, inst, tgt)
     assert rel(outs["registers"]["x"][-1], ref["x"][-1]) <= 1e-9
-    check_grads(outs["registers"], ref, 1e-6, f"registers (coarse {coarse_size})")
+    check_grads(outs["registers"], ref, 1e-6, f"registers (coarse {coarse_size}, rows {rows})")
 
 
 def test_autotuned_handle_matches_oracle():

@@ -3,8 +3,9 @@
 Inputs are seeded and synthetic: caller vertex orders that are random permutations,
 an irregular sheet (jittered rest positions, random cell diagonals), the smallest
 meshes (one triangle, a 2x2 grid), a fully pinned sheet, a one-step rollout, a
-rollout with no loss frames, and the handle options (FP32 stored matrix, other
-aggregate sizes, the tension membrane system). Gates: FP64 handles 1e-9 on
+rollout with no loss frames, a sheet whose rows fill the last workgroup only in part,
+and the handle options (FP32 stored matrix, other aggregate sizes, the tension
+membrane system, the solver's matrix homes). Gates: FP64 handles 1e-9 on
 positions and 1e-6 on gradients (relative, per block), as for the 32x32 workload;
 the FP32 stored matrix is held to the FP32 workload's 1e-5 and 1e-4.
 """
@@ -226,6 +227,29 @@ def test_matrix_home_on_rows_of_more_than_13_blocks():
     for k in ("x", "forces", "x0", "v0", "material"):
         assert np.array_equal(outs["lds"][k], outs["streamed"][k]), k
     check(outs["lds"], ref, 1e-9, 1e-6, "14x14 irregular sheet, LDS and streamed homes")
+
+
+@pytest.mark.parametrize("rows", [64, 128])
+def test_split_register_rows_on_a_ragged_sheet(rows):
+    """A 27x27 sheet (729 vertices): the last workgroup holds only part of its rows
+    and the last run of the middle level is short. Register rows on two wavefront
+    teams (the second team's threads of missing rows hold nothing) agree bit for bit
+    with streamed rows at the same launch shape, and with the oracle."""
+    w = fp64(15)
+    rest, tris = W.grid_sheet(27)
+    inst = instance(rest, tris, [26 * 27, 27 * 27 - 1], w.steps, 8)
+    tgt, ref = reference(w, inst)
+    outs = {}
+    for h in ("streamed", "registers"):
+        s = make_sim(w, [inst], matrix_home=h, rows_per_block=rows)
+        st = s.stats()
+        assert st["rows_per_block"] == rows
+        assert st["solver_row_teams"] == (2 if h == "registers" else 1)
+        outs[h] = gpu_run(s, w, [inst], [tgt])
+    for k in ("x", "forces", "x0", "v0", "material"):
+        assert np.array_equal(outs["registers"][k], outs["streamed"][k]), (rows, k)
+    check(outs["registers"], ref, 1e-9, 1e-6,
+          f"27x27 sheet, {rows} register rows on two teams")
 
 
 def test_rows_per_block_the_coarse_space_cannot_use():

@@ -2173,6 +2173,40 @@ __device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, i
   return ok;
 }
 
+// collect3_tagged in two halves for split register rows (registers to spare): lane q
+// of wavefront 0 reads workgroup iw0 + q (a tagged sheet has at most kTagWgMax <= 64
+// workgroups). The loads are issued first (collect3_issue, so that they travel while
+// the coarse columns are polled), then each is re-read until it carries the tag and
+// the three sums go to s_out (collect3_finish: the same sums in the same order).
+static_assert(kTagWgMax <= 64, "one workgroup per lane");
+__device__ __forceinline__ void collect3_issue(const unsigned long long* trp, int iw0, int nwg,
+                                               unsigned long long w0[3], unsigned long long w1[3]) {
+  const int q = min((int)(threadIdx.x & 63), nwg - 1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    load_tagged(trp + ((size_t)(iw0 + q) * kTagSlots + k) * 2, w0[k], w1[k]);
+}
+
+__device__ __forceinline__ bool collect3_finish(const unsigned long long* trp, int iw0, int nwg,
+                                                double* s_out, unsigned tag, int* abort_flag,
+                                                unsigned long long w0[3],
+                                                unsigned long long w1[3]) {
+  const int lane = threadIdx.x & 63;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  bool ok = true;
+  if (lane < nwg) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ok = ok && poll_tagged(trp + ((size_t)(iw0 + lane) * kTagSlots + k) * 2, tag, abort_flag,
+                             w0[k], w1[k]);
+      t[k] += tag_value(w0[k], w1[k]);
+    }
+  }
+  const double s = wave_sums_scatter<4>(t, lane);   // lane l holds sum l >> 4
+  if ((lane & 15) == 0 && (lane >> 4) < 3) s_out[lane >> 4] = s;
+  return ok;
+}
+
 // e = the rows of A_c^-1 belonging to this workgroup's aggregates times w_c (already
 // in LDS), then y += P_i e on this thread's row. Fixed summation order throughout.
 // Skipped when the step's inversion failed. TEAMS: as for coarse_rows.
@@ -2556,12 +2590,20 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     if (!tagp && !(ok = cluster_wait(bar, w.abort_flag, a.status, inst))) break;
     PHASE_T(t2);
     if (tagp) {
-      // the coarse residual and the dot partials are polled together
+      // the coarse residual and the dot partials are polled together; with split rows
+      // wavefront 0 issues the partials' loads first, so both round trips overlap
       __shared__ int s_late;
+      unsigned long long d0[3], d1[3];
+      if (SPLIT && tid < 64) collect3_issue(trp, iw0, nwg, d0, d1);
       if (tid == 0) s_late = 0;
       __syncthreads();
       bool got = coarse_gather_tagged(crow, s_pidx, s_wc, trp, (unsigned)pep, w.abort_flag);
-      got = collect3_tagged(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag) && got;
+      if constexpr (SPLIT) {
+        if (tid < 64)
+          got = collect3_finish(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag, d0, d1) && got;
+      } else {
+        got = collect3_tagged(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag) && got;
+      }
       if (!got) s_late = 1;
       __syncthreads();
       if (s_late) {

@@ -1476,9 +1476,11 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
 }
 
 // Sheets with at most this many solver workgroups exchange their per-iteration partial
-// sums as tagged words instead of through a cluster barrier (measured: 32 workgroups
-// gain, 157 lose).
-constexpr int kTagWgMax = 64;
+// sums as tagged words instead of through a cluster barrier (measured: 32 and 157
+// workgroups gain); the collection reads up to four workgroups' partials per lane.
+// Split register rows collect one workgroup per lane, so at most kTagWgMaxSplit.
+constexpr int kTagWgMax = 256;
+constexpr int kTagWgMaxSplit = 64;
 
 // Tagged publication of a vertex's three doubles of a row vector as four 64-bit words
 // (word-major, [4][nv]: each store instruction of a wavefront fills whole cache lines),
@@ -2174,11 +2176,11 @@ __device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, i
 }
 
 // collect3_tagged in two halves for split register rows (registers to spare): lane q
-// of wavefront 0 reads workgroup iw0 + q (a tagged sheet has at most kTagWgMax <= 64
-// workgroups). The loads are issued first (collect3_issue, so that they travel while
+// of wavefront 0 reads workgroup iw0 + q (their tagged sheets have at most
+// kTagWgMaxSplit <= 64 workgroups). The loads are issued first (collect3_issue, so that they travel while
 // the coarse columns are polled), then each is re-read until it carries the tag and
 // the three sums go to s_out (collect3_finish: the same sums in the same order).
-static_assert(kTagWgMax <= 64, "one workgroup per lane");
+static_assert(kTagWgMaxSplit <= 64, "one workgroup per lane");
 __device__ __forceinline__ void collect3_issue(const unsigned long long* trp, int iw0, int nwg,
                                                unsigned long long w0[3], unsigned long long w1[3]) {
   const int q = min((int)(threadIdx.x & 63), nwg - 1);
@@ -2315,7 +2317,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
   const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
   int nep = 0, pep = 0;   // tagged publications of m and of the partials
-  const bool tagp = COARSE && nwg <= kTagWgMax;
+  const bool tagp = COARSE && nwg <= (SPLIT ? kTagWgMaxSplit : kTagWgMax);
 
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][RH]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)RH);           // [maxnz][R] local columns
@@ -2570,10 +2572,10 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
                            wv[0] * u[0] + wv[1] * u[1] + wv[2] * u[2],
                            r[0] * r[0] + r[1] * r[1] + r[2] * r[2]};
     double* red_slot = w.red + (size_t)par * plan.nwg * 3;
-    // Coarse space on a sheet of at most kTagWgMax workgroups: the partials go out as
-    // tagged words that every workgroup of the sheet polls (no barrier). Larger
-    // sheets (their all-to-all polling costs more than it saves) and block-Jacobi
-    // only: plain partials released by a cluster barrier.
+    // Coarse space on a sheet of at most kTagWgMax (split rows: kTagWgMaxSplit)
+    // workgroups: the partials go out as tagged words that every workgroup of the sheet
+    // polls (no barrier). Larger sheets and block-Jacobi only: plain partials released
+    // by a cluster barrier.
     const unsigned long long* trp = w.tred + (size_t)par * plan.nwg * kTagSlots * 2;
     PHASE_T(t0);
     if (COARSE) {

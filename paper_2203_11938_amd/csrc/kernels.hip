@@ -1477,8 +1477,9 @@ __device__ __forceinline__ bool cluster_barrier(Barrier& b, int* abort_flag, int
 
 // Sheets with at most this many solver workgroups exchange their per-iteration partial
 // sums as tagged words instead of through a cluster barrier (measured: 32 and 157
-// workgroups gain); the collection reads up to four workgroups' partials per lane.
-// Split register rows collect one workgroup per lane, so at most kTagWgMaxSplit.
+// workgroups gain). The collection reads one workgroup's partials per thread, so a
+// sheet also has at most as many workgroups as a block has threads; split register
+// rows collect on wavefront 0 only (at most kTagWgMaxSplit).
 constexpr int kTagWgMax = 256;
 constexpr int kTagWgMaxSplit = 64;
 
@@ -2145,41 +2146,40 @@ __device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const
   }
 }
 
-__device__ __forceinline__ bool collect3_tagged(const unsigned long long* trp, int iw0, int nwg,
-                                                double* s_out, unsigned tag, int* abort_flag) {
-  const int lane = threadIdx.x & 63;
-  if ((threadIdx.x >> 6) != 0) return true;
+// The dot partials of a tagged sheet spread over the wavefronts: wavefront w reads
+// workgroup 64 w + lane (a tagged sheet has at most one workgroup per thread of the
+// block), and its three sums (fixed-order lane reduction) go to s_wd[3 w + k]. After
+// the caller's barrier the readers add the wavefronts' sums in order; with at most 64
+// workgroups that is wavefront 0's sum alone, the same value as collect3_finish.
+__device__ __forceinline__ bool collect3_waves(const unsigned long long* trp, int iw0, int nwg,
+                                               double* s_wd, unsigned tag, int* abort_flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (wave * 64 >= nwg) return true;   // uniform per wavefront
+  const int q = wave * 64 + lane;
+  unsigned long long w0[3], w1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    load_tagged(trp + ((size_t)(iw0 + min(q, nwg - 1)) * kTagSlots + k) * 2, w0[k], w1[k]);
   double t[4] = {0.0, 0.0, 0.0, 0.0};
   bool ok = true;
-  for (int q0 = lane; q0 < nwg; q0 += 4 * 64) {
-    unsigned long long w0[4][3], w1[4][3];
+  if (q < nwg) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        load_tagged(trp + ((size_t)(iw0 + min(q0 + 64 * u, nwg - 1)) * kTagSlots + k) * 2,
-                    w0[u][k], w1[u][k]);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (q0 + 64 * u >= nwg) continue;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        ok = ok && poll_tagged(trp + ((size_t)(iw0 + q0 + 64 * u) * kTagSlots + k) * 2, tag,
-                               abort_flag, w0[u][k], w1[u][k]);
-        t[k] += tag_value(w0[u][k], w1[u][k]);
-      }
+    for (int k = 0; k < 3; ++k) {
+      ok = ok && poll_tagged(trp + ((size_t)(iw0 + q) * kTagSlots + k) * 2, tag, abort_flag,
+                             w0[k], w1[k]);
+      t[k] += tag_value(w0[k], w1[k]);
     }
   }
-  const double s = wave_sums_scatter<4>(t, lane);   // lane l holds sum l >> 4
-  if ((lane & 15) == 0 && (lane >> 4) < 3) s_out[lane >> 4] = s;
+  const double sm = wave_sums_scatter<4>(t, lane);   // lane l holds sum l >> 4
+  if ((lane & 15) == 0 && (lane >> 4) < 3) s_wd[3 * wave + (lane >> 4)] = sm;
   return ok;
 }
 
-// collect3_tagged in two halves for split register rows (registers to spare): lane q
-// of wavefront 0 reads workgroup iw0 + q (their tagged sheets have at most
-// kTagWgMaxSplit <= 64 workgroups). The loads are issued first (collect3_issue, so that they travel while
+// Wavefront 0's part of collect3_waves in two halves for split register rows
+// (registers to spare; their tagged sheets have at most kTagWgMaxSplit <= 64
+// workgroups): the loads are issued first (collect3_issue, so that they travel while
 // the coarse columns are polled), then each is re-read until it carries the tag and
-// the three sums go to s_out (collect3_finish: the same sums in the same order).
+// the three sums go to s_out (collect3_finish).
 static_assert(kTagWgMaxSplit <= 64, "one workgroup per lane");
 __device__ __forceinline__ void collect3_issue(const unsigned long long* trp, int iw0, int nwg,
                                                unsigned long long w0[3], unsigned long long w1[3]) {
@@ -2298,6 +2298,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   constexpr int SCH = OCC >= 2 ? 4 : kStreamChunk;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ double s_out[3];
+  __shared__ double s_wd[3 * 4];   // tagged dot partials per wavefront (unsplit blocks)
   const int wg = plan.wg_base + blockIdx.x;
   const int inst = plan.wg_inst[wg];
   const int row0 = plan.wg_row0[wg];
@@ -2317,7 +2318,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
   Barrier bar = make_barrier(plan, w, inst, wg, iw0, nwg);
   const int h0 = plan.halo_ptr[wg], nh = plan.halo_ptr[wg + 1] - h0;
   int nep = 0, pep = 0;   // tagged publications of m and of the partials
-  const bool tagp = COARSE && nwg <= (SPLIT ? kTagWgMaxSplit : kTagWgMax);
+  const bool tagp =
+      COARSE && nwg <= (SPLIT ? kTagWgMaxSplit : min(kTagWgMax, (int)blockDim.x));
 
   double* mL = reinterpret_cast<double*>(lds_raw);                 // [2][3][RH]
   int* Cl = reinterpret_cast<int*>(mL + 6 * (size_t)RH);           // [maxnz][R] local columns
@@ -2593,7 +2595,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
     PHASE_T(t2);
     if (tagp) {
       // the coarse residual and the dot partials are polled together; with split rows
-      // wavefront 0 issues the partials' loads first, so both round trips overlap
+      // wavefront 0 issues the partials' loads first, so both round trips overlap;
+      // without, every wavefront collects up to 64 workgroups' partials
       __shared__ int s_late;
       unsigned long long d0[3], d1[3];
       if (SPLIT && tid < 64) collect3_issue(trp, iw0, nwg, d0, d1);
@@ -2604,7 +2607,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
         if (tid < 64)
           got = collect3_finish(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag, d0, d1) && got;
       } else {
-        got = collect3_tagged(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag) && got;
+        got = collect3_waves(trp, iw0, nwg, s_wd, (unsigned)pep, w.abort_flag) && got;
       }
       if (!got) s_late = 1;
       __syncthreads();
@@ -2623,9 +2626,17 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       collect3(red_slot, iw0, nwg, s_out);
       __syncthreads();
     }
-    const double gamma = s_out[0], delta = s_out[1];
+    double gamma = s_out[0], delta = s_out[1];
     rr = s_out[2];
-    __syncthreads();  // s_out is rewritten by the next collect3
+    if (!SPLIT && tagp) {
+      gamma = delta = rr = 0.0;
+      for (int q = 0; q * 64 < nwg; ++q) {
+        gamma += s_wd[3 * q];
+        delta += s_wd[3 * q + 1];
+        rr += s_wd[3 * q + 2];
+      }
+    }
+    __syncthreads();  // s_out and s_wd are rewritten by the next collection
     PHASE_T(t3);
     if (it == 0) bnorm = sqrt(rr);
     if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rr)) {

@@ -141,7 +141,9 @@ typedef enum { SIM_MATERIAL_ISOTROPIC = 0, SIM_MATERIAL_WANG = 1 } sim_material_
  *   SIM_MATRIX_LDS        copied once per solve into LDS (only where they fit).
  *   SIM_MATRIX_REGISTERS  copied once per solve into the registers of each row's
  *                         lane (rows of at most 13 blocks, i.e. grid sheets; one
- *                         solver workgroup per CU).
+ *                         solver workgroup per CU); in workgroups of at most 128
+ *                         rows the blocks may be split over two wavefront teams
+ *                         (sim_stats.solver_row_teams).
  * A home that no launch shape can use makes sim_create fail with SIM_E_INVALID. */
 typedef enum {
   SIM_MATRIX_AUTO = 0,
@@ -196,12 +198,13 @@ typedef struct {
                                when that fits 16 GB, else not at all (rebuilt in the
                                adjoint); with checkpointing see coarse_keep_all       */
   int32_t autotune;         /* 1: sim_create times every feasible solver launch shape
-                               (rows per workgroup; matrix rows in registers, in LDS or
-                               streamed; rows of the coarse inverse in LDS or streamed;
-                               one or two workgroups per CU) on the step system of the
-                               rest state and keeps the fastest; 0 (default): fewest
-                               co-resident launches, then the matrix homes in the order
-                               registers, LDS, streamed, then larger workgroups          */
+                               (rows per workgroup; matrix rows in registers, on one or
+                               two wavefront teams, in LDS or streamed; rows of the
+                               coarse inverse in LDS or streamed; one or two workgroups
+                               per CU) on the step system of the rest state and keeps
+                               the fastest; 0 (default): fewest co-resident launches,
+                               then the matrix homes in the order registers (two teams
+                               first), LDS, streamed, then larger workgroups           */
   int32_t graph;            /* 1: sim_rollout and sim_adjoint capture their launches
                                into a HIP graph (on a stream of the handle) and launch
                                it on the caller's stream; a later call with the same

@@ -1571,6 +1571,10 @@ __device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigne
 // round trip per batch, not per vertex). False (every thread) on a time-out or an
 // abort; the caller then stops.
 constexpr int kHaloBatch = 4;
+// SPREAD: vertices past the end re-read the thread's own first vertex instead of the
+// last one (no single address that every thread of the sheet reads; kept for split
+// register rows, where it measured faster)
+template <bool SPREAD>
 __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
                                                  const int* __restrict__ hidx, int nh,
                                                  double* __restrict__ vl, int R, int RH,
@@ -1585,8 +1589,10 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, i
     unsigned long long w[kHaloBatch][4];
 #pragma unroll
     for (int u = 0; u < kHaloBatch; ++u) {
-      // vertices past the end re-read the last one (no branches around the loads)
-      unsigned long long* p = const_cast<unsigned long long*>(tb) + hidx[min(h0 + u * nb, nh - 1)];
+      // vertices past the end re-read another (no branches around the loads)
+      const int hu = h0 + u * nb;
+      unsigned long long* p = const_cast<unsigned long long*>(tb) +
+                              hidx[SPREAD ? (hu < nh ? hu : h0) : min(hu, nh - 1)];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         w[u][k] = __hip_atomic_load(p + (size_t)k * nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2092,7 +2098,7 @@ __device__ __forceinline__ void coarse_gather(const CoarseRow& cr_, const int* s
 // iteration's tagged publication (slot base trp = [nwg][kTagSlots][2] words): loads are
 // issued together, then each entry is re-read until it carries `tag`. False on a
 // time-out or an abort (per thread; the caller combines).
-template <int NW>
+template <int NW, bool SPREAD>
 __device__ __forceinline__ bool coarse_gather_tagged_n(const CoarseRow& cr_, const int* s_pidx,
                                                        double* s_wc,
                                                        const unsigned long long* trp,
@@ -2106,7 +2112,10 @@ __device__ __forceinline__ bool coarse_gather_tagged_n(const CoarseRow& cr_, con
     const unsigned long long* adr[CU][NW];
 #pragma unroll
     for (int u = 0; u < CU; ++u) {
-      const int col = min(col0 + u * (int)blockDim.x, nc - 1);
+      // columns past the end re-read another (SPREAD: the thread's first one, as for
+      // halo_load_tagged)
+      const int cu = col0 + u * (int)blockDim.x;
+      const int col = SPREAD ? (cu < nc ? cu : col0) : min(cu, nc - 1);
       const int t = col / 6, q = col - 6 * t;
 #pragma unroll
       for (int k = 0; k < NW; ++k) {
@@ -2133,16 +2142,18 @@ __device__ __forceinline__ bool coarse_gather_tagged_n(const CoarseRow& cr_, con
   return ok;
 }
 
+template <bool SPREAD>
 __device__ __forceinline__ bool coarse_gather_tagged(const CoarseRow& cr_, const int* s_pidx,
                                                      double* s_wc,
                                                      const unsigned long long* trp,
                                                      unsigned tag, int* abort_flag) {
   if (!cr_.ok) return true;
   switch (cr_.nwm) {   // uniform
-    case 1: return coarse_gather_tagged_n<1>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
-    case 2: return coarse_gather_tagged_n<2>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
-    case 3: return coarse_gather_tagged_n<3>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
-    default: return coarse_gather_tagged_n<kMaxAggWg>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    case 1: return coarse_gather_tagged_n<1, SPREAD>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    case 2: return coarse_gather_tagged_n<2, SPREAD>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    case 3: return coarse_gather_tagged_n<3, SPREAD>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
+    default:
+      return coarse_gather_tagged_n<kMaxAggWg, SPREAD>(cr_, s_pidx, s_wc, trp, tag, abort_flag);
   }
 }
 
@@ -2602,7 +2613,8 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
       if (SPLIT && tid < 64) collect3_issue(trp, iw0, nwg, d0, d1);
       if (tid == 0) s_late = 0;
       __syncthreads();
-      bool got = coarse_gather_tagged(crow, s_pidx, s_wc, trp, (unsigned)pep, w.abort_flag);
+      bool got =
+          coarse_gather_tagged<SPLIT>(crow, s_pidx, s_wc, trp, (unsigned)pep, w.abort_flag);
       if constexpr (SPLIT) {
         if (tid < 64)
           got = collect3_finish(trp, iw0, nwg, s_out, (unsigned)pep, w.abort_flag, d0, d1) && got;
@@ -2674,7 +2686,7 @@ __global__ void __launch_bounds__(256, OCC) k_pcg(Mesh m, SolverPlan plan, Solve
         for (int c = 0; c < 3; ++c) ml[c * RH + tid] = mm[c];
       }
       PHASE_ADD(4, wall_clock64() - t5);
-      if (!halo_load_tagged(tb, nv, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
+      if (!halo_load_tagged<SPLIT>(tb, nv, s_hidx, nh, ml, R, RH, (unsigned)nep, w.abort_flag)) {
         if (tid == 0) {
           __hip_atomic_store(w.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           set_status(a.status, inst, ST_TIMEOUT);

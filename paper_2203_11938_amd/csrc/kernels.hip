@@ -1567,13 +1567,14 @@ __device__ __forceinline__ void load_tagged(const unsigned long long* p, unsigne
 
 // Halo of a tagged vector into vl[c][R + h]: every halo vertex's four words are polled
 // until all carry the publication's tag (bounded like the barrier's waits). A thread's
-// vertices are read kHaloBatch at a time, all loads issued before any is checked (one
-// round trip per batch, not per vertex). False (every thread) on a time-out or an
+// vertices are read kHaloBatch at a time (one with SPREAD), all loads issued before any
+// is checked (one round trip per batch, not per vertex). False (every thread) on a time-out or an
 // abort; the caller then stops.
 constexpr int kHaloBatch = 4;
 // SPREAD: vertices past the end re-read the thread's own first vertex instead of the
-// last one (no single address that every thread of the sheet reads; kept for split
-// register rows, where it measured faster)
+// last one (no single address that every thread of the sheet reads), and one vertex
+// per thread per pass (a split workgroup's 256 threads cover its halo in one); kept
+// for split register rows, where it measured faster
 template <bool SPREAD>
 __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, int nv,
                                                  const int* __restrict__ hidx, int nh,
@@ -1584,11 +1585,12 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, i
   __syncthreads();
   bool ok = true;
   const unsigned long long t = vtag(pub);
+  constexpr int HB = SPREAD ? 1 : kHaloBatch;
   const int nb = blockDim.x;
-  for (int h0 = threadIdx.x; h0 < nh && ok; h0 += kHaloBatch * nb) {
-    unsigned long long w[kHaloBatch][4];
+  for (int h0 = threadIdx.x; h0 < nh && ok; h0 += HB * nb) {
+    unsigned long long w[HB][4];
 #pragma unroll
-    for (int u = 0; u < kHaloBatch; ++u) {
+    for (int u = 0; u < HB; ++u) {
       // vertices past the end re-read another (no branches around the loads)
       const int hu = h0 + u * nb;
       unsigned long long* p = const_cast<unsigned long long*>(tb) +
@@ -1598,7 +1600,7 @@ __device__ __forceinline__ bool halo_load_tagged(const unsigned long long* tb, i
         w[u][k] = __hip_atomic_load(p + (size_t)k * nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
-    for (int u = 0; u < kHaloBatch; ++u) {
+    for (int u = 0; u < HB; ++u) {
       const int h = h0 + u * nb;
       if (h >= nh) break;
       unsigned long long* p = const_cast<unsigned long long*>(tb) + hidx[h];
@@ -2105,7 +2107,7 @@ __device__ __forceinline__ bool coarse_gather_tagged_n(const CoarseRow& cr_, con
                                                        unsigned tag, int* abort_flag) {
   const int tid = threadIdx.x;
   const int nc = cr_.nc;
-  constexpr int CU = 4;
+  constexpr int CU = SPREAD ? 2 : 4;   // batches of blockDim columns per pass
   bool ok = true;
   for (int col0 = tid; col0 < nc; col0 += CU * blockDim.x) {
     unsigned long long w0[CU][NW], w1[CU][NW];
